@@ -1,0 +1,199 @@
+/*
+ * maid.h -- C ABI of libmaid, the MI355X (gfx950) implementation of the hot
+ * path of MAID (method of adaptive inexact descent) applied to the
+ * Sobolev-regularised analytic deep prior (ADP-beta) for semi-blind
+ * deblurring, after Salehi, Bubba, Korolev, "Fast Inexact Bilevel
+ * Optimization for Analytical Deep Image Priors" (arXiv 2502.09758).
+ *
+ * The problem (Eq. 2.5 with T(b,x) a 2D convolution, Section 4.2):
+ *   upper:  min_theta  g(xhat(theta)) + r(theta),
+ *           g(x) = 1/2 ||a*x - y||^2,
+ *           r(theta) = beta (w0 ||theta-a||^2 + ||D_h(theta-a)||^2 + ||D_v(theta-a)||^2)
+ *   lower:  xhat(theta) = argmin_x h(x;theta) = 1/2 ||theta*x - y||^2 + alpha R(x)
+ * with R the smoothed total variation R(x) = sum_p sqrt(s_p^2 + eps^2) - eps,
+ * s_p the forward-difference gradient magnitude at pixel p (joint over the
+ * colour channels), a the known kernel of the upper-level operator.
+ *
+ * Conventions for every entry point:
+ *   - Images (x, y, q, gradients) are DEVICE arrays, planar [C][H][W],
+ *     row-major, contiguous, element type float (MAID_F32) or double
+ *     (MAID_F64) as fixed at maid_create.  Kernels theta, a are DEVICE arrays
+ *     of K*K doubles, row-major, K odd, centre (c0,c0), c0 = (K-1)/2.
+ *   - (theta*x)_c(i,j) = sum_{u,v} theta(u,v) x_c(i+c0-u, j+c0-v): true
+ *     convolution, zero outside the image, same output size.
+ *   - Arrays are caller-owned and must not alias each other unless stated.
+ *     The library never frees caller memory; a context owns only its
+ *     workspace.
+ *   - Every call enqueues work on `stream` and returns after that work has
+ *     completed (the solvers poll a device-side completion flag once per
+ *     chunk of iterations; scalar results are returned in host memory).
+ *   - Return codes: MAID_OK, or MAID_MAXITER (a warning: results written,
+ *     info holds the last residual), MAID_ACCURACY_FLOOR (maid_step only), or
+ *     a negative error, in which case the output arrays are not written and
+ *     maid_last_error describes the failure.  No exception crosses the ABI.
+ *   - One context serves one stream at a time; calls on one context must not
+ *     overlap.  For a given context and tile configuration, results are
+ *     bitwise reproducible (all reductions run in a fixed order).
+ */
+#ifndef MAID_H
+#define MAID_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { MAID_F32 = 0, MAID_F64 = 1 };
+enum { MAID_REG_TV = 0, MAID_REG_TV_CHANNELWISE = 1, MAID_REG_QUADRATIC = 2 };
+
+enum {
+    MAID_OK = 0,
+    MAID_MAXITER = 1,
+    MAID_ACCURACY_FLOOR = 2,
+    MAID_EINVAL = -1,
+    MAID_ENOMEM = -2,
+    MAID_EHIP = -3,
+    MAID_NOT_SPD = -4,
+    MAID_NONFINITE = -5
+};
+
+/* Problem description.  C in 1..3, K odd with 1 <= K <= 31 and K <= min(H,W).
+   reg: MAID_REG_TV (smoothed TV, one gradient magnitude per pixel over all
+   channels), MAID_REG_TV_CHANNELWISE (one per channel and pixel) or
+   MAID_REG_QUADRATIC (R = 1/2 ||Dx||^2, the Tikhonov case).  alpha >= 0,
+   eps_tv > 0 (TV only), beta >= 0, h1_w0 = weight of the L2 part of the H1
+   norm (1 full norm, 0 seminorm). */
+typedef struct {
+    int32_t H, W, C, K, dtype, reg;
+    double alpha, eps_tv, beta, h1_w0;
+} maid_desc;
+
+typedef struct {
+    int32_t iters;       /* gradient evaluations (lower) / CG iterations */
+    int32_t backtracks;  /* rejected trial steps (lower solve only) */
+    int32_t status;      /* return code of the solve */
+    double res_norm;     /* lower: ||grad h(x)||; CG: recursive residual norm */
+    double obj;          /* reserved (0) */
+    double L;            /* lower: final Lipschitz estimate */
+} maid_solve_info;
+
+/* Algorithm 2 hyperparameters (rho_lo/rho_hi: step-size factors, nu_lo/nu_hi:
+   accuracy factors, lambda: sufficient-decrease constant of Eq. 3.4, mu:
+   lower-level tolerance scale in Algorithm 1 (tol = eps*mu), L_g: Lipschitz
+   constant of grad g in Eq. 3.4 (<= 0: use ||a||_1^2), eps_min: stop with
+   MAID_ACCURACY_FLOOR once eps falls below it). */
+typedef struct {
+    double rho_lo, rho_hi, nu_lo, nu_hi, lambda, mu, L_g, eps_min;
+    int32_t max_bt, max_lower_iter, max_cg_iter;
+} maid_hparams;
+
+/* MAID state: theta (DEVICE, K*K doubles, updated in place), x and q
+   (DEVICE images, warm starts for the lower-level and CG solves, updated in
+   place), accuracies eps (lower level) and delta (CG), step size, lower-level
+   Lipschitz estimate L (<= 0: start from ||theta||_1^2), outer counter k. */
+typedef struct {
+    void* theta;
+    void* x;
+    void* q;
+    double eps, delta, step, L;
+    int32_t k;
+} maid_state;
+
+typedef struct {
+    int32_t accepted, trials, retries, lower_iters, cg_iters, status;
+    double psi, ell_k, ell_next, znorm;
+} maid_step_info;
+
+typedef struct maid_ctx maid_ctx;
+
+/* Allocate a context and its device workspace for problems of this shape on
+   the current HIP device.  Errors: MAID_EINVAL (bad description; nothing
+   allocated), MAID_ENOMEM, MAID_EHIP.  *out is NULL on error. */
+int maid_create(const maid_desc* desc, maid_ctx** out);
+void maid_destroy(maid_ctx* ctx);
+/* Text of the last error on this context ("" if none); valid until the next
+   call on the context.  maid_last_error(NULL) reports the last maid_create
+   failure of the calling thread. */
+const char* maid_last_error(const maid_ctx* ctx);
+/* Name of the tile configuration (rows per thread) chosen for each kernel. */
+const char* maid_config_string(const maid_ctx* ctx);
+/* Override the rows-per-thread tile parameter of the stencil kernels
+   (1, 2 or 4; 0 = automatic).  Used by the autotuner. */
+int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
+
+/* Algorithm 1, lower-level solve: accelerated gradient (FISTA) with
+   backtracking (factor 2) on min_x h(x;theta).  Each iteration evaluates
+   G = grad h(v) at the extrapolated point v and stops there once
+   ||G||_2 <= tol (Algorithm 1 uses tol = eps * mu(b)), returning v; otherwise
+   it steps x+ = v - G/L and doubles L until h(x+) - h(v) <= -||G||^2/(2L).
+   x: in = starting point, out = the returned point.  L_inout: Lipschitz
+   estimate in/out (<= 0 on input: ||theta||_1^2).  trace_bt (HOST, nullable,
+   length >= max_iter): rejected trials per iteration.  info: nullable. */
+int maid_lower_solve(maid_ctx* ctx, const void* theta, const void* y, void* x,
+                     double tol, int32_t max_iter, double* L_inout,
+                     maid_solve_info* info, int32_t* trace_bt, hipStream_t stream);
+
+/* Upper-level value and gradient at x: rho = a*x - y, g = 1/2||rho||^2,
+   grad_out = a.rho (adjoint convolution; nullable), gradnorm = ||grad||_2. */
+int maid_upper_value_grad(maid_ctx* ctx, const void* a, const void* y, const void* x,
+                          void* grad_out, double* g_out, double* gradnorm_out,
+                          hipStream_t stream);
+
+/* Algorithm 1, Hessian system: conjugate gradients on
+   (theta.theta* + alpha grad^2 R(x_tilde)) q = rhs, stopping when the
+   recursive residual satisfies ||r||_2 <= tol (the accuracy delta).
+   q: in = starting point, out = solution.  MAID_NOT_SPD if a curvature
+   <p,Hp> <= 0 is met (q not written). */
+int maid_adjoint_solve(maid_ctx* ctx, const void* theta, const void* x_tilde,
+                       const void* rhs, void* q, double tol, int32_t max_iter,
+                       maid_solve_info* info, hipStream_t stream);
+
+/* Algorithm 1, last line, and Eq. (3.2): the hypergradient
+   z(u,v) = -sum_{c,i,j} [rho_c(i,j) q_c(i+c0-u,j+c0-v) + (theta*q)_c(i,j) x_c(i+c0-u,j+c0-v)]
+            + with_r * grad r(theta)(u,v),
+   rho = theta*x_tilde - y.  z: DEVICE, K*K doubles.  a may be NULL when
+   with_r == 0 or beta == 0.  znorm_out (HOST, nullable) = ||z||_2. */
+int maid_hypergrad(maid_ctx* ctx, const void* theta, const void* a, const void* y,
+                   const void* x_tilde, const void* q, int32_t with_r, double* z,
+                   double* znorm_out, hipStream_t stream);
+
+/* The objective values used by Eq. (3.4): r(theta) (HOST out). */
+int maid_sobolev_value(maid_ctx* ctx, const void* theta, const void* a, double* r_out,
+                       hipStream_t stream);
+
+/* Algorithm 2, one outer iteration k: the retry loop over accuracies
+   (j = max_bt, max_bt+1, ...), each computing InexactGradient and testing up
+   to j step sizes with psi(step) <= 0 (Eq. 3.4, all terms in FP64; the trial
+   lower-level solve runs at the current accuracy eps); on success
+   theta <- theta - step*z and eps, delta, step grow by nu_hi, nu_hi, rho_hi;
+   on failure of all j trials eps, delta shrink by nu_lo.  Returns
+   MAID_ACCURACY_FLOOR (theta unchanged) once eps < eps_min. */
+int maid_step(maid_ctx* ctx, const void* a, const void* y, maid_state* state,
+              const maid_hparams* hp, maid_step_info* info, hipStream_t stream);
+
+/* Kernel timing (for measurement and profiling tools).  maid_profile(ctx, 1)
+   resets the counters and, until maid_profile(ctx, 0), brackets every kernel
+   launch of the context with a pair of HIP events on the launch stream;
+   maid_profile_read returns, for one kernel kind, the number of timed
+   launches and their summed GPU duration in milliseconds. */
+enum {
+    MAID_PROF_CONV = 0,       /* convolution / adjoint passes (setup, upper level, hypergradient) */
+    MAID_PROF_APG_GRAD = 1,   /* lower level: gradient at the extrapolated point */
+    MAID_PROF_APG_TRIAL = 2,  /* lower level: trial step and decrease test */
+    MAID_PROF_CG_DIR = 3,     /* CG: new direction and theta*p */
+    MAID_PROF_CG_HVP = 4,     /* CG: Hessian-vector product and curvature */
+    MAID_PROF_CG_UPDATE = 5,  /* CG: q, r update and residual norm */
+    MAID_PROF_HG_CORR = 6,    /* hypergradient correlation (FP64 MFMA) */
+    MAID_PROF_OTHER = 7,      /* small kernels */
+    MAID_PROF_KINDS = 8
+};
+int maid_profile(maid_ctx* ctx, int32_t enable);
+int maid_profile_read(maid_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms);
+const char* maid_profile_name(int32_t kind);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,196 @@
+"""Torch front end of libmaid: one `Maid` context per problem shape.
+
+Names follow the C ABI (include/maid.h) and the paper: `lower_solve` is the
+lower-level solve of Algorithm 1, `adjoint_solve` its Hessian system,
+`hypergrad` its last line (Eq. 3.2), `maid_step` one iteration of
+Algorithm 2.  Tensors live on the GPU; this module only checks and
+marshals them.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.MAID_F32, torch.float64: L.MAID_F64}
+
+# Algorithm 2 hyperparameters; the four factors and the iteration cap are the
+# values printed in Section 4.1, the rest are this build's readings.
+DEFAULT_HPARAMS = dict(rho_lo=0.5, rho_hi=1.1, nu_lo=0.5, nu_hi=1.25, lambda_=1e-4, mu=1.0,
+                       L_g=0.0, eps_min=1e-12, max_bt=3, max_lower_iter=300, max_cg_iter=1000)
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    backtracks: int = 0
+    res_norm: float = 0.0
+    L: float = 0.0
+    trace: list = field(default_factory=list)
+
+
+@dataclass
+class MaidState:
+    """theta (K x K float64), x and q (C x H x W, storage dtype) on the GPU,
+    updated in place by `Maid.maid_step`."""
+    theta: torch.Tensor
+    x: torch.Tensor
+    q: torch.Tensor
+    eps: float = 1e-2
+    delta: float = 1e-2
+    step: float = 0.1
+    L: float = 0.0
+    k: int = 0
+
+
+class Maid:
+    def __init__(self, C, H, W, K, dtype=torch.float32, alpha=1e-3, eps_tv=1e-2, beta=0.0,
+                 h1_w0=1.0, reg=L.MAID_REG_TV):
+        if dtype not in _DT:
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.C, self.H, self.W, self.K = int(C), int(H), int(W), int(K)
+        self.dtype = dtype
+        self.alpha, self.eps_tv, self.beta, self.h1_w0, self.reg = alpha, eps_tv, beta, h1_w0, reg
+        self.desc = L.maid_desc(self.H, self.W, self.C, self.K, _DT[dtype], int(reg), float(alpha),
+                                float(eps_tv), float(beta), float(h1_w0))
+        self._h = None
+        self._h = L.create(self.desc)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and L is not None and L._lib is not None:
+            L._lib.maid_destroy(ct.c_void_p(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
+
+    # ------------------------------------------------------------------ checks
+    @property
+    def handle(self):
+        return ct.c_void_p(self._h)
+
+    @property
+    def shape(self):
+        return (self.C, self.H, self.W)
+
+    def _img(self, t, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous {self.dtype} of shape {self.shape}, got "
+                             f"{t.dtype} {tuple(t.shape)}")
+        return t
+
+    def _ker(self, t, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != torch.float64 or tuple(t.shape) != (self.K, self.K) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous float64 of shape {(self.K, self.K)}")
+        return t
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise L.MaidError(rc, f"{what}: {L.last_error(self.handle)}")
+        return rc
+
+    def config(self) -> str:
+        return L.lib().maid_config_string(self.handle).decode()
+
+    def set_tile_rows(self, rows: int):
+        self._check(L.lib().maid_set_tile_rows(self.handle, int(rows)), "set_tile_rows")
+
+    def profile(self, enable: bool):
+        """Start (reset) or stop per-launch kernel timing."""
+        self._check(L.lib().maid_profile(self.handle, int(bool(enable))), "profile")
+
+    def profile_read(self) -> dict:
+        """{kernel kind: (launches, total milliseconds)}"""
+        out = {}
+        for k in range(L.PROF_KINDS):
+            n, ms = ct.c_int64(), ct.c_double()
+            self._check(L.lib().maid_profile_read(self.handle, k, ct.byref(n), ct.byref(ms)), "profile_read")
+            out[L.lib().maid_profile_name(k).decode()] = (n.value, ms.value)
+        return out
+
+    # ------------------------------------------------------------------ entry points
+    def lower_solve(self, theta, y, x, tol, max_iter=300, L_est=0.0, trace=False):
+        """Solve the lower level in place in `x` (in: start, out: result)."""
+        self._ker(theta, "theta"), self._img(y, "y"), self._img(x, "x")
+        Lc = ct.c_double(L_est)
+        info = L.maid_solve_info()
+        tr = (ct.c_int32 * max(1, max_iter))() if trace else None
+        rc = L.lib().maid_lower_solve(self.handle, _ptr(theta), _ptr(y), _ptr(x), float(tol), int(max_iter),
+                                      ct.byref(Lc), ct.byref(info), tr, _stream())
+        self._check(rc, "lower_solve")
+        return SolveInfo(rc, info.iters, info.backtracks, info.res_norm, info.L,
+                         list(tr[:info.iters]) if trace else [])
+
+    def upper_value_grad(self, a, y, x, grad_out=None):
+        self._ker(a, "a"), self._img(y, "y"), self._img(x, "x")
+        if grad_out is not None:
+            self._img(grad_out, "grad_out")
+        g, gn = ct.c_double(), ct.c_double()
+        rc = L.lib().maid_upper_value_grad(self.handle, _ptr(a), _ptr(y), _ptr(x),
+                                           _ptr(grad_out) if grad_out is not None else None,
+                                           ct.byref(g), ct.byref(gn), _stream())
+        self._check(rc, "upper_value_grad")
+        return g.value, gn.value
+
+    def adjoint_solve(self, theta, x_tilde, rhs, q, tol, max_iter=1000):
+        """CG on the lower-level Hessian, in place in `q`."""
+        self._ker(theta, "theta"), self._img(x_tilde, "x_tilde"), self._img(rhs, "rhs"), self._img(q, "q")
+        info = L.maid_solve_info()
+        rc = L.lib().maid_adjoint_solve(self.handle, _ptr(theta), _ptr(x_tilde), _ptr(rhs), _ptr(q), float(tol),
+                                        int(max_iter), ct.byref(info), _stream())
+        self._check(rc, "adjoint_solve")
+        return SolveInfo(rc, info.iters, 0, info.res_norm, 0.0)
+
+    def hypergrad(self, theta, a, y, x_tilde, q, with_r=True, z=None):
+        self._ker(theta, "theta"), self._img(y, "y"), self._img(x_tilde, "x_tilde"), self._img(q, "q")
+        if a is not None:
+            self._ker(a, "a")
+        if z is None:
+            z = torch.empty((self.K, self.K), dtype=torch.float64, device=theta.device)
+        self._ker(z, "z")
+        zn = ct.c_double()
+        rc = L.lib().maid_hypergrad(self.handle, _ptr(theta), _ptr(a) if a is not None else None, _ptr(y),
+                                    _ptr(x_tilde), _ptr(q), int(bool(with_r)), _ptr(z), ct.byref(zn), _stream())
+        self._check(rc, "hypergrad")
+        return z, zn.value
+
+    def sobolev_value(self, theta, a):
+        self._ker(theta, "theta"), self._ker(a, "a")
+        r = ct.c_double()
+        self._check(L.lib().maid_sobolev_value(self.handle, _ptr(theta), _ptr(a), ct.byref(r), _stream()),
+                    "sobolev_value")
+        return r.value
+
+    def maid_step(self, a, y, state: MaidState, **hp):
+        self._ker(a, "a"), self._img(y, "y"), self._ker(state.theta, "theta")
+        self._img(state.x, "x"), self._img(state.q, "q")
+        h = dict(DEFAULT_HPARAMS)
+        h.update(hp)
+        hpc = L.maid_hparams(**h)
+        st = L.maid_state(state.theta.data_ptr(), state.x.data_ptr(), state.q.data_ptr(), state.eps, state.delta,
+                          state.step, state.L, state.k)
+        info = L.maid_step_info()
+        rc = L.lib().maid_step(self.handle, _ptr(a), _ptr(y), ct.byref(st), ct.byref(hpc), ct.byref(info), _stream())
+        self._check(rc, "maid_step")
+        state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
+        return rc, {f: getattr(info, f) for f, _ in L.maid_step_info._fields_}

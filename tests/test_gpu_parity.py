@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle
+on the same seeded inputs.
+
+Tolerances: the FP64 instantiation to 1e-10..1e-12 relative (rounding-order
+differences only); the FP32-storage path to 1e-5 relative, the bar set for
+lower-level solutions and hypergradients.  Solver comparisons use the
+decision-replay protocol: the GPU records its backtracking decisions and
+iteration counts and the oracle replays them, so both sides run the same
+sequence of operations and differ only by rounding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2502_09758_amd import synth
+from paper_2502_09758_amd.maid import Maid, MaidState
+from paper_2502_09758_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f32": torch.float32, "f64": torch.float64}
+TOL = {"f32": 1e-5, "f64": 1e-11}
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def stored(a, dt):
+    """the values the GPU actually holds for an input array"""
+    return np.asarray(a, dtype=np.float32).astype(np.float64) if dt == "f32" else np.asarray(a, np.float64)
+
+
+def problem(C, H, W, K, seed=1, reg=0):
+    inst = synth.make("cfg1", H=H, W=W, C=C, K=K, seed=seed)
+    p = O.Problem(C, H, W, K, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta, reg=reg)
+    return inst, p
+
+
+SHAPES = [(1, 16, 16, 3), (1, 37, 70, 7), (3, 45, 130, 9), (2, 64, 64, 15), (1, 33, 40, 31), (3, 70, 67, 5),
+          (1, 9, 200, 1)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("C,H,W,K", SHAPES)
+@pytest.mark.parametrize("rows", [1, 2, 4])
+def test_upper_value_grad(dt, C, H, W, K, rows):
+    print(f"[case] upper_value_grad {dt} C={C} H={H} W={W} K={K} rows={rows}", flush=True)
+    inst, p = problem(C, H, W, K)
+    rng = np.random.default_rng(3)
+    x = stored(inst.y + 0.05 * rng.standard_normal(inst.y.shape), dt)
+    y = stored(inst.y, dt)
+    m = Maid(C, H, W, K, DT[dt], alpha=p.alpha, eps_tv=p.eps_tv, beta=p.beta)
+    m.set_tile_rows(rows)
+    grad = torch.empty((C, H, W), dtype=DT[dt], device="cuda")
+    g, gn = m.upper_value_grad(dev(inst.a, torch.float64), dev(y, DT[dt]), dev(x, DT[dt]), grad)
+    gref, g0, gn0 = O.upper_value_grad(p, inst.a, y, x)
+    assert rel(host(grad), gref) <= TOL[dt]
+    assert abs(g - g0) <= TOL[dt] * abs(g0)
+    assert abs(gn - gn0) <= TOL[dt] * gn0
+
+
+LOWER = [(1, 32, 32, 7, "f64"), (3, 40, 72, 5, "f64"), (1, 64, 64, 7, "f32"), (1, 96, 80, 9, "f32"),
+         (3, 48, 100, 15, "f32"), (2, 50, 50, 31, "f32"), (1, 24, 24, 3, "f64")]
+
+
+@pytest.mark.parametrize("C,H,W,K,dt", LOWER)
+@pytest.mark.parametrize("reg", [0, 1, 2])
+def test_lower_solve_replay_parity(C, H, W, K, dt, reg):
+    print(f"[case] lower_solve {dt} C={C} H={H} W={W} K={K} reg={reg}", flush=True)
+    inst, p = problem(C, H, W, K, seed=2, reg=reg)
+    y = stored(inst.y, dt)
+    tol = 1e-4 if dt == "f64" else 3e-3
+    m = Maid(C, H, W, K, DT[dt], alpha=p.alpha, eps_tv=p.eps_tv, reg=reg)
+    x = dev(y, DT[dt])
+    info = m.lower_solve(dev(inst.a, torch.float64), dev(y, DT[dt]), x, tol, max_iter=3000, L_est=0.0, trace=True)
+    assert info.status == L.OK and info.iters > 3
+    xr, ir, tr = O.lower_solve(p, inst.a, y, y, tol=0.0, max_iter=info.iters, L=0.0, replay_bt=info.trace)
+    assert ir["L"] == pytest.approx(info.L, rel=1e-15)
+    assert rel(host(x), xr) <= (1e-10 if dt == "f64" else 1e-5)
+    # the returned point meets the tolerance when its gradient is recomputed in FP64
+    assert np.linalg.norm(O.h_grad(p, inst.a, y, host(x))) <= tol * (1.0 + (1e-9 if dt == "f64" else 1e-2))
+    if dt == "f64":
+        xf, iff, trf = O.lower_solve(p, inst.a, y, y, tol=tol, max_iter=3000, L=0.0)
+        assert iff["iters"] == info.iters and list(trf) == info.trace
+
+
+@pytest.mark.parametrize("C,H,W,K,dt", [(1, 32, 32, 7, "f64"), (3, 40, 72, 5, "f64"), (1, 64, 64, 9, "f32"),
+                                        (3, 48, 100, 15, "f32"), (1, 50, 50, 31, "f32")])
+@pytest.mark.parametrize("reg", [0, 1, 2])
+def test_adjoint_solve_parity(C, H, W, K, dt, reg):
+    print(f"[case] adjoint_solve {dt} C={C} H={H} W={W} K={K} reg={reg}", flush=True)
+    inst, p = problem(C, H, W, K, seed=4, reg=reg)
+    y = stored(inst.y, dt)
+    xt, _, _ = O.lower_solve(p, inst.a, y, y, tol=1e-4, max_iter=500)
+    xt = stored(xt, dt)
+    b, _, _ = O.upper_value_grad(p, inst.a, y, xt)
+    b = stored(b, dt)
+    m = Maid(C, H, W, K, DT[dt], alpha=p.alpha, eps_tv=p.eps_tv, reg=reg)
+    q = torch.zeros((C, H, W), dtype=DT[dt], device="cuda")
+    tol = 1e-3 * np.linalg.norm(b)
+    info = m.adjoint_solve(dev(inst.a, torch.float64), dev(xt, DT[dt]), dev(b, DT[dt]), q, tol, max_iter=2000)
+    assert info.status == L.OK and info.iters > 2
+    qr, ir = O.adjoint_solve(p, inst.a, xt, b, tol=0.0, max_iter=info.iters)
+    # CG iterates react to rounding-order differences in the dot products
+    # (loss of orthogonality); the FP64 bound reflects that, not FP64 noise
+    assert rel(host(q), qr) <= (1e-6 if dt == "f64" else 1e-5)
+    if dt == "f64":
+        qf, iff = O.adjoint_solve(p, inst.a, xt, b, tol=tol, max_iter=2000)
+        assert iff["iters"] == info.iters
+
+
+@pytest.mark.parametrize("C,H,W,K", [(1, 32, 32, 7), (3, 45, 130, 9), (2, 64, 64, 15), (1, 33, 40, 31),
+                                     (3, 70, 67, 5), (1, 20, 20, 1), (1, 17, 64, 17)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("with_r", [True, False])
+def test_hypergrad_parity(C, H, W, K, dt, with_r):
+    print(f"[case] hypergrad {dt} C={C} H={H} W={W} K={K} with_r={with_r}", flush=True)
+    inst, p = problem(C, H, W, K, seed=5)
+    rng = np.random.default_rng(9)
+    th = inst.a + 0.01 * rng.standard_normal(inst.a.shape)
+    y = stored(inst.y, dt)
+    xt = stored(inst.y + 0.02 * rng.standard_normal(inst.y.shape), dt)
+    q = stored(rng.standard_normal(inst.y.shape), dt)
+    m = Maid(C, H, W, K, DT[dt], alpha=p.alpha, eps_tv=p.eps_tv, beta=p.beta)
+    z, zn = m.hypergrad(dev(th, torch.float64), dev(inst.a, torch.float64), dev(y, DT[dt]), dev(xt, DT[dt]),
+                        dev(q, DT[dt]), with_r=with_r)
+    zr, znr = O.hypergrad(p, th, inst.a, y, xt, q, with_r=with_r)
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert rel(host(z), zr) <= tol
+    assert abs(zn - znr) <= tol * znr
+
+
+def test_sobolev_value():
+    inst, p = problem(1, 32, 32, 9)
+    th = inst.a + 0.01
+    m = Maid(1, 32, 32, 9, torch.float64, alpha=p.alpha, eps_tv=p.eps_tv, beta=p.beta)
+    r = m.sobolev_value(dev(th, torch.float64), dev(inst.a, torch.float64))
+    assert r == pytest.approx(O.sobolev_value(p, th, inst.a), rel=1e-13)
+
+
+def _well_conditioned(H=24, W=24):
+    a = np.array([[0.0, 0.1, 0.0], [0.1, 0.6, 0.1], [0.0, 0.1, 0.0]])
+    inst = synth.make("cfg1", H=H, W=W, C=1, K=7, seed=3)
+    import scipy.signal as ss
+    true = a + 0.05 * np.array([[1, 0, -1], [0, 0, 0], [-1, 0, 1.0]])
+    y = ss.convolve2d(inst.x_true[0], true, mode="same")[None] + 0.01 * np.random.default_rng(3).standard_normal((1, H, W))
+    return O.Problem(1, H, W, 3, alpha=2e-3, eps_tv=1e-2, beta=1e-3), a, y
+
+
+def test_maid_step_fp64_matches_oracle_decisions():
+    print("[case] maid_step f64", flush=True)
+    p, a, y = _well_conditioned()
+    m = Maid(1, p.H, p.W, 3, torch.float64, alpha=p.alpha, eps_tv=p.eps_tv, beta=p.beta)
+    st = MaidState(dev(a, torch.float64), dev(y, torch.float64), torch.zeros((1, p.H, p.W), dtype=torch.float64,
+                   device="cuda"), eps=1e-4, delta=1e-4, step=0.3)
+    so = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    for k in range(3):
+        rc, info = m.maid_step(dev(a, torch.float64), dev(y, torch.float64), st, eps_min=1e-7)
+        rco, infoo = O.maid_step(p, a, y, so, eps_min=1e-7)
+        assert rc == rco
+        for f in ("accepted", "trials", "retries", "lower_iters", "cg_iters"):
+            assert info[f] == infoo[f], (k, f, info, infoo)
+        assert st.eps == so.eps and st.step == so.step and st.k == so.k
+        assert rel(host(st.theta), so.theta) <= 1e-9
+        assert info["psi"] == pytest.approx(infoo["psi"], rel=1e-6, abs=1e-15)
+        if rc != L.OK:
+            break
+
+
+def test_error_paths_on_gpu():
+    H = W = 16
+    # theta = 0 and alpha = 0 make the Hessian zero: the first curvature is 0
+    m = Maid(1, H, W, 3, torch.float64, alpha=0.0, reg=L.MAID_REG_QUADRATIC)
+    th = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    b = dev((np.indices((1, H, W)).sum(0) % 2) * 2.0 - 1.0, torch.float64)
+    q = torch.zeros((1, H, W), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.MaidError) as e:
+        m.adjoint_solve(th, torch.zeros_like(q), b, q, 1e-12, 50)
+    assert e.value.code == L.NOT_SPD
+    assert torch.count_nonzero(q) == 0
+    inst, p = problem(1, 32, 32, 7)
+    m2 = Maid(1, 32, 32, 7, torch.float32, alpha=p.alpha)
+    x = dev(inst.y, torch.float32)
+    info = m2.lower_solve(dev(inst.a, torch.float64), dev(inst.y, torch.float32), x, 1e-12, max_iter=3)
+    assert info.status == L.MAXITER and info.iters == 3
+    with pytest.raises(L.MaidError):
+        m2.lower_solve(dev(inst.a, torch.float64), dev(inst.y, torch.float32), x, -1.0)
+    ynan = dev(inst.y, torch.float32)
+    ynan[0, 3, 3] = float("nan")
+    with pytest.raises(L.MaidError) as e2:
+        m2.lower_solve(dev(inst.a, torch.float64), ynan, dev(inst.y, torch.float32), 1e-3)
+    assert e2.value.code == L.NONFINITE
+
+
+def test_deterministic_bitwise():
+    inst, p = problem(3, 64, 80, 9, seed=7)
+    outs = []
+    for _ in range(2):
+        m = Maid(3, 64, 80, 9, torch.float32, alpha=p.alpha, eps_tv=p.eps_tv, beta=p.beta)
+        x = dev(inst.y, torch.float32)
+        m.lower_solve(dev(inst.a, torch.float64), dev(inst.y, torch.float32), x, 1e-3, 200)
+        q = torch.zeros_like(x)
+        m.adjoint_solve(dev(inst.a, torch.float64), x, dev(inst.y, torch.float32), q, 1e-2, 200)
+        z, _ = m.hypergrad(dev(inst.a, torch.float64), dev(inst.a, torch.float64), dev(inst.y, torch.float32), x, q)
+        outs.append((x.clone(), q.clone(), z.clone()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
