@@ -3,18 +3,22 @@
 //
 // The host side only enqueues kernels and polls: every arithmetic step runs
 // on the GPU, and every solver decision (stop tests, backtracking, CG
-// coefficients) is taken on the GPU by the last block of a reduction pass
-// and kept in the device-resident DevCtx.  The host copies that small
-// struct back once per chunk of iterations to learn whether the solve has
-// finished; MAID's outer loop (Algorithm 2) runs on the host over scalars
-// that the kernels computed in FP64.
+// coefficients) is taken on the GPU by the pass that consumes the
+// reduction, and kept in the device-resident DevCtx.  Solver passes are
+// replayed in chunks from captured HIP graphs; the host copies the small
+// solver state back once per chunk to learn whether the solve has finished.
+// MAID's outer loop (Algorithm 2) runs on the host over scalars that the
+// kernels computed in FP64.  Setting MAID_GRAPHS=0 in the environment
+// launches the passes directly instead of through graphs.
 #include "maid.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -52,11 +56,17 @@ struct maid_ctx {
     void* af_c = nullptr;
     double* th_trial = nullptr;
     double* zbuf = nullptr;
-    double* partials = nullptr;
+    double* pA = nullptr;      // per-block partials: gradient pass
+    double* pB = nullptr;      //                     trial pass
+    double* pR = nullptr;      //                     CG residual
+    double* pK = nullptr;      //                     CG curvature
+    double* pC = nullptr;      //                     convolution passes
     double* hg_part = nullptr;
-    int hg_blocks = 0;
     int ew_blocks = 0;
-    unsigned* counter = nullptr;
+    hipStream_t cap = nullptr; // private stream for graph capture
+    bool use_graphs = true;
+    struct Graph { int kind; const void* k1; const void* k2; int chunk; int R; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
     int* trace = nullptr;
     int trace_cap = 0;
     std::string err;
@@ -70,6 +80,8 @@ struct maid_ctx {
     double prof_ms[MAID_PROF_KINDS] = {};
 
     int R() const { return R_override ? R_override : R_auto; }
+    Params params() const { return Params{d.C, d.H, d.W, d.reg, d.alpha, d.eps_tv}; }
+    double* red(int k) const { return &dev->red[k]; }
 };
 
 namespace {
@@ -118,16 +130,19 @@ int validate_desc(const maid_desc* d, std::string& why) {
     return MAID_OK;
 }
 
-int sync_state(maid_ctx* c, hipStream_t s) {
-    HIP_TRY(hipMemcpyAsync(c->host, c->dev, sizeof(DevCtx), hipMemcpyDeviceToHost, s));
+// copy a field range of the device state to / from the pinned mirror
+int pull(maid_ctx* c, hipStream_t s, size_t off, size_t n) {
+    HIP_TRY(hipMemcpyAsync((char*)c->host + off, (char*)c->dev + off, n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MAID_OK;
 }
-
-int push_state(maid_ctx* c, hipStream_t s) {
-    HIP_TRY(hipMemcpyAsync(c->dev, c->host, sizeof(DevCtx), hipMemcpyHostToDevice, s));
+int push(maid_ctx* c, hipStream_t s, size_t off, size_t n) {
+    HIP_TRY(hipMemcpyAsync((char*)c->dev + off, (char*)c->host + off, n, hipMemcpyHostToDevice, s));
     return MAID_OK;
 }
+constexpr size_t kOffApg = offsetof(DevCtx, apg);
+constexpr size_t kOffCg = offsetof(DevCtx, cg);
+constexpr size_t kOffRed = offsetof(DevCtx, red);
 
 int status_code(int st) {
     switch (st) {
@@ -192,38 +207,74 @@ struct ProfScope {
         HIP_TRY(expr);                           \
     } while (0)
 
+// ------------------------------------------------------------------ graph-captured chunks
+// A chunk of solver passes is captured once into a HIP graph (per kind, the
+// caller pointers the launches embed, chunk length and tile rows) and
+// replayed; the passes read everything that changes between replays from
+// the device-resident state.  With profiling on, passes launch directly so
+// that each one is bracketed by its own events.
+enum { G_APG = 1, G_CG = 2 };
+
+template <typename F>
+int run_chunk(maid_ctx* c, int kind, const void* k1, const void* k2, int chunk, hipStream_t s, F enqueue) {
+    if (c->prof_on || !c->use_graphs) return enqueue(s);
+    const int R = c->R();
+    for (auto& g : c->graphs)
+        if (g.kind == kind && g.k1 == k1 && g.k2 == k2 && g.chunk == chunk && g.R == R) {
+            HIP_TRY(hipGraphLaunch(g.exec, s));
+            return MAID_OK;
+        }
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    int rc = enqueue(c->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (rc != MAID_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, MAID_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, MAID_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    if (c->graphs.size() >= 48) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({kind, k1, k2, chunk, R, exec});
+    HIP_TRY(hipGraphLaunch(exec, s));
+    return MAID_OK;
+}
+
 // ------------------------------------------------------------------ lower level
 template <typename T>
 int lower_solve_t(maid_ctx* c, const double* theta, const T* y, T* x, double tol, int max_iter, double* L_inout,
                   maid_solve_info* info, int32_t* trace_bt, hipStream_t s) {
     const Shape& d = c->shape;
     const int R = c->R();
-    DevCtx* h = c->host;
-    h->L = *L_inout;
-    h->t = 1.0;
-    h->t_prev = 1.0;
-    h->m = 0.0;
-    h->gn2 = 0.0;
-    h->tol = tol;
-    h->delta_last = 0.0;
-    h->max_iter = max_iter;
-    h->iters = h->bt = h->nb_iter = 0;
-    h->status = ST_OK;
-    h->done = 0;
-    h->phase = 0;
-    h->cur = 0;
-    h->prev = 1;
-    h->nxt = 2;
-    h->trace_cap = c->trace_cap;
-    int rc = push_state(c, s);
+    ApgState& h = c->host->apg[0];
+    std::memset(&h, 0, sizeof(h));
+    h.L = *L_inout;
+    h.t = 1.0;
+    h.t_prev = 1.0;
+    h.m = 0.0;
+    h.tol = tol;
+    h.max_iter = max_iter;
+    h.status = ST_OK;
+    h.phase = PH_START;
+    h.cur = 0;
+    h.prev = 1;
+    h.nxt = 2;
+    h.trace_cap = c->trace_cap;
+    int rc = push(c, s, kOffApg, sizeof(ApgState));
     if (rc) return rc;
     T* th = (T*)c->th_c;
     T* thf = (T*)c->thf_c;
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(c->dev, theta, th, thf, d.K, 1, -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(&c->dev->apg[0].L, nullptr, theta, th, thf, d.K, s));
     const size_t bytes = (size_t)c->N * sizeof(T);
     HIP_TRY(hipMemcpyAsync(c->X[0], x, bytes, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(c->X[1], x, bytes, hipMemcpyDeviceToDevice, s));
-    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, c->dev, thf, (const T*)c->X[0], nullptr, (T*)c->KX[0], -1, c->partials, c->counter, s));
+    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, thf, (const T*)c->X[0], nullptr, (T*)c->KX[0], nullptr, s));
     HIP_TRY(hipMemcpyAsync(c->KX[1], c->KX[0], bytes, hipMemcpyDeviceToDevice, s));
     ApgBufs<T> b;
     for (int i = 0; i < 3; ++i) {
@@ -234,43 +285,49 @@ int lower_solve_t(maid_ctx* c, const double* theta, const T* y, T* x, double tol
     b.y = y;
     b.th = th;
     b.thf = thf;
-    b.partials = c->partials;
-    b.counter = c->counter;
+    b.pA = c->pA;
+    b.pB = c->pB;
+    b.nbA = b.nbB = stencil_blocks(d, R);
     b.trace = c->trace;
     // each slot is one gradient pass and one trial pass; a slot advances the
-    // solve by one iteration or one backtracking step
+    // solve by one iteration or by one backtracking step
     const long slot_cap = (long)max_iter + 256 + 1;
+    const Params pr = c->params();
     long slots = 0;
     int chunk = 1;
     for (;;) {
-        for (int k = 0; k < chunk; ++k) {
-            LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(d, R, c->dev, b, s));
-            LAUNCH(MAID_PROF_APG_TRIAL, Ops<T>::apg_trial(d, R, c->dev, b, s));
-        }
-        slots += chunk;
-        rc = sync_state(c, s);
+        rc = run_chunk(c, G_APG, y, nullptr, chunk, s, [&](hipStream_t s) {
+            for (int k = 0; k < chunk; ++k) {
+                LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(d, R, pr, &c->dev->apg[0], &c->dev->apg[1], b, s));
+                LAUNCH(MAID_PROF_APG_TRIAL, Ops<T>::apg_trial(d, R, pr, &c->dev->apg[1], &c->dev->apg[0], b, s));
+            }
+            return (int)MAID_OK;
+        });
         if (rc) return rc;
-        if (h->done) break;
+        slots += chunk;
+        rc = pull(c, s, kOffApg, sizeof(ApgState));
+        if (rc) return rc;
+        if (h.done) break;
         if (slots > slot_cap) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
         chunk = std::min(chunk * 2, 16);
     }
-    const int code = status_code(h->status);
+    const int code = status_code(h.status);
     if (code >= 0) {
-        LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->dev, b, x, c->N, s));
+        LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(&c->dev->apg[0], b, x, c->N, s));
         HIP_TRY(hipStreamSynchronize(s));
-        *L_inout = h->L;
+        *L_inout = h.L;
     }
-    if (trace_bt && h->iters > 0) {
-        const int n = std::min(h->iters, c->trace_cap);
+    if (trace_bt && h.iters > 0) {
+        const int n = std::min(h.iters, c->trace_cap);
         HIP_TRY(hipMemcpy(trace_bt, c->trace, n * sizeof(int), hipMemcpyDeviceToHost));
     }
     if (info) {
-        info->iters = h->iters;
-        info->backtracks = h->bt;
+        info->iters = h.iters;
+        info->backtracks = h.bt;
         info->status = code;
-        info->res_norm = std::sqrt(h->gn2);
+        info->res_norm = std::sqrt(h.gn2);
         info->obj = 0.0;
-        info->L = h->L;
+        info->L = h.L;
     }
     if (code < 0) return fail(c, code, "lower_solve: non-finite values met");
     return code;
@@ -281,13 +338,16 @@ int upper_value_grad_t(maid_ctx* c, const double* a, const T* y, const T* x, T* 
                        hipStream_t s) {
     const Shape& d = c->shape;
     const int R = c->R();
+    const int nb = stencil_blocks(d, R);
     T* ac = (T*)c->a_c;
     T* af = (T*)c->af_c;
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(c->dev, a, ac, af, d.K, 0, -1, s));
-    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, c->dev, af, x, y, (T*)c->tmp0, kRedG, c->partials, c->counter, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(nullptr, nullptr, a, ac, af, d.K, s));
+    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, af, x, y, (T*)c->tmp0, c->pC, s));
+    LAUNCH(MAID_PROF_OTHER, launch_reduce(c->pC, nb, c->red(kRedG), s));
     T* gout = grad_out ? grad_out : (T*)c->gradg;
-    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, c->dev, ac, (const T*)c->tmp0, nullptr, gout, kRedGrad, c->partials, c->counter, s));
-    int rc = sync_state(c, s);
+    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, ac, (const T*)c->tmp0, nullptr, gout, c->pC, s));
+    LAUNCH(MAID_PROF_OTHER, launch_reduce(c->pC, nb, c->red(kRedGrad), s));
+    int rc = pull(c, s, kOffRed, sizeof(c->host->red));
     if (rc) return rc;
     if (g_out) *g_out = 0.5 * c->host->red[kRedG];
     if (gn_out) *gn_out = std::sqrt(c->host->red[kRedGrad]);
@@ -300,19 +360,17 @@ int adjoint_solve_t(maid_ctx* c, const double* theta, const T* xt, const T* rhs,
                     maid_solve_info* info, hipStream_t s) {
     const Shape& d = c->shape;
     const int R = c->R();
-    DevCtx* h = c->host;
-    h->gamma = h->kappa = h->cg_a = h->cg_b = 0.0;
-    h->cg_tol = tol;
-    h->cg_max = max_iter;
-    h->cg_iters = 0;
-    h->cg_status = ST_OK;
-    h->cg_done = 0;
-    h->pc = 0;
-    int rc = push_state(c, s);
+    CgState& h = c->host->cg[0];
+    std::memset(&h, 0, sizeof(h));
+    h.tol = tol;
+    h.max = max_iter;
+    h.status = ST_OK;
+    h.first = 1;
+    int rc = push(c, s, kOffCg, sizeof(CgState));
     if (rc) return rc;
     T* th = (T*)c->th_c;
     T* thf = (T*)c->thf_c;
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(c->dev, theta, th, thf, d.K, 0, -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(nullptr, nullptr, theta, th, thf, d.K, s));
     const size_t bytes = (size_t)c->N * sizeof(T);
     HIP_TRY(hipMemcpyAsync(c->cq, q, bytes, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(c->cr, q, bytes, hipMemcpyDeviceToDevice, s));
@@ -327,38 +385,45 @@ int adjoint_solve_t(maid_ctx* c, const double* theta, const T* xt, const T* rhs,
     b.b = rhs;
     b.th = th;
     b.thf = thf;
-    b.partials = c->partials;
-    b.counter = c->counter;
-    // r = rhs - H q0 (the direction pass with beta = 0 copies q0 into p)
-    LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(d, R, c->dev, b, s));
-    LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(d, R, c->dev, b, 1, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->dev, b, c->N, c->ew_blocks, s));
-    rc = sync_state(c, s);
-    if (rc) return rc;
-    int chunk = 2;
-    long passes = 0;
-    while (!h->cg_done) {
-        for (int k = 0; k < chunk; ++k) {
-            LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(d, R, c->dev, b, s));
-            LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(d, R, c->dev, b, 0, s));
-            LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(c->dev, b, c->N, c->ew_blocks, s));
-        }
-        passes += chunk;
-        rc = sync_state(c, s);
+    b.pR = c->pR;
+    b.pK = c->pK;
+    b.nbK = stencil_blocks(d, R);
+    b.nbR = c->ew_blocks;
+    // r = rhs - H q0 (the direction pass in set-up mode copies q0 into p)
+    const Params pr = c->params();
+    CgState* S = c->dev->cg;
+    LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(d, R, pr, &S[0], &S[1], b, 1, s));
+    LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(d, R, pr, &S[0], &S[2], b, 1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(b, c->N, c->ew_blocks, s));
+    int chunk = 1;
+    long slots = 0;
+    for (;;) {
+        rc = run_chunk(c, G_CG, xt, rhs, chunk, s, [&](hipStream_t s) {
+            for (int k = 0; k < chunk; ++k) {
+                LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(d, R, pr, &S[0], &S[1], b, 0, s));
+                LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(d, R, pr, &S[1], &S[2], b, 0, s));
+                LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(&S[2], &S[0], b, c->N, c->ew_blocks, s));
+            }
+            return (int)MAID_OK;
+        });
         if (rc) return rc;
-        if (passes > (long)max_iter + 4 && !h->cg_done) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
+        slots += chunk;
+        rc = pull(c, s, kOffCg, sizeof(CgState));
+        if (rc) return rc;
+        if (h.done) break;
+        if (slots > (long)max_iter + 2) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
         chunk = std::min(chunk * 2, 16);
     }
-    const int code = status_code(h->cg_status);
+    const int code = status_code(h.status);
     if (code >= 0) {
         HIP_TRY(hipMemcpyAsync(q, c->cq, bytes, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
     if (info) {
-        info->iters = h->cg_iters;
+        info->iters = h.iters;
         info->backtracks = 0;
         info->status = code;
-        info->res_norm = std::sqrt(h->gamma);
+        info->res_norm = std::sqrt(h.gamma);
         info->obj = 0.0;
         info->L = 0.0;
     }
@@ -374,12 +439,14 @@ int hypergrad_t(maid_ctx* c, const double* theta, const double* a, const T* y, c
     const int R = c->R();
     T* th = (T*)c->th_c;
     T* thf = (T*)c->thf_c;
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(c->dev, theta, th, thf, d.K, 0, -1, s));
-    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, c->dev, thf, xt, y, (T*)c->tmp0, -1, c->partials, c->counter, s));
-    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, c->dev, thf, q, nullptr, (T*)c->tmp1, -1, c->partials, c->counter, s));
-    LAUNCH(MAID_PROF_HG_CORR, Ops<T>::hg_corr(d, (const T*)c->tmp0, q, (const T*)c->tmp1, xt, c->hg_part, c->hg_blocks, s));
-    LAUNCH(MAID_PROF_OTHER, launch_hg_final(d, c->dev, c->hg_part, c->hg_blocks, theta, with_r ? a : nullptr, with_r, z, kRedZ, s));
-    int rc = sync_state(c, s);
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(nullptr, nullptr, theta, th, thf, d.K, s));
+    const int nblk = std::min(kHgMaxBlocks, hg_items(d));
+    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, thf, xt, y, (T*)c->tmp0, nullptr, s));
+    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, R, thf, q, nullptr, (T*)c->tmp1, nullptr, s));
+    LAUNCH(MAID_PROF_HG_CORR, Ops<T>::hg_corr(d, (const T*)c->tmp0, q, (const T*)c->tmp1, xt, c->hg_part, nblk, s));
+    LAUNCH(MAID_PROF_OTHER, launch_hg_final(d, c->d.beta, c->d.h1_w0, c->hg_part, nblk, theta, with_r ? a : nullptr, with_r, z,
+                                            c->red(kRedZ), s));
+    int rc = pull(c, s, kOffRed, sizeof(c->host->red));
     if (rc) return rc;
     if (znorm_out) *znorm_out = std::sqrt(c->host->red[kRedZ]);
     return MAID_OK;
@@ -390,8 +457,8 @@ int sobolev_value_impl(maid_ctx* c, const double* theta, const double* a, double
         *r = 0.0;
         return MAID_OK;
     }
-    LAUNCH(MAID_PROF_OTHER, launch_sobolev(c->dev, theta, a, c->d.K, kRedSob, s));
-    int rc = sync_state(c, s);
+    LAUNCH(MAID_PROF_OTHER, launch_sobolev(c->d.beta, c->d.h1_w0, theta, a, c->d.K, c->red(kRedSob), s));
+    int rc = pull(c, s, kOffRed, sizeof(c->host->red));
     if (rc) return rc;
     *r = c->host->red[kRedSob];
     return MAID_OK;
@@ -414,8 +481,8 @@ int maid_step_t(maid_ctx* c, const double* a, const T* y, maid_state* st, const 
     std::memset(&I, 0, sizeof(I));
     double Lg = hp->L_g;
     if (!(Lg > 0)) {
-        LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(c->dev, a, (T*)c->a_c, (T*)c->af_c, c->d.K, 0, kRedAbs, s));
-        int rc = sync_state(c, s);
+        LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(nullptr, c->red(kRedAbs), a, (T*)c->a_c, (T*)c->af_c, c->d.K, s));
+        int rc = pull(c, s, kOffRed, sizeof(c->host->red));
         if (rc) return rc;
         Lg = c->host->red[kRedAbs] * c->host->red[kRedAbs];
     }
@@ -517,14 +584,13 @@ int maid_create(const maid_desc* desc, maid_ctx** out) {
     c->esz = desc->dtype == MAID_F64 ? 8 : 4;
     c->R_auto = auto_rows(c->shape);
     c->ew_blocks = (int)std::min<int64_t>((c->N + kNT - 1) / kNT, 2048);
-    c->hg_blocks = kHgMaxBlocks;
     c->trace_cap = kTraceCap;
     const size_t img = ((size_t)c->N * c->esz + 255) / 256 * 256;
     const size_t kern = 1024 * 8;
     const size_t nblk = std::max<size_t>(stencil_blocks(c->shape, 1), (size_t)c->ew_blocks);
-    const size_t part = ((nblk * 4 * sizeof(double)) + 255) / 256 * 256;
+    const size_t part = ((nblk * sizeof(double)) + 255) / 256 * 256;
     const size_t hgp = (size_t)kHgMaxBlocks * 1024 * sizeof(double);
-    c->ws_bytes = 18 * img + 6 * kern + part + hgp + 256 + kTraceCap * sizeof(int);
+    c->ws_bytes = 18 * img + 6 * kern + 5 * part + hgp + kTraceCap * sizeof(int);
     hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
     if (e != hipSuccess) {
         g_create_error = std::string("hipMalloc of the workspace failed: ") + hipGetErrorString(e);
@@ -553,14 +619,18 @@ int maid_create(const maid_desc* desc, maid_ctx** out) {
     c->af_c = take(kern);
     c->th_trial = (double*)take(kern);
     c->zbuf = (double*)take(kern);
-    c->partials = (double*)take(part);
+    c->pA = (double*)take(part);
+    c->pB = (double*)take(part);
+    c->pR = (double*)take(part);
+    c->pK = (double*)take(part);
+    c->pC = (double*)take(part);
     c->hg_part = (double*)take(hgp);
-    c->counter = (unsigned*)take(256);
     c->trace = (int*)take(kTraceCap * sizeof(int));
     e = hipMalloc((void**)&c->dev, sizeof(DevCtx));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->host, sizeof(DevCtx), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemset(c->counter, 0, 256);
     if (e == hipSuccess) e = hipMemset(c->ws, 0, c->ws_bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
     if (e != hipSuccess) {
         g_create_error = std::string("allocation failed: ") + hipGetErrorString(e);
         maid_destroy(c);
@@ -577,7 +647,6 @@ int maid_create(const maid_desc* desc, maid_ctx** out) {
     h->eps_tv = desc->eps_tv;
     h->beta = desc->beta;
     h->h1_w0 = desc->h1_w0;
-    h->trace_cap = c->trace_cap;
     e = hipMemcpy(c->dev, c->host, sizeof(DevCtx), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         g_create_error = std::string("hipMemcpy failed: ") + hipGetErrorString(e);
@@ -595,6 +664,8 @@ void maid_destroy(maid_ctx* c) {
     if (!c) return;
     prof_harvest(c);
     for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->ws) (void)hipFree(c->ws);
     if (c->dev) (void)hipFree(c->dev);
     if (c->host) (void)hipHostFree(c->host);

@@ -17,28 +17,44 @@ constexpr int kNT = 256;       // threads per block (4 waves)
 
 enum Status : int32_t { ST_OK = 0, ST_MAXITER = 1, ST_NOT_SPD = -4, ST_NONFINITE = -5 };
 
+// Lower-level (FISTA) solver state.  Two copies live in DevCtx: the
+// gradient pass reads apg[0] and its block 0 writes apg[1]; the trial pass
+// reads apg[1] and writes apg[0].  No kernel writes the copy it reads, so
+// every block of a launch sees the same state.
+enum ApgPhase : int32_t { PH_START = 0, PH_GRAD_READY = 1, PH_RETRY = 2, PH_TRIALED = 3 };
+
+struct ApgState {
+    double L, t, t_prev, m;      // Lipschitz estimate, momentum sequence, m = (t_prev-1)/t
+    double gn2;                  // ||G||^2 at the current extrapolated point
+    double tol;                  // stop when ||G|| <= tol
+    double delta_last;           // last h(x+) - h(v)
+    int32_t max_iter, iters, bt, nb_iter;
+    int32_t status, done, phase;
+    int32_t cur, prev, nxt;      // rotation of the three x / Kx buffers
+    int32_t trace_cap, pad;
+};
+
+// CG state: three copies; the direction pass reads cg[0] and writes cg[1],
+// the Hessian pass cg[1] -> cg[2], the update pass cg[2] -> cg[0].
+struct CgState {
+    double gamma, kappa, a, tol;
+    int32_t max, iters, status, done, pc, first;
+};
+
+// Problem parameters the kernels need, passed by value (kernel arguments
+// live in the constant kernarg segment and are read with scalar loads).
+struct Params {
+    int32_t C, H, W, reg;
+    double alpha, eps_tv;
+};
+
 struct DevCtx {
     // ---------------- problem (fixed per context)
     int32_t C, H, W, K, reg;
     int32_t pad0;
     double alpha, eps_tv, beta, h1_w0;
-
-    // ---------------- lower-level solver (FISTA with backtracking)
-    double L, t, t_prev, m;      // Lipschitz estimate, momentum sequence, m = (t_prev-1)/t
-    double gn2;                  // ||G||^2 at the current extrapolated point
-    double tol;                  // stop when ||G|| <= tol
-    double delta_last;           // last h(x+)-h(v)
-    int32_t max_iter, iters, bt, nb_iter;
-    int32_t status, done, phase; // phase 0: gradient pass next; 1: trial pass next
-    int32_t cur, prev, nxt;      // rotation of the three x / Kx buffers
-    int32_t trace_cap;
-    int32_t pad1;
-
-    // ---------------- conjugate gradients
-    double gamma, kappa, cg_a, cg_b, cg_tol;
-    int32_t cg_max, cg_iters, cg_status, cg_done, pc;   // pc: index of the current p buffer
-    int32_t pad2;
-
+    ApgState apg[2];
+    CgState cg[3];
     // ---------------- generic reduction results
     double red[8];
 };
@@ -74,10 +90,11 @@ template <typename T> struct ApgBufs {
     T* KX[3];          // theta * x_k, kept by linearity
     T* G;              // gradient at the extrapolated point
     const T* y;
-    const T* th;       // theta (correlation form, adjoint)
-    const T* thf;      // theta flipped (convolution form)
-    double* partials;
-    unsigned* counter;
+    const T* th;       // theta, correlation (adjoint) form, column-major
+    const T* thf;      // theta flipped (convolution form), column-major
+    double* pA;        // per-block partials of ||G||^2 (gradient pass)
+    double* pB;        // per-block partials of h(x+) - h(v) (trial pass)
+    int nbA, nbB;      // grid sizes of the two passes
     int* trace;        // rejected trials per iteration
 };
 
@@ -91,8 +108,9 @@ template <typename T> struct CgBufs {
     const T* b;        // right-hand side
     const T* th;
     const T* thf;
-    double* partials;
-    unsigned* counter;
+    double* pR;        // per-block partials of ||r||^2 (update / init pass)
+    double* pK;        // per-block partials of <p, Hp> (Hessian pass)
+    int nbR, nbK;
 };
 
 }  // namespace maid

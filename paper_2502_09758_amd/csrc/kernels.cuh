@@ -12,12 +12,13 @@
 // the same XCD and share its L2.
 //
 // Reductions are accumulated in double: per thread, then wave64 butterfly,
-// then the four waves in a fixed order, then the per-block partials are
-// combined by the last block to finish (agent-scope acquire/release
-// counter), in a fixed order.  That last block also takes the solver's
-// scalar decisions (stop tests, backtracking, CG coefficients) and writes
-// them to the device-resident DevCtx, so no host round trip is needed
-// between passes.
+// then the four waves in a fixed order, giving one partial per block.  The
+// kernel that needs the total sums the partials itself, every block in the
+// same order, so all blocks hold the bitwise-same value and take the same
+// solver decision (stop tests, backtracking, CG coefficients) without a
+// host round trip and without atomics or fences: the kernel boundary orders
+// the partials before they are read.  Solver state is double-buffered in
+// DevCtx (each pass reads one copy and its block 0 writes the other).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -48,51 +49,53 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Grid-wide sum of NV doubles per thread.  Returns true in the block that
-// finishes last; there tot[k] (shared) holds the totals for every thread.
-// The counter is reset to zero by that block for the next launch.
-template <int NV>
-__device__ bool grid_reduce(const double (&v)[NV], double* partials, unsigned* counter, double* tot) {
-    __shared__ double s_w[NV][4];
-    __shared__ int s_last;
+// Sum of one double per thread over the block, returned to every thread
+// (wave butterflies, then the four waves in a fixed order).
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double s_w[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nb = gridDim.x;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double w = wave_sum(v[k]);
-        if (lane == 0) s_w[k][wid] = w;
-    }
+    v = wave_sum(v);
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const double s = ((s_w[k][0] + s_w[k][1]) + s_w[k][2]) + s_w[k][3];
-            __hip_atomic_store(&partials[(size_t)k * nb + blockIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __threadfence();
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == (unsigned)(nb - 1));
-    }
+    if (lane == 0) s_w[wid] = v;
     __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kNT)
-            s += __hip_atomic_load(&partials[(size_t)k * nb + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double w = wave_sum(s);
-        if (lane == 0) s_w[k][wid] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        const int k = threadIdx.x;
-        tot[k] = ((s_w[k][0] + s_w[k][1]) + s_w[k][2]) + s_w[k][3];
-    }
-    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    return true;
+    return ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
+
+// Producer side of a grid-wide sum: one partial per block, plain store.
+__device__ __forceinline__ void block_partial(double v, double* part) {
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Consumer side, at the start of the next kernel: every block sums the nb
+// partials in the same fixed order and so obtains the bitwise-same total and
+// takes the same decision; kernel boundaries order the producer's stores
+// before these loads.  No atomics or fences are involved.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int nb) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kNT) s += part[b];
+    return block_sum(s);
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return v == v && v <= 1.0e300 && v >= -1.0e300; }
+
+// Field-by-field state stores (no whole-struct copy, so the local state stays
+// in scalar registers) and select-based buffer picks (no runtime indexing
+// into by-value argument arrays, which would go through scratch memory).
+__device__ __forceinline__ void put_state(ApgState* __restrict__ o, const ApgState& s) {
+    o->L = s.L; o->t = s.t; o->t_prev = s.t_prev; o->m = s.m; o->gn2 = s.gn2; o->tol = s.tol;
+    o->delta_last = s.delta_last; o->max_iter = s.max_iter; o->iters = s.iters; o->bt = s.bt;
+    o->nb_iter = s.nb_iter; o->status = s.status; o->done = s.done; o->phase = s.phase; o->cur = s.cur;
+    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->pad = 0;
+}
+__device__ __forceinline__ void put_state(CgState* __restrict__ o, const CgState& s) {
+    o->gamma = s.gamma; o->kappa = s.kappa; o->a = s.a; o->tol = s.tol; o->max = s.max; o->iters = s.iters;
+    o->status = s.status; o->done = s.done; o->pc = s.pc; o->first = s.first;
+}
+template <typename P>
+__device__ __forceinline__ P pick(P a0, P a1, P a2, int i) { return i == 0 ? a0 : (i == 1 ? a1 : a2); }
+template <typename P>
+__device__ __forceinline__ P pick(P a0, P a1, int i) { return i == 0 ? a0 : a1; }
 
 // Stage f(global flat index) into an LDS tile s[ROWS][PITCH] covering rows
 // gi0.., columns gj0..; zero outside [0,H) x [0,W).
@@ -191,15 +194,14 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
 
 // ------------------------------------------------------------------ generic convolution pass
 // out = ker (x) in  [- sub]   (correlation with ker; pass the flipped kernel
-// for the true convolution), optional grid total of out^2 into c->red[slot].
+// for the true convolution); with part != nullptr, per-block partials of
+// sum out^2 (finished by k_reduce).
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_conv(DevCtx* __restrict__ c, const T* __restrict__ ker, const T* __restrict__ in,
-                                              const T* __restrict__ sub, T* __restrict__ out, int slot,
-                                              double* partials, unsigned* counter) {
+__global__ __launch_bounds__(kNT) void k_conv(int C, int H, int W, const T* __restrict__ ker, const T* __restrict__ in,
+                                              const T* __restrict__ sub, T* __restrict__ out, double* __restrict__ part) {
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
-    const int C = c->C, H = c->H, W = c->W;
     const int64_t HW = (int64_t)H * W;
     const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
@@ -228,43 +230,88 @@ __global__ __launch_bounds__(kNT) void k_conv(DevCtx* __restrict__ c, const T* _
             }
         }
     }
-    if (slot >= 0) {
-        __shared__ double tot[1];
-        const double v[1] = {sq};
-        if (grid_reduce<1>(v, partials, counter, tot) && threadIdx.x == 0) c->red[slot] = tot[0];
-    }
+    if (part) block_partial(sq, part);
 }
 
 // ------------------------------------------------------------------ lower level: FISTA
-// Pass A: at the extrapolated point v = x + m (x - x_prev), with
-// theta*v = Kx + m (Kx - Kx_prev) by linearity,
-//   G = theta . (theta*v - y) + alpha grad R(v),  and ||G||^2 (grid total);
-// the last block applies the stop test ||G|| <= tol.
+// Gradient pass.  Reads apg[0], block 0 writes apg[1].  If the previous
+// trial pass ran, first finish its decrease h(x+) - h(v) from the partials
+// and take the backtracking decision: accept (rotate buffers, advance the
+// momentum sequence, then evaluate the new gradient) or reject (double L,
+// no gradient work).  The gradient at v = x + m (x - x_prev), with
+// theta*v = Kx + m (Kx - Kx_prev) by linearity, is
+//   G = theta . (theta*v - y) + alpha grad R(v),
+// and its per-block partials of ||G||^2 go to pA.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_grad(DevCtx* __restrict__ c, ApgBufs<T> b) {
-    if (c->done | (c->phase != 0)) return;
+__global__ __launch_bounds__(kNT) void k_apg_grad(const Params pr, const ApgState* __restrict__ sin, ApgState* __restrict__ sout,
+                                                  ApgBufs<T> b) {
+    ApgState st = *sin;
+    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(sout, st);
+        return;
+    }
+    bool compute = true;
+    if (st.phase == PH_TRIALED) {
+        const double delta = reduce_partials(b.pB, b.nbB) + 0.0;
+        st.delta_last = delta;
+        if (!finite_d(delta)) {
+            st.done = 1;
+            st.status = ST_NONFINITE;
+            compute = false;
+        } else if (delta <= -st.gn2 / (2.0 * st.L)) {
+            if (writer && b.trace && st.iters < st.trace_cap) b.trace[st.iters] = st.nb_iter;
+            st.iters += 1;
+            const int p = st.prev;
+            st.prev = st.cur;
+            st.cur = st.nxt;
+            st.nxt = p;
+            const double t = st.t;
+            const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            st.t_prev = t;
+            st.t = tn;
+            st.m = (t - 1.0) / tn;
+            st.phase = PH_GRAD_READY;
+        } else {
+            st.L = 2.0 * st.L;
+            st.bt += 1;
+            st.nb_iter += 1;
+            st.phase = PH_RETRY;
+            compute = false;
+            if (st.nb_iter > 200) {
+                st.done = 1;
+                st.status = ST_NONFINITE;
+            }
+        }
+    } else {
+        st.phase = PH_GRAD_READY;
+    }
+    if (writer) put_state(sout, st);
+    if (!compute) return;
+
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = c->C, H = c->H, W = c->W, reg = c->reg;
+    const int C = pr.C, H = pr.H, W = pr.W, reg = pr.reg;
     const int64_t HW = (int64_t)H * W;
     const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
-    const T m = (T)c->m;
-    const T alpha = (T)c->alpha;
-    const T* __restrict__ X = b.X[c->cur];
-    const T* __restrict__ XP = b.X[c->prev];
-    const T* __restrict__ KX = b.KX[c->cur];
-    const T* __restrict__ KXP = b.KX[c->prev];
+    const T m = (T)st.m;
+    const T alpha = (T)pr.alpha;
+    const T* __restrict__ X = pick(b.X[0], b.X[1], b.X[2], st.cur);
+    const T* __restrict__ XP = pick(b.X[0], b.X[1], b.X[2], st.prev);
+    const T* __restrict__ KX = pick(b.KX[0], b.KX[1], b.KX[2], st.cur);
+    const T* __restrict__ KXP = pick(b.KX[0], b.KX[1], b.KX[2], st.prev);
     const T* __restrict__ Y = b.y;
 
     // ---- TV gradient at v (all channels staged: the magnitude couples them)
     T* s_v = sm;
     T* s_w = sm + C * VR * VP;
+    __syncthreads();
     for (int ch = 0; ch < C; ++ch) {
         const T* Xc = X + ch * HW;
         const T* XPc = XP + ch * HW;
@@ -272,7 +319,7 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(DevCtx* __restrict__ c, ApgBuf
                               [&](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); });
     }
     __syncthreads();
-    tv_weights<T, R>(s_v, s_w, C, reg, (T)(c->eps_tv * c->eps_tv), ti0, tj0, H, W);
+    tv_weights<T, R>(s_v, s_w, C, reg, (T)(pr.eps_tv * pr.eps_tv), ti0, tj0, H, W);
     __syncthreads();
     T tg0[R], tg1[R], tg2[R];
 #pragma unroll
@@ -309,66 +356,78 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(DevCtx* __restrict__ c, ApgBuf
             }
         }
     }
-
-    __shared__ double tot[1];
-    const double v[1] = {gsq};
-    if (grid_reduce<1>(v, b.partials, b.counter, tot) && threadIdx.x == 0) {
-        const double gn2 = tot[0];
-        c->gn2 = gn2;
-        c->nb_iter = 0;
-        if (!(gn2 <= 1.0e300)) {
-            c->done = 1;
-            c->status = ST_NONFINITE;
-        } else if (sqrt(gn2) <= c->tol) {
-            c->done = 1;
-            c->status = ST_OK;
-        } else if (c->iters >= c->max_iter) {
-            c->done = 1;
-            c->status = ST_MAXITER;
-        } else {
-            c->phase = 1;
-        }
-    }
+    block_partial(gsq, b.pA);
 }
 
-// Pass B: trial x+ = v + dl with dl = -G/L.  Writes x+ and theta*x+ =
-// theta*v + theta*dl into the spare buffers and forms the decrease
-// h(x+) - h(v) through the increment (no cancellation of objective values):
+// Trial pass.  Reads apg[1], block 0 writes apg[0].  After a fresh gradient
+// it finishes ||G||^2 and applies the stop tests (||G|| <= tol: done, the
+// point is v; iteration cap: done with MAXITER); otherwise (or on a retry)
+// it takes the trial x+ = v + dl, dl = -G/L, writes x+ and theta*x+ =
+// theta*v + theta*dl into the spare buffers, and forms per-block partials of
+// the decrease h(x+) - h(v) through the increment (no cancellation of
+// objective values):
 //   data: sum d (r_v + d/2), d = theta*dl;
 //   TV:   sum_sites (s'^2 - s^2) / (sqrt(s'^2+eps^2) + sqrt(s^2+eps^2)),
 //         s'^2 - s^2 = sum a (a + 2 b), a = D dl, b = D v,
-// all per-element products in double.  The last block accepts the step
-// (h(x+) - h(v) <= -||G||^2 / (2L)) and rotates the buffers, or doubles L.
+// with every per-element product in double.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_trial(DevCtx* __restrict__ c, ApgBufs<T> b) {
-    if (c->done | (c->phase != 1)) return;
+__global__ __launch_bounds__(kNT) void k_apg_trial(const Params pr, const ApgState* __restrict__ sin, ApgState* __restrict__ sout,
+                                                   ApgBufs<T> b) {
+    ApgState st = *sin;
+    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(sout, st);
+        return;
+    }
+    bool trial = true;
+    if (st.phase == PH_GRAD_READY) {
+        const double gn2 = reduce_partials(b.pA, b.nbA);
+        st.gn2 = gn2;
+        st.nb_iter = 0;
+        if (!finite_d(gn2)) {
+            st.done = 1;
+            st.status = ST_NONFINITE;
+            trial = false;
+        } else if (sqrt(gn2) <= st.tol) {
+            st.done = 1;
+            st.status = ST_OK;
+            trial = false;
+        } else if (st.iters >= st.max_iter) {
+            st.done = 1;
+            st.status = ST_MAXITER;
+            trial = false;
+        }
+    }
+    if (trial) st.phase = PH_TRIALED;
+    if (writer) put_state(sout, st);
+    if (!trial) return;
+
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = c->C, H = c->H, W = c->W, reg = c->reg;
+    const int C = pr.C, H = pr.H, W = pr.W, reg = pr.reg;
     const int64_t HW = (int64_t)H * W;
     const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
-    const double L = c->L;
-    const T m = (T)c->m;
-    const T ninvL = (T)(-1.0 / L);
-    const int cur = c->cur, prv = c->prev, nxt = c->nxt;
-    const T* __restrict__ X = b.X[cur];
-    const T* __restrict__ XP = b.X[prv];
-    const T* __restrict__ KX = b.KX[cur];
-    const T* __restrict__ KXP = b.KX[prv];
-    T* __restrict__ XN = b.X[nxt];
-    T* __restrict__ KXN = b.KX[nxt];
+    const T m = (T)st.m;
+    const T ninvL = (T)(-1.0 / st.L);
+    const T* __restrict__ X = pick(b.X[0], b.X[1], b.X[2], st.cur);
+    const T* __restrict__ XP = pick(b.X[0], b.X[1], b.X[2], st.prev);
+    const T* __restrict__ KX = pick(b.KX[0], b.KX[1], b.KX[2], st.cur);
+    const T* __restrict__ KXP = pick(b.KX[0], b.KX[1], b.KX[2], st.prev);
+    T* __restrict__ XN = pick(b.X[0], b.X[1], b.X[2], st.nxt);
+    T* __restrict__ KXN = pick(b.KX[0], b.KX[1], b.KX[2], st.nxt);
     const T* __restrict__ G = b.G;
     const T* __restrict__ Y = b.y;
 
     T* s_v = sm;
     T* s_d = sm + C * VR * VP;
     T* s_c = sm + 2 * C * VR * VP;
+    __syncthreads();
     for (int ch = 0; ch < C; ++ch) {
         const T* Xc = X + ch * HW;
         const T* XPc = XP + ch * HW;
@@ -380,7 +439,7 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(DevCtx* __restrict__ c, ApgBu
     __syncthreads();
 
     // ---- TV part of the decrease, per site
-    const double e2 = c->eps_tv * c->eps_tv;
+    const double e2 = pr.eps_tv * pr.eps_tv;
     double dtv = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
@@ -440,47 +499,17 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(DevCtx* __restrict__ c, ApgBu
             }
         }
     }
-
-    __shared__ double tot[1];
-    const double v[1] = {ddat + c->alpha * dtv};
-    if (grid_reduce<1>(v, b.partials, b.counter, tot) && threadIdx.x == 0) {
-        const double delta = tot[0];
-        c->delta_last = delta;
-        if (!(delta <= 1.0e300 && delta >= -1.0e300)) {
-            c->done = 1;
-            c->status = ST_NONFINITE;
-        } else if (delta <= -c->gn2 / (2.0 * L)) {
-            if (b.trace && c->iters < c->trace_cap) b.trace[c->iters] = c->nb_iter;
-            c->iters += 1;
-            const int p = c->prev;
-            c->prev = c->cur;
-            c->cur = c->nxt;
-            c->nxt = p;
-            const double t = c->t;
-            const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-            c->t_prev = t;
-            c->t = tn;
-            c->m = (t - 1.0) / tn;
-            c->phase = 0;
-        } else {
-            c->L = 2.0 * L;
-            c->bt += 1;
-            c->nb_iter += 1;
-            if (c->nb_iter > 200) {
-                c->done = 1;
-                c->status = ST_NONFINITE;
-            }
-        }
-    }
+    block_partial(ddat + pr.alpha * dtv, b.pB);
 }
 
 // x_out = v = x + m (x - x_prev): the point that passed the stop test
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_apg_final(const DevCtx* __restrict__ c, const T* __restrict__ X0, const T* __restrict__ X1,
+__global__ __launch_bounds__(kNT) void k_apg_final(const ApgState* __restrict__ sin, const T* __restrict__ X0, const T* __restrict__ X1,
                                                    const T* __restrict__ X2, T* __restrict__ out, int64_t n) {
-    const T* X = c->cur == 0 ? X0 : (c->cur == 1 ? X1 : X2);
-    const T* XP = c->prev == 0 ? X0 : (c->prev == 1 ? X1 : X2);
-    const T m = (T)c->m;
+    const ApgState st = *sin;
+    const T* X = st.cur == 0 ? X0 : (st.cur == 1 ? X1 : X2);
+    const T* XP = st.prev == 0 ? X0 : (st.prev == 1 ? X1 : X2);
+    const T m = (T)st.m;
     for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
         const T xv = X[e];
         out[e] = dfma(m, xv - XP[e], xv);
@@ -488,24 +517,57 @@ __global__ __launch_bounds__(kNT) void k_apg_final(const DevCtx* __restrict__ c,
 }
 
 // ------------------------------------------------------------------ conjugate gradients
-// Pass 1: p_new = r + beta p_old (p_new = r when beta = 0) and Kp = theta*p_new.
+// Direction pass.  Reads cg[0], block 0 writes cg[1].  Finishes
+// gamma = ||r||^2 from the partials of the update (or init) pass, applies
+// the stop tests (sqrt(gamma) <= tol; iteration cap), then forms
+// p_new = r + beta p_old (p_new = r on the first iteration, beta =
+// gamma / gamma_prev) and Kp = theta*p_new.  init = 1: the set-up call that
+// only copies r (holding q0) into p and forms theta*q0, without touching
+// the state.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_dir(DevCtx* __restrict__ c, CgBufs<T> b) {
-    if (c->cg_done) return;
+__global__ __launch_bounds__(kNT) void k_cg_dir(const Params pr, const CgState* __restrict__ sin, CgState* __restrict__ sout,
+                                                CgBufs<T> b, int init) {
+    CgState st = *sin;
+    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    double beta = 0.0;
+    if (!init) {
+        if (st.done) {
+            if (writer) put_state(sout, st);
+            return;
+        }
+        const double g = reduce_partials(b.pR, b.nbR);
+        if (st.first) {
+            st.first = 0;
+        } else {
+            beta = g / st.gamma;
+        }
+        st.gamma = g;
+        if (!finite_d(g)) {
+            st.done = 1;
+            st.status = ST_NONFINITE;
+        } else if (sqrt(g) <= st.tol) {
+            st.done = 1;
+            st.status = ST_OK;
+        } else if (st.iters >= st.max) {
+            st.done = 1;
+            st.status = ST_MAXITER;
+        }
+        if (writer) put_state(sout, st);
+        if (st.done) return;
+    }
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
-    const int C = c->C, H = c->H, W = c->W;
+    const int C = pr.C, H = pr.H, W = pr.W;
     const int64_t HW = (int64_t)H * W;
     const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
-    const double beta = c->cg_b;
     const T bT = (T)beta;
-    const T* __restrict__ Pold = b.P[c->pc];
-    T* __restrict__ Pnew = b.P[c->pc ^ 1];
+    const T* __restrict__ Pold = pick(b.P[0], b.P[1], st.pc);
+    T* __restrict__ Pnew = pick(b.P[0], b.P[1], st.pc ^ 1);
     for (int ch = 0; ch < C; ++ch) {
         const T* rc = b.r + ch * HW;
         const T* pc = Pold + ch * HW;
@@ -531,17 +593,23 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(DevCtx* __restrict__ c, CgBufs<T
     }
 }
 
-// Pass 2: Hp = theta . Kp + alpha grad^2 R(xt)[p] and the curvature <p,Hp>.
+// Hessian pass.  Reads cg[1], block 0 writes cg[2].
+// Hp = theta . Kp + alpha grad^2 R(xt)[p] and per-block partials of <p,Hp>;
 // grad^2 R(x)[p] = D^T (w Dp - w^3 m Dx), m = <Dx, Dp> over the coupled
-// channels.  init = 1 computes H q0 only (no solver decisions).
+// channels.  init = 1 computes H q0 only.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_hvp(DevCtx* __restrict__ c, CgBufs<T> b, int init) {
-    if (c->cg_done) return;
+__global__ __launch_bounds__(kNT) void k_cg_hvp(const Params pr, const CgState* __restrict__ sin, CgState* __restrict__ sout,
+                                                CgBufs<T> b, int init) {
+    const CgState st = *sin;
+    if (!init) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) put_state(sout, st);
+        if (st.done) return;
+    }
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = c->C, H = c->H, W = c->W, reg = c->reg;
+    const int C = pr.C, H = pr.H, W = pr.W, reg = pr.reg;
     const int nw = reg == 1 ? C : 1;
     const int64_t HW = (int64_t)H * W;
     const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
@@ -549,8 +617,8 @@ __global__ __launch_bounds__(kNT) void k_cg_hvp(DevCtx* __restrict__ c, CgBufs<T
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
-    const T alpha = (T)c->alpha;
-    const T* __restrict__ P = b.P[c->pc ^ 1];
+    const T alpha = (T)pr.alpha;
+    const T* __restrict__ P = pick(b.P[0], b.P[1], st.pc ^ 1);
 
     T* s_x = sm;
     T* s_p = sm + C * VR * VP;
@@ -563,7 +631,7 @@ __global__ __launch_bounds__(kNT) void k_cg_hvp(DevCtx* __restrict__ c, CgBufs<T
         load_tile<VR, VP, VP>(s_p + ch * VR * VP, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return pc[g]; });
     }
     __syncthreads();
-    const T eps2 = (T)(c->eps_tv * c->eps_tv);
+    const T eps2 = (T)(pr.eps_tv * pr.eps_tv);
     for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
         const int r = idx / WP, cc = idx - r * WP;
         const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
@@ -652,28 +720,35 @@ __global__ __launch_bounds__(kNT) void k_cg_hvp(DevCtx* __restrict__ c, CgBufs<T
             }
         }
     }
-    if (init) return;
-    __shared__ double tot[1];
-    const double v[1] = {kap};
-    if (grid_reduce<1>(v, b.partials, b.counter, tot) && threadIdx.x == 0) {
-        const double kappa = tot[0];
-        c->kappa = kappa;
-        if (!(kappa > 0.0) || !(kappa <= 1.0e300)) {
-            c->cg_done = 1;
-            c->cg_status = (kappa <= 1.0e300) ? ST_NOT_SPD : ST_NONFINITE;
-        } else {
-            c->cg_a = c->gamma / kappa;
-        }
-    }
+    if (!init) block_partial(kap, b.pK);
 }
 
-// Pass 3: q += a p, r -= a Hp, gamma+ = ||r||^2; the last block forms
-// beta = gamma+/gamma and applies the stop test sqrt(gamma) <= tol.
+// Update pass.  Reads cg[2], block 0 writes cg[0].  Finishes the curvature
+// kappa = <p,Hp> (not positive: MAID_NOT_SPD), a = gamma/kappa, then
+// q += a p, r -= a Hp and per-block partials of ||r||^2.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_update(DevCtx* __restrict__ c, CgBufs<T> b, int64_t n) {
-    if (c->cg_done) return;
-    const T a = (T)c->cg_a;
-    const T* __restrict__ P = b.P[c->pc ^ 1];
+__global__ __launch_bounds__(kNT) void k_cg_update(const CgState* __restrict__ sin, CgState* __restrict__ sout, CgBufs<T> b,
+                                                   int64_t n) {
+    CgState st = *sin;
+    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(sout, st);
+        return;
+    }
+    const double kappa = reduce_partials(b.pK, b.nbK);
+    st.kappa = kappa;
+    if (!(kappa > 0.0) || !finite_d(kappa)) {
+        st.done = 1;
+        st.status = finite_d(kappa) ? ST_NOT_SPD : ST_NONFINITE;
+        if (writer) put_state(sout, st);
+        return;
+    }
+    const T* __restrict__ P = pick(b.P[0], b.P[1], st.pc ^ 1);
+    st.a = st.gamma / kappa;
+    st.iters += 1;
+    st.pc ^= 1;
+    if (writer) put_state(sout, st);
+    const T a = (T)st.a;
     double rs = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
         const T pv = P[e];
@@ -682,64 +757,28 @@ __global__ __launch_bounds__(kNT) void k_cg_update(DevCtx* __restrict__ c, CgBuf
         b.r[e] = rv;
         rs += (double)rv * (double)rv;
     }
-    __shared__ double tot[1];
-    const double v[1] = {rs};
-    if (grid_reduce<1>(v, b.partials, b.counter, tot) && threadIdx.x == 0) {
-        const double g = tot[0];
-        c->cg_iters += 1;
-        c->pc ^= 1;
-        if (!(g <= 1.0e300)) {
-            c->cg_done = 1;
-            c->cg_status = ST_NONFINITE;
-            return;
-        }
-        c->cg_b = g / c->gamma;
-        c->gamma = g;
-        if (sqrt(g) <= c->cg_tol) {
-            c->cg_done = 1;
-            c->cg_status = ST_OK;
-        } else if (c->cg_iters >= c->cg_max) {
-            c->cg_done = 1;
-            c->cg_status = ST_MAXITER;
-        }
-    }
+    block_partial(rs, b.pR);
 }
 
-// r = b - H q0 (Hp holds H q0), gamma = ||r||^2, initial stop test.
+// r = b - H q0 (Hp holds H q0) and per-block partials of ||r||^2.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_init(DevCtx* __restrict__ c, CgBufs<T> b, int64_t n) {
+__global__ __launch_bounds__(kNT) void k_cg_init(CgBufs<T> b, int64_t n) {
     double rs = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
         const T rv = b.b[e] - b.Hp[e];
         b.r[e] = rv;
         rs += (double)rv * (double)rv;
     }
-    __shared__ double tot[1];
-    const double v[1] = {rs};
-    if (grid_reduce<1>(v, b.partials, b.counter, tot) && threadIdx.x == 0) {
-        const double g = tot[0];
-        c->gamma = g;
-        c->cg_b = 0.0;
-        c->cg_iters = 0;
-        if (!(g <= 1.0e300)) {
-            c->cg_done = 1;
-            c->cg_status = ST_NONFINITE;
-        } else if (sqrt(g) <= c->cg_tol) {
-            c->cg_done = 1;
-            c->cg_status = ST_OK;
-        } else if (c->cg_max <= 0) {
-            c->cg_done = 1;
-            c->cg_status = ST_MAXITER;
-        }
-    }
+    block_partial(rs, b.pR);
 }
 
 // ------------------------------------------------------------------ small kernels
 // theta (double, KxK) -> compute type, plain and flipped; optionally its
-// l1 norm squared into c->L when c->L <= 0 (starting Lipschitz estimate).
+// l1 norm squared into *L_io when *L_io <= 0 (starting Lipschitz estimate)
+// and the l1 norm into *abs_out (both nullable).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_prep_kernel(DevCtx* __restrict__ c, const double* __restrict__ th, T* __restrict__ out, T* __restrict__ outf,
-                              int K, int set_L, int red_slot) {
+__global__ __launch_bounds__(1024) void k_prep_kernel(double* __restrict__ L_io, double* __restrict__ abs_out,
+                                                      const double* __restrict__ th, T* __restrict__ out, T* __restrict__ outf, int K) {
     __shared__ double s_abs[1024];
     const int KK = K * K;
     const int t = threadIdx.x;
@@ -757,8 +796,8 @@ __global__ __launch_bounds__(1024) void k_prep_kernel(DevCtx* __restrict__ c, co
     if (t == 0) {
         double s = 0.0;
         for (int i = 0; i < KK; ++i) s += s_abs[i];
-        if (set_L && !(c->L > 0.0)) c->L = s * s;
-        if (red_slot >= 0) c->red[red_slot] = s;
+        if (L_io && !(*L_io > 0.0)) *L_io = s * s;
+        if (abs_out) *abs_out = s;
     }
 }
 
@@ -849,10 +888,11 @@ __global__ __launch_bounds__(kNT) void k_hg_corr(int C, int H, int W, int K, con
         part[(size_t)blockIdx.x * KT * KT + i] = ((s_red[0][i] + s_red[1][i]) + s_red[2][i]) + s_red[3][i];
 }
 
-// z = -sum_blocks Z + with_r * grad r(theta); ||z||^2 into c->red[slot].
+// z = -sum_blocks Z + with_r * grad r(theta); ||z||^2 into *znorm2.
 template <int KT>
-__global__ __launch_bounds__(1024) void k_hg_final(DevCtx* __restrict__ c, const double* __restrict__ part, int nblk, int K, const double* __restrict__ th,
-                           const double* __restrict__ a, int with_r, double* __restrict__ z, int slot) {
+__global__ __launch_bounds__(1024) void k_hg_final(double beta, double h1_w0, const double* __restrict__ part, int nblk, int K,
+                                                   const double* __restrict__ th, const double* __restrict__ a, int with_r,
+                                                   double* __restrict__ z, double* __restrict__ znorm2) {
     __shared__ double s_e[1024];
     __shared__ double s_z[1024];
     const int t = threadIdx.x, KK = K * K;
@@ -862,6 +902,7 @@ __global__ __launch_bounds__(1024) void k_hg_final(DevCtx* __restrict__ c, const
     if (t < KK) {
         const int u = t / K, v = t - u * K;
         double s = 0.0;
+#pragma unroll 8
         for (int bidx = 0; bidx < nblk; ++bidx) s += part[(size_t)bidx * KT * KT + u * KT + v];
         double gr = 0.0;
         if (with_r && a) {
@@ -872,7 +913,7 @@ __global__ __launch_bounds__(1024) void k_hg_final(DevCtx* __restrict__ c, const
             if (u < K - 1) lap += e - s_e[t + K];
             if (v > 0) lap += e - s_e[t - 1];
             if (v < K - 1) lap += e - s_e[t + 1];
-            gr = 2.0 * c->beta * (c->h1_w0 * e + lap);
+            gr = 2.0 * beta * (h1_w0 * e + lap);
         }
         zz = -s + gr;
         z[t] = zz;
@@ -882,7 +923,7 @@ __global__ __launch_bounds__(1024) void k_hg_final(DevCtx* __restrict__ c, const
     if (t == 0) {
         double s = 0.0;
         for (int i = 0; i < KK; ++i) s += s_z[i];
-        c->red[slot] = s;
+        *znorm2 = s;
     }
 }
 

@@ -18,55 +18,58 @@ static inline hipError_t ensure_lds(Kern kern, size_t bytes) {
 }
 
 template <typename T, int K, int R>
-static hipError_t conv_kr(const Shape& d, DevCtx* c, const T* ker, const T* in, const T* sub, T* out, int slot, double* partials,
-                          unsigned* counter, hipStream_t s) {
+static hipError_t conv_kr(const Shape& d, const T* ker, const T* in, const T* sub, T* out, double* part, hipStream_t s) {
     const size_t lds = sizeof(T) * lds_conv(K, R);
     auto kern = k_conv<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, c, ker, in, sub, out, slot, partials, counter);
+    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, d.C, d.H, d.W, ker, in, sub, out, part);
     return hipGetLastError();
 }
 
 template <typename T, int K, int R>
-static hipError_t apg_grad_kr(const Shape& d, DevCtx* c, const ApgBufs<T>& b, hipStream_t s) {
+static hipError_t apg_grad_kr(const Shape& d, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+                              hipStream_t s) {
     const int nw = d.reg == 1 ? d.C : 1;
     const size_t lds = sizeof(T) * lds_apg_grad(K, R, d.C, nw);
     auto kern = k_apg_grad<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, c, b);
+    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, p, sin, sout, b);
     return hipGetLastError();
 }
 
 template <typename T, int K, int R>
-static hipError_t apg_trial_kr(const Shape& d, DevCtx* c, const ApgBufs<T>& b, hipStream_t s) {
+static hipError_t apg_trial_kr(const Shape& d, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+                               hipStream_t s) {
     const size_t lds = sizeof(T) * lds_apg_trial(K, R, d.C);
     auto kern = k_apg_trial<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, c, b);
+    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, p, sin, sout, b);
     return hipGetLastError();
 }
 
 template <typename T, int K, int R>
-static hipError_t cg_dir_kr(const Shape& d, DevCtx* c, const CgBufs<T>& b, hipStream_t s) {
+static hipError_t cg_dir_kr(const Shape& d, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b, int init,
+                            hipStream_t s) {
     const size_t lds = sizeof(T) * lds_conv(K, R);
     auto kern = k_cg_dir<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, c, b);
+    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, p, sin, sout, b, init);
     return hipGetLastError();
 }
 
 template <typename T, int K, int R>
-static hipError_t cg_hvp_kr(const Shape& d, DevCtx* c, const CgBufs<T>& b, int init, hipStream_t s) {
+static hipError_t cg_hvp_kr(const Shape& d, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b, int init,
+                            hipStream_t s) {
     const int nw = d.reg == 1 ? d.C : 1;
     const size_t lds = sizeof(T) * lds_cg_hvp(K, R, d.C, nw);
     auto kern = k_cg_hvp<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, c, b, init);
+    hipLaunchKernelGGL(kern, dim3(stencil_blocks(d, R)), dim3(kNT), lds, s, p, sin, sout, b, init);
     return hipGetLastError();
 }
 
@@ -79,40 +82,43 @@ static hipError_t cg_hvp_kr(const Shape& d, DevCtx* c, const CgBufs<T>& b, int i
     }
 
 template <typename T, int K>
-hipError_t conv_k(const Shape& d, int R, DevCtx* c, const T* ker, const T* in, const T* sub, T* out, int slot,
-                  double* partials, unsigned* counter, hipStream_t s) {
-    MAID_R_DISPATCH(conv_kr, d, c, ker, in, sub, out, slot, partials, counter, s)
+hipError_t conv_k(const Shape& d, int R, const T* ker, const T* in, const T* sub, T* out, double* part, hipStream_t s) {
+    MAID_R_DISPATCH(conv_kr, d, ker, in, sub, out, part, s)
 }
 template <typename T, int K>
-hipError_t apg_grad_k(const Shape& d, int R, DevCtx* c, const ApgBufs<T>& b, hipStream_t s) {
-    MAID_R_DISPATCH(apg_grad_kr, d, c, b, s)
+hipError_t apg_grad_k(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+                      hipStream_t s) {
+    MAID_R_DISPATCH(apg_grad_kr, d, p, sin, sout, b, s)
 }
 template <typename T, int K>
-hipError_t apg_trial_k(const Shape& d, int R, DevCtx* c, const ApgBufs<T>& b, hipStream_t s) {
-    MAID_R_DISPATCH(apg_trial_kr, d, c, b, s)
+hipError_t apg_trial_k(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+                       hipStream_t s) {
+    MAID_R_DISPATCH(apg_trial_kr, d, p, sin, sout, b, s)
 }
 template <typename T, int K>
-hipError_t cg_dir_k(const Shape& d, int R, DevCtx* c, const CgBufs<T>& b, hipStream_t s) {
-    MAID_R_DISPATCH(cg_dir_kr, d, c, b, s)
+hipError_t cg_dir_k(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b, int init,
+                    hipStream_t s) {
+    MAID_R_DISPATCH(cg_dir_kr, d, p, sin, sout, b, init, s)
 }
 template <typename T, int K>
-hipError_t cg_hvp_k(const Shape& d, int R, DevCtx* c, const CgBufs<T>& b, int init, hipStream_t s) {
-    MAID_R_DISPATCH(cg_hvp_kr, d, c, b, init, s)
+hipError_t cg_hvp_k(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b, int init,
+                    hipStream_t s) {
+    MAID_R_DISPATCH(cg_hvp_kr, d, p, sin, sout, b, init, s)
 }
 
 // Instantiate every stencil launcher of both storage types for one K.
-#define MAID_INSTANTIATE_K(KV)                                                                                           \
-    template hipError_t conv_k<float, KV>(const Shape&, int, DevCtx*, const float*, const float*, const float*, float*,  \
-                                          int, double*, unsigned*, hipStream_t);                                       \
-    template hipError_t conv_k<double, KV>(const Shape&, int, DevCtx*, const double*, const double*, const double*,     \
-                                           double*, int, double*, unsigned*, hipStream_t);                             \
-    template hipError_t apg_grad_k<float, KV>(const Shape&, int, DevCtx*, const ApgBufs<float>&, hipStream_t);          \
-    template hipError_t apg_grad_k<double, KV>(const Shape&, int, DevCtx*, const ApgBufs<double>&, hipStream_t);        \
-    template hipError_t apg_trial_k<float, KV>(const Shape&, int, DevCtx*, const ApgBufs<float>&, hipStream_t);         \
-    template hipError_t apg_trial_k<double, KV>(const Shape&, int, DevCtx*, const ApgBufs<double>&, hipStream_t);       \
-    template hipError_t cg_dir_k<float, KV>(const Shape&, int, DevCtx*, const CgBufs<float>&, hipStream_t);             \
-    template hipError_t cg_dir_k<double, KV>(const Shape&, int, DevCtx*, const CgBufs<double>&, hipStream_t);           \
-    template hipError_t cg_hvp_k<float, KV>(const Shape&, int, DevCtx*, const CgBufs<float>&, int, hipStream_t);        \
-    template hipError_t cg_hvp_k<double, KV>(const Shape&, int, DevCtx*, const CgBufs<double>&, int, hipStream_t);
+#define MAID_INSTANTIATE_T(T, KV)                                                                                        \
+    template hipError_t conv_k<T, KV>(const Shape&, int, const T*, const T*, const T*, T*, double*, hipStream_t);       \
+    template hipError_t apg_grad_k<T, KV>(const Shape&, int, const Params&, const ApgState*, ApgState*,                \
+                                          const ApgBufs<T>&, hipStream_t);                                             \
+    template hipError_t apg_trial_k<T, KV>(const Shape&, int, const Params&, const ApgState*, ApgState*,               \
+                                           const ApgBufs<T>&, hipStream_t);                                            \
+    template hipError_t cg_dir_k<T, KV>(const Shape&, int, const Params&, const CgState*, CgState*, const CgBufs<T>&,  \
+                                        int, hipStream_t);                                                             \
+    template hipError_t cg_hvp_k<T, KV>(const Shape&, int, const Params&, const CgState*, CgState*, const CgBufs<T>&,  \
+                                        int, hipStream_t);
+
+// Instantiate every stencil launcher of both storage types for one K.
+#define MAID_INSTANTIATE_K(KV) MAID_INSTANTIATE_T(float, KV) MAID_INSTANTIATE_T(double, KV)
 
 }  // namespace maid

@@ -16,7 +16,8 @@ __global__ void k_theta_step(const double* __restrict__ th, const double* __rest
 // gradient 2 beta (w0 e + D^T D e).  One block of 1024 threads.
 __device__ __forceinline__ double sob_e(const double* s_e, int K, int u, int v) { return s_e[u * K + v]; }
 
-__global__ __launch_bounds__(1024) void k_sobolev(DevCtx* __restrict__ c, const double* __restrict__ th, const double* __restrict__ a, int K, int slot) {
+__global__ __launch_bounds__(1024) void k_sobolev(double beta, double h1_w0, const double* __restrict__ th,
+                                                  const double* __restrict__ a, int K, double* __restrict__ out) {
     __shared__ double s_e[1024];
     __shared__ double s_r[1024];
     const int t = threadIdx.x, KK = K * K;
@@ -28,32 +29,37 @@ __global__ __launch_bounds__(1024) void k_sobolev(DevCtx* __restrict__ c, const 
         const double e = s_e[t];
         const double dh = (v < K - 1) ? sob_e(s_e, K, u, v + 1) - e : 0.0;
         const double dv = (u < K - 1) ? sob_e(s_e, K, u + 1, v) - e : 0.0;
-        val = c->h1_w0 * e * e + dh * dh + dv * dv;
+        val = h1_w0 * e * e + dh * dh + dv * dv;
     }
     s_r[t] = val;
     __syncthreads();
     if (t == 0) {
         double s = 0.0;
         for (int i = 0; i < KK; ++i) s += s_r[i];
-        c->red[slot] = c->beta * s;
+        *out = beta * s;
     }
 }
 
+
+// *out = sum of nb partials (one block)
+__global__ __launch_bounds__(kNT) void k_reduce(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    const double s = reduce_partials(part, nb);
+    if (threadIdx.x == 0) *out = s;
+}
 
 #define MAID_FOR_EACH_K(X) X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
 
 template <typename T>
-hipError_t Ops<T>::prep_kernel(DevCtx* c, const double* th, T* out, T* outf, int K, int set_L, int red_slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep_kernel<T>, dim3(1), dim3(1024), 0, s, c, th, out, outf, K, set_L, red_slot);
+hipError_t Ops<T>::prep_kernel(double* L_io, double* abs_out, const double* th, T* out, T* outf, int K, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep_kernel<T>, dim3(1), dim3(1024), 0, s, L_io, abs_out, th, out, outf, K);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Ops<T>::conv(const Shape& d, int R, DevCtx* c, const T* ker, const T* in, const T* sub, T* out, int slot,
-                        double* partials, unsigned* counter, hipStream_t s) {
+hipError_t Ops<T>::conv(const Shape& d, int R, const T* ker, const T* in, const T* sub, T* out, double* part, hipStream_t s) {
     switch (d.K) {
 #define MAID_CASE(KV) \
-    case KV: return conv_k<T, KV>(d, R, c, ker, in, sub, out, slot, partials, counter, s);
+    case KV: return conv_k<T, KV>(d, R, ker, in, sub, out, part, s);
         MAID_FOR_EACH_K(MAID_CASE)
 #undef MAID_CASE
         default: return hipErrorInvalidValue;
@@ -61,10 +67,11 @@ hipError_t Ops<T>::conv(const Shape& d, int R, DevCtx* c, const T* ker, const T*
 }
 
 template <typename T>
-hipError_t Ops<T>::apg_grad(const Shape& d, int R, DevCtx* c, const ApgBufs<T>& b, hipStream_t s) {
+hipError_t Ops<T>::apg_grad(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+                            hipStream_t s) {
     switch (d.K) {
 #define MAID_CASE(KV) \
-    case KV: return apg_grad_k<T, KV>(d, R, c, b, s);
+    case KV: return apg_grad_k<T, KV>(d, R, p, sin, sout, b, s);
         MAID_FOR_EACH_K(MAID_CASE)
 #undef MAID_CASE
         default: return hipErrorInvalidValue;
@@ -72,10 +79,11 @@ hipError_t Ops<T>::apg_grad(const Shape& d, int R, DevCtx* c, const ApgBufs<T>& 
 }
 
 template <typename T>
-hipError_t Ops<T>::apg_trial(const Shape& d, int R, DevCtx* c, const ApgBufs<T>& b, hipStream_t s) {
+hipError_t Ops<T>::apg_trial(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+                             hipStream_t s) {
     switch (d.K) {
 #define MAID_CASE(KV) \
-    case KV: return apg_trial_k<T, KV>(d, R, c, b, s);
+    case KV: return apg_trial_k<T, KV>(d, R, p, sin, sout, b, s);
         MAID_FOR_EACH_K(MAID_CASE)
 #undef MAID_CASE
         default: return hipErrorInvalidValue;
@@ -83,10 +91,11 @@ hipError_t Ops<T>::apg_trial(const Shape& d, int R, DevCtx* c, const ApgBufs<T>&
 }
 
 template <typename T>
-hipError_t Ops<T>::cg_dir(const Shape& d, int R, DevCtx* c, const CgBufs<T>& b, hipStream_t s) {
+hipError_t Ops<T>::cg_dir(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b,
+                          int init, hipStream_t s) {
     switch (d.K) {
 #define MAID_CASE(KV) \
-    case KV: return cg_dir_k<T, KV>(d, R, c, b, s);
+    case KV: return cg_dir_k<T, KV>(d, R, p, sin, sout, b, init, s);
         MAID_FOR_EACH_K(MAID_CASE)
 #undef MAID_CASE
         default: return hipErrorInvalidValue;
@@ -94,10 +103,11 @@ hipError_t Ops<T>::cg_dir(const Shape& d, int R, DevCtx* c, const CgBufs<T>& b, 
 }
 
 template <typename T>
-hipError_t Ops<T>::cg_hvp(const Shape& d, int R, DevCtx* c, const CgBufs<T>& b, int init, hipStream_t s) {
+hipError_t Ops<T>::cg_hvp(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b,
+                          int init, hipStream_t s) {
     switch (d.K) {
 #define MAID_CASE(KV) \
-    case KV: return cg_hvp_k<T, KV>(d, R, c, b, init, s);
+    case KV: return cg_hvp_k<T, KV>(d, R, p, sin, sout, b, init, s);
         MAID_FOR_EACH_K(MAID_CASE)
 #undef MAID_CASE
         default: return hipErrorInvalidValue;
@@ -105,22 +115,22 @@ hipError_t Ops<T>::cg_hvp(const Shape& d, int R, DevCtx* c, const CgBufs<T>& b, 
 }
 
 template <typename T>
-hipError_t Ops<T>::apg_final(DevCtx* c, const ApgBufs<T>& b, T* out, int64_t n, hipStream_t s) {
+hipError_t Ops<T>::apg_final(const ApgState* sin, const ApgBufs<T>& b, T* out, int64_t n, hipStream_t s) {
     int64_t nb = (n + kNT - 1) / kNT;
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_apg_final<T>, dim3((unsigned)nb), dim3(kNT), 0, s, c, b.X[0], b.X[1], b.X[2], out, n);
+    hipLaunchKernelGGL(k_apg_final<T>, dim3((unsigned)nb), dim3(kNT), 0, s, sin, b.X[0], b.X[1], b.X[2], out, n);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Ops<T>::cg_update(DevCtx* c, const CgBufs<T>& b, int64_t n, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(nblk), dim3(kNT), 0, s, c, b, n);
+hipError_t Ops<T>::cg_update(const CgState* sin, CgState* sout, const CgBufs<T>& b, int64_t n, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(nblk), dim3(kNT), 0, s, sin, sout, b, n);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Ops<T>::cg_init(DevCtx* c, const CgBufs<T>& b, int64_t n, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(nblk), dim3(kNT), 0, s, c, b, n);
+hipError_t Ops<T>::cg_init(const CgBufs<T>& b, int64_t n, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(nblk), dim3(kNT), 0, s, b, n);
     return hipGetLastError();
 }
 
@@ -137,12 +147,21 @@ hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w,
 template struct Ops<float>;
 template struct Ops<double>;
 
-hipError_t launch_hg_final(const Shape& d, DevCtx* c, const double* part, int nblk, const double* th, const double* a,
-                           int with_r, double* z, int slot, hipStream_t s) {
+hipError_t launch_reduce(const double* part, int nb, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kNT), 0, s, part, nb, out);
+    return hipGetLastError();
+}
+
+int hg_items(const Shape& d) {
+    return ((d.W + kHgTJ - 1) / kHgTJ) * ((d.H + kHgTI - 1) / kHgTI) * d.C * 2;
+}
+
+hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
+                           const double* a, int with_r, double* z, double* znorm2, hipStream_t s) {
     if (d.K <= 16)
-        hipLaunchKernelGGL(k_hg_final<16>, dim3(1), dim3(1024), 0, s, c, part, nblk, d.K, th, a, with_r, z, slot);
+        hipLaunchKernelGGL(k_hg_final<16>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
     else
-        hipLaunchKernelGGL(k_hg_final<32>, dim3(1), dim3(1024), 0, s, c, part, nblk, d.K, th, a, with_r, z, slot);
+        hipLaunchKernelGGL(k_hg_final<32>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
     return hipGetLastError();
 }
 
@@ -151,8 +170,8 @@ hipError_t launch_theta_step(const double* th, const double* z, double step, dou
     return hipGetLastError();
 }
 
-hipError_t launch_sobolev(DevCtx* c, const double* th, const double* a, int K, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_sobolev, dim3(1), dim3(1024), 0, s, c, th, a, K, slot);
+hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sobolev, dim3(1), dim3(1024), 0, s, beta, h1_w0, th, a, K, out);
     return hipGetLastError();
 }
 
