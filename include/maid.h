@@ -159,6 +159,12 @@ int maid_hypergrad(maid_ctx* ctx, const void* theta, const void* a, const void* 
                    const void* x_tilde, const void* q, int32_t with_r, double* z,
                    double* znorm_out, hipStream_t stream);
 
+/* The blur operator T(theta, .) of Eq. (2.4) as a 2D convolution:
+   out = theta * in (adjoint = 0) or out = theta . in, the adjoint correlation
+   (adjoint = 1), zero boundary, same size.  in and out must not alias. */
+int maid_apply_operator(maid_ctx* ctx, const void* theta, const void* in, void* out, int32_t adjoint,
+                        hipStream_t stream);
+
 /* The objective values used by Eq. (3.4): r(theta) (HOST out). */
 int maid_sobolev_value(maid_ctx* ctx, const void* theta, const void* a, double* r_out,
                        hipStream_t stream);

@@ -24,7 +24,7 @@ CODE_NAMES = {OK: "OK", MAXITER: "MAXITER", ACCURACY_FLOOR: "ACCURACY_FLOOR", EI
 # every entry point declared in include/maid.h
 EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string",
            "maid_set_tile_rows", "maid_lower_solve", "maid_upper_value_grad",
-           "maid_adjoint_solve", "maid_hypergrad", "maid_sobolev_value", "maid_step",
+           "maid_adjoint_solve", "maid_hypergrad", "maid_apply_operator", "maid_sobolev_value", "maid_step",
            "maid_profile", "maid_profile_read", "maid_profile_name")
 PROF_KINDS = 8
 
@@ -99,6 +99,8 @@ def lib():
     L.maid_adjoint_solve.restype = ct.c_int
     L.maid_hypergrad.argtypes = [P, P, P, P, P, P, i32, P, dp, P]
     L.maid_hypergrad.restype = ct.c_int
+    L.maid_apply_operator.argtypes = [P, P, P, P, i32, P]
+    L.maid_apply_operator.restype = ct.c_int
     L.maid_sobolev_value.argtypes = [P, P, P, dp, P]
     L.maid_sobolev_value.restype = ct.c_int
     L.maid_step.argtypes = [P, P, P, ct.POINTER(maid_state), ct.POINTER(maid_hparams),

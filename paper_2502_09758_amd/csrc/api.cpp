@@ -452,6 +452,17 @@ int hypergrad_t(maid_ctx* c, const double* theta, const double* a, const T* y, c
     return MAID_OK;
 }
 
+template <typename T>
+int apply_operator_t(maid_ctx* c, const double* theta, const T* in, T* out, int adjoint, hipStream_t s) {
+    const Shape& d = c->shape;
+    T* th = (T*)c->th_c;
+    T* thf = (T*)c->thf_c;
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(nullptr, nullptr, theta, th, thf, d.K, s));
+    LAUNCH(MAID_PROF_CONV, Ops<T>::conv(d, c->R(), adjoint ? th : thf, in, nullptr, out, nullptr, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAID_OK;
+}
+
 int sobolev_value_impl(maid_ctx* c, const double* theta, const double* a, double* r, hipStream_t s) {
     if (c->d.beta == 0.0) {
         *r = 0.0;
@@ -769,6 +780,16 @@ int maid_hypergrad(maid_ctx* c, const void* theta, const void* a, const void* y,
                                    (const double*)q, with_r && c->d.beta != 0.0, z, znorm_out, s);
     return hypergrad_t<float>(c, (const double*)theta, (const double*)a, (const float*)y, (const float*)x_tilde,
                               (const float*)q, with_r && c->d.beta != 0.0, z, znorm_out, s);
+}
+
+int maid_apply_operator(maid_ctx* c, const void* theta, const void* in, void* out, int32_t adjoint, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (!theta || !in || !out) return fail(c, MAID_EINVAL, "apply_operator: NULL argument");
+    if (in == out) return fail(c, MAID_EINVAL, "apply_operator: in and out must not alias");
+    if (c->d.dtype == MAID_F64)
+        return apply_operator_t<double>(c, (const double*)theta, (const double*)in, (double*)out, adjoint, s);
+    return apply_operator_t<float>(c, (const double*)theta, (const float*)in, (float*)out, adjoint, s);
 }
 
 int maid_sobolev_value(maid_ctx* c, const void* theta, const void* a, double* r_out, hipStream_t s) {

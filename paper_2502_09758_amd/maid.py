@@ -174,6 +174,16 @@ class Maid:
         self._check(rc, "hypergrad")
         return z, zn.value
 
+    def apply_operator(self, theta, x, out=None, adjoint=False):
+        """theta * x (or the adjoint correlation theta . x)."""
+        self._ker(theta, "theta"), self._img(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        self._img(out, "out")
+        self._check(L.lib().maid_apply_operator(self.handle, _ptr(theta), _ptr(x), _ptr(out), int(bool(adjoint)),
+                                                _stream()), "apply_operator")
+        return out
+
     def sobolev_value(self, theta, a):
         self._ker(theta, "theta"), self._ker(a, "a")
         r = ct.c_double()
