@@ -68,12 +68,17 @@ def kernel_model(kind: str, K: int, esz: int, C: int):
 
 
 def roofline_for(prof: dict, N: int, K: int, esz: int, C: int):
-    name, (launches, ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    """Roofline of the kernel kind with the largest total GPU time.  Solver
+    passes launched in chunks exit early once a solve has finished; only the
+    launches that did a pass of work carry algorithmic bytes, so the bytes per
+    launch are the work launches' bytes averaged over all launches, divided
+    by the average duration of all launches (= work bytes / total time)."""
+    name, (launches, work, ms) = max(prof.items(), key=lambda kv: kv[1][2])
     if launches == 0:
         return None, name
     avg_s = ms / launches / 1e3
     b, f = kernel_model(name, K, esz, C)
-    bytes_launch, flops_launch = b * N, f * N
+    bytes_launch, flops_launch = b * N * work / launches, f * N * work / launches
     peak_alu = PEAK_FP64 if (esz == 8 or name == "hg_corr") else PEAK_FP32
     t_hbm, t_alu = bytes_launch / PEAK_HBM, flops_launch / peak_alu
     if t_hbm >= t_alu:
@@ -84,8 +89,8 @@ def roofline_for(prof: dict, N: int, K: int, esz: int, C: int):
         ach = flops_launch / avg_s / 1e12
         roof = dict(bound="mfma" if name == "hg_corr" else "alu", achieved=round(ach, 3),
                     peak=peak_alu / 1e12, unit="TFLOP/s", frac=round(ach / (peak_alu / 1e12), 4), traffic=None)
-    roof.update(kernel=name, launches=launches, avg_us=round(avg_s * 1e6, 3),
-                algorithmic_bytes_per_launch=bytes_launch, algorithmic_flops_per_launch=flops_launch)
+    roof.update(kernel=name, launches=launches, work_launches=work, avg_us=round(avg_s * 1e6, 3),
+                algorithmic_bytes_per_work_launch=b * N, algorithmic_flops_per_work_launch=f * N)
     return roof, name
 
 
@@ -221,7 +226,7 @@ def main():
         "lower_iters": lower, "cg_iters": cg, "accepted_steps": accepted, "psi_trials": trials,
         "maid_restarts": restarts,
         "time_to_hypergrad": tth,
-        "kernel_ms": {k: dict(launches=v[0], ms=round(v[1], 3)) for k, v in prof.items()},
+        "kernel_ms": {k: dict(launches=v[0], work=v[1], ms=round(v[2], 3)) for k, v in prof.items()},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst)

@@ -117,7 +117,8 @@ void maid_destroy(maid_ctx* ctx);
    call on the context.  maid_last_error(NULL) reports the last maid_create
    failure of the calling thread. */
 const char* maid_last_error(const maid_ctx* ctx);
-/* Name of the tile configuration (rows per thread) chosen for each kernel. */
+/* Name of the tile configuration (rows per thread) chosen for each group of
+   instances. */
 const char* maid_config_string(const maid_ctx* ctx);
 /* Override the rows-per-thread tile parameter of the stencil kernels
    (1, 2 or 4; 0 = automatic).  Used by the autotuner. */
@@ -179,11 +180,55 @@ int maid_sobolev_value(maid_ctx* ctx, const void* theta, const void* a, double* 
 int maid_step(maid_ctx* ctx, const void* a, const void* y, maid_state* state,
               const maid_hparams* hp, maid_step_info* info, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batched form
+   One context over n independent problem instances of different sizes (a
+   ragged batch; each instance has its own maid_desc, all with the same
+   dtype).  Every solver pass is one kernel launch per group of instances
+   that share K and the tile configuration, covering all tiles of all
+   instances of the group; elementwise passes are one launch for the whole
+   batch.  Each instance keeps its own solver state, tolerance, step sizes
+   and decisions, so its results are bitwise those of a context created for
+   it alone (same tile configuration).  maid_create(desc, out) is
+   maid_create_batch(desc, 1, out); the single-instance entry points above
+   require a context of one instance (MAID_EINVAL otherwise), the
+   maid_batch_* entry points accept any.
+
+   Per-instance arguments are HOST arrays of length n: of DEVICE pointers
+   (images and kernels, as for the single-instance calls), of tolerances, of
+   Lipschitz estimates (in/out), of maid_state (updated in place), of info
+   records (nullable; info[i].status holds instance i's code).  The return
+   value is a negative error of the call as a whole (bad argument, HIP
+   failure; nothing written), else MAID_OK if every instance returned
+   MAID_OK, else the code of the first instance that did not (instances with
+   a negative code leave their outputs unwritten; the others are written). */
+int maid_create_batch(const maid_desc* descs, int32_t n, maid_ctx** out);
+/* Number of instances of a context (0 for NULL). */
+int32_t maid_batch_size(const maid_ctx* ctx);
+/* maid_lower_solve for every instance i: theta[i], y[i], x[i] (in/out),
+   tol[i], L_inout[i]; one max_iter for all. */
+int maid_batch_lower_solve(maid_ctx* ctx, const void* const* theta, const void* const* y,
+                           void* const* x, const double* tol, int32_t max_iter,
+                           double* L_inout, maid_solve_info* info, hipStream_t stream);
+/* maid_adjoint_solve for every instance i. */
+int maid_batch_adjoint_solve(maid_ctx* ctx, const void* const* theta, const void* const* x_tilde,
+                             const void* const* rhs, void* const* q, const double* tol,
+                             int32_t max_iter, maid_solve_info* info, hipStream_t stream);
+/* maid_step for every instance i (one outer iteration of Algorithm 2 each,
+   run in lockstep: the lower-level, CG and trial solves of all instances
+   that need one at the same point of the algorithm share launches); one set
+   of hyperparameters for all. */
+int maid_batch_step(maid_ctx* ctx, const void* const* a, const void* const* y,
+                    maid_state* states, const maid_hparams* hp, maid_step_info* info,
+                    hipStream_t stream);
+
 /* Kernel timing (for measurement and profiling tools).  maid_profile(ctx, 1)
    resets the counters and, until maid_profile(ctx, 0), brackets every kernel
    launch of the context with a pair of HIP events on the launch stream;
    maid_profile_read returns, for one kernel kind, the number of timed
-   launches and their summed GPU duration in milliseconds. */
+   launches, how many of them did a pass of work (solver passes launched in
+   a chunk exit early once the solve has finished or when a backtracking
+   step needs no gradient; work_launches is nullable), and their summed GPU
+   duration in milliseconds. */
 enum {
     MAID_PROF_CONV = 0,       /* convolution / adjoint passes (setup, upper level, hypergradient) */
     MAID_PROF_APG_GRAD = 1,   /* lower level: gradient at the extrapolated point */
@@ -196,7 +241,7 @@ enum {
     MAID_PROF_KINDS = 8
 };
 int maid_profile(maid_ctx* ctx, int32_t enable);
-int maid_profile_read(maid_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms);
+int maid_profile_read(maid_ctx* ctx, int32_t kind, int64_t* launches, int64_t* work_launches, double* total_ms);
 const char* maid_profile_name(int32_t kind);
 
 #ifdef __cplusplus

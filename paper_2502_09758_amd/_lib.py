@@ -25,7 +25,9 @@ CODE_NAMES = {OK: "OK", MAXITER: "MAXITER", ACCURACY_FLOOR: "ACCURACY_FLOOR", EI
 EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string",
            "maid_set_tile_rows", "maid_lower_solve", "maid_upper_value_grad",
            "maid_adjoint_solve", "maid_hypergrad", "maid_apply_operator", "maid_sobolev_value", "maid_step",
-           "maid_profile", "maid_profile_read", "maid_profile_name")
+           "maid_profile", "maid_profile_read", "maid_profile_name",
+           "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
+           "maid_batch_step")
 PROF_KINDS = 8
 
 
@@ -108,10 +110,22 @@ def lib():
     L.maid_step.restype = ct.c_int
     L.maid_profile.argtypes = [P, i32]
     L.maid_profile.restype = ct.c_int
-    L.maid_profile_read.argtypes = [P, i32, ct.POINTER(ct.c_int64), dp]
+    L.maid_profile_read.argtypes = [P, i32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64), dp]
     L.maid_profile_read.restype = ct.c_int
     L.maid_profile_name.argtypes = [i32]
     L.maid_profile_name.restype = ct.c_char_p
+    PP = ct.POINTER(P)
+    L.maid_create_batch.argtypes = [ct.POINTER(maid_desc), i32, ct.POINTER(P)]
+    L.maid_create_batch.restype = ct.c_int
+    L.maid_batch_size.argtypes = [P]
+    L.maid_batch_size.restype = i32
+    L.maid_batch_lower_solve.argtypes = [P, PP, PP, PP, dp, i32, dp, ct.POINTER(maid_solve_info), P]
+    L.maid_batch_lower_solve.restype = ct.c_int
+    L.maid_batch_adjoint_solve.argtypes = [P, PP, PP, PP, PP, dp, i32, ct.POINTER(maid_solve_info), P]
+    L.maid_batch_adjoint_solve.restype = ct.c_int
+    L.maid_batch_step.argtypes = [P, PP, PP, ct.POINTER(maid_state), ct.POINTER(maid_hparams),
+                                  ct.POINTER(maid_step_info), P]
+    L.maid_batch_step.restype = ct.c_int
     _lib = L
     return L
 
@@ -119,6 +133,15 @@ def lib():
 def create(desc: maid_desc) -> int:
     h = ct.c_void_p()
     rc = lib().maid_create(ct.byref(desc), ct.byref(h))
+    if rc != OK:
+        raise MaidError(rc, lib().maid_last_error(None).decode())
+    return h.value
+
+
+def create_batch(descs) -> int:
+    arr = (maid_desc * len(descs))(*descs)
+    h = ct.c_void_p()
+    rc = lib().maid_create_batch(arr, len(descs), ct.byref(h))
     if rc != OK:
         raise MaidError(rc, lib().maid_last_error(None).decode())
     return h.value

@@ -1,9 +1,17 @@
-// devctx.h -- device-resident state shared by the host control code and the
-// kernels of libmaid.  One DevCtx lives in device memory per context; the
-// host writes it before a solve and reads it back when polling.  Kernels
-// read it through scalar loads; only the last block of a reduction pass
-// writes it (with ordinary vector stores), and the next kernel launch orders
-// those writes before any further read.
+// devctx.h -- data shared by the host control code and the kernels of
+// libmaid: the per-instance table every pass reads, the solver states, and
+// the LDS sizing rules.
+//
+// A context holds one or more problem instances (a batch of ragged images).
+// Each pass launch covers the tiles of a group of instances with the same
+// kernel size K and tile height: a block looks up its instance in a
+// block -> instance map, reads that instance's entry of the table (pointers,
+// sizes, parameters; read-only in kernels, so scalar loads) and its solver
+// state.  Solver states are kept in separate arrays (two copies for the
+// lower-level solver, three for CG, one element per instance): a pass reads
+// one copy through a const __restrict__ pointer and its block 0 of each
+// instance writes the next copy, so every block of a launch sees the same
+// state.  A plain solve is a batch of one.
 #pragma once
 #include <stdint.h>
 #include <hip/hip_runtime.h>
@@ -17,10 +25,10 @@ constexpr int kNT = 256;       // threads per block (4 waves)
 
 enum Status : int32_t { ST_OK = 0, ST_MAXITER = 1, ST_NOT_SPD = -4, ST_NONFINITE = -5 };
 
-// Lower-level (FISTA) solver state.  Two copies live in DevCtx: the
-// gradient pass reads apg[0] and its block 0 writes apg[1]; the trial pass
-// reads apg[1] and writes apg[0].  No kernel writes the copy it reads, so
-// every block of a launch sees the same state.
+// Lower-level (FISTA) solver state, one per instance, in two arrays: the
+// gradient pass reads the first and its block 0 of each instance writes the
+// second; the trial pass reads the second and writes the first.  No kernel
+// writes the copy it reads, so every block of a launch sees the same state.
 enum ApgPhase : int32_t { PH_START = 0, PH_GRAD_READY = 1, PH_RETRY = 2, PH_TRIALED = 3 };
 
 struct ApgState {
@@ -34,29 +42,19 @@ struct ApgState {
     int32_t trace_cap, pad;
 };
 
-// CG state: three copies; the direction pass reads cg[0] and writes cg[1],
-// the Hessian pass cg[1] -> cg[2], the update pass cg[2] -> cg[0].
+// CG state, one per instance, in three arrays: the direction pass reads the
+// first and writes the second, the Hessian pass second -> third, the update
+// pass third -> first.
 struct CgState {
     double gamma, kappa, a, tol;
     int32_t max, iters, status, done, pc, first;
 };
 
-// Problem parameters the kernels need, passed by value (kernel arguments
-// live in the constant kernarg segment and are read with scalar loads).
+// Problem parameters the kernels need (part of the instance table, which
+// kernels only read, so they come in through scalar loads).
 struct Params {
     int32_t C, H, W, reg;
     double alpha, eps_tv;
-};
-
-struct DevCtx {
-    // ---------------- problem (fixed per context)
-    int32_t C, H, W, K, reg;
-    int32_t pad0;
-    double alpha, eps_tv, beta, h1_w0;
-    ApgState apg[2];
-    CgState cg[3];
-    // ---------------- generic reduction results
-    double red[8];
 };
 
 __host__ __device__ constexpr int tile_h(int R) { return 4 * R; }
@@ -84,33 +82,44 @@ __host__ __device__ constexpr int lds_cg_hvp(int K, int R, int C, int nw) {
     return cmax(2 * C * tv_rows(R) * tv_pitch() + 2 * nw * fx_rows(R) * fx_pitch(), lds_conv(K, R));
 }
 
-// ------------------------------------------------------------------ buffers
-template <typename T> struct ApgBufs {
-    T* X[3];           // iterates x_k (rotating: cur, prev, next)
-    T* KX[3];          // theta * x_k, kept by linearity
-    T* G;              // gradient at the extrapolated point
+// ------------------------------------------------------------------ instance table
+template <typename T> struct Inst {
+    Params pr;                   // C, H, W, reg, alpha, eps_tv
+    int32_t K;                   // kernel size
+    int32_t nb, base;            // stencil blocks (tiles) and first block within its group launch
+    int32_t nbe, base_e;         // elementwise blocks and first block within the elementwise launch
+    int32_t pad;
+    int64_t N;                   // C*H*W
+    // lower level (FISTA)
+    T* X[3];                     // iterates (rotating: cur, prev, next)
+    T* KX[3];                    // theta * x, kept by linearity
+    T* G;                        // gradient at the extrapolated point
     const T* y;
-    const T* th;       // theta, correlation (adjoint) form, column-major
-    const T* thf;      // theta flipped (convolution form), column-major
-    double* pA;        // per-block partials of ||G||^2 (gradient pass)
-    double* pB;        // per-block partials of h(x+) - h(v) (trial pass)
-    int nbA, nbB;      // grid sizes of the two passes
-    int* trace;        // rejected trials per iteration
-};
-
-template <typename T> struct CgBufs {
+    T* th;                       // theta in the compute type, correlation form, column-major
+    T* thf;                      // the flipped kernel (convolution form), column-major
+    double* pA;                  // per-block partials, gradient pass (nb entries)
+    double* pB;                  // per-block partials, trial pass (nb entries)
+    int* trace;                  // rejected trials per iteration
+    T* xout;                     // where the returned point is written
+    // conjugate gradients
     T* q;
     T* r;
-    T* P[2];           // search direction (ping-pong)
-    T* Kp;             // theta * p
+    T* P[2];                     // search direction (ping-pong)
+    T* Kp;                       // theta * p
     T* Hp;
-    const T* xt;       // lower-level point the Hessian is taken at
-    const T* b;        // right-hand side
-    const T* th;
-    const T* thf;
-    double* pR;        // per-block partials of ||r||^2 (update / init pass)
-    double* pK;        // per-block partials of <p, Hp> (Hessian pass)
-    int nbR, nbK;
+    const T* xt;                 // point the Hessian is taken at
+    const T* b;                  // right-hand side
+    double* pR;                  // per-block partials of ||r||^2 (nbe entries)
+    double* pK;                  // per-block partials of <p, Hp> (nb entries)
+    // one convolution job: cv_out = cv_ker (x) cv_in [- cv_sub], partials of its square
+    const T* cv_ker;
+    const T* cv_in;
+    const T* cv_sub;
+    T* cv_out;
+    double* cv_part;             // nullable
+    // kernel preparation: theta64 (K*K doubles) -> th / thf
+    const double* theta64;       // nullable: nothing to prepare
+    double* red;                 // per-instance reduction results (8 doubles)
 };
 
 }  // namespace maid

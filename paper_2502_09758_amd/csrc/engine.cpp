@@ -1,0 +1,962 @@
+// engine.cpp -- context set-up, launch layout, instance tables, graph
+// capture, timing, and the batched solver drivers (Algorithm 1's lower-level
+// solve and Hessian system, the upper-level value and gradient, the
+// hypergradient of Eq. 3.2, and Algorithm 2 in lockstep over the instances).
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace maid {
+
+static_assert(sizeof(Inst<float>) == sizeof(Inst<double>), "instance tables share one layout");
+
+int fail(maid_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                        \
+    do {                                                                                                     \
+        hipError_t e_ = (expr);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            return fail(c, MAID_EHIP, std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)               \
+    do {                        \
+        int rc_ = (expr);       \
+        if (rc_) return rc_;    \
+    } while (0)
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int auto_rows(const Shape& d) {
+    // the largest tile height that still gives every CU (256) four blocks
+    if (stencil_blocks(d, 4) >= 1024) return 4;
+    if (stencil_blocks(d, 2) >= 1024) return 2;
+    return 1;
+}
+
+int round8(int v) { return (v + 7) & ~7; }
+
+int status_code(int st) {
+    switch (st) {
+        case ST_OK: return MAID_OK;
+        case ST_MAXITER: return MAID_MAXITER;
+        case ST_NOT_SPD: return MAID_NOT_SPD;
+        default: return MAID_NONFINITE;
+    }
+}
+
+bool any(const std::vector<char>& v) {
+    for (char b : v)
+        if (b) return true;
+    return false;
+}
+
+template <typename T> Inst<T>* tab_host(maid_ctx* c, int role) {
+    return reinterpret_cast<Inst<T>*>(c->tab_host) + (size_t)role * c->n;
+}
+template <typename T> const Inst<T>* tab_dev(maid_ctx* c, int role) {
+    return reinterpret_cast<const Inst<T>*>(c->tab_dev) + (size_t)role * c->n;
+}
+
+// copy a byte range of the state block between device and the pinned mirror
+int pull(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n) {
+    const size_t off = (const char*)dev_ptr - c->st_dev;
+    HIP_TRY(hipMemcpyAsync(c->st_host + off, c->st_dev + off, n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAID_OK;
+}
+int push(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n) {
+    const size_t off = (const char*)dev_ptr - c->st_dev;
+    HIP_TRY(hipMemcpyAsync(c->st_dev + off, c->st_host + off, n, hipMemcpyHostToDevice, s));
+    return MAID_OK;
+}
+template <typename T> int upload(maid_ctx* c, int role, hipStream_t s) {
+    const size_t bytes = sizeof(Inst<T>) * c->n;
+    HIP_TRY(hipMemcpyAsync(c->tab_dev + role * bytes, c->tab_host + role * bytes, bytes, hipMemcpyHostToDevice, s));
+    return MAID_OK;
+}
+int pull_red(maid_ctx* c, hipStream_t s) { return pull(c, s, c->red, sizeof(double) * kRedSlots * c->n); }
+
+// Table entry of instance i with every workspace pointer set; the caller
+// adds the per-call pointers.
+template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
+    std::memset(&I, 0, sizeof(I));
+    const Member& M = c->m[i];
+    I.pr = Params{M.d.C, M.d.H, M.d.W, M.d.reg, M.d.alpha, M.d.eps_tv};
+    I.K = M.d.K;
+    I.nb = M.nb;
+    I.base = M.base;
+    I.nbe = M.nbe;
+    I.base_e = M.base_e;
+    I.N = M.N;
+    for (int k = 0; k < 3; ++k) {
+        I.X[k] = (T*)M.X[k];
+        I.KX[k] = (T*)M.KX[k];
+    }
+    I.G = (T*)M.G;
+    I.th = (T*)M.th_c;
+    I.thf = (T*)M.thf_c;
+    I.pA = M.pA;
+    I.pB = M.pB;
+    I.trace = M.trace;
+    I.q = (T*)M.cq;
+    I.r = (T*)M.cr;
+    I.P[0] = (T*)M.cP[0];
+    I.P[1] = (T*)M.cP[1];
+    I.Kp = (T*)M.cKp;
+    I.Hp = (T*)M.cHp;
+    I.pR = M.pR;
+    I.pK = M.pK;
+    I.red = c->red + (size_t)i * kRedSlots;
+}
+
+}  // namespace
+
+int combine_codes(const int* codes, int n) {
+    for (int i = 0; i < n; ++i)
+        if (codes[i] != MAID_OK) return codes[i];
+    return MAID_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+namespace {
+
+hipEvent_t prof_event(maid_ctx* c) {
+    if (!c->prof_pool.empty()) {
+        hipEvent_t e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    maid_ctx* c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(maid_ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
+        if (!c->prof_on) return;
+        a = prof_event(c);
+        b = prof_event(c);
+        if (a) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!c->prof_on || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        c->prof_pending.push_back({kind, a, b});
+        if (c->prof_pending.size() >= 4096) prof_harvest(c);
+    }
+};
+
+}  // namespace
+
+// Accumulate the durations of recorded launches (waits for the last one).
+void prof_harvest(maid_ctx* c) {
+    if (c->prof_pending.empty()) return;
+    (void)hipEventSynchronize(c->prof_pending.back().b);
+    for (auto& r : c->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            c->prof_launches[r.kind] += 1;
+            c->prof_ms[r.kind] += ms;
+            // kinds without early exits: every launch works
+            if (r.kind != MAID_PROF_APG_GRAD && r.kind != MAID_PROF_APG_TRIAL && r.kind != MAID_PROF_CG_DIR &&
+                r.kind != MAID_PROF_CG_HVP && r.kind != MAID_PROF_CG_UPDATE)
+                c->prof_work[r.kind] += 1;
+        }
+        c->prof_pool.push_back(r.a);
+        c->prof_pool.push_back(r.b);
+    }
+    c->prof_pending.clear();
+}
+
+// Launch expression `expr` (returning hipError_t) timed as `kind`.
+#define LAUNCH(kind, expr)                       \
+    do {                                         \
+        ProfScope ps_(c, (kind), s);             \
+        HIP_TRY(expr);                           \
+    } while (0)
+
+// ------------------------------------------------------------------ graph-captured chunks
+// A chunk of solver passes is captured once into a HIP graph (per pass
+// family, chunk length and launch layout) and replayed; the passes read
+// everything that changes between replays from the instance table and the
+// state arrays, whose addresses are fixed.  With timing on, passes launch
+// directly so that each one is bracketed by its own events.
+namespace {
+
+enum { G_APG = 1, G_CG = 2 };
+
+template <typename F>
+int run_chunk(maid_ctx* c, int kind, int chunk, hipStream_t s, F enqueue) {
+    if (c->prof_on || !c->use_graphs) return enqueue(s);
+    for (auto& g : c->graphs)
+        if (g.kind == kind && g.chunk == chunk && g.gen == c->layout_gen) {
+            HIP_TRY(hipGraphLaunch(g.exec, s));
+            return MAID_OK;
+        }
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    int rc = enqueue(c->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (rc != MAID_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, MAID_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, MAID_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    if (c->graphs.size() >= 48) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({kind, chunk, c->layout_gen, exec});
+    HIP_TRY(hipGraphLaunch(exec, s));
+    return MAID_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ set-up
+int validate_desc(const maid_desc* d, std::string& why) {
+    if (!d) { why = "desc is NULL"; return MAID_EINVAL; }
+    if (d->H < 1 || d->W < 1) { why = "H and W must be >= 1"; return MAID_EINVAL; }
+    if (d->C < 1 || d->C > kMaxC) { why = "C must be 1, 2 or 3"; return MAID_EINVAL; }
+    if (d->K < 1 || d->K > kMaxK || (d->K % 2) == 0) { why = "K must be odd, 1 <= K <= 31"; return MAID_EINVAL; }
+    if (d->K > d->H || d->K > d->W) { why = "K must not exceed H or W"; return MAID_EINVAL; }
+    if (d->dtype != MAID_F32 && d->dtype != MAID_F64) { why = "dtype must be MAID_F32 or MAID_F64"; return MAID_EINVAL; }
+    if (d->reg < 0 || d->reg > 2) { why = "reg must be 0, 1 or 2"; return MAID_EINVAL; }
+    if (!finite(d->alpha) || d->alpha < 0) { why = "alpha must be finite and >= 0"; return MAID_EINVAL; }
+    if (d->reg != MAID_REG_QUADRATIC && !(d->eps_tv > 0 && finite(d->eps_tv))) { why = "eps_tv must be > 0"; return MAID_EINVAL; }
+    if (!finite(d->beta) || d->beta < 0) { why = "beta must be finite and >= 0"; return MAID_EINVAL; }
+    if (!finite(d->h1_w0) || d->h1_w0 < 0) { why = "h1_w0 must be finite and >= 0"; return MAID_EINVAL; }
+    const double n = (double)d->H * d->W * d->C;
+    if (n > 4.0e9) { why = "image too large"; return MAID_EINVAL; }
+    return MAID_OK;
+}
+
+// Group the instances by (K, tile rows), give each instance a block range
+// starting at a multiple of 8 (so that the XCD-major tile order holds within
+// every instance), build the block -> instance maps and upload them.
+int relayout(maid_ctx* c) {
+    c->groups.clear();
+    std::vector<int> host;
+    for (int i = 0; i < c->n; ++i) {
+        Member& M = c->m[i];
+        M.R = c->R_override ? c->R_override : M.R_auto;
+        M.nb = stencil_blocks(M.shape, M.R);
+    }
+    std::vector<char> placed(c->n, 0);
+    for (int i = 0; i < c->n; ++i) {
+        if (placed[i]) continue;
+        LaunchGroup lg;
+        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr};
+        for (int k = i; k < c->n; ++k)
+            if (!placed[k] && c->m[k].d.K == lg.g.K && c->m[k].R == lg.g.R) {
+                placed[k] = 1;
+                lg.members.push_back(k);
+            }
+        int base = 0;
+        for (size_t t = 0; t < lg.members.size(); ++t) {
+            Member& M = c->m[lg.members[t]];
+            M.base = base;
+            lg.g.C = std::max(lg.g.C, M.d.C);
+            lg.g.nw = std::max(lg.g.nw, M.d.reg == MAID_REG_TV_CHANNELWISE ? M.d.C : 1);
+            lg.g.grid = base + M.nb;
+            base = round8(base + M.nb);
+        }
+        c->groups.push_back(lg);
+    }
+    int base_e = 0;
+    for (int i = 0; i < c->n; ++i) {
+        c->m[i].base_e = base_e;
+        c->grid_e = base_e + c->m[i].nbe;
+        base_e = round8(base_e + c->m[i].nbe);
+    }
+    // maps: every group's stencil map, then the elementwise map
+    std::vector<size_t> offs;
+    for (auto& lg : c->groups) {
+        offs.push_back(host.size());
+        host.resize(host.size() + lg.g.grid);
+        int* mp = host.data() + offs.back();
+        for (size_t t = 0; t < lg.members.size(); ++t) {
+            const Member& M = c->m[lg.members[t]];
+            const int end = t + 1 < lg.members.size() ? c->m[lg.members[t + 1]].base : lg.g.grid;
+            for (int b = M.base; b < end; ++b) mp[b] = lg.members[t];
+        }
+    }
+    const size_t off_e = host.size();
+    host.resize(host.size() + c->grid_e);
+    for (int i = 0; i < c->n; ++i) {
+        const int end = i + 1 < c->n ? c->m[i + 1].base_e : c->grid_e;
+        for (int b = c->m[i].base_e; b < end; ++b) host[off_e + b] = i;
+    }
+    if (host.size() > c->maps_cap) return fail(c, MAID_EHIP, "relayout: block maps exceed their allocation");
+    HIP_TRY(hipMemcpy(c->maps, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (size_t g = 0; g < c->groups.size(); ++g) c->groups[g].g.blk = c->maps + offs[g];
+    c->blk_e = c->maps + off_e;
+    c->layout_gen += 1;
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    char buf[96];
+    c->cfg.clear();
+    for (auto& lg : c->groups) {
+        std::snprintf(buf, sizeof(buf), "%sK=%d rows_per_thread=%d tile=64x%d instances=%zu", c->cfg.empty() ? "" : "; ",
+                      lg.g.K, lg.g.R, tile_h(lg.g.R), lg.members.size());
+        c->cfg += buf;
+    }
+    return MAID_OK;
+}
+
+void destroy_ctx(maid_ctx* c) {
+    if (!c) return;
+    prof_harvest(c);
+    for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->st_dev) (void)hipFree(c->st_dev);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->tab_dev) (void)hipFree(c->tab_dev);
+    if (c->tab_host) (void)hipHostFree(c->tab_host);
+    if (c->maps) (void)hipFree(c->maps);
+    delete c;
+}
+
+int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) {
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        int rc = validate_desc(&descs[i], why);
+        if (rc) {
+            if (n > 1) why = "instance " + std::to_string(i) + ": " + why;
+            return rc;
+        }
+        if (descs[i].dtype != descs[0].dtype) {
+            why = "all instances of a batch must share the storage type";
+            return MAID_EINVAL;
+        }
+    }
+    maid_ctx* c = new maid_ctx();
+    c->n = n;
+    c->dtype = descs[0].dtype;
+    c->esz = c->dtype == MAID_F64 ? 8 : 4;
+    c->m.resize(n);
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t total = 0, maps = 0;
+    const size_t kern = 1024 * 8;
+    for (int i = 0; i < n; ++i) {
+        Member& M = c->m[i];
+        std::memset(&M, 0, sizeof(M));
+        M.d = descs[i];
+        M.shape = Shape{M.d.C, M.d.H, M.d.W, M.d.K, M.d.reg};
+        M.N = (int64_t)M.d.C * M.d.H * M.d.W;
+        M.R_auto = auto_rows(M.shape);
+        M.nbe = (int)std::min<int64_t>((M.N + kNT - 1) / kNT, kEwMaxBlocks);
+        const size_t img = al((size_t)M.N * c->esz);
+        const size_t nblk = std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe);
+        const size_t part = al(nblk * sizeof(double));
+        total += 17 * img + 6 * kern + 5 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
+                 al(kTraceCap * sizeof(int));
+        maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe);
+    }
+    c->ws_bytes = total;
+    c->maps_cap = maps;
+    c->st_bytes = al(2 * n * sizeof(ApgState)) + al(3 * n * sizeof(CgState)) + al(n * kRedSlots * sizeof(double));
+    const size_t tab_bytes = (size_t)kRoles * n * sizeof(Inst<double>);
+    hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->st_dev, c->st_bytes);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->st_host, c->st_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->tab_dev, tab_bytes);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->tab_host, tab_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->maps, maps * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(c->ws, 0, c->ws_bytes);
+    if (e == hipSuccess) e = hipMemset(c->st_dev, 0, c->st_bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        why = std::string("allocation failed: ") + hipGetErrorString(e);
+        const int code = e == hipErrorOutOfMemory ? MAID_ENOMEM : MAID_EHIP;
+        destroy_ctx(c);
+        return code;
+    }
+    if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
+    std::memset(c->st_host, 0, c->st_bytes);
+    std::memset(c->tab_host, 0, tab_bytes);
+    {
+        char* p = c->st_dev;
+        c->apg[0] = (ApgState*)p;
+        c->apg[1] = c->apg[0] + n;
+        p += al(2 * n * sizeof(ApgState));
+        c->cg[0] = (CgState*)p;
+        c->cg[1] = c->cg[0] + n;
+        c->cg[2] = c->cg[1] + n;
+        p += al(3 * n * sizeof(CgState));
+        c->red = (double*)p;
+        c->apg_h = (ApgState*)(c->st_host + ((char*)c->apg[0] - c->st_dev));
+        c->cg_h = (CgState*)(c->st_host + ((char*)c->cg[0] - c->st_dev));
+        c->red_h = (double*)(c->st_host + ((char*)c->red - c->st_dev));
+    }
+    char* p = c->ws;
+    auto take = [&](size_t b) { char* r = p; p += b; return (void*)r; };
+    for (int i = 0; i < n; ++i) {
+        Member& M = c->m[i];
+        const size_t img = al((size_t)M.N * c->esz);
+        const size_t nblk = std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe);
+        const size_t part = al(nblk * sizeof(double));
+        for (int k = 0; k < 3; ++k) M.X[k] = take(img);
+        for (int k = 0; k < 3; ++k) M.KX[k] = take(img);
+        M.G = take(img);
+        M.cq = take(img);
+        M.cr = take(img);
+        M.cP[0] = take(img);
+        M.cP[1] = take(img);
+        M.cKp = take(img);
+        M.cHp = take(img);
+        M.tmp0 = take(img);
+        M.tmp1 = take(img);
+        M.xtrial = take(img);
+        M.gradg = take(img);
+        M.th_c = take(kern);
+        M.thf_c = take(kern);
+        M.a_c = take(kern);
+        M.af_c = take(kern);
+        M.th_trial = (double*)take(kern);
+        M.zbuf = (double*)take(kern);
+        M.pA = (double*)take(part);
+        M.pB = (double*)take(part);
+        M.pR = (double*)take(part);
+        M.pK = (double*)take(part);
+        M.pC = (double*)take(part);
+        M.hg_part = (double*)take(al((size_t)kHgMaxBlocks * 1024 * sizeof(double)));
+        M.trace = (int*)take(al(kTraceCap * sizeof(int)));
+    }
+    int rc = relayout(c);
+    if (rc) {
+        why = c->err;
+        destroy_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return MAID_OK;
+}
+
+// ------------------------------------------------------------------ lower level (Algorithm 1, FISTA)
+template <typename T>
+int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                const std::vector<const T*>& y, const std::vector<T*>& x, const std::vector<double>& tol, int max_iter,
+                double* L_inout, maid_solve_info* info, int* codes, int32_t* trace_bt, hipStream_t s) {
+    const int n = c->n;
+    Inst<T>* tab = tab_host<T>(c, ROLE_APG);
+    const Inst<T>* tabd = tab_dev<T>(c, ROLE_APG);
+    for (int i = 0; i < n; ++i) {
+        ApgState& h = c->apg_h[i];
+        std::memset(&h, 0, sizeof(h));
+        h.status = ST_OK;
+        fill_base(c, i, tab[i]);
+        if (!act[i]) {
+            h.done = 1;
+            continue;
+        }
+        h.L = L_inout[i];
+        h.t = 1.0;
+        h.t_prev = 1.0;
+        h.tol = tol[i];
+        h.max_iter = max_iter;
+        h.phase = PH_START;
+        h.cur = 0;
+        h.prev = 1;
+        h.nxt = 2;
+        h.trace_cap = kTraceCap;
+        Inst<T>& I = tab[i];
+        I.y = y[i];
+        I.xout = x[i];
+        I.theta64 = theta[i];
+        I.cv_ker = I.thf;
+        I.cv_in = I.X[0];
+        I.cv_out = I.KX[0];
+    }
+    TRY(push(c, s, c->apg[0], n * sizeof(ApgState)));
+    TRY(upload<T>(c, ROLE_APG, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, c->apg[0], -1, s));
+    for (int i = 0; i < n; ++i)
+        if (act[i]) {
+            const size_t bytes = (size_t)c->m[i].N * sizeof(T);
+            HIP_TRY(hipMemcpyAsync(c->m[i].X[0], x[i], bytes, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(c->m[i].X[1], x[i], bytes, hipMemcpyDeviceToDevice, s));
+        }
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, tabd, s));
+    for (int i = 0; i < n; ++i)
+        if (act[i])
+            HIP_TRY(hipMemcpyAsync(c->m[i].KX[1], c->m[i].KX[0], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    // each slot is one gradient pass and one trial pass; a slot advances every
+    // unfinished solve by one iteration or by one backtracking step
+    const long slot_cap = (long)max_iter + 256 + 1;
+    long slots = 0;
+    int chunk = 1;
+    for (;;) {
+        int rc = run_chunk(c, G_APG, chunk, s, [&](hipStream_t s) {
+            for (int k = 0; k < chunk; ++k) {
+                for (auto& lg : c->groups)
+                    LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(lg.g, tabd, c->apg[0], c->apg[1], s));
+                for (auto& lg : c->groups)
+                    LAUNCH(MAID_PROF_APG_TRIAL, Ops<T>::apg_trial(lg.g, tabd, c->apg[1], c->apg[0], s));
+            }
+            return (int)MAID_OK;
+        });
+        if (rc) return rc;
+        slots += chunk;
+        TRY(pull(c, s, c->apg[0], n * sizeof(ApgState)));
+        bool done = true;
+        for (int i = 0; i < n; ++i) done = done && c->apg_h[i].done;
+        if (done) break;
+        if (slots > slot_cap) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
+        chunk = std::min(chunk * 2, 16);
+    }
+    if (c->prof_on) {
+        // passes that did work: a gradient at the start and after every
+        // accepted step, a trial for every accepted or rejected step (the
+        // busiest instance of the batch)
+        int64_t wg = 0, wt = 0;
+        for (int i = 0; i < n; ++i)
+            if (act[i]) {
+                wg = std::max<int64_t>(wg, c->apg_h[i].iters + 1);
+                wt = std::max<int64_t>(wt, c->apg_h[i].iters + c->apg_h[i].bt);
+            }
+        c->prof_work[MAID_PROF_APG_GRAD] += wg;
+        c->prof_work[MAID_PROF_APG_TRIAL] += wt;
+    }
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, tabd, c->apg[0], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+        codes[i] = MAID_OK;
+        if (!act[i]) continue;
+        const ApgState& h = c->apg_h[i];
+        codes[i] = status_code(h.status);
+        if (codes[i] >= 0) L_inout[i] = h.L;
+        if (info) {
+            info[i].iters = h.iters;
+            info[i].backtracks = h.bt;
+            info[i].status = codes[i];
+            info[i].res_norm = std::sqrt(h.gn2);
+            info[i].obj = 0.0;
+            info[i].L = h.L;
+        }
+    }
+    if (trace_bt && n == 1 && c->apg_h[0].iters > 0) {
+        const int cnt = std::min(c->apg_h[0].iters, kTraceCap);
+        HIP_TRY(hipMemcpy(trace_bt, c->m[0].trace, cnt * sizeof(int), hipMemcpyDeviceToHost));
+    }
+    return MAID_OK;
+}
+
+// ------------------------------------------------------------------ adjoint (Algorithm 1, CG)
+template <typename T>
+int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                  const std::vector<const T*>& xt, const std::vector<const T*>& rhs, const std::vector<T*>& q,
+                  const std::vector<double>& tol, int max_iter, maid_solve_info* info, int* codes, hipStream_t s) {
+    const int n = c->n;
+    Inst<T>* tab = tab_host<T>(c, ROLE_CG);
+    const Inst<T>* tabd = tab_dev<T>(c, ROLE_CG);
+    for (int i = 0; i < n; ++i) {
+        CgState& h = c->cg_h[i];
+        std::memset(&h, 0, sizeof(h));
+        h.status = ST_OK;
+        fill_base(c, i, tab[i]);
+        if (!act[i]) {
+            h.done = 1;
+            continue;
+        }
+        h.tol = tol[i];
+        h.max = max_iter;
+        h.first = 1;
+        tab[i].xt = xt[i];
+        tab[i].b = rhs[i];
+        tab[i].theta64 = theta[i];
+    }
+    TRY(push(c, s, c->cg[0], n * sizeof(CgState)));
+    TRY(upload<T>(c, ROLE_CG, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, nullptr, -1, s));
+    for (int i = 0; i < n; ++i)
+        if (act[i]) {
+            const size_t bytes = (size_t)c->m[i].N * sizeof(T);
+            HIP_TRY(hipMemcpyAsync(c->m[i].cq, q[i], bytes, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(c->m[i].cr, q[i], bytes, hipMemcpyDeviceToDevice, s));
+        }
+    // r = rhs - H q0 (the direction pass in set-up mode copies q0 into p)
+    CgState** S = c->cg;
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->grid_e, c->blk_e, tabd, S[0], s));
+    int chunk = 1;
+    long slots = 0;
+    for (;;) {
+        int rc = run_chunk(c, G_CG, chunk, s, [&](hipStream_t s) {
+            for (int k = 0; k < chunk; ++k) {
+                for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
+                for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
+                LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(c->grid_e, c->blk_e, tabd, S[2], S[0], s));
+            }
+            return (int)MAID_OK;
+        });
+        if (rc) return rc;
+        slots += chunk;
+        TRY(pull(c, s, c->cg[0], n * sizeof(CgState)));
+        bool done = true;
+        for (int i = 0; i < n; ++i) done = done && c->cg_h[i].done;
+        if (done) break;
+        if (slots > (long)max_iter + 2) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
+        chunk = std::min(chunk * 2, 16);
+    }
+    if (c->prof_on) {
+        // the set-up direction and Hessian passes, then one of each per iteration
+        int64_t w = 0;
+        for (int i = 0; i < n; ++i)
+            if (act[i]) w = std::max<int64_t>(w, c->cg_h[i].iters);
+        c->prof_work[MAID_PROF_CG_DIR] += w + 1;
+        c->prof_work[MAID_PROF_CG_HVP] += w + 1;
+        c->prof_work[MAID_PROF_CG_UPDATE] += w;
+    }
+    for (int i = 0; i < n; ++i) {
+        codes[i] = MAID_OK;
+        if (!act[i]) continue;
+        const CgState& h = c->cg_h[i];
+        codes[i] = status_code(h.status);
+        if (codes[i] >= 0)
+            HIP_TRY(hipMemcpyAsync(q[i], c->m[i].cq, (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
+        if (info) {
+            info[i].iters = h.iters;
+            info[i].backtracks = 0;
+            info[i].status = codes[i];
+            info[i].res_norm = std::sqrt(h.gamma);
+            info[i].obj = 0.0;
+            info[i].L = 0.0;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAID_OK;
+}
+
+// ------------------------------------------------------------------ upper level at x
+// rho = a*x - y, g = 1/2 ||rho||^2, grad = a . rho, ||grad||.
+template <typename T>
+int upper_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& a,
+                const std::vector<const T*>& y, const std::vector<const T*>& x, const std::vector<T*>& grad,
+                double* g_out, double* gn_out, hipStream_t s) {
+    const int n = c->n;
+    Inst<T>* t0 = tab_host<T>(c, ROLE_CV0);
+    Inst<T>* t1 = tab_host<T>(c, ROLE_CV1);
+    for (int i = 0; i < n; ++i) {
+        fill_base(c, i, t0[i]);
+        fill_base(c, i, t1[i]);
+        if (!act[i]) continue;
+        const Member& M = c->m[i];
+        t0[i].th = (T*)M.a_c;
+        t0[i].thf = (T*)M.af_c;
+        t0[i].theta64 = a[i];
+        t0[i].cv_ker = (T*)M.af_c;
+        t0[i].cv_in = x[i];
+        t0[i].cv_sub = y[i];
+        t0[i].cv_out = (T*)M.tmp0;
+        t0[i].cv_part = M.pC;
+        t1[i].cv_ker = (T*)M.a_c;
+        t1[i].cv_in = (T*)M.tmp0;
+        t1[i].cv_out = grad[i] ? grad[i] : (T*)M.gradg;
+        t1[i].cv_part = M.pC;
+    }
+    TRY(upload<T>(c, ROLE_CV0, s));
+    TRY(upload<T>(c, ROLE_CV1, s));
+    const Inst<T>* d0 = tab_dev<T>(c, ROLE_CV0);
+    const Inst<T>* d1 = tab_dev<T>(c, ROLE_CV1);
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, -1, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d0, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::reduce(d0, n, kRedG, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::reduce(d1, n, kRedGrad, s));
+    TRY(pull_red(c, s));
+    for (int i = 0; i < n; ++i)
+        if (act[i]) {
+            if (g_out) g_out[i] = 0.5 * c->red_h[i * kRedSlots + kRedG];
+            if (gn_out) gn_out[i] = std::sqrt(c->red_h[i * kRedSlots + kRedGrad]);
+        }
+    return MAID_OK;
+}
+
+// ------------------------------------------------------------------ hypergradient (Eq. 3.2)
+template <typename T>
+int hypergrad_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                    const std::vector<const double*>& a, const std::vector<const T*>& y, const std::vector<const T*>& xt,
+                    const std::vector<const T*>& q, int with_r, const std::vector<double*>& z, double* znorm_out,
+                    hipStream_t s) {
+    const int n = c->n;
+    Inst<T>* t2 = tab_host<T>(c, ROLE_CV2);
+    Inst<T>* t3 = tab_host<T>(c, ROLE_CV3);
+    for (int i = 0; i < n; ++i) {
+        fill_base(c, i, t2[i]);
+        fill_base(c, i, t3[i]);
+        if (!act[i]) continue;
+        const Member& M = c->m[i];
+        t2[i].theta64 = theta[i];
+        t2[i].cv_ker = (T*)M.thf_c;
+        t2[i].cv_in = xt[i];
+        t2[i].cv_sub = y[i];
+        t2[i].cv_out = (T*)M.tmp0;
+        t3[i].cv_ker = (T*)M.thf_c;
+        t3[i].cv_in = q[i];
+        t3[i].cv_out = (T*)M.tmp1;
+    }
+    TRY(upload<T>(c, ROLE_CV2, s));
+    TRY(upload<T>(c, ROLE_CV3, s));
+    const Inst<T>* d2 = tab_dev<T>(c, ROLE_CV2);
+    const Inst<T>* d3 = tab_dev<T>(c, ROLE_CV3);
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d2, n, nullptr, -1, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d2, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d3, s));
+    for (int i = 0; i < n; ++i) {
+        if (!act[i]) continue;
+        const Member& M = c->m[i];
+        const int nblk = std::min(kHgMaxBlocks, hg_items(M.shape));
+        const int wr = with_r && M.d.beta != 0.0;
+        LAUNCH(MAID_PROF_HG_CORR, Ops<T>::hg_corr(M.shape, (const T*)M.tmp0, q[i], (const T*)M.tmp1, xt[i], M.hg_part,
+                                                  nblk, s));
+        LAUNCH(MAID_PROF_OTHER, launch_hg_final(M.shape, M.d.beta, M.d.h1_w0, M.hg_part, nblk, theta[i],
+                                                wr ? a[i] : nullptr, wr, z[i], c->red + (size_t)i * kRedSlots + kRedZ, s));
+    }
+    TRY(pull_red(c, s));
+    for (int i = 0; i < n; ++i)
+        if (act[i] && znorm_out) znorm_out[i] = std::sqrt(c->red_h[i * kRedSlots + kRedZ]);
+    return MAID_OK;
+}
+
+int sobolev_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                  const std::vector<const double*>& a, double* r_out, hipStream_t s) {
+    bool any_work = false;
+    for (int i = 0; i < c->n; ++i) {
+        if (!act[i]) continue;
+        const Member& M = c->m[i];
+        if (M.d.beta == 0.0) {
+            r_out[i] = 0.0;
+            continue;
+        }
+        LAUNCH(MAID_PROF_OTHER, launch_sobolev(M.d.beta, M.d.h1_w0, theta[i], a[i], M.d.K,
+                                               c->red + (size_t)i * kRedSlots + kRedSob, s));
+        any_work = true;
+    }
+    if (!any_work) return MAID_OK;
+    TRY(pull_red(c, s));
+    for (int i = 0; i < c->n; ++i)
+        if (act[i] && c->m[i].d.beta != 0.0) r_out[i] = c->red_h[i * kRedSlots + kRedSob];
+    return MAID_OK;
+}
+
+template <typename T>
+int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, int adjoint, hipStream_t s) {
+    Inst<T>* t = tab_host<T>(c, ROLE_CV0);
+    fill_base(c, 0, t[0]);
+    t[0].theta64 = theta;
+    t[0].cv_ker = adjoint ? t[0].th : t[0].thf;
+    t[0].cv_in = in;
+    t[0].cv_out = out;
+    TRY(upload<T>(c, ROLE_CV0, s));
+    const Inst<T>* d = tab_dev<T>(c, ROLE_CV0);
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d, 1, nullptr, -1, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAID_OK;
+}
+
+// ------------------------------------------------------------------ MAID (Algorithm 2)
+// One outer iteration per instance, in lockstep: every round computes
+// InexactGradient for the instances that need one (one batched lower solve,
+// upper-level pass, CG solve and hypergradient), then runs the psi trials of
+// Eq. (3.4) as batched lower solves over the instances still testing step
+// sizes; an instance whose j trials all fail shrinks its accuracies and
+// joins the next round.  Each instance takes exactly the decisions, and
+// performs exactly the solves, it would take on its own.
+template <typename T>
+int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
+               const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s) {
+    const int n = c->n;
+    std::vector<maid_step_info> I(n);
+    std::memset(I.data(), 0, n * sizeof(maid_step_info));
+    std::vector<double> Lg(n, hp->L_g);
+    if (!(hp->L_g > 0)) {
+        Inst<T>* t0 = tab_host<T>(c, ROLE_CV0);
+        for (int i = 0; i < n; ++i) {
+            fill_base(c, i, t0[i]);
+            t0[i].th = (T*)c->m[i].a_c;
+            t0[i].thf = (T*)c->m[i].af_c;
+            t0[i].theta64 = a[i];
+        }
+        TRY(upload<T>(c, ROLE_CV0, s));
+        LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tab_dev<T>(c, ROLE_CV0), n, nullptr, kRedAbs, s));
+        TRY(pull_red(c, s));
+        for (int i = 0; i < n; ++i) Lg[i] = c->red_h[i * kRedSlots + kRedAbs] * c->red_h[i * kRedSlots + kRedAbs];
+    }
+    std::vector<const double*> theta(n), th2c(n);
+    std::vector<double*> th2(n), z(n);
+    std::vector<T*> x(n), q(n), xs(n), grad(n), none(n, nullptr);
+    std::vector<const T*> xc(n), qc(n), xsc(n), gradc(n);
+    for (int i = 0; i < n; ++i) {
+        theta[i] = (const double*)st[i].theta;
+        x[i] = (T*)st[i].x;
+        q[i] = (T*)st[i].q;
+        xc[i] = x[i];
+        qc[i] = q[i];
+        xs[i] = (T*)c->m[i].xtrial;
+        xsc[i] = xs[i];
+        grad[i] = (T*)c->m[i].gradg;
+        gradc[i] = grad[i];
+        th2[i] = c->m[i].th_trial;
+        th2c[i] = th2[i];
+        z[i] = c->m[i].zbuf;
+        codes[i] = MAID_OK;
+    }
+    std::vector<int> j(n, hp->max_bt), rc(n);
+    std::vector<char> need(n, 1);
+    std::vector<double> tol(n), dtol(n), L(n), g_k(n), n_k(n), r_k(n), ell_k(n), znorm(n), g_n(n), n_n(n), r_n(n);
+    std::vector<maid_solve_info> li(n), ci(n);
+    while (any(need)) {
+        // InexactGradient(theta_k, eps_k, delta_k)
+        for (int i = 0; i < n; ++i) {
+            tol[i] = st[i].eps * hp->mu;
+            dtol[i] = st[i].delta;
+            L[i] = st[i].L;
+        }
+        TRY(lower_batch<T>(c, need, theta, y, x, tol, hp->max_lower_iter, L.data(), li.data(), rc.data(), nullptr, s));
+        for (int i = 0; i < n; ++i) {
+            if (!need[i]) continue;
+            if (rc[i] < 0) {
+                codes[i] = rc[i];
+                need[i] = 0;
+                continue;
+            }
+            st[i].L = L[i];
+            I[i].lower_iters += li[i].iters;
+        }
+        TRY(upper_batch<T>(c, need, a, y, xc, grad, g_k.data(), n_k.data(), s));
+        TRY(sobolev_batch(c, need, theta, a, r_k.data(), s));
+        TRY(adjoint_batch<T>(c, need, theta, xc, gradc, q, dtol, hp->max_cg_iter, ci.data(), rc.data(), s));
+        for (int i = 0; i < n; ++i) {
+            if (!need[i]) continue;
+            I[i].cg_iters += ci[i].iters;
+            if (rc[i] < 0) {
+                codes[i] = rc[i];
+                need[i] = 0;
+            }
+        }
+        TRY(hypergrad_batch<T>(c, need, theta, a, y, xc, qc, 1, z, znorm.data(), s));
+        for (int i = 0; i < n; ++i)
+            if (need[i]) {
+                ell_k[i] = g_k[i] + r_k[i];
+                I[i].ell_k = ell_k[i];
+                I[i].znorm = znorm[i];
+            }
+        // the psi trials
+        std::vector<char> tr = need;
+        std::vector<int> cnt(n, 0);
+        while (any(tr)) {
+            for (int i = 0; i < n; ++i) {
+                if (!tr[i]) continue;
+                const int KK = c->m[i].d.K * c->m[i].d.K;
+                LAUNCH(MAID_PROF_OTHER, launch_theta_step(theta[i], z[i], st[i].step, th2[i], KK, s));
+                HIP_TRY(hipMemcpyAsync(xs[i], x[i], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                L[i] = st[i].L;
+            }
+            TRY(lower_batch<T>(c, tr, th2c, y, xs, tol, hp->max_lower_iter, L.data(), li.data(), rc.data(), nullptr, s));
+            for (int i = 0; i < n; ++i) {
+                if (!tr[i]) continue;
+                if (rc[i] < 0) {
+                    codes[i] = rc[i];
+                    tr[i] = 0;
+                    need[i] = 0;
+                    continue;
+                }
+                st[i].L = L[i];
+                I[i].lower_iters += li[i].iters;
+            }
+            TRY(upper_batch<T>(c, tr, a, y, xsc, none, g_n.data(), n_n.data(), s));
+            TRY(sobolev_batch(c, tr, th2c, a, r_n.data(), s));
+            bool copied = false;
+            for (int i = 0; i < n; ++i) {
+                if (!tr[i]) continue;
+                const double ell_n = g_n[i] + r_n[i];
+                const double e = st[i].eps;
+                const double psi = ell_n + n_n[i] * e + 0.5 * Lg[i] * e * e - ell_k[i] + n_k[i] * e +
+                                   hp->lambda * st[i].step * znorm[i] * znorm[i];
+                I[i].trials += 1;
+                I[i].psi = psi;
+                I[i].ell_next = ell_n;
+                if (psi <= 0.0) {
+                    const int KK = c->m[i].d.K * c->m[i].d.K;
+                    HIP_TRY(hipMemcpyAsync(st[i].theta, th2[i], KK * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    HIP_TRY(hipMemcpyAsync(x[i], xs[i], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
+                    copied = true;
+                    st[i].eps *= hp->nu_hi;
+                    st[i].delta *= hp->nu_hi;
+                    st[i].step *= hp->rho_hi;
+                    st[i].k += 1;
+                    I[i].accepted = 1;
+                    tr[i] = 0;
+                    need[i] = 0;
+                    continue;
+                }
+                st[i].step *= hp->rho_lo;
+                if (++cnt[i] >= j[i]) tr[i] = 0;
+            }
+            if (copied) HIP_TRY(hipStreamSynchronize(s));
+        }
+        for (int i = 0; i < n; ++i) {
+            if (!need[i]) continue;
+            st[i].eps *= hp->nu_lo;
+            st[i].delta *= hp->nu_lo;
+            j[i] += 1;
+            I[i].retries += 1;
+            if (st[i].eps < hp->eps_min) {
+                codes[i] = MAID_ACCURACY_FLOOR;
+                need[i] = 0;
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        I[i].status = codes[i];
+        if (out) out[i] = I[i];
+    }
+    return MAID_OK;
+}
+
+#define MAID_ENGINE_INSTANTIATE(T)                                                                                       \
+    template int lower_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,                 \
+                                const std::vector<const T*>&, const std::vector<T*>&, const std::vector<double>&, int,  \
+                                double*, maid_solve_info*, int*, int32_t*, hipStream_t);                                 \
+    template int adjoint_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,               \
+                                  const std::vector<const T*>&, const std::vector<const T*>&, const std::vector<T*>&,   \
+                                  const std::vector<double>&, int, maid_solve_info*, int*, hipStream_t);                 \
+    template int upper_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,                 \
+                                const std::vector<const T*>&, const std::vector<const T*>&, const std::vector<T*>&,     \
+                                double*, double*, hipStream_t);                                                          \
+    template int hypergrad_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,             \
+                                    const std::vector<const double*>&, const std::vector<const T*>&,                    \
+                                    const std::vector<const T*>&, const std::vector<const T*>&, int,                    \
+                                    const std::vector<double*>&, double*, hipStream_t);                                  \
+    template int apply_operator_one<T>(maid_ctx*, const double*, const T*, T*, int, hipStream_t);                       \
+    template int step_batch<T>(maid_ctx*, const std::vector<const double*>&, const std::vector<const T*>&, maid_state*, \
+                               const maid_hparams*, maid_step_info*, int*, hipStream_t);
+
+MAID_ENGINE_INSTANTIATE(float)
+MAID_ENGINE_INSTANTIATE(double)
+
+}  // namespace maid

@@ -1,0 +1,164 @@
+// engine.h -- the host side of libmaid: a context over one or more problem
+// instances (a ragged batch), its device workspace, solver states and
+// instance tables, and the drivers of the solver passes.
+//
+// The host only enqueues kernels and polls: every arithmetic step runs on
+// the GPU, and every solver decision (stop tests, backtracking, CG
+// coefficients) is taken on the GPU by the pass that consumes the
+// reduction, per instance, in the device-resident state arrays.  Solver
+// passes are replayed in chunks from captured HIP graphs; the host copies
+// the small state arrays back once per chunk to learn whether every solve
+// has finished.  MAID's outer loop (Algorithm 2) runs on the host over
+// scalars the kernels computed in FP64, in lockstep over the instances.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "devctx.h"
+#include "maid.h"
+#include "ops.h"
+
+namespace maid {
+
+constexpr int kRedSlots = 8;   // per-instance reduction results
+constexpr int kRedG = 0, kRedGrad = 1, kRedZ = 2, kRedSob = 3, kRedAbs = 4;
+constexpr int kTraceCap = 1 << 16;
+constexpr int kHgMaxBlocks = 512;
+constexpr int kEwMaxBlocks = 2048;
+
+// Each pass family reads its own device copy of the instance table, so a
+// captured graph (which embeds the table address) always sees the entries
+// written for its family, and a later call can rewrite another family's
+// entries while an earlier one is still queued.
+enum Role { ROLE_APG = 0, ROLE_CG = 1, ROLE_CV0 = 2, ROLE_CV1 = 3, ROLE_CV2 = 4, ROLE_CV3 = 5, kRoles = 6 };
+
+struct Member {
+    maid_desc d;
+    Shape shape;
+    int64_t N;
+    int R_auto;
+    int nbe;                    // elementwise blocks
+    // current layout (depends on the tile rows)
+    int R, nb, base, base_e;
+    // device workspace, carved from the context's allocation
+    void* X[3];
+    void* KX[3];
+    void* G;
+    void* cq;
+    void* cr;
+    void* cP[2];
+    void* cKp;
+    void* cHp;
+    void* tmp0;
+    void* tmp1;
+    void* xtrial;
+    void* gradg;
+    void* th_c;
+    void* thf_c;
+    void* a_c;
+    void* af_c;
+    double* th_trial;
+    double* zbuf;
+    double* pA;
+    double* pB;
+    double* pR;
+    double* pK;
+    double* pC;
+    double* hg_part;
+    int* trace;
+};
+
+struct LaunchGroup {
+    Group g;
+    std::vector<int> members;
+};
+
+}  // namespace maid
+
+struct maid_ctx {
+    int n = 0;
+    int dtype = 0;
+    size_t esz = 0;
+    std::vector<maid::Member> m;
+    int R_override = 0;
+    // layout: stencil groups and the elementwise map (device maps in `maps`)
+    std::vector<maid::LaunchGroup> groups;
+    int grid_e = 0;
+    const int* blk_e = nullptr;
+    int* maps = nullptr;
+    size_t maps_cap = 0;
+    int layout_gen = 0;
+    // device-resident solver states (+ pinned host mirror of the same layout)
+    char* st_dev = nullptr;
+    char* st_host = nullptr;
+    size_t st_bytes = 0;
+    maid::ApgState* apg[2] = {};      // device arrays of n
+    maid::CgState* cg[3] = {};
+    double* red = nullptr;            // n x kRedSlots
+    maid::ApgState* apg_h = nullptr;  // host mirror of apg[0]
+    maid::CgState* cg_h = nullptr;    // host mirror of cg[0]
+    double* red_h = nullptr;
+    // instance tables: kRoles x n entries, device and pinned host
+    char* tab_dev = nullptr;
+    char* tab_host = nullptr;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;        // private stream for graph capture
+    bool use_graphs = true;
+    struct Graph { int kind; int chunk; int gen; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
+    std::string err;
+    std::string cfg;
+    // per-launch timing with HIP events on the launch stream
+    bool prof_on = false;
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    int64_t prof_launches[MAID_PROF_KINDS] = {};
+    int64_t prof_work[MAID_PROF_KINDS] = {};
+    double prof_ms[MAID_PROF_KINDS] = {};
+};
+
+namespace maid {
+
+int fail(maid_ctx* c, int code, const std::string& msg);
+int validate_desc(const maid_desc* d, std::string& why);
+int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why);
+void destroy_ctx(maid_ctx* c);
+int relayout(maid_ctx* c);
+void prof_harvest(maid_ctx* c);
+
+// Per-instance results go to codes[i] (MAID_OK for inactive instances); the
+// return value is MAID_OK or a negative error of the call as a whole.
+template <typename T>
+int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                const std::vector<const T*>& y, const std::vector<T*>& x, const std::vector<double>& tol, int max_iter,
+                double* L_inout, maid_solve_info* info, int* codes, int32_t* trace_bt, hipStream_t s);
+template <typename T>
+int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                  const std::vector<const T*>& xt, const std::vector<const T*>& rhs, const std::vector<T*>& q,
+                  const std::vector<double>& tol, int max_iter, maid_solve_info* info, int* codes, hipStream_t s);
+template <typename T>
+int upper_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& a,
+                const std::vector<const T*>& y, const std::vector<const T*>& x, const std::vector<T*>& grad,
+                double* g_out, double* gn_out, hipStream_t s);
+template <typename T>
+int hypergrad_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                    const std::vector<const double*>& a, const std::vector<const T*>& y, const std::vector<const T*>& xt,
+                    const std::vector<const T*>& q, int with_r, const std::vector<double*>& z, double* znorm_out,
+                    hipStream_t s);
+int sobolev_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                  const std::vector<const double*>& a, double* r_out, hipStream_t s);
+template <typename T>
+int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, int adjoint, hipStream_t s);
+template <typename T>
+int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
+               const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s);
+
+// MAID_OK if every code is MAID_OK, else the first code that is not.
+int combine_codes(const int* codes, int n);
+
+}  // namespace maid

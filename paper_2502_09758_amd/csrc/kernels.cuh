@@ -17,8 +17,13 @@
 // same order, so all blocks hold the bitwise-same value and take the same
 // solver decision (stop tests, backtracking, CG coefficients) without a
 // host round trip and without atomics or fences: the kernel boundary orders
-// the partials before they are read.  Solver state is double-buffered in
-// DevCtx (each pass reads one copy and its block 0 writes the other).
+// the partials before they are read.
+//
+// Every pass serves a batch: block b belongs to instance blk[b] of the
+// instance table (a plain solve is a batch of one); the instance's blocks
+// start at a multiple of 8 so that the XCD-major tile order holds within
+// each instance.  Solver states are arrays over instances, read through one
+// copy and written by the instance's block 0 into the next.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -61,10 +66,11 @@ __device__ __forceinline__ double block_sum(double v) {
     return ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
 
-// Producer side of a grid-wide sum: one partial per block, plain store.
-__device__ __forceinline__ void block_partial(double v, double* part) {
+// Producer side of a grid-wide sum: one partial per block (index lb within
+// its instance), plain store.
+__device__ __forceinline__ void block_partial(double v, double* part, int lb) {
     const double s = block_sum(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[lb] = s;
 }
 
 // Consumer side, at the start of the next kernel: every block sums the nb
@@ -192,21 +198,40 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
     return Wt[r * WP + cc - 1] * dh_left - w0 * dh_here + Wt[(r - 1) * WP + cc] * dv_up - w0 * dv_here;
 }
 
+// ------------------------------------------------------------------ instance lookup
+// Block -> (instance, local block).  Padding blocks (lb >= nb) return at once.
+#define MAID_STENCIL_PROLOGUE                                         \
+    const int ii = blk[blockIdx.x];                                   \
+    const Inst<T>& I = insts[ii];                                     \
+    const int lb = (int)blockIdx.x - I.base;                          \
+    if (lb >= I.nb) return;
+
+#define MAID_EW_PROLOGUE                                              \
+    const int ii = blk[blockIdx.x];                                   \
+    const Inst<T>& I = insts[ii];                                     \
+    const int lb = (int)blockIdx.x - I.base_e;                        \
+    if (lb >= I.nbe) return;
+
 // ------------------------------------------------------------------ generic convolution pass
-// out = ker (x) in  [- sub]   (correlation with ker; pass the flipped kernel
-// for the true convolution); with part != nullptr, per-block partials of
-// sum out^2 (finished by k_reduce).
+// cv_out = cv_ker (x) cv_in  [- cv_sub]   (correlation with cv_ker; the
+// flipped kernel gives the true convolution); with cv_part, per-block
+// partials of sum cv_out^2.  Instances without cv_out take no part.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_conv(int C, int H, int W, const T* __restrict__ ker, const T* __restrict__ in,
-                                              const T* __restrict__ sub, T* __restrict__ out, double* __restrict__ part) {
+__global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts, const int* __restrict__ blk) {
+    MAID_STENCIL_PROLOGUE
+    if (!I.cv_out) return;
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
+    const int C = I.pr.C, H = I.pr.H, W = I.pr.W;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int ntx = (W + kTW - 1) / kTW;
+    const int tile = xcd_tile(lb, I.nb);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
+    const T* __restrict__ in = I.cv_in;
+    const T* __restrict__ sub = I.cv_sub;
+    T* __restrict__ out = I.cv_out;
     double sq = 0.0;
     for (int ch = 0; ch < C; ++ch) {
         const T* src = in + ch * HW;
@@ -216,7 +241,7 @@ __global__ __launch_bounds__(kNT) void k_conv(int C, int H, int W, const T* __re
         T acc[R];
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s, CP, ker, li0, tx, acc);
+        correlate<T, K, R>(s, CP, I.cv_ker, li0, tx, acc);
         const int gj = tj0 + tx;
 #pragma unroll
         for (int o = 0; o < R; ++o) {
@@ -230,37 +255,38 @@ __global__ __launch_bounds__(kNT) void k_conv(int C, int H, int W, const T* __re
             }
         }
     }
-    if (part) block_partial(sq, part);
+    if (I.cv_part) block_partial(sq, I.cv_part, lb);
 }
 
 // ------------------------------------------------------------------ lower level: FISTA
-// Gradient pass.  Reads apg[0], block 0 writes apg[1].  If the previous
-// trial pass ran, first finish its decrease h(x+) - h(v) from the partials
-// and take the backtracking decision: accept (rotate buffers, advance the
-// momentum sequence, then evaluate the new gradient) or reject (double L,
-// no gradient work).  The gradient at v = x + m (x - x_prev), with
-// theta*v = Kx + m (Kx - Kx_prev) by linearity, is
+// Gradient pass.  Per instance: reads sin, block 0 writes sout.  If the
+// previous trial pass ran, first finish its decrease h(x+) - h(v) from the
+// partials and take the backtracking decision: accept (rotate buffers,
+// advance the momentum sequence, then evaluate the new gradient) or reject
+// (double L, no gradient work).  The gradient at v = x + m (x - x_prev),
+// with theta*v = Kx + m (Kx - Kx_prev) by linearity, is
 //   G = theta . (theta*v - y) + alpha grad R(v),
 // and its per-block partials of ||G||^2 go to pA.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_grad(const Params pr, const ApgState* __restrict__ sin, ApgState* __restrict__ sout,
-                                                  ApgBufs<T> b) {
-    ApgState st = *sin;
-    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+__global__ __launch_bounds__(kNT) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                  const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
+    MAID_STENCIL_PROLOGUE
+    ApgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
     if (st.done) {
-        if (writer) put_state(sout, st);
+        if (writer) put_state(&sout[ii], st);
         return;
     }
     bool compute = true;
     if (st.phase == PH_TRIALED) {
-        const double delta = reduce_partials(b.pB, b.nbB) + 0.0;
+        const double delta = reduce_partials(I.pB, I.nb);
         st.delta_last = delta;
         if (!finite_d(delta)) {
             st.done = 1;
             st.status = ST_NONFINITE;
             compute = false;
         } else if (delta <= -st.gn2 / (2.0 * st.L)) {
-            if (writer && b.trace && st.iters < st.trace_cap) b.trace[st.iters] = st.nb_iter;
+            if (writer && I.trace && st.iters < st.trace_cap) I.trace[st.iters] = st.nb_iter;
             st.iters += 1;
             const int p = st.prev;
             st.prev = st.cur;
@@ -286,27 +312,27 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(const Params pr, const ApgStat
     } else {
         st.phase = PH_GRAD_READY;
     }
-    if (writer) put_state(sout, st);
+    if (writer) put_state(&sout[ii], st);
     if (!compute) return;
 
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = pr.C, H = pr.H, W = pr.W, reg = pr.reg;
+    const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int ntx = (W + kTW - 1) / kTW;
+    const int tile = xcd_tile(lb, I.nb);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
     const T m = (T)st.m;
-    const T alpha = (T)pr.alpha;
-    const T* __restrict__ X = pick(b.X[0], b.X[1], b.X[2], st.cur);
-    const T* __restrict__ XP = pick(b.X[0], b.X[1], b.X[2], st.prev);
-    const T* __restrict__ KX = pick(b.KX[0], b.KX[1], b.KX[2], st.cur);
-    const T* __restrict__ KXP = pick(b.KX[0], b.KX[1], b.KX[2], st.prev);
-    const T* __restrict__ Y = b.y;
+    const T alpha = (T)I.pr.alpha;
+    const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], st.cur);
+    const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
+    const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], st.cur);
+    const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], st.prev);
+    const T* __restrict__ Y = I.y;
 
     // ---- TV gradient at v (all channels staged: the magnitude couples them)
     T* s_v = sm;
@@ -319,7 +345,7 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(const Params pr, const ApgStat
                               [&](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); });
     }
     __syncthreads();
-    tv_weights<T, R>(s_v, s_w, C, reg, (T)(pr.eps_tv * pr.eps_tv), ti0, tj0, H, W);
+    tv_weights<T, R>(s_v, s_w, C, reg, (T)(I.pr.eps_tv * I.pr.eps_tv), ti0, tj0, H, W);
     __syncthreads();
     T tg0[R], tg1[R], tg2[R];
 #pragma unroll
@@ -345,43 +371,44 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(const Params pr, const ApgStat
         T acc[R];
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(sm, CP, b.th, li0, tx, acc);
+        correlate<T, K, R>(sm, CP, I.th, li0, tx, acc);
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int gi = ti0 + li0 + o;
             if (gi < H && gj < W) {
                 const T gv = dfma(alpha, pick3<T, R>(tg0, tg1, tg2, ch, o), acc[o]);
-                b.G[ch * HW + (int64_t)gi * W + gj] = gv;
+                I.G[ch * HW + (int64_t)gi * W + gj] = gv;
                 gsq += (double)gv * (double)gv;
             }
         }
     }
-    block_partial(gsq, b.pA);
+    block_partial(gsq, I.pA, lb);
 }
 
-// Trial pass.  Reads apg[1], block 0 writes apg[0].  After a fresh gradient
-// it finishes ||G||^2 and applies the stop tests (||G|| <= tol: done, the
-// point is v; iteration cap: done with MAXITER); otherwise (or on a retry)
-// it takes the trial x+ = v + dl, dl = -G/L, writes x+ and theta*x+ =
-// theta*v + theta*dl into the spare buffers, and forms per-block partials of
-// the decrease h(x+) - h(v) through the increment (no cancellation of
-// objective values):
+// Trial pass.  Per instance: reads sin, block 0 writes sout.  After a fresh
+// gradient it finishes ||G||^2 and applies the stop tests (||G|| <= tol:
+// done, the point is v; iteration cap: done with MAXITER); otherwise (or on
+// a retry) it takes the trial x+ = v + dl, dl = -G/L, writes x+ and
+// theta*x+ = theta*v + theta*dl into the spare buffers, and forms per-block
+// partials of the decrease h(x+) - h(v) through the increment (no
+// cancellation of objective values):
 //   data: sum d (r_v + d/2), d = theta*dl;
 //   TV:   sum_sites (s'^2 - s^2) / (sqrt(s'^2+eps^2) + sqrt(s^2+eps^2)),
 //         s'^2 - s^2 = sum a (a + 2 b), a = D dl, b = D v,
 // with every per-element product in double.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_trial(const Params pr, const ApgState* __restrict__ sin, ApgState* __restrict__ sout,
-                                                   ApgBufs<T> b) {
-    ApgState st = *sin;
-    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+__global__ __launch_bounds__(kNT) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                   const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
+    MAID_STENCIL_PROLOGUE
+    ApgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
     if (st.done) {
-        if (writer) put_state(sout, st);
+        if (writer) put_state(&sout[ii], st);
         return;
     }
     bool trial = true;
     if (st.phase == PH_GRAD_READY) {
-        const double gn2 = reduce_partials(b.pA, b.nbA);
+        const double gn2 = reduce_partials(I.pA, I.nb);
         st.gn2 = gn2;
         st.nb_iter = 0;
         if (!finite_d(gn2)) {
@@ -399,30 +426,30 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Params pr, const ApgSta
         }
     }
     if (trial) st.phase = PH_TRIALED;
-    if (writer) put_state(sout, st);
+    if (writer) put_state(&sout[ii], st);
     if (!trial) return;
 
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = pr.C, H = pr.H, W = pr.W, reg = pr.reg;
+    const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int ntx = (W + kTW - 1) / kTW;
+    const int tile = xcd_tile(lb, I.nb);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
     const T m = (T)st.m;
     const T ninvL = (T)(-1.0 / st.L);
-    const T* __restrict__ X = pick(b.X[0], b.X[1], b.X[2], st.cur);
-    const T* __restrict__ XP = pick(b.X[0], b.X[1], b.X[2], st.prev);
-    const T* __restrict__ KX = pick(b.KX[0], b.KX[1], b.KX[2], st.cur);
-    const T* __restrict__ KXP = pick(b.KX[0], b.KX[1], b.KX[2], st.prev);
-    T* __restrict__ XN = pick(b.X[0], b.X[1], b.X[2], st.nxt);
-    T* __restrict__ KXN = pick(b.KX[0], b.KX[1], b.KX[2], st.nxt);
-    const T* __restrict__ G = b.G;
-    const T* __restrict__ Y = b.y;
+    const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], st.cur);
+    const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
+    const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], st.cur);
+    const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], st.prev);
+    T* __restrict__ XN = pick(I.X[0], I.X[1], I.X[2], st.nxt);
+    T* __restrict__ KXN = pick(I.KX[0], I.KX[1], I.KX[2], st.nxt);
+    const T* __restrict__ G = I.G;
+    const T* __restrict__ Y = I.y;
 
     T* s_v = sm;
     T* s_d = sm + C * VR * VP;
@@ -439,7 +466,7 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Params pr, const ApgSta
     __syncthreads();
 
     // ---- TV part of the decrease, per site
-    const double e2 = pr.eps_tv * pr.eps_tv;
+    const double e2 = I.pr.eps_tv * I.pr.eps_tv;
     double dtv = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
@@ -481,7 +508,7 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Params pr, const ApgSta
         T acc[R];
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s_c, CP, b.thf, li0, tx, acc);
+        correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
         const T* V = s_v + ch * VR * VP;
 #pragma unroll
         for (int o = 0; o < R; ++o) {
@@ -499,43 +526,48 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Params pr, const ApgSta
             }
         }
     }
-    block_partial(ddat + pr.alpha * dtv, b.pB);
+    block_partial(ddat + I.pr.alpha * dtv, I.pB, lb);
 }
 
-// x_out = v = x + m (x - x_prev): the point that passed the stop test
+// xout = v = x + m (x - x_prev): the point that passed the stop test
+// (instances whose solve failed are left untouched).
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_apg_final(const ApgState* __restrict__ sin, const T* __restrict__ X0, const T* __restrict__ X1,
-                                                   const T* __restrict__ X2, T* __restrict__ out, int64_t n) {
-    const ApgState st = *sin;
-    const T* X = st.cur == 0 ? X0 : (st.cur == 1 ? X1 : X2);
-    const T* XP = st.prev == 0 ? X0 : (st.prev == 1 ? X1 : X2);
+__global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                   const ApgState* __restrict__ sin) {
+    MAID_EW_PROLOGUE
+    const ApgState st = sin[ii];
+    if (st.status < 0 || !I.xout) return;
+    const T* X = pick(I.X[0], I.X[1], I.X[2], st.cur);
+    const T* XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
     const T m = (T)st.m;
-    for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
+    T* out = I.xout;
+    for (int64_t e = (int64_t)lb * kNT + threadIdx.x; e < I.N; e += (int64_t)I.nbe * kNT) {
         const T xv = X[e];
         out[e] = dfma(m, xv - XP[e], xv);
     }
 }
 
 // ------------------------------------------------------------------ conjugate gradients
-// Direction pass.  Reads cg[0], block 0 writes cg[1].  Finishes
-// gamma = ||r||^2 from the partials of the update (or init) pass, applies
+// Direction pass.  Per instance: reads sin, block 0 writes sout.  Finishes
+// gamma = ||r||^2 from the partials of the update (or set-up) pass, applies
 // the stop tests (sqrt(gamma) <= tol; iteration cap), then forms
 // p_new = r + beta p_old (p_new = r on the first iteration, beta =
 // gamma / gamma_prev) and Kp = theta*p_new.  init = 1: the set-up call that
-// only copies r (holding q0) into p and forms theta*q0, without touching
-// the state.
+// only copies r (holding q0) into p and forms theta*q0, without touching the
+// state.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_dir(const Params pr, const CgState* __restrict__ sin, CgState* __restrict__ sout,
-                                                CgBufs<T> b, int init) {
-    CgState st = *sin;
-    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+__global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
+    MAID_STENCIL_PROLOGUE
+    CgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer && !init) put_state(&sout[ii], st);
+        return;
+    }
     double beta = 0.0;
     if (!init) {
-        if (st.done) {
-            if (writer) put_state(sout, st);
-            return;
-        }
-        const double g = reduce_partials(b.pR, b.nbR);
+        const double g = reduce_partials(I.pR, I.nbe);
         if (st.first) {
             st.first = 0;
         } else {
@@ -552,24 +584,24 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Params pr, const CgState* 
             st.done = 1;
             st.status = ST_MAXITER;
         }
-        if (writer) put_state(sout, st);
+        if (writer) put_state(&sout[ii], st);
         if (st.done) return;
     }
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
-    const int C = pr.C, H = pr.H, W = pr.W;
+    const int C = I.pr.C, H = I.pr.H, W = I.pr.W;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int ntx = (W + kTW - 1) / kTW;
+    const int tile = xcd_tile(lb, I.nb);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
     const T bT = (T)beta;
-    const T* __restrict__ Pold = pick(b.P[0], b.P[1], st.pc);
-    T* __restrict__ Pnew = pick(b.P[0], b.P[1], st.pc ^ 1);
+    const T* __restrict__ Pold = pick(I.P[0], I.P[1], st.pc);
+    T* __restrict__ Pnew = pick(I.P[0], I.P[1], st.pc ^ 1);
     for (int ch = 0; ch < C; ++ch) {
-        const T* rc = b.r + ch * HW;
+        const T* rc = I.r + ch * HW;
         const T* pc = Pold + ch * HW;
         __syncthreads();
         if (beta == 0.0)
@@ -580,58 +612,57 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Params pr, const CgState* 
         T acc[R];
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s, CP, b.thf, li0, tx, acc);
+        correlate<T, K, R>(s, CP, I.thf, li0, tx, acc);
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int li = li0 + o, gi = ti0 + li;
             if (gi < H && gj < W) {
                 const int64_t e = ch * HW + (int64_t)gi * W + gj;
                 Pnew[e] = s[(li + c0) * CP + tx + c0];
-                b.Kp[e] = acc[o];
+                I.Kp[e] = acc[o];
             }
         }
     }
 }
 
-// Hessian pass.  Reads cg[1], block 0 writes cg[2].
+// Hessian pass.  Per instance: reads sin, block 0 writes sout.
 // Hp = theta . Kp + alpha grad^2 R(xt)[p] and per-block partials of <p,Hp>;
 // grad^2 R(x)[p] = D^T (w Dp - w^3 m Dx), m = <Dx, Dp> over the coupled
 // channels.  init = 1 computes H q0 only.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_hvp(const Params pr, const CgState* __restrict__ sin, CgState* __restrict__ sout,
-                                                CgBufs<T> b, int init) {
-    const CgState st = *sin;
-    if (!init) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) put_state(sout, st);
-        if (st.done) return;
-    }
+__global__ __launch_bounds__(kNT) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
+    MAID_STENCIL_PROLOGUE
+    const CgState st = sin[ii];
+    if (!init && lb == 0 && threadIdx.x == 0) put_state(&sout[ii], st);
+    if (st.done) return;
     constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = pr.C, H = pr.H, W = pr.W, reg = pr.reg;
+    const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
     const int nw = reg == 1 ? C : 1;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW, nty = (H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int ntx = (W + kTW - 1) / kTW;
+    const int tile = xcd_tile(lb, I.nb);
     const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
-    const T alpha = (T)pr.alpha;
-    const T* __restrict__ P = pick(b.P[0], b.P[1], st.pc ^ 1);
+    const T alpha = (T)I.pr.alpha;
+    const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
 
     T* s_x = sm;
     T* s_p = sm + C * VR * VP;
     T* s_w = sm + 2 * C * VR * VP;
     T* s_mw = s_w + nw * WR * WP;
     for (int ch = 0; ch < C; ++ch) {
-        const T* xc = b.xt + ch * HW;
+        const T* xc = I.xt + ch * HW;
         const T* pc = P + ch * HW;
         load_tile<VR, VP, VP>(s_x + ch * VR * VP, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return xc[g]; });
         load_tile<VR, VP, VP>(s_p + ch * VR * VP, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return pc[g]; });
     }
     __syncthreads();
-    const T eps2 = (T)(pr.eps_tv * pr.eps_tv);
+    const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
     for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
         const int r = idx / WP, cc = idx - r * WP;
         const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
@@ -701,94 +732,107 @@ __global__ __launch_bounds__(kNT) void k_cg_hvp(const Params pr, const CgState* 
 
     double kap = 0.0;
     for (int ch = 0; ch < C; ++ch) {
-        const T* kc = b.Kp + ch * HW;
+        const T* kc = I.Kp + ch * HW;
         __syncthreads();
         load_tile<CR, CP, CP>(sm, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return kc[g]; });
         __syncthreads();
         T acc[R];
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(sm, CP, b.th, li0, tx, acc);
+        correlate<T, K, R>(sm, CP, I.th, li0, tx, acc);
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int gi = ti0 + li0 + o;
             if (gi < H && gj < W) {
                 const int64_t e = ch * HW + (int64_t)gi * W + gj;
                 const T hp = dfma(alpha, pick3<T, R>(hv0, hv1, hv2, ch, o), acc[o]);
-                b.Hp[e] = hp;
+                I.Hp[e] = hp;
                 kap += (double)pick3<T, R>(pp0, pp1, pp2, ch, o) * (double)hp;
             }
         }
     }
-    if (!init) block_partial(kap, b.pK);
+    if (!init) block_partial(kap, I.pK, lb);
 }
 
-// Update pass.  Reads cg[2], block 0 writes cg[0].  Finishes the curvature
-// kappa = <p,Hp> (not positive: MAID_NOT_SPD), a = gamma/kappa, then
-// q += a p, r -= a Hp and per-block partials of ||r||^2.
+// Update pass.  Per instance: reads sin, block 0 writes sout.  Finishes the
+// curvature kappa = <p,Hp> (not positive: MAID_NOT_SPD), a = gamma/kappa,
+// then q += a p, r -= a Hp and per-block partials of ||r||^2.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_update(const CgState* __restrict__ sin, CgState* __restrict__ sout, CgBufs<T> b,
-                                                   int64_t n) {
-    CgState st = *sin;
-    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+__global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                   const CgState* __restrict__ sin, CgState* __restrict__ sout) {
+    MAID_EW_PROLOGUE
+    CgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
     if (st.done) {
-        if (writer) put_state(sout, st);
+        if (writer) put_state(&sout[ii], st);
         return;
     }
-    const double kappa = reduce_partials(b.pK, b.nbK);
+    const double kappa = reduce_partials(I.pK, I.nb);
     st.kappa = kappa;
     if (!(kappa > 0.0) || !finite_d(kappa)) {
         st.done = 1;
         st.status = finite_d(kappa) ? ST_NOT_SPD : ST_NONFINITE;
-        if (writer) put_state(sout, st);
+        if (writer) put_state(&sout[ii], st);
         return;
     }
-    const T* __restrict__ P = pick(b.P[0], b.P[1], st.pc ^ 1);
+    const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
     st.a = st.gamma / kappa;
     st.iters += 1;
     st.pc ^= 1;
-    if (writer) put_state(sout, st);
+    if (writer) put_state(&sout[ii], st);
     const T a = (T)st.a;
+    T* __restrict__ q = I.q;
+    T* __restrict__ r = I.r;
+    const T* __restrict__ Hp = I.Hp;
     double rs = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
+    for (int64_t e = (int64_t)lb * kNT + threadIdx.x; e < I.N; e += (int64_t)I.nbe * kNT) {
         const T pv = P[e];
-        b.q[e] = dfma(a, pv, b.q[e]);
-        const T rv = dfma(-a, b.Hp[e], b.r[e]);
-        b.r[e] = rv;
+        q[e] = dfma(a, pv, q[e]);
+        const T rv = dfma(-a, Hp[e], r[e]);
+        r[e] = rv;
         rs += (double)rv * (double)rv;
     }
-    block_partial(rs, b.pR);
+    block_partial(rs, I.pR, lb);
 }
 
 // r = b - H q0 (Hp holds H q0) and per-block partials of ||r||^2.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_init(CgBufs<T> b, int64_t n) {
+__global__ __launch_bounds__(kNT) void k_cg_init(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+                                                 const CgState* __restrict__ sin) {
+    MAID_EW_PROLOGUE
+    if (sin[ii].done) return;
+    const T* __restrict__ b = I.b;
+    const T* __restrict__ Hp = I.Hp;
+    T* __restrict__ r = I.r;
     double rs = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
-        const T rv = b.b[e] - b.Hp[e];
-        b.r[e] = rv;
+    for (int64_t e = (int64_t)lb * kNT + threadIdx.x; e < I.N; e += (int64_t)I.nbe * kNT) {
+        const T rv = b[e] - Hp[e];
+        r[e] = rv;
         rs += (double)rv * (double)rv;
     }
-    block_partial(rs, b.pR);
+    block_partial(rs, I.pR, lb);
 }
 
 // ------------------------------------------------------------------ small kernels
-// theta (double, KxK) -> compute type, plain and flipped; optionally its
-// l1 norm squared into *L_io when *L_io <= 0 (starting Lipschitz estimate)
-// and the l1 norm into *abs_out (both nullable).
+// One block per instance: theta64 (double, KxK) -> th (correlation form) and
+// thf (flipped, convolution form), both column-major in the compute type;
+// with L_io, the l1 norm squared becomes the starting Lipschitz estimate
+// when that is <= 0; red[slot_abs] receives the l1 norm when slot_abs >= 0.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_prep_kernel(double* __restrict__ L_io, double* __restrict__ abs_out,
-                                                      const double* __restrict__ th, T* __restrict__ out, T* __restrict__ outf, int K) {
+__global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* __restrict__ insts, ApgState* __restrict__ Lst,
+                                                      int slot_abs) {
     __shared__ double s_abs[1024];
-    const int KK = K * K;
+    const Inst<T>& I = insts[blockIdx.x];
+    if (!I.theta64) return;
+    const int K = I.K, KK = K * K;
     const int t = threadIdx.x;
     double a = 0.0;
     if (t < KK) {
         const int u = t / K, v = t - u * K;
-        const double w = th[t];
+        const double w = I.theta64[t];
         // column-major: out(u,v) at v*K+u; the flipped kernel f(u',v') = theta(K-1-u', K-1-v')
-        out[v * K + u] = (T)w;
-        outf[(K - 1 - v) * K + (K - 1 - u)] = (T)w;
+        I.th[v * K + u] = (T)w;
+        I.thf[(K - 1 - v) * K + (K - 1 - u)] = (T)w;
         a = fabs(w);
     }
     s_abs[t] = a;
@@ -796,9 +840,18 @@ __global__ __launch_bounds__(1024) void k_prep_kernel(double* __restrict__ L_io,
     if (t == 0) {
         double s = 0.0;
         for (int i = 0; i < KK; ++i) s += s_abs[i];
-        if (L_io && !(*L_io > 0.0)) *L_io = s * s;
-        if (abs_out) *abs_out = s;
+        if (Lst && !(Lst[blockIdx.x].L > 0.0)) Lst[blockIdx.x].L = s * s;
+        if (slot_abs >= 0) I.red[slot_abs] = s;
     }
+}
+
+// One block per instance: red[slot] = sum of the instance's cv_part partials.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_reduce(const Inst<T>* __restrict__ insts, int slot) {
+    const Inst<T>& I = insts[blockIdx.x];
+    if (!I.cv_part) return;
+    const double s = reduce_partials(I.cv_part, I.nb);
+    if (threadIdx.x == 0) I.red[slot] = s;
 }
 
 // ------------------------------------------------------------------ hypergradient

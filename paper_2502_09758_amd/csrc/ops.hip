@@ -41,96 +41,82 @@ __global__ __launch_bounds__(1024) void k_sobolev(double beta, double h1_w0, con
 }
 
 
-// *out = sum of nb partials (one block)
-__global__ __launch_bounds__(kNT) void k_reduce(const double* __restrict__ part, int nb, double* __restrict__ out) {
-    const double s = reduce_partials(part, nb);
-    if (threadIdx.x == 0) *out = s;
-}
-
 #define MAID_FOR_EACH_K(X) X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
 
+#define MAID_K_SWITCH(CALL)                                  \
+    switch (g.K) {                                           \
+        MAID_FOR_EACH_K(CALL)                                \
+        default: return hipErrorInvalidValue;                \
+    }
+
 template <typename T>
-hipError_t Ops<T>::prep_kernel(double* L_io, double* abs_out, const double* th, T* out, T* outf, int K, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep_kernel<T>, dim3(1), dim3(1024), 0, s, L_io, abs_out, th, out, outf, K);
+hipError_t Ops<T>::prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, int slot_abs, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, slot_abs);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Ops<T>::conv(const Shape& d, int R, const T* ker, const T* in, const T* sub, T* out, double* part, hipStream_t s) {
-    switch (d.K) {
-#define MAID_CASE(KV) \
-    case KV: return conv_k<T, KV>(d, R, ker, in, sub, out, part, s);
-        MAID_FOR_EACH_K(MAID_CASE)
-#undef MAID_CASE
-        default: return hipErrorInvalidValue;
-    }
+hipError_t Ops<T>::reduce(const Inst<T>* insts, int n, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce<T>, dim3(n), dim3(kNT), 0, s, insts, slot);
+    return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Ops<T>::apg_grad(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
-                            hipStream_t s) {
-    switch (d.K) {
+hipError_t Ops<T>::conv(const Group& g, const Inst<T>* insts, hipStream_t s) {
 #define MAID_CASE(KV) \
-    case KV: return apg_grad_k<T, KV>(d, R, p, sin, sout, b, s);
-        MAID_FOR_EACH_K(MAID_CASE)
+    case KV: return conv_k<T, KV>(g, insts, s);
+    MAID_K_SWITCH(MAID_CASE)
 #undef MAID_CASE
-        default: return hipErrorInvalidValue;
-    }
 }
 
 template <typename T>
-hipError_t Ops<T>::apg_trial(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
+hipError_t Ops<T>::apg_grad(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return apg_grad_k<T, KV>(g, insts, sin, sout, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
+hipError_t Ops<T>::apg_trial(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return apg_trial_k<T, KV>(g, insts, sin, sout, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
+hipError_t Ops<T>::cg_dir(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return cg_dir_k<T, KV>(g, insts, sin, sout, init, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
+hipError_t Ops<T>::cg_hvp(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return cg_hvp_k<T, KV>(g, insts, sin, sout, init, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
+hipError_t Ops<T>::apg_final(int grid_e, const int* blk_e, const Inst<T>* insts, const ApgState* sin, hipStream_t s) {
+    hipLaunchKernelGGL(k_apg_final<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Ops<T>::cg_update(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, CgState* sout,
                              hipStream_t s) {
-    switch (d.K) {
-#define MAID_CASE(KV) \
-    case KV: return apg_trial_k<T, KV>(d, R, p, sin, sout, b, s);
-        MAID_FOR_EACH_K(MAID_CASE)
-#undef MAID_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t Ops<T>::cg_dir(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b,
-                          int init, hipStream_t s) {
-    switch (d.K) {
-#define MAID_CASE(KV) \
-    case KV: return cg_dir_k<T, KV>(d, R, p, sin, sout, b, init, s);
-        MAID_FOR_EACH_K(MAID_CASE)
-#undef MAID_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t Ops<T>::cg_hvp(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b,
-                          int init, hipStream_t s) {
-    switch (d.K) {
-#define MAID_CASE(KV) \
-    case KV: return cg_hvp_k<T, KV>(d, R, p, sin, sout, b, init, s);
-        MAID_FOR_EACH_K(MAID_CASE)
-#undef MAID_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t Ops<T>::apg_final(const ApgState* sin, const ApgBufs<T>& b, T* out, int64_t n, hipStream_t s) {
-    int64_t nb = (n + kNT - 1) / kNT;
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_apg_final<T>, dim3((unsigned)nb), dim3(kNT), 0, s, sin, b.X[0], b.X[1], b.X[2], out, n);
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin, sout);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Ops<T>::cg_update(const CgState* sin, CgState* sout, const CgBufs<T>& b, int64_t n, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(nblk), dim3(kNT), 0, s, sin, sout, b, n);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t Ops<T>::cg_init(const CgBufs<T>& b, int64_t n, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(nblk), dim3(kNT), 0, s, b, n);
+hipError_t Ops<T>::cg_init(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
     return hipGetLastError();
 }
 
@@ -146,11 +132,6 @@ hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w,
 
 template struct Ops<float>;
 template struct Ops<double>;
-
-hipError_t launch_reduce(const double* part, int nb, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kNT), 0, s, part, nb, out);
-    return hipGetLastError();
-}
 
 int hg_items(const Shape& d) {
     return ((d.W + kHgTJ - 1) / kHgTJ) * ((d.H + kHgTI - 1) / kHgTI) * d.C * 2;

@@ -6,17 +6,13 @@
 
 namespace maid {
 template <typename T, int K>
-hipError_t conv_k(const Shape& d, int R, const T* ker, const T* in, const T* sub, T* out, double* part, hipStream_t s);
+hipError_t conv_k(const Group& g, const Inst<T>* insts, hipStream_t s);
 template <typename T, int K>
-hipError_t apg_grad_k(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
-                      hipStream_t s);
+hipError_t apg_grad_k(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
 template <typename T, int K>
-hipError_t apg_trial_k(const Shape& d, int R, const Params& p, const ApgState* sin, ApgState* sout, const ApgBufs<T>& b,
-                       hipStream_t s);
+hipError_t apg_trial_k(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
 template <typename T, int K>
-hipError_t cg_dir_k(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b, int init,
-                    hipStream_t s);
+hipError_t cg_dir_k(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);
 template <typename T, int K>
-hipError_t cg_hvp_k(const Shape& d, int R, const Params& p, const CgState* sin, CgState* sout, const CgBufs<T>& b, int init,
-                    hipStream_t s);
+hipError_t cg_hvp_k(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);
 }  // namespace maid

@@ -120,12 +120,13 @@ class Maid:
         self._check(L.lib().maid_profile(self.handle, int(bool(enable))), "profile")
 
     def profile_read(self) -> dict:
-        """{kernel kind: (launches, total milliseconds)}"""
+        """{kernel kind: (launches, launches that did a pass of work, total milliseconds)}"""
         out = {}
         for k in range(L.PROF_KINDS):
-            n, ms = ct.c_int64(), ct.c_double()
-            self._check(L.lib().maid_profile_read(self.handle, k, ct.byref(n), ct.byref(ms)), "profile_read")
-            out[L.lib().maid_profile_name(k).decode()] = (n.value, ms.value)
+            n, w, ms = ct.c_int64(), ct.c_int64(), ct.c_double()
+            self._check(L.lib().maid_profile_read(self.handle, k, ct.byref(n), ct.byref(w), ct.byref(ms)),
+                        "profile_read")
+            out[L.lib().maid_profile_name(k).decode()] = (n.value, w.value, ms.value)
         return out
 
     # ------------------------------------------------------------------ entry points
@@ -204,3 +205,95 @@ class Maid:
         self._check(rc, "maid_step")
         state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
         return rc, {f: getattr(info, f) for f, _ in L.maid_step_info._fields_}
+
+
+class MaidBatch:
+    """A ragged batch of independent instances in one context (the batched
+    form of the C ABI).  `specs` is a list of dicts with keys C, H, W, K and
+    optionally alpha, eps_tv, beta, h1_w0, reg; one storage dtype for all.
+    Per-instance tensors are passed as lists."""
+
+    def __init__(self, specs, dtype=torch.float32):
+        if dtype not in _DT:
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        self.specs = [dict(alpha=1e-3, eps_tv=1e-2, beta=0.0, h1_w0=1.0, reg=L.MAID_REG_TV) | dict(s) for s in specs]
+        self.n = len(self.specs)
+        self.descs = [L.maid_desc(int(s["H"]), int(s["W"]), int(s["C"]), int(s["K"]), _DT[dtype], int(s["reg"]),
+                                  float(s["alpha"]), float(s["eps_tv"]), float(s["beta"]), float(s["h1_w0"]))
+                      for s in self.specs]
+        self._h = None
+        self._h = L.create_batch(self.descs)
+
+    close = Maid.close
+    __del__ = Maid.__del__
+    handle = Maid.handle
+    config = Maid.config
+    set_tile_rows = Maid.set_tile_rows
+    profile = Maid.profile
+    profile_read = Maid.profile_read
+    _check = Maid._check
+
+    def _imgs(self, ts, name):
+        if len(ts) != self.n:
+            raise ValueError(f"{name}: need {self.n} tensors")
+        for i, t in enumerate(ts):
+            s = self.specs[i]
+            shape = (s["C"], s["H"], s["W"])
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.dtype or \
+                    tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name}[{i}] must be a contiguous CUDA {self.dtype} tensor of shape {shape}")
+        return (ct.c_void_p * self.n)(*[t.data_ptr() for t in ts])
+
+    def _kers(self, ts, name):
+        if len(ts) != self.n:
+            raise ValueError(f"{name}: need {self.n} tensors")
+        for i, t in enumerate(ts):
+            K = self.specs[i]["K"]
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or \
+                    tuple(t.shape) != (K, K) or not t.is_contiguous():
+                raise ValueError(f"{name}[{i}] must be a contiguous CUDA float64 tensor of shape {(K, K)}")
+        return (ct.c_void_p * self.n)(*[t.data_ptr() for t in ts])
+
+    def _rc(self, rc, what):
+        if rc < 0 and rc not in (L.NOT_SPD, L.NONFINITE):
+            raise L.MaidError(rc, f"{what}: {L.last_error(self.handle)}")
+        return rc
+
+    def lower_solve(self, thetas, ys, xs, tols, max_iter=300, L_est=None):
+        """Batched lower-level solve, in place in `xs`; returns (rc, [SolveInfo])."""
+        th, y, x = self._kers(thetas, "theta"), self._imgs(ys, "y"), self._imgs(xs, "x")
+        tol = (ct.c_double * self.n)(*[float(t) for t in tols])
+        Lc = (ct.c_double * self.n)(*([0.0] * self.n if L_est is None else [float(v) for v in L_est]))
+        info = (L.maid_solve_info * self.n)()
+        rc = L.lib().maid_batch_lower_solve(self.handle, th, y, x, tol, int(max_iter), Lc, info, _stream())
+        self._rc(rc, "batch_lower_solve")
+        return rc, [SolveInfo(i.status, i.iters, i.backtracks, i.res_norm, i.L) for i in info]
+
+    def adjoint_solve(self, thetas, xts, rhss, qs, tols, max_iter=1000):
+        """Batched CG solve, in place in `qs`; returns (rc, [SolveInfo])."""
+        th, xt, b, q = self._kers(thetas, "theta"), self._imgs(xts, "x_tilde"), self._imgs(rhss, "rhs"), \
+            self._imgs(qs, "q")
+        tol = (ct.c_double * self.n)(*[float(t) for t in tols])
+        info = (L.maid_solve_info * self.n)()
+        rc = L.lib().maid_batch_adjoint_solve(self.handle, th, xt, b, q, tol, int(max_iter), info, _stream())
+        self._rc(rc, "batch_adjoint_solve")
+        return rc, [SolveInfo(i.status, i.iters, 0, i.res_norm, 0.0) for i in info]
+
+    def maid_step(self, as_, ys, states, **hp):
+        """One Algorithm 2 iteration for every instance (lockstep); the states
+        are updated in place.  Returns (rc, [info dict])."""
+        a, y = self._kers(as_, "a"), self._imgs(ys, "y")
+        self._kers([s.theta for s in states], "theta")
+        self._imgs([s.x for s in states], "x"), self._imgs([s.q for s in states], "q")
+        h = dict(DEFAULT_HPARAMS)
+        h.update(hp)
+        hpc = L.maid_hparams(**h)
+        st = (L.maid_state * self.n)(*[L.maid_state(s.theta.data_ptr(), s.x.data_ptr(), s.q.data_ptr(), s.eps,
+                                                    s.delta, s.step, s.L, s.k) for s in states])
+        info = (L.maid_step_info * self.n)()
+        rc = L.lib().maid_batch_step(self.handle, a, y, st, ct.byref(hpc), info, _stream())
+        self._rc(rc, "batch_step")
+        for s, c in zip(states, st):
+            s.eps, s.delta, s.step, s.L, s.k = c.eps, c.delta, c.step, c.L, c.k
+        return rc, [{f: getattr(i, f) for f, _ in L.maid_step_info._fields_} for i in info]
