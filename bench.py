@@ -11,14 +11,25 @@ resident in HBM.  The default workload is the 256x256 grayscale FP32 case
 (9x9 kernel).
 
 Prints ONE JSON line.  Extra objects: `roofline` for the kernel with the
-largest total GPU time in the timed region (durations from HIP events on
-the library's stream, algorithmic bytes or flops per launch from the kernel
-model below), and `cpu_baseline`, the FP64 oracle timed on the host cores on
-a bounded sample of the same workload (fixed lower-level and CG iterations).
+largest total GPU time (durations from HIP events on the library's launch
+stream, algorithmic bytes or flops per launch from the kernel model below),
+and `cpu_baseline`, the FP64 oracle timed on the host cores on a bounded
+sample of the same workload (fixed lower-level and CG iterations).
+
+The timed region runs the steps as a user would (graph-replayed solver
+chunks, no timing events); the same steps are then replayed from the same
+starting state with every launch bracketed by HIP events (direct launches),
+and the roofline comes from that replay.  `traffic` is filled from the
+rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ when that summary
+was taken on the current kernel sources (checked by a hash), else null.
+
+`--calibrate-copy` instead runs a plain device copy of known size, the
+reference for scaling the PMC byte counters.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -94,6 +105,56 @@ def roofline_for(prof: dict, N: int, K: int, esz: int, C: int):
     return roof, name
 
 
+KERNEL_SOURCES = ("paper_2502_09758_amd/csrc/kernels.cuh", "paper_2502_09758_amd/csrc/launch.cuh",
+                  "paper_2502_09758_amd/csrc/devctx.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload: str, kernel: str, launches_per_work: float):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (profiles/hbm_traffic_<workload>.txt: lines `key = value`), scaled by
+    its copy-kernel calibration; None when absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    key = f"{kernel}.bytes_per_work_launch"
+    if key not in kv:
+        return None
+    return float(kv[key]) / launches_per_work
+
+
+def calibrate_copy(mib: int = 512, reps: int = 5):
+    """A plain device-to-device copy kernel (torch's elementwise copy) of
+    known size: reads and writes `mib` MiB per launch."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
+                      "launches": reps, "GB_s": round(2 * n * 4 / dt / 1e9, 1)}), flush=True)
+
+
 def cpu_baseline(inst, budget_s: float = 15.0):
     """The FP64 oracle on the host cores: fixed lower-level (FISTA) and CG
     iterations on the same instance, scaled to pixel-iterations/s."""
@@ -112,7 +173,7 @@ def cpu_baseline(inst, budget_s: float = 15.0):
         return time.perf_counter() - t0
 
     t1 = run(1)
-    n = max(2, min(400, int(budget_s / max(t1, 1e-4) / 2)))
+    n = max(2, min(20000, int(budget_s / max(t1, 1e-4) / 2)))
     t = run(n)
     return dict(value=2 * n * N / t, unit="pixel-iterations/s", cores=O.num_threads(), kind="oracle",
                 sample=f"{n} FISTA + {n} CG iterations (fixed, no backtracking) on the full {inst.C}x{inst.H}x{inst.W} "
@@ -127,11 +188,15 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import numpy as np
     import torch
@@ -170,8 +235,13 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    if not args.no_profile:
-        m.profile(True)
+    print(f"[bench] {args.workload}: warm-up done, timing {args.steps} steps", file=sys.stderr, flush=True)
+
+    def snapshot():
+        return (MaidState(state.theta.clone(), state.x.clone(), state.q.clone(), state.eps, state.delta, state.step,
+                          state.L, state.k), restarts)
+
+    start = snapshot()
     lower = cg = accepted = trials = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -182,12 +252,26 @@ def main():
         trials += info["trials"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = m.profile_read() if not args.no_profile else {}
-    m.profile(False)
     elapsed = t1 - t0
     value = (lower + cg) * N / elapsed
 
-    roof, dom = roofline_for(prof, N, K, esz, C) if prof else (None, None)
+    prof, roof = {}, None
+    if not args.no_profile:
+        # the same steps again from the same state, every launch timed
+        state, restarts = start
+        m.profile(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        prof = m.profile_read()
+        m.profile(False)
+        roof, dom = roofline_for(prof, N, K, esz, C)
+        if roof is not None:
+            launches, work, _ = prof[dom]
+            t = traffic_for(args.workload, dom, launches / max(work, 1))
+            roof["traffic"] = round(t, 1) if t is not None else None
+            roof["traffic_unit"] = "bytes/launch"
+    print("[bench] timed region done", file=sys.stderr, flush=True)
 
     # time to hypergradient: one cold InexactGradient at eps = delta = tol
     tth = {}

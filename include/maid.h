@@ -222,8 +222,9 @@ int maid_batch_step(maid_ctx* ctx, const void* const* a, const void* const* y,
                     hipStream_t stream);
 
 /* Kernel timing (for measurement and profiling tools).  maid_profile(ctx, 1)
-   resets the counters and, until maid_profile(ctx, 0), brackets every kernel
-   launch of the context with a pair of HIP events on the launch stream;
+   resets the counters and, until maid_profile(ctx, 0), launches every kernel
+   of the context directly (no graph replay) with a pair of HIP events that
+   the dispatch stamps with the kernel's own start and end times;
    maid_profile_read returns, for one kernel kind, the number of timed
    launches, how many of them did a pass of work (solver passes launched in
    a chunk exit early once the solve has finished or when a backtracking

@@ -147,15 +147,17 @@ struct ProfScope {
     int kind;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
+    // the events ride on the one launch made inside the scope and carry that
+    // kernel's start and end timestamps
     ProfScope(maid_ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
         if (!c->prof_on) return;
         a = prof_event(c);
         b = prof_event(c);
-        if (a) (void)hipEventRecord(a, s);
+        if (a && b) launch_timing() = LaunchTiming{a, b};
     }
     ~ProfScope() {
         if (!c->prof_on || !a || !b) return;
-        (void)hipEventRecord(b, s);
+        launch_timing() = LaunchTiming{};
         c->prof_pending.push_back({kind, a, b});
         if (c->prof_pending.size() >= 4096) prof_harvest(c);
     }

@@ -20,8 +20,7 @@ static hipError_t conv_kr(const Group& g, const Inst<T>* insts, hipStream_t s) {
     auto kern = k_conv<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk);
-    return hipGetLastError();
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk);
 }
 
 template <typename T, int K, int R>
@@ -30,8 +29,7 @@ static hipError_t apg_grad_kr(const Group& g, const Inst<T>* insts, const ApgSta
     auto kern = k_apg_grad<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout);
-    return hipGetLastError();
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout);
 }
 
 template <typename T, int K, int R>
@@ -40,8 +38,7 @@ static hipError_t apg_trial_kr(const Group& g, const Inst<T>* insts, const ApgSt
     auto kern = k_apg_trial<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout);
-    return hipGetLastError();
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout);
 }
 
 template <typename T, int K, int R>
@@ -51,8 +48,7 @@ static hipError_t cg_dir_kr(const Group& g, const Inst<T>* insts, const CgState*
     auto kern = k_cg_dir<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout, init);
-    return hipGetLastError();
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout, init);
 }
 
 template <typename T, int K, int R>
@@ -62,8 +58,7 @@ static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState*
     auto kern = k_cg_hvp<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout, init);
-    return hipGetLastError();
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout, init);
 }
 
 #define MAID_R_DISPATCH(FN, ...)                                   \

@@ -4,6 +4,7 @@
 // matching template instantiation); elementwise passes cover every instance
 // of the table in one launch.  All launches are asynchronous on `s`.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -20,6 +21,24 @@ inline int stencil_blocks(const Shape& d, int R) {
 }
 
 inline bool valid_rows(int R) { return R == 1 || R == 2 || R == 4; }
+
+// Kernel timing: while a pair of events is set (per host thread), every
+// launch hands them to the dispatch, which stamps them with the kernel's own
+// start and end times (no host-side gaps), as a profiler's kernel trace does.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTiming& launch_timing();
+
+template <typename F, typename... Args>
+inline hipError_t launch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+    const LaunchTiming& t = launch_timing();
+    if (t.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t.start, t.stop, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    return hipGetLastError();
+}
 
 // One stencil launch: the instances of a group, their block -> instance map.
 struct Group {

@@ -51,14 +51,12 @@ __global__ __launch_bounds__(1024) void k_sobolev(double beta, double h1_w0, con
 
 template <typename T>
 hipError_t Ops<T>::prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, int slot_abs, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, slot_abs);
-    return hipGetLastError();
+    return launch(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, slot_abs);
 }
 
 template <typename T>
 hipError_t Ops<T>::reduce(const Inst<T>* insts, int n, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce<T>, dim3(n), dim3(kNT), 0, s, insts, slot);
-    return hipGetLastError();
+    return launch(k_reduce<T>, dim3(n), dim3(kNT), 0, s, insts, slot);
 }
 
 template <typename T>
@@ -103,35 +101,35 @@ hipError_t Ops<T>::cg_hvp(const Group& g, const Inst<T>* insts, const CgState* s
 
 template <typename T>
 hipError_t Ops<T>::apg_final(int grid_e, const int* blk_e, const Inst<T>* insts, const ApgState* sin, hipStream_t s) {
-    hipLaunchKernelGGL(k_apg_final<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
-    return hipGetLastError();
+    return launch(k_apg_final<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
 }
 
 template <typename T>
 hipError_t Ops<T>::cg_update(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, CgState* sout,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin, sout);
-    return hipGetLastError();
+    return launch(k_cg_update<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin, sout);
 }
 
 template <typename T>
 hipError_t Ops<T>::cg_init(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
-    return hipGetLastError();
+    return launch(k_cg_init<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
 }
 
 template <typename T>
 hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w, const T* xt, double* part, int nblk,
                            hipStream_t s) {
     if (d.K <= 16)
-        hipLaunchKernelGGL((k_hg_corr<T, 16>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
-    else
-        hipLaunchKernelGGL((k_hg_corr<T, 32>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
-    return hipGetLastError();
+        return launch((k_hg_corr<T, 16>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
+    return launch((k_hg_corr<T, 32>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
 }
 
 template struct Ops<float>;
 template struct Ops<double>;
+
+LaunchTiming& launch_timing() {
+    static thread_local LaunchTiming t;
+    return t;
+}
 
 int hg_items(const Shape& d) {
     return ((d.W + kHgTJ - 1) / kHgTJ) * ((d.H + kHgTI - 1) / kHgTI) * d.C * 2;
@@ -140,20 +138,16 @@ int hg_items(const Shape& d) {
 hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
                            const double* a, int with_r, double* z, double* znorm2, hipStream_t s) {
     if (d.K <= 16)
-        hipLaunchKernelGGL(k_hg_final<16>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
-    else
-        hipLaunchKernelGGL(k_hg_final<32>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
-    return hipGetLastError();
+        return launch(k_hg_final<16>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
+    return launch(k_hg_final<32>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
 }
 
 hipError_t launch_theta_step(const double* th, const double* z, double step, double* out, int KK, hipStream_t s) {
-    hipLaunchKernelGGL(k_theta_step, dim3((KK + 255) / 256), dim3(256), 0, s, th, z, step, out, KK);
-    return hipGetLastError();
+    return launch(k_theta_step, dim3((KK + 255) / 256), dim3(256), 0, s, th, z, step, out, KK);
 }
 
 hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sobolev, dim3(1), dim3(1024), 0, s, beta, h1_w0, th, a, K, out);
-    return hipGetLastError();
+    return launch(k_sobolev, dim3(1), dim3(1024), 0, s, beta, h1_w0, th, a, K, out);
 }
 
 }  // namespace maid
