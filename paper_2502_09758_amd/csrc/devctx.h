@@ -72,21 +72,30 @@ __host__ __device__ constexpr int cv_rows(int K, int R) { return tile_h(R) + K -
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 __host__ __device__ constexpr int lds_conv(int K, int R) { return cv_rows(K, R) * cv_pitch(K); }
+// Large kernels are ALU-bound and need occupancy: their passes stage the TV
+// tiles and the convolution tile one after the other in one LDS region.
+// Small kernels are latency-bound: all tiles are staged at once, side by side.
+__host__ __device__ constexpr bool seq_lds(int K) { return K >= 13; }
+__host__ __device__ constexpr int lds_side(bool seq, int a, int b) { return seq ? cmax(a, b) : a + b; }
 __host__ __device__ constexpr int lds_apg_grad(int K, int R, int C, int nw) {
-    return cmax(C * tv_rows(R) * tv_pitch() + nw * fx_rows(R) * fx_pitch(), lds_conv(K, R));
+    // sequential staging parks the TV gradient of each output past the tile region
+    return lds_side(seq_lds(K), C * tv_rows(R) * tv_pitch() + nw * fx_rows(R) * fx_pitch(), lds_conv(K, R)) +
+           (seq_lds(K) ? R * 256 : 0);
 }
-__host__ __device__ constexpr int lds_apg_trial(int K, int R, int C) {
-    return 2 * C * tv_rows(R) * tv_pitch() + lds_conv(K, R);
-}
+__host__ __device__ constexpr int lds_apg_trial(int K, int R, int C) { return lds_conv(K, R); }
 __host__ __device__ constexpr int lds_cg_hvp(int K, int R, int C, int nw) {
-    return cmax(2 * C * tv_rows(R) * tv_pitch() + 2 * nw * fx_rows(R) * fx_pitch(), lds_conv(K, R));
+    // sequential staging parks the TV Hessian term and p of each output in LDS
+    // across the convolution (2 R values per thread)
+    return lds_side(seq_lds(K), 2 * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch(), lds_conv(K, R)) +
+           (seq_lds(K) ? 2 * R * 256 : 0);
 }
+__host__ __device__ constexpr int lds_cg_dir(int K, int R) { return seq_lds(K) ? lds_conv(K, R) : 2 * lds_conv(K, R); }
 
 // ------------------------------------------------------------------ instance table
 template <typename T> struct Inst {
     Params pr;                   // C, H, W, reg, alpha, eps_tv
     int32_t K;                   // kernel size
-    int32_t nb, base;            // stencil blocks (tiles) and first block within its group launch
+    int32_t nb, base;            // stencil blocks (tiles x channels) and first block within its group launch
     int32_t nbe, base_e;         // elementwise blocks and first block within the elementwise launch
     int32_t pad;
     int64_t N;                   // C*H*W

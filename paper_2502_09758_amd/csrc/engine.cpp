@@ -267,7 +267,7 @@ int relayout(maid_ctx* c) {
     for (int i = 0; i < c->n; ++i) {
         if (placed[i]) continue;
         LaunchGroup lg;
-        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr};
+        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr, -1};
         for (int k = i; k < c->n; ++k)
             if (!placed[k] && c->m[k].d.K == lg.g.K && c->m[k].R == lg.g.R) {
                 placed[k] = 1;
@@ -310,8 +310,12 @@ int relayout(maid_ctx* c) {
     }
     if (host.size() > c->maps_cap) return fail(c, MAID_EHIP, "relayout: block maps exceed their allocation");
     HIP_TRY(hipMemcpy(c->maps, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
-    for (size_t g = 0; g < c->groups.size(); ++g) c->groups[g].g.blk = c->maps + offs[g];
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        c->groups[g].g.blk = c->maps + offs[g];
+        c->groups[g].g.only = c->groups[g].members.size() == 1 ? c->groups[g].members[0] : -1;
+    }
     c->blk_e = c->maps + off_e;
+    c->only_e = c->n == 1 ? 0 : -1;
     c->layout_gen += 1;
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
@@ -541,7 +545,7 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         c->prof_work[MAID_PROF_APG_GRAD] += wg;
         c->prof_work[MAID_PROF_APG_TRIAL] += wt;
     }
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, tabd, c->apg[0], s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, c->only_e, tabd, c->apg[0], s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int i = 0; i < n; ++i) {
         codes[i] = MAID_OK;
@@ -602,7 +606,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
     CgState** S = c->cg;
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->grid_e, c->blk_e, tabd, S[0], s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->grid_e, c->blk_e, c->only_e, tabd, S[0], s));
     int chunk = 1;
     long slots = 0;
     for (;;) {
@@ -610,7 +614,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
             for (int k = 0; k < chunk; ++k) {
                 for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
                 for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
-                LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(c->grid_e, c->blk_e, tabd, S[2], S[0], s));
+                LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
             }
             return (int)MAID_OK;
         });

@@ -87,6 +87,7 @@ struct maid_ctx {
     std::vector<maid::LaunchGroup> groups;
     int grid_e = 0;
     const int* blk_e = nullptr;
+    int only_e = -1;                  // 0 for a single instance (no map lookup), else -1
     int* maps = nullptr;
     size_t maps_cap = 0;
     int layout_gen = 0;

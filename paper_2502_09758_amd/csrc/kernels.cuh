@@ -2,8 +2,9 @@
 // kernel size K and rows per thread R).
 //
 // Layout: images are planar [C][H][W]; a block of 256 threads (four wave64s)
-// owns a 64-wide, 4R-tall tile of output pixels for all channels.  Lane tx of
-// wave wy computes the R pixels in rows wy*R .. wy*R+R-1 of column tx.
+// owns a 64-wide, 4R-tall tile of output pixels of one channel (the TV terms,
+// which couple the channels, stage every channel's small halo tile).  Lane tx
+// of wave wy computes the R pixels in rows wy*R .. wy*R+R-1 of column tx.
 // Inputs with the halo a stencil needs are staged through LDS with zero fill
 // outside the image; convolution taps are read through uniform (scalar)
 // loads, so every FMA takes its tap from an SGPR and its pixel from a VGPR
@@ -19,11 +20,17 @@
 // host round trip and without atomics or fences: the kernel boundary orders
 // the partials before they are read.
 //
+// The total is needed only after the pass has staged its own inputs, so the
+// partial loads are issued first and summed after the tile loads: the two
+// latencies overlap.  A pass whose decision may discard its work (a
+// rejected trial step) computes speculatively and gates only its stores.
+//
 // Every pass serves a batch: block b belongs to instance blk[b] of the
-// instance table (a plain solve is a batch of one); the instance's blocks
-// start at a multiple of 8 so that the XCD-major tile order holds within
-// each instance.  Solver states are arrays over instances, read through one
-// copy and written by the instance's block 0 into the next.
+// instance table (a plain solve is a batch of one; a launch over a single
+// instance passes its index as `only` and skips the map); the instance's
+// blocks start at a multiple of 8 so that the XCD-major tile order holds
+// within each instance.  Solver states are arrays over instances, read
+// through one copy and written by the instance's block 0 into the next.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -80,6 +87,28 @@ __device__ __forceinline__ void block_partial(double v, double* part, int lb) {
 __device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int nb) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nb; b += kNT) s += part[b];
+    return block_sum(s);
+}
+
+// The same sum in two steps: partials_issue loads the thread's first four
+// partials into registers (the loads stay in flight while the caller stages
+// its tiles), partials_finish adds them and any further ones in the same
+// order as reduce_partials and sums over the block.
+struct Partials {
+    double v[4];
+};
+__device__ __forceinline__ Partials partials_issue(const double* __restrict__ part, int nb) {
+    Partials p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int b = threadIdx.x + k * kNT;
+        p.v[k] = b < nb ? part[b] : 0.0;
+    }
+    return p;
+}
+__device__ __forceinline__ double partials_finish(const double* __restrict__ part, int nb, const Partials& p) {
+    double s = ((p.v[0] + p.v[1]) + p.v[2]) + p.v[3];
+    for (int b = threadIdx.x + 4 * kNT; b < nb; b += kNT) s += part[b];
     return block_sum(s);
 }
 
@@ -198,77 +227,92 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
     return Wt[r * WP + cc - 1] * dh_left - w0 * dh_here + Wt[(r - 1) * WP + cc] * dv_up - w0 * dv_here;
 }
 
+// Occupancy floor (waves per SIMD) the compiler must keep: the ALU-bound
+// large-kernel passes need enough waves to hide their LDS latency, so their
+// register budget is capped at that of the plain convolution.
+// (FP32 storage only; the FP64 instantiations keep the compiler's choice).
+template <typename T> __host__ __device__ constexpr int min_waves(int K) { return sizeof(T) == 4 && seq_lds(K) ? 6 : 1; }
+
 // ------------------------------------------------------------------ instance lookup
 // Block -> (instance, local block).  Padding blocks (lb >= nb) return at once.
 #define MAID_STENCIL_PROLOGUE                                         \
-    const int ii = blk[blockIdx.x];                                   \
+    const int ii = only >= 0 ? only : blk[blockIdx.x];                \
     const Inst<T>& I = insts[ii];                                     \
     const int lb = (int)blockIdx.x - I.base;                          \
     if (lb >= I.nb) return;
 
 #define MAID_EW_PROLOGUE                                              \
-    const int ii = blk[blockIdx.x];                                   \
+    const int ii = only >= 0 ? only : blk[blockIdx.x];                \
     const Inst<T>& I = insts[ii];                                     \
     const int lb = (int)blockIdx.x - I.base_e;                        \
     if (lb >= I.nbe) return;
+
+// Local block -> tile origin and channel.  The C channel blocks of one tile
+// are adjacent in the XCD-major order (they share halo loads in L2).
+template <int R>
+__device__ __forceinline__ void tile_pos(const Params& pr, int lb, int nb, int& ti0, int& tj0, int& ch) {
+    const int t = xcd_tile(lb, nb);
+    const int tile = t / pr.C;
+    ch = t - tile * pr.C;
+    const int ntx = (pr.W + kTW - 1) / kTW;
+    ti0 = (tile / ntx) * tile_h(R);
+    tj0 = (tile % ntx) * kTW;
+}
 
 // ------------------------------------------------------------------ generic convolution pass
 // cv_out = cv_ker (x) cv_in  [- cv_sub]   (correlation with cv_ker; the
 // flipped kernel gives the true convolution); with cv_part, per-block
 // partials of sum cv_out^2.  Instances without cv_out take no part.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts, const int* __restrict__ blk) {
+__global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only) {
     MAID_STENCIL_PROLOGUE
     if (!I.cv_out) return;
-    constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
+    constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
-    const int C = I.pr.C, H = I.pr.H, W = I.pr.W;
+    const int H = I.pr.H, W = I.pr.W;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW;
-    const int tile = xcd_tile(lb, I.nb);
-    const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
+    int ti0, tj0, ch;
+    tile_pos<R>(I.pr, lb, I.nb, ti0, tj0, ch);
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
-    const T* __restrict__ in = I.cv_in;
+    const T* __restrict__ src = I.cv_in + ch * HW;
     const T* __restrict__ sub = I.cv_sub;
     T* __restrict__ out = I.cv_out;
+    load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return src[g]; });
+    __syncthreads();
+    T acc[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) acc[o] = T(0);
+    correlate<T, K, R>(s, CP, I.cv_ker, li0, tx, acc);
+    const int gj = tj0 + tx;
     double sq = 0.0;
-    for (int ch = 0; ch < C; ++ch) {
-        const T* src = in + ch * HW;
-        __syncthreads();
-        load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return src[g]; });
-        __syncthreads();
-        T acc[R];
 #pragma unroll
-        for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s, CP, I.cv_ker, li0, tx, acc);
-        const int gj = tj0 + tx;
-#pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int gi = ti0 + li0 + o;
-            if (gi < H && gj < W) {
-                const int64_t e = ch * HW + (int64_t)gi * W + gj;
-                T val = acc[o];
-                if (sub) val -= sub[e];
-                out[e] = val;
-                sq += (double)val * (double)val;
-            }
+    for (int o = 0; o < R; ++o) {
+        const int gi = ti0 + li0 + o;
+        if (gi < H && gj < W) {
+            const int64_t e = ch * HW + (int64_t)gi * W + gj;
+            T val = acc[o];
+            if (sub) val -= sub[e];
+            out[e] = val;
+            sq += (double)val * (double)val;
         }
     }
     if (I.cv_part) block_partial(sq, I.cv_part, lb);
 }
 
 // ------------------------------------------------------------------ lower level: FISTA
-// Gradient pass.  Per instance: reads sin, block 0 writes sout.  If the
-// previous trial pass ran, first finish its decrease h(x+) - h(v) from the
-// partials and take the backtracking decision: accept (rotate buffers,
-// advance the momentum sequence, then evaluate the new gradient) or reject
-// (double L, no gradient work).  The gradient at v = x + m (x - x_prev),
-// with theta*v = Kx + m (Kx - Kx_prev) by linearity, is
+// Gradient pass.  Per instance: reads sin, block 0 writes sout.  After a
+// trial pass, the decrease h(x+) - h(v) is finished from the partials and
+// decides: accept (rotate buffers, advance the momentum sequence, then
+// evaluate the new gradient) or reject (double L, no gradient work).  The
+// gradient at v = x + m (x - x_prev), with theta*v = Kx + m (Kx - Kx_prev) by
+// linearity, is
 //   G = theta . (theta*v - y) + alpha grad R(v),
-// and its per-block partials of ||G||^2 go to pA.
+// and its per-block partials of ||G||^2 go to pA.  The gradient at the point
+// an acceptance would move to is computed while the partials are in flight;
+// a rejection drops it before any store.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                   const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
     MAID_STENCIL_PROLOGUE
     ApgState st = sin[ii];
@@ -277,109 +321,138 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(const Inst<T>* __restrict__ in
         if (writer) put_state(&sout[ii], st);
         return;
     }
-    bool compute = true;
-    if (st.phase == PH_TRIALED) {
-        const double delta = reduce_partials(I.pB, I.nb);
-        st.delta_last = delta;
-        if (!finite_d(delta)) {
-            st.done = 1;
-            st.status = ST_NONFINITE;
-            compute = false;
-        } else if (delta <= -st.gn2 / (2.0 * st.L)) {
-            if (writer && I.trace && st.iters < st.trace_cap) I.trace[st.iters] = st.nb_iter;
-            st.iters += 1;
-            const int p = st.prev;
-            st.prev = st.cur;
-            st.cur = st.nxt;
-            st.nxt = p;
-            const double t = st.t;
-            const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-            st.t_prev = t;
-            st.t = tn;
-            st.m = (t - 1.0) / tn;
-            st.phase = PH_GRAD_READY;
-        } else {
-            st.L = 2.0 * st.L;
-            st.bt += 1;
-            st.nb_iter += 1;
-            st.phase = PH_RETRY;
-            compute = false;
-            if (st.nb_iter > 200) {
-                st.done = 1;
-                st.status = ST_NONFINITE;
-            }
-        }
-    } else {
-        st.phase = PH_GRAD_READY;
+    const bool trialed = st.phase == PH_TRIALED;
+    Partials pv;
+    if (trialed) pv = partials_issue(I.pB, I.nb);
+    // the point of the next gradient if the trial is accepted (at the start: the current one)
+    int cur = st.cur, prev = st.prev;
+    double mnext = st.m, tnext = st.t;
+    if (trialed) {
+        cur = st.nxt;
+        prev = st.cur;
+        tnext = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.t * st.t));
+        mnext = (st.t - 1.0) / tnext;
     }
-    if (writer) put_state(&sout[ii], st);
-    if (!compute) return;
 
-    constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
-    constexpr int VP = tv_pitch(), VR = tv_rows(R);
+    constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
+    constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
+    const int nw = reg == 1 ? C : 1;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW;
-    const int tile = xcd_tile(lb, I.nb);
-    const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
+    int ti0, tj0, ch;
+    tile_pos<R>(I.pr, lb, I.nb, ti0, tj0, ch);
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
-    const T m = (T)st.m;
+    const T m = (T)mnext;
     const T alpha = (T)I.pr.alpha;
-    const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], st.cur);
-    const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
-    const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], st.cur);
-    const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], st.prev);
-    const T* __restrict__ Y = I.y;
+    const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], cur);
+    const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], prev);
+    const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], cur) + ch * HW;
+    const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], prev) + ch * HW;
+    const T* __restrict__ Yc = I.y + ch * HW;
 
-    // ---- TV gradient at v (all channels staged: the magnitude couples them)
+    // stage v for every channel (the TV magnitude couples them) and the data
+    // residual theta*v - y of this block's channel
+    constexpr bool SEQ = seq_lds(K);
     T* s_v = sm;
-    T* s_w = sm + C * VR * VP;
-    __syncthreads();
-    for (int ch = 0; ch < C; ++ch) {
-        const T* Xc = X + ch * HW;
-        const T* XPc = XP + ch * HW;
-        load_tile<VR, VP, VP>(s_v + ch * VR * VP, ti0 - 1, tj0 - 1, H, W,
+    T* s_w = s_v + C * VR * VP;
+    T* s_c = SEQ ? sm : s_w + nw * WR * WP;
+    auto stage_residual = [&]() {
+        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) {
+            const T kx = KX[g];
+            return dfma(m, kx - KXP[g], kx) - Yc[g];
+        });
+    };
+    for (int c = 0; c < C; ++c) {
+        const T* Xc = X + c * HW;
+        const T* XPc = XP + c * HW;
+        load_tile<VR, VP, VP>(s_v + c * VR * VP, ti0 - 1, tj0 - 1, H, W,
                               [&](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); });
     }
+    // the backtracking decision; large kernels take it before their
+    // convolution (occupancy first), small ones after it (latency first)
+    bool compute = true;
+    auto decide = [&]() {
+        if (trialed) {
+            const double delta = partials_finish(I.pB, I.nb, pv);
+            st.delta_last = delta;
+            if (!finite_d(delta)) {
+                st.done = 1;
+                st.status = ST_NONFINITE;
+                compute = false;
+            } else if (delta <= -st.gn2 / (2.0 * st.L)) {
+                if (writer && I.trace && st.iters < st.trace_cap) I.trace[st.iters] = st.nb_iter;
+                st.iters += 1;
+                st.nxt = st.prev;
+                st.prev = st.cur;
+                st.cur = cur;
+                st.t_prev = st.t;
+                st.t = tnext;
+                st.m = mnext;
+                st.phase = PH_GRAD_READY;
+            } else {
+                st.L = 2.0 * st.L;
+                st.bt += 1;
+                st.nb_iter += 1;
+                st.phase = PH_RETRY;
+                compute = false;
+                if (st.nb_iter > 200) {
+                    st.done = 1;
+                    st.status = ST_NONFINITE;
+                }
+            }
+        } else {
+            st.phase = PH_GRAD_READY;
+        }
+        if (writer) put_state(&sout[ii], st);
+    };
+    if (!SEQ) stage_residual();
     __syncthreads();
+    if (SEQ) {
+        decide();
+        if (!compute) return;
+    }
     tv_weights<T, R>(s_v, s_w, C, reg, (T)(I.pr.eps_tv * I.pr.eps_tv), ti0, tj0, H, W);
+    T acc[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) acc[o] = T(0);
+    if (!SEQ) correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
     __syncthreads();
-    T tg0[R], tg1[R], tg2[R];
+    // SEQ: the TV gradient waits in LDS past the tile region while the
+    // convolution tile reuses it (registers stay with the convolution)
+    T* s_park = sm + cmax(C * VR * VP + nw * WR * WP, lds_conv(K, R));
+    T tg[SEQ ? 1 : R];
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int li = li0 + o, gi = ti0 + li;
-        tg0[o] = tv_grad_px<T, R>(s_v, s_w, 0, reg, li, tx, gi, gj, H, W);
-        tg1[o] = C > 1 ? tv_grad_px<T, R>(s_v, s_w, 1, reg, li, tx, gi, gj, H, W) : T(0);
-        tg2[o] = C > 2 ? tv_grad_px<T, R>(s_v, s_w, 2, reg, li, tx, gi, gj, H, W) : T(0);
+        const T g = tv_grad_px<T, R>(s_v, s_w, ch, reg, li, tx, gi, gj, H, W);
+        if constexpr (SEQ) s_park[o * kNT + threadIdx.x] = g;
+        else tg[o] = g;
     }
+    if (SEQ) {
+        __syncthreads();
+        stage_residual();
+        __syncthreads();
+        correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+    }
+    T gv[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) gv[o] = dfma(alpha, SEQ ? s_park[o * kNT + threadIdx.x] : tg[SEQ ? 0 : o], acc[o]);
 
-    // ---- data term: theta . r_v, channel by channel
+    if (!SEQ) {
+        decide();
+        if (!compute) return;
+    }
     double gsq = 0.0;
-    for (int ch = 0; ch < C; ++ch) {
-        const T* KXc = KX + ch * HW;
-        const T* KXPc = KXP + ch * HW;
-        const T* Yc = Y + ch * HW;
-        __syncthreads();
-        load_tile<CR, CP, CP>(sm, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) {
-            const T kx = KXc[g];
-            return dfma(m, kx - KXPc[g], kx) - Yc[g];
-        });
-        __syncthreads();
-        T acc[R];
+    T* __restrict__ G = I.G + ch * HW;
 #pragma unroll
-        for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(sm, CP, I.th, li0, tx, acc);
-#pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int gi = ti0 + li0 + o;
-            if (gi < H && gj < W) {
-                const T gv = dfma(alpha, pick3<T, R>(tg0, tg1, tg2, ch, o), acc[o]);
-                I.G[ch * HW + (int64_t)gi * W + gj] = gv;
-                gsq += (double)gv * (double)gv;
-            }
+    for (int o = 0; o < R; ++o) {
+        const int gi = ti0 + li0 + o;
+        if (gi < H && gj < W) {
+            G[(int64_t)gi * W + gj] = gv[o];
+            gsq += (double)gv[o] * (double)gv[o];
         }
     }
     block_partial(gsq, I.pA, lb);
@@ -395,9 +468,10 @@ __global__ __launch_bounds__(kNT) void k_apg_grad(const Inst<T>* __restrict__ in
 //   data: sum d (r_v + d/2), d = theta*dl;
 //   TV:   sum_sites (s'^2 - s^2) / (sqrt(s'^2+eps^2) + sqrt(s^2+eps^2)),
 //         s'^2 - s^2 = sum a (a + 2 b), a = D dl, b = D v,
-// with every per-element product in double.
+// with every per-element product in double.  The TV part couples the
+// channels; each of a tile's channel blocks takes a share of its rows.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                    const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
     MAID_STENCIL_PROLOGUE
     ApgState st = sin[ii];
@@ -406,9 +480,38 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Inst<T>* __restrict__ i
         if (writer) put_state(&sout[ii], st);
         return;
     }
+    const bool fresh = st.phase == PH_GRAD_READY;
+    Partials pv;
+    if (fresh) pv = partials_issue(I.pA, I.nb);
+
+    constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
+    const int64_t HW = (int64_t)H * W;
+    int ti0, tj0, ch;
+    tile_pos<R>(I.pr, lb, I.nb, ti0, tj0, ch);
+    const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
+    const int gj = tj0 + tx;
+    const T m = (T)st.m;
+    const T ninvL = (T)(-1.0 / st.L);
+    const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], st.cur);
+    const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
+    const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], st.cur);
+    const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], st.prev);
+    T* __restrict__ XN = pick(I.X[0], I.X[1], I.X[2], st.nxt);
+    T* __restrict__ KXN = pick(I.KX[0], I.KX[1], I.KX[2], st.nxt);
+    const T* __restrict__ G = I.G;
+    const T* __restrict__ Y = I.y;
+
+    T* s_c = sm;
+    const T* Gc = G + ch * HW;
+    load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return Gc[g] * ninvL; });
+    __syncthreads();
+
     bool trial = true;
-    if (st.phase == PH_GRAD_READY) {
-        const double gn2 = reduce_partials(I.pA, I.nb);
+    if (fresh) {
+        const double gn2 = partials_finish(I.pA, I.nb, pv);
         st.gn2 = gn2;
         st.nb_iter = 0;
         if (!finite_d(gn2)) {
@@ -429,101 +532,64 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Inst<T>* __restrict__ i
     if (writer) put_state(&sout[ii], st);
     if (!trial) return;
 
-    constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
-    constexpr int VP = tv_pitch(), VR = tv_rows(R);
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
-    const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
-    const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW;
-    const int tile = xcd_tile(lb, I.nb);
-    const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
-    const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
-    const int gj = tj0 + tx;
-    const T m = (T)st.m;
-    const T ninvL = (T)(-1.0 / st.L);
-    const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], st.cur);
-    const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
-    const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], st.cur);
-    const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], st.prev);
-    T* __restrict__ XN = pick(I.X[0], I.X[1], I.X[2], st.nxt);
-    T* __restrict__ KXN = pick(I.KX[0], I.KX[1], I.KX[2], st.nxt);
-    const T* __restrict__ G = I.G;
-    const T* __restrict__ Y = I.y;
-
-    T* s_v = sm;
-    T* s_d = sm + C * VR * VP;
-    T* s_c = sm + 2 * C * VR * VP;
-    __syncthreads();
-    for (int ch = 0; ch < C; ++ch) {
-        const T* Xc = X + ch * HW;
-        const T* XPc = XP + ch * HW;
-        const T* Gc = G + ch * HW;
-        load_tile<VR, VP, VP>(s_v + ch * VR * VP, ti0 - 1, tj0 - 1, H, W,
-                              [&](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); });
-        load_tile<VR, VP, VP>(s_d + ch * VR * VP, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return Gc[g] * ninvL; });
-    }
-    __syncthreads();
-
-    // ---- TV part of the decrease, per site
+    // ---- TV part of the decrease, per site: the tile's rows are dealt to its
+    // channel blocks in turn; v and dl come from global memory (L1/L2)
     const double e2 = I.pr.eps_tv * I.pr.eps_tv;
     double dtv = 0.0;
+    {
+#pragma unroll
+        for (int o = 0; o < R; ++o) {
+            const int li = li0 + o, gi = ti0 + li;
+            if (li % C == ch && gi < H && gj < W) {
+                const int64_t e = (int64_t)gi * W + gj;
+                const bool hx = gj < W - 1, vx = gi < H - 1;
+                double ds2 = 0.0, s2 = 0.0;
+                for (int c = 0; c < C; ++c) {
+                    const T* Xc = X + c * HW;
+                    const T* XPc = XP + c * HW;
+                    const T* Gcc = G + c * HW;
+                    auto vat = [&](int64_t f) { const T xv = Xc[f]; return dfma(m, xv - XPc[f], xv); };
+                    const T v0 = vat(e), d0 = Gcc[e] * ninvL;
+                    const double bh = hx ? (double)(vat(e + 1) - v0) : 0.0;
+                    const double bv = vx ? (double)(vat(e + W) - v0) : 0.0;
+                    const double ah = hx ? (double)(Gcc[e + 1] * ninvL - d0) : 0.0;
+                    const double av = vx ? (double)(Gcc[e + W] * ninvL - d0) : 0.0;
+                    if (reg == 2) {
+                        ds2 += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
+                    } else if (reg == 1) {
+                        const double d2 = ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
+                        const double q2 = bh * bh + bv * bv;
+                        dtv += d2 / (sqrt(q2 + d2 + e2) + sqrt(q2 + e2));
+                    } else {
+                        ds2 += ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
+                        s2 += bh * bh + bv * bv;
+                    }
+                }
+                if (reg == 2) dtv += ds2;
+                else if (reg == 0) dtv += ds2 / (sqrt(s2 + ds2 + e2) + sqrt(s2 + e2));
+            }
+        }
+    }
+
+    // ---- data part of this block's channel, and the new iterate
+    T acc[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) acc[o] = T(0);
+    correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
+    double ddat = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int li = li0 + o, gi = ti0 + li;
         if (gi < H && gj < W) {
-            const int idx = (li + 1) * VP + tx + 1;
-            const bool hx = gj < W - 1, vx = gi < H - 1;
-            double ds2 = 0.0, s2 = 0.0;
-            for (int ch = 0; ch < C; ++ch) {
-                const T* V = s_v + ch * VR * VP;
-                const T* D = s_d + ch * VR * VP;
-                const double bh = hx ? (double)(V[idx + 1] - V[idx]) : 0.0;
-                const double bv = vx ? (double)(V[idx + VP] - V[idx]) : 0.0;
-                const double ah = hx ? (double)(D[idx + 1] - D[idx]) : 0.0;
-                const double av = vx ? (double)(D[idx + VP] - D[idx]) : 0.0;
-                if (reg == 2) {
-                    ds2 += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
-                } else if (reg == 1) {
-                    const double d2 = ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
-                    const double q2 = bh * bh + bv * bv;
-                    dtv += d2 / (sqrt(q2 + d2 + e2) + sqrt(q2 + e2));
-                } else {
-                    ds2 += ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
-                    s2 += bh * bh + bv * bv;
-                }
-            }
-            if (reg == 2) dtv += ds2;
-            else if (reg == 0) dtv += ds2 / (sqrt(s2 + ds2 + e2) + sqrt(s2 + e2));
-        }
-    }
-
-    // ---- data part, and the new iterate
-    double ddat = 0.0;
-    for (int ch = 0; ch < C; ++ch) {
-        const T* Gc = G + ch * HW;
-        __syncthreads();
-        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return Gc[g] * ninvL; });
-        __syncthreads();
-        T acc[R];
-#pragma unroll
-        for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
-        const T* V = s_v + ch * VR * VP;
-#pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int li = li0 + o, gi = ti0 + li;
-            if (gi < H && gj < W) {
-                const int64_t e = ch * HW + (int64_t)gi * W + gj;
-                const T kx = KX[e];
-                const T kv = dfma(m, kx - KXP[e], kx);
-                const T d = acc[o];
-                const double rv = (double)kv - (double)Y[e];
-                ddat += (double)d * (rv + 0.5 * (double)d);
-                const int idx = (li + 1) * VP + tx + 1;
-                XN[e] = V[idx] + s_d[ch * VR * VP + idx];
-                KXN[e] = kv + d;
-            }
+            const int64_t e = ch * HW + (int64_t)gi * W + gj;
+            const T kx = KX[e];
+            const T kv = dfma(m, kx - KXP[e], kx);
+            const T d = acc[o];
+            const double rv = (double)kv - (double)Y[e];
+            ddat += (double)d * (rv + 0.5 * (double)d);
+            const T xv = X[e];
+            XN[e] = dfma(m, xv - XP[e], xv) + s_c[(li + c0) * CP + tx + c0];
+            KXN[e] = kv + d;
         }
     }
     block_partial(ddat + I.pr.alpha * dtv, I.pB, lb);
@@ -532,7 +598,7 @@ __global__ __launch_bounds__(kNT) void k_apg_trial(const Inst<T>* __restrict__ i
 // xout = v = x + m (x - x_prev): the point that passed the stop test
 // (instances whose solve failed are left untouched).
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                    const ApgState* __restrict__ sin) {
     MAID_EW_PROLOGUE
     const ApgState st = sin[ii];
@@ -552,11 +618,12 @@ __global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ i
 // gamma = ||r||^2 from the partials of the update (or set-up) pass, applies
 // the stop tests (sqrt(gamma) <= tol; iteration cap), then forms
 // p_new = r + beta p_old (p_new = r on the first iteration, beta =
-// gamma / gamma_prev) and Kp = theta*p_new.  init = 1: the set-up call that
-// only copies r (holding q0) into p and forms theta*q0, without touching the
-// state.
+// gamma / gamma_prev) and Kp = theta*p_new.  r and p_old are staged while the
+// partials are in flight and combined once beta is known.  init = 1: the
+// set-up call that only copies r (holding q0) into p and forms theta*q0,
+// without touching the state.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                 const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
     MAID_STENCIL_PROLOGUE
     CgState st = sin[ii];
@@ -565,9 +632,30 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
         if (writer && !init) put_state(&sout[ii], st);
         return;
     }
+    Partials pv;
+    if (!init) pv = partials_issue(I.pR, I.nbe);
+    constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* s = reinterpret_cast<T*>(smem_raw);
+    constexpr bool SEQ = seq_lds(K);   // SEQ: stage r + beta p once beta is known
+    T* s_p = s + lds_conv(K, R);
+    const int H = I.pr.H, W = I.pr.W;
+    const int64_t HW = (int64_t)H * W;
+    int ti0, tj0, ch;
+    tile_pos<R>(I.pr, lb, I.nb, ti0, tj0, ch);
+    const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
+    const int gj = tj0 + tx;
+    const T* __restrict__ Pold = pick(I.P[0], I.P[1], st.pc) + ch * HW;
+    T* __restrict__ Pnew = pick(I.P[0], I.P[1], st.pc ^ 1) + ch * HW;
+    const T* __restrict__ rc = I.r + ch * HW;
+    const bool with_p = !init && !st.first;
+    if (!SEQ) {
+        load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return rc[g]; });
+        if (with_p) load_tile<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return Pold[g]; });
+    }
     double beta = 0.0;
     if (!init) {
-        const double g = reduce_partials(I.pR, I.nbe);
+        const double g = partials_finish(I.pR, I.nbe, pv);
         if (st.first) {
             st.first = 0;
         } else {
@@ -587,40 +675,30 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
         if (writer) put_state(&sout[ii], st);
         if (st.done) return;
     }
-    constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* s = reinterpret_cast<T*>(smem_raw);
-    const int C = I.pr.C, H = I.pr.H, W = I.pr.W;
-    const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW;
-    const int tile = xcd_tile(lb, I.nb);
-    const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
-    const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
-    const int gj = tj0 + tx;
-    const T bT = (T)beta;
-    const T* __restrict__ Pold = pick(I.P[0], I.P[1], st.pc);
-    T* __restrict__ Pnew = pick(I.P[0], I.P[1], st.pc ^ 1);
-    for (int ch = 0; ch < C; ++ch) {
-        const T* rc = I.r + ch * HW;
-        const T* pc = Pold + ch * HW;
-        __syncthreads();
-        if (beta == 0.0)
-            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return rc[g]; });
+    if (SEQ) {
+        const T bT = (T)beta;
+        if (with_p)
+            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return dfma(bT, Pold[g], rc[g]); });
         else
-            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return dfma(bT, pc[g], rc[g]); });
+            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return rc[g]; });
+    } else if (with_p) {
         __syncthreads();
-        T acc[R];
+        const T bT = (T)beta;
+        for (int idx = threadIdx.x; idx < CR * CP; idx += kNT) s[idx] = dfma(bT, s_p[idx], s[idx]);
+    }
+    __syncthreads();
+    T acc[R];
 #pragma unroll
-        for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s, CP, I.thf, li0, tx, acc);
+    for (int o = 0; o < R; ++o) acc[o] = T(0);
+    correlate<T, K, R>(s, CP, I.thf, li0, tx, acc);
+    T* __restrict__ Kp = I.Kp + ch * HW;
 #pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int li = li0 + o, gi = ti0 + li;
-            if (gi < H && gj < W) {
-                const int64_t e = ch * HW + (int64_t)gi * W + gj;
-                Pnew[e] = s[(li + c0) * CP + tx + c0];
-                I.Kp[e] = acc[o];
-            }
+    for (int o = 0; o < R; ++o) {
+        const int li = li0 + o, gi = ti0 + li;
+        if (gi < H && gj < W) {
+            const int64_t e = (int64_t)gi * W + gj;
+            Pnew[e] = s[(li + c0) * CP + tx + c0];
+            Kp[e] = acc[o];
         }
     }
 }
@@ -630,38 +708,44 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
 // grad^2 R(x)[p] = D^T (w Dp - w^3 m Dx), m = <Dx, Dp> over the coupled
 // channels.  init = 1 computes H q0 only.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                 const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
     MAID_STENCIL_PROLOGUE
     const CgState st = sin[ii];
     if (!init && lb == 0 && threadIdx.x == 0) put_state(&sout[ii], st);
     if (st.done) return;
-    constexpr int TH = tile_h(R), c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
+    constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const int C = I.pr.C, H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
-    const int nw = reg == 1 ? C : 1;
     const int64_t HW = (int64_t)H * W;
-    const int ntx = (W + kTW - 1) / kTW;
-    const int tile = xcd_tile(lb, I.nb);
-    const int ti0 = (tile / ntx) * TH, tj0 = (tile % ntx) * kTW;
+    int ti0, tj0, ch;
+    tile_pos<R>(I.pr, lb, I.nb, ti0, tj0, ch);
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const int gj = tj0 + tx;
     const T alpha = (T)I.pr.alpha;
     const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
 
-    T* s_x = sm;
-    T* s_p = sm + C * VR * VP;
-    T* s_w = sm + 2 * C * VR * VP;
-    T* s_mw = s_w + nw * WR * WP;
-    for (int ch = 0; ch < C; ++ch) {
+    // LDS: x and p of this block's channel with a one-pixel halo, and the
+    // weight planes w, w^3 m of the flux sites; the weights couple the
+    // channels and are formed from global memory (L1/L2-resident neighbours),
+    // which keeps the footprint independent of C.
+    constexpr bool SEQ = seq_lds(K);
+    T* s_c = sm;
+    T* s_x = SEQ ? sm : s_c + lds_conv(K, R);
+    T* s_p = s_x + VR * VP;
+    T* s_w = s_p + VR * VP;
+    T* s_mw = s_w + WR * WP;
+    const T* kc = I.Kp + ch * HW;
+    auto stage_kp = [&]() { load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return kc[g]; }); };
+    if (!SEQ) stage_kp();
+    {
         const T* xc = I.xt + ch * HW;
         const T* pc = P + ch * HW;
-        load_tile<VR, VP, VP>(s_x + ch * VR * VP, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return xc[g]; });
-        load_tile<VR, VP, VP>(s_p + ch * VR * VP, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return pc[g]; });
+        load_tile<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return xc[g]; });
+        load_tile<VR, VP, VP>(s_p, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return pc[g]; });
     }
-    __syncthreads();
     const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
     for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
         const int r = idx / WP, cc = idx - r * WP;
@@ -669,86 +753,85 @@ __global__ __launch_bounds__(kNT) void k_cg_hvp(const Inst<T>* __restrict__ inst
         const bool in = (gi >= 0 && gi < H && gj2 >= 0 && gj2 < W);
         const bool hx = gj2 < W - 1, vx = gi < H - 1;
         T s2 = T(0), mm = T(0);
-        for (int ch = 0; ch < C; ++ch) {
-            const T* Xv = s_x + ch * VR * VP;
-            const T* Pv = s_p + ch * VR * VP;
-            const int i0 = r * VP + cc;
-            const T xh = hx ? Xv[i0 + 1] - Xv[i0] : T(0);
-            const T xv = vx ? Xv[i0 + VP] - Xv[i0] : T(0);
-            const T ph = hx ? Pv[i0 + 1] - Pv[i0] : T(0);
-            const T pv = vx ? Pv[i0 + VP] - Pv[i0] : T(0);
-            if (reg == 1) {
-                const T w = in ? T(1) / dsqrt(xh * xh + xv * xv + eps2) : T(0);
-                s_w[ch * WR * WP + idx] = w;
-                s_mw[ch * WR * WP + idx] = w * w * w * (xh * ph + xv * pv);
-            } else {
+        if (in && reg != 2) {
+            const int64_t e = (int64_t)gi * W + gj2;
+            const int c_lo = reg == 1 ? ch : 0, c_hi = reg == 1 ? ch + 1 : C;
+            for (int c = c_lo; c < c_hi; ++c) {
+                const T* xc = I.xt + c * HW;
+                const T* pc = P + c * HW;
+                const T x0 = xc[e], p0 = pc[e];
+                const T xh = hx ? xc[e + 1] - x0 : T(0);
+                const T xv = vx ? xc[e + W] - x0 : T(0);
+                const T ph = hx ? pc[e + 1] - p0 : T(0);
+                const T pv = vx ? pc[e + W] - p0 : T(0);
                 s2 += xh * xh + xv * xv;
                 mm += xh * ph + xv * pv;
             }
         }
-        if (reg == 0) {
+        if (reg == 2) {
+            s_w[idx] = in ? T(1) : T(0);
+            s_mw[idx] = T(0);
+        } else {
             const T w = in ? T(1) / dsqrt(s2 + eps2) : T(0);
             s_w[idx] = w;
             s_mw[idx] = w * w * w * mm;
-        } else if (reg == 2) {
-            s_w[idx] = in ? T(1) : T(0);
-            s_mw[idx] = T(0);
         }
     }
     __syncthreads();
-    T hv0[R], hv1[R], hv2[R], pp0[R], pp1[R], pp2[R];
+    T acc[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) acc[o] = T(0);
+    if (!SEQ) correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+    const T* Xv = s_x;
+    const T* Pv = s_p;
+    const T* Wt = s_w;
+    const T* Mw = s_mw;
+    // SEQ: the TV term and p of each output wait in LDS past the tile region
+    // while the convolution tile reuses it (registers stay with the convolution)
+    T* s_park = sm + cmax(2 * VR * VP + 2 * WR * WP, lds_conv(K, R));
+    T hvv[SEQ ? 1 : R], pc[SEQ ? 1 : R];
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int li = li0 + o, gi = ti0 + li;
         const int r = li + 1, cc = tx + 1;
-#pragma unroll
-        for (int ch = 0; ch < kMaxC; ++ch) {
-            T hv = T(0), pcen = T(0);
-            if (ch < C) {
-                const T* Xv = s_x + ch * VR * VP;
-                const T* Pv = s_p + ch * VR * VP;
-                const T* Wt = s_w + (reg == 1 ? ch * WR * WP : 0);
-                const T* Mw = s_mw + (reg == 1 ? ch * WR * WP : 0);
-                const int i0 = r * VP + cc;
-                pcen = Pv[i0];
-                const T xh_h = (gj < W - 1) ? Xv[i0 + 1] - Xv[i0] : T(0);
-                const T ph_h = (gj < W - 1) ? Pv[i0 + 1] - Pv[i0] : T(0);
-                const T xv_h = (gi < H - 1) ? Xv[i0 + VP] - Xv[i0] : T(0);
-                const T pv_h = (gi < H - 1) ? Pv[i0 + VP] - Pv[i0] : T(0);
-                const T xh_l = Xv[i0] - Xv[i0 - 1], ph_l = Pv[i0] - Pv[i0 - 1];
-                const T xv_u = Xv[i0] - Xv[i0 - VP], pv_u = Pv[i0] - Pv[i0 - VP];
-                const int f0 = r * WP + cc, fl = f0 - 1, fu = f0 - WP;
-                const T fh_here = Wt[f0] * ph_h - Mw[f0] * xh_h;
-                const T fv_here = Wt[f0] * pv_h - Mw[f0] * xv_h;
-                const T fh_left = Wt[fl] * ph_l - Mw[fl] * xh_l;
-                const T fv_up = Wt[fu] * pv_u - Mw[fu] * xv_u;
-                hv = fh_left - fh_here + fv_up - fv_here;
-            }
-            if (ch == 0) { hv0[o] = hv; pp0[o] = pcen; }
-            if (ch == 1) { hv1[o] = hv; pp1[o] = pcen; }
-            if (ch == 2) { hv2[o] = hv; pp2[o] = pcen; }
+        const int i0 = r * VP + cc;
+        const T xh_h = (gj < W - 1) ? Xv[i0 + 1] - Xv[i0] : T(0);
+        const T ph_h = (gj < W - 1) ? Pv[i0 + 1] - Pv[i0] : T(0);
+        const T xv_h = (gi < H - 1) ? Xv[i0 + VP] - Xv[i0] : T(0);
+        const T pv_h = (gi < H - 1) ? Pv[i0 + VP] - Pv[i0] : T(0);
+        const T xh_l = Xv[i0] - Xv[i0 - 1], ph_l = Pv[i0] - Pv[i0 - 1];
+        const T xv_u = Xv[i0] - Xv[i0 - VP], pv_u = Pv[i0] - Pv[i0 - VP];
+        const int f0 = r * WP + cc, fl = f0 - 1, fu = f0 - WP;
+        const T fh_here = Wt[f0] * ph_h - Mw[f0] * xh_h;
+        const T fv_here = Wt[f0] * pv_h - Mw[f0] * xv_h;
+        const T fh_left = Wt[fl] * ph_l - Mw[fl] * xh_l;
+        const T fv_up = Wt[fu] * pv_u - Mw[fu] * xv_u;
+        const T hv = fh_left - fh_here + fv_up - fv_here;
+        if constexpr (SEQ) {
+            s_park[o * kNT + threadIdx.x] = hv;
+            s_park[(R + o) * kNT + threadIdx.x] = Pv[i0];
+        } else {
+            hvv[o] = hv;
+            pc[o] = Pv[i0];
         }
     }
-
+    if (SEQ) {
+        __syncthreads();
+        stage_kp();
+        __syncthreads();
+        correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+    }
     double kap = 0.0;
-    for (int ch = 0; ch < C; ++ch) {
-        const T* kc = I.Kp + ch * HW;
-        __syncthreads();
-        load_tile<CR, CP, CP>(sm, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return kc[g]; });
-        __syncthreads();
-        T acc[R];
+    T* __restrict__ Hp = I.Hp + ch * HW;
 #pragma unroll
-        for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(sm, CP, I.th, li0, tx, acc);
-#pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int gi = ti0 + li0 + o;
-            if (gi < H && gj < W) {
-                const int64_t e = ch * HW + (int64_t)gi * W + gj;
-                const T hp = dfma(alpha, pick3<T, R>(hv0, hv1, hv2, ch, o), acc[o]);
-                I.Hp[e] = hp;
-                kap += (double)pick3<T, R>(pp0, pp1, pp2, ch, o) * (double)hp;
-            }
+    for (int o = 0; o < R; ++o) {
+        const int gi = ti0 + li0 + o;
+        if (gi < H && gj < W) {
+            const T hv = SEQ ? s_park[o * kNT + threadIdx.x] : hvv[SEQ ? 0 : o];
+            const T pp = SEQ ? s_park[(R + o) * kNT + threadIdx.x] : pc[SEQ ? 0 : o];
+            const T hp = dfma(alpha, hv, acc[o]);
+            Hp[(int64_t)gi * W + gj] = hp;
+            kap += (double)pp * (double)hp;
         }
     }
     if (!init) block_partial(kap, I.pK, lb);
@@ -756,9 +839,10 @@ __global__ __launch_bounds__(kNT) void k_cg_hvp(const Inst<T>* __restrict__ inst
 
 // Update pass.  Per instance: reads sin, block 0 writes sout.  Finishes the
 // curvature kappa = <p,Hp> (not positive: MAID_NOT_SPD), a = gamma/kappa,
-// then q += a p, r -= a Hp and per-block partials of ||r||^2.
+// then q += a p, r -= a Hp and per-block partials of ||r||^2.  The first
+// element of every thread is loaded while the partials are in flight.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                    const CgState* __restrict__ sin, CgState* __restrict__ sout) {
     MAID_EW_PROLOGUE
     CgState st = sin[ii];
@@ -767,7 +851,20 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
         if (writer) put_state(&sout[ii], st);
         return;
     }
-    const double kappa = reduce_partials(I.pK, I.nb);
+    const Partials pv = partials_issue(I.pK, I.nb);
+    const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
+    T* __restrict__ q = I.q;
+    T* __restrict__ r = I.r;
+    const T* __restrict__ Hp = I.Hp;
+    const int64_t e0 = (int64_t)lb * kNT + threadIdx.x, stride = (int64_t)I.nbe * kNT;
+    T p0 = T(0), q0 = T(0), r0 = T(0), h0 = T(0);
+    if (e0 < I.N) {
+        p0 = P[e0];
+        q0 = q[e0];
+        r0 = r[e0];
+        h0 = Hp[e0];
+    }
+    const double kappa = partials_finish(I.pK, I.nb, pv);
     st.kappa = kappa;
     if (!(kappa > 0.0) || !finite_d(kappa)) {
         st.done = 1;
@@ -775,19 +872,21 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
         if (writer) put_state(&sout[ii], st);
         return;
     }
-    const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
     st.a = st.gamma / kappa;
     st.iters += 1;
     st.pc ^= 1;
     if (writer) put_state(&sout[ii], st);
     const T a = (T)st.a;
-    T* __restrict__ q = I.q;
-    T* __restrict__ r = I.r;
-    const T* __restrict__ Hp = I.Hp;
     double rs = 0.0;
-    for (int64_t e = (int64_t)lb * kNT + threadIdx.x; e < I.N; e += (int64_t)I.nbe * kNT) {
-        const T pv = P[e];
-        q[e] = dfma(a, pv, q[e]);
+    if (e0 < I.N) {
+        q[e0] = dfma(a, p0, q0);
+        const T rv = dfma(-a, h0, r0);
+        r[e0] = rv;
+        rs += (double)rv * (double)rv;
+    }
+    for (int64_t e = e0 + stride; e < I.N; e += stride) {
+        const T pe = P[e];
+        q[e] = dfma(a, pe, q[e]);
         const T rv = dfma(-a, Hp[e], r[e]);
         r[e] = rv;
         rs += (double)rv * (double)rv;
@@ -797,7 +896,7 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
 
 // r = b - H q0 (Hp holds H q0) and per-block partials of ||r||^2.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_init(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kNT) void k_cg_init(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                  const CgState* __restrict__ sin) {
     MAID_EW_PROLOGUE
     if (sin[ii].done) return;

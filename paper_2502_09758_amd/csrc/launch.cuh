@@ -20,7 +20,7 @@ static hipError_t conv_kr(const Group& g, const Inst<T>* insts, hipStream_t s) {
     auto kern = k_conv<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk);
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only);
 }
 
 template <typename T, int K, int R>
@@ -29,7 +29,7 @@ static hipError_t apg_grad_kr(const Group& g, const Inst<T>* insts, const ApgSta
     auto kern = k_apg_grad<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout);
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout);
 }
 
 template <typename T, int K, int R>
@@ -38,17 +38,17 @@ static hipError_t apg_trial_kr(const Group& g, const Inst<T>* insts, const ApgSt
     auto kern = k_apg_trial<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout);
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout);
 }
 
 template <typename T, int K, int R>
 static hipError_t cg_dir_kr(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init,
                             hipStream_t s) {
-    const size_t lds = sizeof(T) * lds_conv(K, R);
+    const size_t lds = sizeof(T) * lds_cg_dir(K, R);
     auto kern = k_cg_dir<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout, init);
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout, init);
 }
 
 template <typename T, int K, int R>
@@ -58,7 +58,7 @@ static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState*
     auto kern = k_cg_hvp<T, K, R>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, sin, sout, init);
+    return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout, init);
 }
 
 #define MAID_R_DISPATCH(FN, ...)                                   \

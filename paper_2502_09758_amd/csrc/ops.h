@@ -16,8 +16,9 @@ struct Shape {
     int C, H, W, K, reg;
 };
 
+// blocks of one stencil pass: one per tile and channel
 inline int stencil_blocks(const Shape& d, int R) {
-    return ((d.W + kTW - 1) / kTW) * ((d.H + tile_h(R) - 1) / tile_h(R));
+    return ((d.W + kTW - 1) / kTW) * ((d.H + tile_h(R) - 1) / tile_h(R)) * d.C;
 }
 
 inline bool valid_rows(int R) { return R == 1 || R == 2 || R == 4; }
@@ -46,6 +47,7 @@ struct Group {
     int C, nw;         // LDS sizing: most channels and TV-weight planes in the group
     int grid;          // blocks of one pass over the group
     const int* blk;    // device map, grid entries
+    int only;          // the instance index if the group has one instance, else -1
 };
 
 template <typename T> struct Ops {
@@ -54,12 +56,14 @@ template <typename T> struct Ops {
     static hipError_t conv(const Group& g, const Inst<T>* insts, hipStream_t s);
     static hipError_t apg_grad(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
     static hipError_t apg_trial(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
-    static hipError_t apg_final(int grid_e, const int* blk_e, const Inst<T>* insts, const ApgState* sin, hipStream_t s);
+    static hipError_t apg_final(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const ApgState* sin,
+                                hipStream_t s);
     static hipError_t cg_dir(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);
     static hipError_t cg_hvp(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);
-    static hipError_t cg_update(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, CgState* sout,
-                                hipStream_t s);
-    static hipError_t cg_init(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, hipStream_t s);
+    static hipError_t cg_update(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const CgState* sin,
+                                CgState* sout, hipStream_t s);
+    static hipError_t cg_init(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const CgState* sin,
+                              hipStream_t s);
     static hipError_t hg_corr(const Shape& d, const T* rho, const T* q, const T* w, const T* xt, double* part, int nblk,
                               hipStream_t s);
 };

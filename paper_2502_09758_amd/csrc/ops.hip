@@ -100,19 +100,21 @@ hipError_t Ops<T>::cg_hvp(const Group& g, const Inst<T>* insts, const CgState* s
 }
 
 template <typename T>
-hipError_t Ops<T>::apg_final(int grid_e, const int* blk_e, const Inst<T>* insts, const ApgState* sin, hipStream_t s) {
-    return launch(k_apg_final<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
-}
-
-template <typename T>
-hipError_t Ops<T>::cg_update(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, CgState* sout,
+hipError_t Ops<T>::apg_final(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const ApgState* sin,
                              hipStream_t s) {
-    return launch(k_cg_update<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin, sout);
+    return launch(k_apg_final<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, only, sin);
 }
 
 template <typename T>
-hipError_t Ops<T>::cg_init(int grid_e, const int* blk_e, const Inst<T>* insts, const CgState* sin, hipStream_t s) {
-    return launch(k_cg_init<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, sin);
+hipError_t Ops<T>::cg_update(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const CgState* sin,
+                             CgState* sout, hipStream_t s) {
+    return launch(k_cg_update<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, only, sin, sout);
+}
+
+template <typename T>
+hipError_t Ops<T>::cg_init(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const CgState* sin,
+                           hipStream_t s) {
+    return launch(k_cg_init<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, only, sin);
 }
 
 template <typename T>
