@@ -155,6 +155,120 @@ def calibrate_copy(mib: int = 512, reps: int = 5):
                       "launches": reps, "GB_s": round(2 * n * 4 / dt / 1e9, 1)}), flush=True)
 
 
+def inexact_gradient_work(insts, dt, tol_lower=1e-3, tol_cg=1e-3):
+    """Batched against plain at the same accuracy: Algorithm 1's
+    InexactGradient (lower-level solve to tol_lower, upper-level gradient, CG
+    to tol_cg, hypergradient) for every instance of a ragged batch, once
+    through one batched context and once through one plain context per
+    instance (same tile heights, so the same iterations and bitwise the same
+    results).  Pixel-iterations count (lower + CG iterations) x C*H*W."""
+    import torch
+    from paper_2502_09758_amd import _lib as L
+    from paper_2502_09758_amd.maid import Maid, MaidBatch
+
+    specs = [dict(C=i.C, H=i.H, W=i.W, K=i.K, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta) for i in insts]
+    th = [torch.tensor(i.a, dtype=torch.float64, device="cuda") for i in insts]
+    ys = [torch.tensor(i.y, dtype=dt, device="cuda") for i in insts]
+    mb = MaidBatch(specs, dt)
+    rows = mb.autotune(th, ys)
+    solos = []
+    for k, i in enumerate(insts):
+        m = Maid(i.C, i.H, i.W, i.K, dt, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta)
+        m.set_tile_rows(rows[k])
+        solos.append(m)
+    n = len(insts)
+
+    def batched():
+        xs = [y.clone() for y in ys]
+        qs = [torch.zeros_like(y) for y in ys]
+        gs = [torch.empty_like(y) for y in ys]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, li = mb.lower_solve(th, ys, xs, [tol_lower] * n, max_iter=300)
+        mb.upper_value_grad(th, ys, xs, gs)
+        _, ci = mb.adjoint_solve(th, xs, gs, qs, [tol_cg] * n, max_iter=1000)
+        mb.hypergrad(th, th, ys, xs, qs)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, li, ci, xs, qs
+
+    def plain():
+        xs = [y.clone() for y in ys]
+        qs = [torch.zeros_like(y) for y in ys]
+        gs = [torch.empty_like(y) for y in ys]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        li, ci = [], []
+        for k in range(n):
+            li.append(solos[k].lower_solve(th[k], ys[k], xs[k], tol_lower, max_iter=300))
+            solos[k].upper_value_grad(th[k], ys[k], xs[k], gs[k])
+            ci.append(solos[k].adjoint_solve(th[k], xs[k], gs[k], qs[k], tol_cg, max_iter=1000))
+            solos[k].hypergrad(th[k], th[k], ys[k], xs[k], qs[k])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, li, ci, xs, qs
+
+    batched(), plain()                       # graph capture and warm caches
+    tb, lib_, cib, xb, qb = batched()
+    tp, lip, cip, xp, qp = plain()
+    same = all(torch.equal(a, b) for a, b in zip(xb, xp)) and all(torch.equal(a, b) for a, b in zip(qb, qp))
+    work = sum((a.iters + b.iters) * i.C * i.H * i.W for a, b, i in zip(lib_, cib, insts))
+    out = dict(instances=n, pixels=sum(i.C * i.H * i.W for i in insts), tol_lower=tol_lower, tol_cg=tol_cg,
+               lower_iters=sum(a.iters for a in lib_), cg_iters=sum(b.iters for b in cib),
+               batched_ms=round(tb * 1e3, 3), plain_ms=round(tp * 1e3, 3),
+               batched_pixel_iterations_per_s=round(work / tb, 1), plain_pixel_iterations_per_s=round(work / tp, 1),
+               speedup=round(tp / tb, 3), bitwise_equal=bool(same), tiles=mb.config())
+    mb.close()
+    for m in solos:
+        m.close()
+    return out
+
+
+def autograd_work(inst, dt, tol=1e-3, cg_tol=1e-3):
+    """The autograd form (forward: lower-level solve; backward: CG adjoint and
+    the theta correlation) against the same three plain calls, at the same
+    tolerances (bitwise the same iterations)."""
+    import torch
+    from paper_2502_09758_amd.autograd import maid_solve
+    from paper_2502_09758_amd.maid import Maid
+
+    m = Maid(inst.C, inst.H, inst.W, inst.K, dt, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta)
+    th0 = torch.tensor(inst.a, dtype=torch.float64, device="cuda")
+    y = torch.tensor(inst.y, dtype=dt, device="cuda")
+    m.autotune(th0, y)
+    w = torch.ones_like(y)
+
+    def ag():
+        th = th0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = maid_solve(th, y, m, tol=tol, cg_tol=cg_tol, max_iter=300, max_cg=1000)
+        (x * w).sum().backward()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, th.grad
+
+    def plain():
+        x = y.clone()
+        q = torch.zeros_like(y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        li = m.lower_solve(th0, y, x, tol, max_iter=300)
+        ci = m.adjoint_solve(th0, x, w, q, cg_tol * float(w.double().norm()), max_iter=1000)
+        z, _ = m.hypergrad(th0, None, y, x, q, with_r=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, li, ci
+
+    ag(), plain()
+    ta, g = ag()
+    tp, li, ci = plain()
+    N = inst.C * inst.H * inst.W
+    work = (li.iters + ci.iters) * N
+    out = dict(workload=f"{inst.C}x{inst.H}x{inst.W}, K={inst.K}", tol=tol, cg_tol=cg_tol, lower_iters=li.iters,
+               cg_iters=ci.iters, autograd_ms=round(ta * 1e3, 3), plain_ms=round(tp * 1e3, 3),
+               autograd_pixel_iterations_per_s=round(work / ta, 1), plain_pixel_iterations_per_s=round(work / tp, 1),
+               tiles=m.config())
+    m.close()
+    return out
+
+
 def cpu_baseline(inst, budget_s: float = 15.0):
     """The FP64 oracle on the host cores: fixed lower-level (FISTA) and CG
     iterations on the same instance, scaled to pixel-iterations/s."""
@@ -172,8 +286,11 @@ def cpu_baseline(inst, budget_s: float = 15.0):
         O.adjoint_solve(p, inst.a, x, g, tol=0.0, max_iter=n)
         return time.perf_counter() - t0
 
-    t1 = run(1)
-    n = max(2, min(20000, int(budget_s / max(t1, 1e-4) / 2)))
+    # per-iteration cost from two short runs (each run also pays one
+    # upper-level gradient), then one run sized to the budget
+    t10, t40 = run(10), run(40)
+    per_iter = max((t40 - t10) / 30.0, 1e-6)
+    n = max(40, min(100000, int(budget_s / per_iter)))
     t = run(n)
     return dict(value=2 * n * N / t, unit="pixel-iterations/s", cores=O.num_threads(), kind="oracle",
                 sample=f"{n} FISTA + {n} CG iterations (fixed, no backtracking) on the full {inst.C}x{inst.H}x{inst.W} "
@@ -189,6 +306,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-vs-plain comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X (asked for --gpus {args.gpus}).",
@@ -220,6 +339,7 @@ def main():
         return MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=ms["eps0"], delta=ms["eps0"],
                          step=ms["step0"])
 
+    tuned_rows = m.autotune(a, y)
     hp = dict(eps_min=1e-6)
     state = fresh()
     restarts = 0
@@ -305,14 +425,21 @@ def main():
         "config": {"workload": f"{args.workload}: {H}x{W}x{C} piecewise-constant image, {K}x{K} kernel, "
                                f"alpha={inst.alpha:g}, smoothed TV eps={inst.eps_tv:g}, "
                                f"{'FP64' if esz == 8 else 'FP32 storage / FP64 reductions'}, plain MAID",
-                   "eps0": ms["eps0"], "step0": ms["step0"], "tiles": m.config()},
+                   "eps0": ms["eps0"], "step0": ms["step0"], "tiles": m.config(), "autotuned_rows": tuned_rows},
         "roofline": roof,
         "lower_iters": lower, "cg_iters": cg, "accepted_steps": accepted, "psi_trials": trials,
         "maid_restarts": restarts,
         "time_to_hypergrad": tth,
         "kernel_ms": {k: dict(launches=v[0], work=v[1], ms=round(v[2], 3)) for k, v in prof.items()},
     }
+    if not args.no_batch:
+        print("[bench] batched vs plain (64-instance ragged batch)", file=sys.stderr, flush=True)
+        out["batched_vs_plain"] = inexact_gradient_work(synth.make_batch(), torch.float32)
+    if not args.no_autograd:
+        print("[bench] autograd vs plain (512x512x3, K=15)", file=sys.stderr, flush=True)
+        out["autograd_vs_plain"] = autograd_work(synth.make("cfg3"), torch.float32)
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(out), flush=True)
 

@@ -120,9 +120,19 @@ const char* maid_last_error(const maid_ctx* ctx);
 /* Name of the tile configuration (rows per thread) chosen for each group of
    instances. */
 const char* maid_config_string(const maid_ctx* ctx);
-/* Override the rows-per-thread tile parameter of the stencil kernels
-   (1, 2 or 4; 0 = automatic).  Used by the autotuner. */
+/* Override the rows-per-thread tile parameter of the stencil kernels for
+   every instance (1, 2 or 4; 0 = back to the autotuner's choice, else the
+   size rule). */
 int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
+/* Autotuner: for each group of instances with the same K, time a short
+   lower-level solve and a short CG solve (probe_iters iterations each,
+   1..1000, tolerance 0) with every rows-per-thread candidate (1, 2, 4) on
+   the caller's data (theta[i], y[i]: HOST arrays of n DEVICE pointers, as
+   for the batched calls; only workspace is written) and keep the fastest.
+   rows_out (HOST, n, nullable): the choice per instance.  A later
+   maid_set_tile_rows(ctx, r != 0) overrides the choice. */
+int maid_autotune(maid_ctx* ctx, const void* const* theta, const void* const* y, int32_t probe_iters,
+                  int32_t* rows_out, hipStream_t stream);
 
 /* Algorithm 1, lower-level solve: accelerated gradient (FISTA) with
    backtracking (factor 2) on min_x h(x;theta).  Each iteration evaluates
@@ -213,6 +223,17 @@ int maid_batch_lower_solve(maid_ctx* ctx, const void* const* theta, const void* 
 int maid_batch_adjoint_solve(maid_ctx* ctx, const void* const* theta, const void* const* x_tilde,
                              const void* const* rhs, void* const* q, const double* tol,
                              int32_t max_iter, maid_solve_info* info, hipStream_t stream);
+/* maid_upper_value_grad for every instance i: a[i], y[i], x[i], grad_out[i]
+   (grad_out nullable, or any of its entries NULL), g_out[i] and
+   gradnorm_out[i] (HOST arrays of n, nullable). */
+int maid_batch_upper_value_grad(maid_ctx* ctx, const void* const* a, const void* const* y,
+                                const void* const* x, void* const* grad_out, double* g_out,
+                                double* gradnorm_out, hipStream_t stream);
+/* maid_hypergrad for every instance i: z[i] (DEVICE, K_i*K_i doubles),
+   znorm_out[i] (HOST array of n, nullable); a may be NULL when with_r == 0. */
+int maid_batch_hypergrad(maid_ctx* ctx, const void* const* theta, const void* const* a,
+                         const void* const* y, const void* const* x_tilde, const void* const* q,
+                         int32_t with_r, void* const* z, double* znorm_out, hipStream_t stream);
 /* maid_step for every instance i (one outer iteration of Algorithm 2 each,
    run in lockstep: the lower-level, CG and trial solves of all instances
    that need one at the same point of the algorithm share launches); one set

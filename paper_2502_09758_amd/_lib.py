@@ -27,7 +27,7 @@ EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string
            "maid_adjoint_solve", "maid_hypergrad", "maid_apply_operator", "maid_sobolev_value", "maid_step",
            "maid_profile", "maid_profile_read", "maid_profile_name",
            "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
-           "maid_batch_step")
+           "maid_batch_step", "maid_autotune", "maid_batch_upper_value_grad", "maid_batch_hypergrad")
 PROF_KINDS = 8
 
 
@@ -126,6 +126,12 @@ def lib():
     L.maid_batch_step.argtypes = [P, PP, PP, ct.POINTER(maid_state), ct.POINTER(maid_hparams),
                                   ct.POINTER(maid_step_info), P]
     L.maid_batch_step.restype = ct.c_int
+    L.maid_batch_upper_value_grad.argtypes = [P, PP, PP, PP, PP, dp, dp, P]
+    L.maid_batch_upper_value_grad.restype = ct.c_int
+    L.maid_batch_hypergrad.argtypes = [P, PP, PP, PP, PP, PP, i32, PP, dp, P]
+    L.maid_batch_hypergrad.restype = ct.c_int
+    L.maid_autotune.argtypes = [P, PP, PP, i32, ct.POINTER(i32), P]
+    L.maid_autotune.restype = ct.c_int
     _lib = L
     return L
 

@@ -261,6 +261,22 @@ int maid_step(maid_ctx* c, const void* a, const void* y, maid_state* st, const m
     return report(c, code, "maid_step");
 }
 
+int maid_autotune(maid_ctx* c, const void* const* theta, const void* const* y, int32_t probe_iters, int32_t* rows_out,
+                  hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (!theta || !y) return fail(c, MAID_EINVAL, "autotune: NULL argument");
+    if (probe_iters < 1 || probe_iters > 1000) return fail(c, MAID_EINVAL, "autotune: probe_iters must be in 1..1000");
+    for (int i = 0; i < c->n; ++i)
+        if (!theta[i] || !y[i]) return fail(c, MAID_EINVAL, "autotune: NULL argument");
+    const int n = c->n;
+    if (c->dtype == MAID_F64)
+        return autotune_batch<double>(c, cast_all<const double*>(theta, n), cast_all<const double*>(y, n), probe_iters,
+                                      rows_out, s);
+    return autotune_batch<float>(c, cast_all<const double*>(theta, n), cast_all<const float*>(y, n), probe_iters, rows_out,
+                                 s);
+}
+
 // ---------------------------------------------------------------------- batched form
 int maid_batch_lower_solve(maid_ctx* c, const void* const* theta, const void* const* y, void* const* x, const double* tol,
                            int32_t max_iter, double* L_inout, maid_solve_info* info, hipStream_t s) {
@@ -313,6 +329,65 @@ int maid_batch_adjoint_solve(maid_ctx* c, const void* const* theta, const void* 
                                   s);
     if (rc) return rc;
     return report(c, combine_codes(codes.data(), n), "batch_adjoint_solve");
+}
+
+int maid_batch_upper_value_grad(maid_ctx* c, const void* const* a, const void* const* y, const void* const* x,
+                                void* const* grad_out, double* g_out, double* gradnorm_out, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (!a || !y || !x) return fail(c, MAID_EINVAL, "batch_upper_value_grad: NULL argument");
+    const int n = c->n;
+    for (int i = 0; i < n; ++i)
+        if (!a[i] || !y[i] || !x[i]) return fail(c, MAID_EINVAL, "batch_upper_value_grad: NULL argument");
+    std::vector<char> act(n, 1);
+    std::vector<double> g(n, 0.0), gn(n, 0.0);
+    std::vector<void*> go(n, nullptr);
+    if (grad_out)
+        for (int i = 0; i < n; ++i) go[i] = grad_out[i];
+    int rc;
+    if (c->dtype == MAID_F64)
+        rc = upper_batch<double>(c, act, cast_all<const double*>(a, n), cast_all<const double*>(y, n),
+                                 cast_all<const double*>(x, n), cast_all<double*>(go.data(), n), g.data(), gn.data(), s);
+    else
+        rc = upper_batch<float>(c, act, cast_all<const double*>(a, n), cast_all<const float*>(y, n),
+                                cast_all<const float*>(x, n), cast_all<float*>(go.data(), n), g.data(), gn.data(), s);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (g_out) g_out[i] = g[i];
+        if (gradnorm_out) gradnorm_out[i] = gn[i];
+    }
+    return MAID_OK;
+}
+
+int maid_batch_hypergrad(maid_ctx* c, const void* const* theta, const void* const* a, const void* const* y,
+                         const void* const* x_tilde, const void* const* q, int32_t with_r, void* const* z,
+                         double* znorm_out, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (!theta || !y || !x_tilde || !q || !z) return fail(c, MAID_EINVAL, "batch_hypergrad: NULL argument");
+    const int n = c->n;
+    std::vector<const void*> av(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        if (!theta[i] || !y[i] || !x_tilde[i] || !q[i] || !z[i]) return fail(c, MAID_EINVAL, "batch_hypergrad: NULL argument");
+        if (a) av[i] = a[i];
+        if (with_r && c->m[i].d.beta != 0.0 && !av[i])
+            return fail(c, MAID_EINVAL, "batch_hypergrad: a is needed for the Sobolev term");
+    }
+    std::vector<char> act(n, 1);
+    std::vector<double> zn(n, 0.0);
+    int rc;
+    if (c->dtype == MAID_F64)
+        rc = hypergrad_batch<double>(c, act, cast_all<const double*>(theta, n), cast_all<const double*>(av.data(), n),
+                                     cast_all<const double*>(y, n), cast_all<const double*>(x_tilde, n),
+                                     cast_all<const double*>(q, n), with_r != 0, cast_all<double*>(z, n), zn.data(), s);
+    else
+        rc = hypergrad_batch<float>(c, act, cast_all<const double*>(theta, n), cast_all<const double*>(av.data(), n),
+                                    cast_all<const float*>(y, n), cast_all<const float*>(x_tilde, n),
+                                    cast_all<const float*>(q, n), with_r != 0, cast_all<double*>(z, n), zn.data(), s);
+    if (rc) return rc;
+    if (znorm_out)
+        for (int i = 0; i < n; ++i) znorm_out[i] = zn[i];
+    return MAID_OK;
 }
 
 int maid_batch_step(maid_ctx* c, const void* const* a, const void* const* y, maid_state* states, const maid_hparams* hp,

@@ -260,7 +260,7 @@ int relayout(maid_ctx* c) {
     std::vector<int> host;
     for (int i = 0; i < c->n; ++i) {
         Member& M = c->m[i];
-        M.R = c->R_override ? c->R_override : M.R_auto;
+        M.R = c->R_override ? c->R_override : (M.R_tuned ? M.R_tuned : M.R_auto);
         M.nb = stencil_blocks(M.shape, M.R);
     }
     std::vector<char> placed(c->n, 0);
@@ -784,6 +784,95 @@ int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, in
     return MAID_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+// For every candidate tile height (rows per thread 1, 2, 4) all instances
+// take that candidate; a short lower-level solve and a short CG solve (fixed
+// iteration counts, tolerance 0, on the caller's data, writing only
+// workspace) run with per-launch timing, and the GPU time of the solver
+// passes is summed per kernel size K.  Each K group keeps its fastest
+// candidate.  The caller's own timing state is restored.
+template <typename T>
+int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const std::vector<const T*>& y, int probe_iters,
+                   int32_t* rows_out, hipStream_t s) {
+    const int n = c->n;
+    const int cands[3] = {1, 2, 4};
+    std::vector<int> Ks;
+    for (int i = 0; i < n; ++i)
+        if (std::find(Ks.begin(), Ks.end(), c->m[i].d.K) == Ks.end()) Ks.push_back(c->m[i].d.K);
+    std::vector<double> best(Ks.size(), 1e300);
+    std::vector<int> best_R(Ks.size(), 0);
+    // keep the caller's timing state
+    prof_harvest(c);
+    const bool prof_was = c->prof_on;
+    int64_t sv_l[MAID_PROF_KINDS], sv_w[MAID_PROF_KINDS];
+    double sv_ms[MAID_PROF_KINDS];
+    std::memcpy(sv_l, c->prof_launches, sizeof(sv_l));
+    std::memcpy(sv_w, c->prof_work, sizeof(sv_w));
+    std::memcpy(sv_ms, c->prof_ms, sizeof(sv_ms));
+    const int R_over = c->R_override;
+    int rc = MAID_OK;
+    std::vector<T*> xs(n);
+    std::vector<const T*> xsc(n), rhs(n);
+    std::vector<T*> qs(n);
+    for (int i = 0; i < n; ++i) {
+        xs[i] = (T*)c->m[i].xtrial;
+        xsc[i] = xs[i];
+        rhs[i] = y[i];
+        qs[i] = (T*)c->m[i].tmp1;
+    }
+    std::vector<double> tol(n, 0.0), L(n, 0.0);
+    std::vector<int> codes(n);
+    for (int k = 0; k < (int)Ks.size() && rc == MAID_OK; ++k) {
+        std::vector<char> act(n, 0);
+        for (int i = 0; i < n; ++i) act[i] = c->m[i].d.K == Ks[k];
+        for (int ci = 0; ci < 3 && rc == MAID_OK; ++ci) {
+            c->R_override = cands[ci];
+            if ((rc = relayout(c))) break;
+            for (int i = 0; i < n; ++i)
+                if (act[i]) {
+                    const size_t bytes = (size_t)c->m[i].N * sizeof(T);
+                    hipError_t e = hipMemcpyAsync(xs[i], y[i], bytes, hipMemcpyDeviceToDevice, s);
+                    if (e == hipSuccess) e = hipMemsetAsync(qs[i], 0, bytes, s);
+                    if (e != hipSuccess) {
+                        rc = fail(c, MAID_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    L[i] = 0.0;
+                }
+            if (rc) break;
+            c->prof_on = true;
+            for (int t = 0; t < MAID_PROF_KINDS; ++t) c->prof_ms[t] = 0.0;
+            rc = lower_batch<T>(c, act, theta, y, xs, tol, probe_iters, L.data(), nullptr, codes.data(), nullptr, s);
+            if (rc == MAID_OK)
+                rc = adjoint_batch<T>(c, act, theta, xsc, rhs, qs, tol, probe_iters, nullptr, codes.data(), s);
+            prof_harvest(c);
+            c->prof_on = false;
+            if (rc) break;
+            const double t = c->prof_ms[MAID_PROF_APG_GRAD] + c->prof_ms[MAID_PROF_APG_TRIAL] +
+                             c->prof_ms[MAID_PROF_CG_DIR] + c->prof_ms[MAID_PROF_CG_HVP];
+            if (t < best[k]) {
+                best[k] = t;
+                best_R[k] = cands[ci];
+            }
+        }
+    }
+    std::memcpy(c->prof_launches, sv_l, sizeof(sv_l));
+    std::memcpy(c->prof_work, sv_w, sizeof(sv_w));
+    std::memcpy(c->prof_ms, sv_ms, sizeof(sv_ms));
+    c->prof_on = prof_was;
+    c->R_override = R_over;
+    if (rc == MAID_OK)
+        for (int i = 0; i < n; ++i)
+            for (size_t k = 0; k < Ks.size(); ++k)
+                if (c->m[i].d.K == Ks[k]) c->m[i].R_tuned = best_R[k];
+    const int rc2 = relayout(c);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (rows_out)
+        for (int i = 0; i < n; ++i) rows_out[i] = c->m[i].R;
+    return MAID_OK;
+}
+
 // ------------------------------------------------------------------ MAID (Algorithm 2)
 // One outer iteration per instance, in lockstep: every round computes
 // InexactGradient for the instances that need one (one batched lower solve,
@@ -959,6 +1048,8 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                                     const std::vector<const T*>&, const std::vector<const T*>&, int,                    \
                                     const std::vector<double*>&, double*, hipStream_t);                                  \
     template int apply_operator_one<T>(maid_ctx*, const double*, const T*, T*, int, hipStream_t);                       \
+    template int autotune_batch<T>(maid_ctx*, const std::vector<const double*>&, const std::vector<const T*>&, int,   \
+                                   int32_t*, hipStream_t);                                                               \
     template int step_batch<T>(maid_ctx*, const std::vector<const double*>&, const std::vector<const T*>&, maid_state*, \
                                const maid_hparams*, maid_step_info*, int*, hipStream_t);
 

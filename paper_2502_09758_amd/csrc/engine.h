@@ -38,7 +38,8 @@ struct Member {
     maid_desc d;
     Shape shape;
     int64_t N;
-    int R_auto;
+    int R_auto;                 // rows per thread from the size rule
+    int R_tuned;                // rows per thread chosen by the autotuner (0: none)
     int nbe;                    // elementwise blocks
     // current layout (depends on the tile rows)
     int R, nb, base, base_e;
@@ -155,6 +156,12 @@ int sobolev_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
                   const std::vector<const double*>& a, double* r_out, hipStream_t s);
 template <typename T>
 int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, int adjoint, hipStream_t s);
+// Time short lower-level and CG probes with each rows-per-thread candidate
+// per group of instances sharing K, keep the fastest (rows_out: nullable,
+// the choice per instance).
+template <typename T>
+int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const std::vector<const T*>& y, int probe_iters,
+                   int32_t* rows_out, hipStream_t s);
 template <typename T>
 int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
                const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s);

@@ -115,6 +115,16 @@ class Maid:
     def set_tile_rows(self, rows: int):
         self._check(L.lib().maid_set_tile_rows(self.handle, int(rows)), "set_tile_rows")
 
+    def autotune(self, theta, y, probe_iters=6):
+        """Pick the tile height by timing short probe solves; returns the rows
+        per thread chosen."""
+        self._ker(theta, "theta"), self._img(y, "y")
+        th = (ct.c_void_p * 1)(theta.data_ptr())
+        yy = (ct.c_void_p * 1)(y.data_ptr())
+        rows = (ct.c_int32 * 1)()
+        self._check(L.lib().maid_autotune(self.handle, th, yy, int(probe_iters), rows, _stream()), "autotune")
+        return rows[0]
+
     def profile(self, enable: bool):
         """Start (reset) or stop per-launch kernel timing."""
         self._check(L.lib().maid_profile(self.handle, int(bool(enable))), "profile")
@@ -260,6 +270,14 @@ class MaidBatch:
             raise L.MaidError(rc, f"{what}: {L.last_error(self.handle)}")
         return rc
 
+    def autotune(self, thetas, ys, probe_iters=6):
+        """Per K group, pick the tile height by timing short probe solves;
+        returns the rows per thread chosen for each instance."""
+        th, y = self._kers(thetas, "theta"), self._imgs(ys, "y")
+        rows = (ct.c_int32 * self.n)()
+        self._check(L.lib().maid_autotune(self.handle, th, y, int(probe_iters), rows, _stream()), "autotune")
+        return list(rows)
+
     def lower_solve(self, thetas, ys, xs, tols, max_iter=300, L_est=None):
         """Batched lower-level solve, in place in `xs`; returns (rc, [SolveInfo])."""
         th, y, x = self._kers(thetas, "theta"), self._imgs(ys, "y"), self._imgs(xs, "x")
@@ -279,6 +297,29 @@ class MaidBatch:
         rc = L.lib().maid_batch_adjoint_solve(self.handle, th, xt, b, q, tol, int(max_iter), info, _stream())
         self._rc(rc, "batch_adjoint_solve")
         return rc, [SolveInfo(i.status, i.iters, 0, i.res_norm, 0.0) for i in info]
+
+    def upper_value_grad(self, as_, ys, xs, grads=None):
+        """Batched upper-level value and gradient; returns ([g], [||grad g||])."""
+        a, y, x = self._kers(as_, "a"), self._imgs(ys, "y"), self._imgs(xs, "x")
+        go = self._imgs(grads, "grad_out") if grads is not None else None
+        g = (ct.c_double * self.n)()
+        gn = (ct.c_double * self.n)()
+        self._check(L.lib().maid_batch_upper_value_grad(self.handle, a, y, x, go, g, gn, _stream()),
+                    "batch_upper_value_grad")
+        return list(g), list(gn)
+
+    def hypergrad(self, thetas, as_, ys, xts, qs, with_r=True, zs=None):
+        """Batched hypergradient; returns ([z], [||z||])."""
+        th, y, xt, q = self._kers(thetas, "theta"), self._imgs(ys, "y"), self._imgs(xts, "x_tilde"), \
+            self._imgs(qs, "q")
+        a = self._kers(as_, "a") if as_ is not None else None
+        if zs is None:
+            zs = [torch.empty((s["K"], s["K"]), dtype=torch.float64, device=thetas[0].device) for s in self.specs]
+        z = self._kers(zs, "z")
+        zn = (ct.c_double * self.n)()
+        self._check(L.lib().maid_batch_hypergrad(self.handle, th, a, y, xt, q, int(bool(with_r)), z, zn, _stream()),
+                    "batch_hypergrad")
+        return zs, list(zn)
 
     def maid_step(self, as_, ys, states, **hp):
         """One Algorithm 2 iteration for every instance (lockstep); the states

@@ -192,3 +192,65 @@ def test_ragged_64_instance_batch_full_size():
         assert info.iters == infos[k].iters and torch.equal(x, xs[k]), f"instance {k}"
         m.close()
     mb.close()
+
+
+def test_autotune_plain_and_batch():
+    """The autotuner picks a valid tile height per K group, writes nothing the
+    caller owns, and a solve afterwards equals a solo solve forced to the
+    chosen tile height (bitwise)."""
+    print("[case] autotune plain + batch", flush=True)
+    dt = torch.float32
+    insts = small_batch()[:4]
+    th = [dev(i.a, torch.float64) for i in insts]
+    ys = [dev(i.y, dt) for i in insts]
+    ys_before = [y.clone() for y in ys]
+    m = solo(insts[2], dt)
+    r = m.autotune(th[2], ys[2], probe_iters=4)
+    assert r in (1, 2, 4) and f"rows_per_thread={r}" in m.config()
+    assert torch.equal(ys[2], ys_before[2])
+    mb = MaidBatch([spec(i) for i in insts], dt)
+    rows = mb.autotune(th, ys, probe_iters=4)
+    assert len(rows) == len(insts) and all(v in (1, 2, 4) for v in rows)
+    for k in range(len(insts)):
+        assert torch.equal(ys[k], ys_before[k])
+        for j in range(len(insts)):
+            if insts[j].K == insts[k].K:
+                assert rows[j] == rows[k]
+    xs = [y.clone() for y in ys]
+    mb.lower_solve(th, ys, xs, [1e-3] * len(insts), max_iter=300)
+    for k in range(len(insts)):
+        ms = solo(insts[k], dt)
+        ms.set_tile_rows(rows[k])
+        x = ys[k].clone()
+        ms.lower_solve(th[k], ys[k], x, 1e-3, max_iter=300)
+        assert torch.equal(x, xs[k]), f"instance {k}"
+        ms.close()
+    m.close()
+    mb.close()
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_batch_upper_and_hypergrad_equal_solo_bitwise(dt):
+    print(f"[case] batch upper_value_grad + hypergrad == solo, {dt}", flush=True)
+    insts = small_batch()
+    for i in insts:
+        i.beta = i.alpha / 2
+    mb = MaidBatch([spec(i) for i in insts], dt)
+    th = [dev(i.a + 0.01 * synth.directions(1, i.K, seed=5)[0], torch.float64) for i in insts]
+    a = [dev(i.a, torch.float64) for i in insts]
+    ys = [dev(i.y, dt) for i in insts]
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    xs = [y + 0.01 * torch.randn(y.shape, generator=gen, device="cuda", dtype=dt) for y in ys]
+    qs = [torch.randn(y.shape, generator=gen, device="cuda", dtype=dt) for y in ys]
+    grads = [torch.empty_like(y) for y in ys]
+    g, gn = mb.upper_value_grad(a, ys, xs, grads)
+    zs, zn = mb.hypergrad(th, a, ys, xs, qs, with_r=True)
+    for k, inst in enumerate(insts):
+        m = solo(inst, dt)
+        gk = torch.empty_like(ys[k])
+        gv, gnv = m.upper_value_grad(a[k], ys[k], xs[k], gk)
+        assert (gv, gnv) == (g[k], gn[k]) and torch.equal(gk, grads[k])
+        z, znv = m.hypergrad(th[k], a[k], ys[k], xs[k], qs[k], with_r=True)
+        assert znv == zn[k] and torch.equal(z, zs[k]), f"instance {k}"
+        m.close()
+    mb.close()
