@@ -39,7 +39,8 @@ struct ApgState {
     int32_t max_iter, iters, bt, nb_iter;
     int32_t status, done, phase;
     int32_t cur, prev, nxt;      // rotation of the three x / Kx buffers
-    int32_t trace_cap, pad;
+    int32_t trace_cap;
+    int32_t resync;              // theta*x recomputed exactly when iters % resync < 2 (0: never)
 };
 
 // CG state, one per instance, in three arrays: the direction pass reads the

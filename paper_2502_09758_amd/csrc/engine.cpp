@@ -400,6 +400,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         return code;
     }
     if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
+    // period of the exact recomputation of theta*x in the lower-level solve
+    c->kx_resync = c->dtype == MAID_F64 ? 32 : 8;
+    if (const char* r = std::getenv("MAID_KX_RESYNC")) c->kx_resync = std::max(0, std::atoi(r));
     std::memset(c->st_host, 0, c->st_bytes);
     std::memset(c->tab_host, 0, tab_bytes);
     {
@@ -487,6 +490,7 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         h.prev = 1;
         h.nxt = 2;
         h.trace_cap = kTraceCap;
+        h.resync = c->kx_resync;
         Inst<T>& I = tab[i];
         I.y = y[i];
         I.xout = x[i];

@@ -110,6 +110,7 @@ struct maid_ctx {
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;        // private stream for graph capture
     bool use_graphs = true;
+    int kx_resync = 16;               // exact theta*x every kx_resync iterations (twice in a row)
     struct Graph { int kind; int chunk; int gen; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
     std::string err;

@@ -121,7 +121,7 @@ __device__ __forceinline__ void put_state(ApgState* __restrict__ o, const ApgSta
     o->L = s.L; o->t = s.t; o->t_prev = s.t_prev; o->m = s.m; o->gn2 = s.gn2; o->tol = s.tol;
     o->delta_last = s.delta_last; o->max_iter = s.max_iter; o->iters = s.iters; o->bt = s.bt;
     o->nb_iter = s.nb_iter; o->status = s.status; o->done = s.done; o->phase = s.phase; o->cur = s.cur;
-    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->pad = 0;
+    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->resync = s.resync;
 }
 __device__ __forceinline__ void put_state(CgState* __restrict__ o, const CgState& s) {
     o->gamma = s.gamma; o->kappa = s.kappa; o->a = s.a; o->tol = s.tol; o->max = s.max; o->iters = s.iters;
@@ -470,6 +470,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 //         s'^2 - s^2 = sum a (a + 2 b), a = D dl, b = D v,
 // with every per-element product in double.  The TV part couples the
 // channels; each of a tile's channel blocks takes a share of its rows.
+// theta*x+ by linearity accumulates the rounding of the x and theta*x
+// recurrences (the momentum makes it grow faster than a random walk), so on
+// two consecutive iterations of every `resync` it is recomputed exactly as
+// the convolution of the stored x+ (two consecutive, so that both theta*x
+// and theta*x_prev, i.e. the momentum term, are exact again).
 template <typename T, int K, int R>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                    const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
@@ -572,6 +577,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     }
 
     // ---- data part of this block's channel, and the new iterate
+    const bool exact = st.resync > 0 && (st.iters % st.resync) < 2;
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
@@ -589,7 +595,26 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
             ddat += (double)d * (rv + 0.5 * (double)d);
             const T xv = X[e];
             XN[e] = dfma(m, xv - XP[e], xv) + s_c[(li + c0) * CP + tx + c0];
-            KXN[e] = kv + d;
+            if (!exact) KXN[e] = kv + d;
+        }
+    }
+    if (exact) {
+        // theta*x+ from the stored x+ = v + dl, staged with its halo
+        const T* Xc = X + ch * HW;
+        const T* XPc = XP + ch * HW;
+        __syncthreads();
+        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) {
+            const T xv = Xc[g];
+            return dfma(m, xv - XPc[g], xv) + Gc[g] * ninvL;
+        });
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < R; ++o) acc[o] = T(0);
+        correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
+#pragma unroll
+        for (int o = 0; o < R; ++o) {
+            const int gi = ti0 + li0 + o;
+            if (gi < H && gj < W) KXN[ch * HW + (int64_t)gi * W + gj] = acc[o];
         }
     }
     block_partial(ddat + I.pr.alpha * dtv, I.pB, lb);

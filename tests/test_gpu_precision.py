@@ -1,0 +1,87 @@
+"""Precision form at full size: 2048x2048x3, 31x31 motion blur, alpha 1e-4.
+
+Per result, the error against the FP64 oracle (or against the FP64 GPU
+path where the oracle cannot run at this size, the FP64 path itself being
+pinned to the oracle here and at every smaller size):
+  * FP64 lower-level solve: the oracle's full-size gradient at the returned
+    point meets the tolerance and equals the GPU's own stop-test value;
+  * FP32 lower-level solve at tolerance 1e-3: distance to the FP64 solution;
+  * CG: FP32 and FP64 on the same (FP32-rounded) system take the same
+    iterations and agree (FP64 inner products on both sides);
+  * hypergradient: FP64 GPU against the oracle's full-size correlation, and
+    FP32 against FP64 at the same point."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2502_09758_amd import _lib as L
+from paper_2502_09758_amd import synth
+from paper_2502_09758_amd.maid import Maid
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.timeout(600)
+def test_precision_form_full_size():
+    print("[case] precision form 2048x2048x3 K=31", flush=True)
+    inst = synth.make("cfg5")
+    C, H, W, K = inst.C, inst.H, inst.W, inst.K
+    kw = dict(alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta)
+    p = O.Problem.of(inst)
+    th = torch.tensor(inst.a, dtype=torch.float64, device="cuda")
+    y32 = torch.tensor(inst.y, dtype=torch.float32, device="cuda")
+    y64 = y32.double()                       # one problem for both precisions
+    y_np = y64.cpu().numpy()
+    m64 = Maid(C, H, W, K, torch.float64, **kw)
+    m32 = Maid(C, H, W, K, torch.float32, **kw)
+
+    # FP64 lower level, checked by the oracle's full-size gradient
+    x64 = y64.clone()
+    i64 = m64.lower_solve(th, y64, x64, 1e-5, max_iter=20000)
+    assert i64.status == L.OK
+    g_or = np.linalg.norm(O.h_grad(p, inst.a, y_np, x64.cpu().numpy()))
+    print(f"[prec] FP64 lower: {i64.iters} iterations, GPU ||G|| {i64.res_norm:.6e}, oracle ||grad h|| {g_or:.6e}",
+          flush=True)
+    assert g_or <= 1e-5 * (1 + 1e-6)
+    assert abs(g_or - i64.res_norm) <= 1e-6 * g_or
+
+    # FP32 lower level against the FP64 solution
+    x32 = y32.clone()
+    i32 = m32.lower_solve(th, y32, x32, 1e-3, max_iter=20000)
+    assert i32.status == L.OK
+    ex = rel(x32.double().cpu().numpy(), x64.cpu().numpy())
+    print(f"[prec] FP32 lower at tol 1e-3: {i32.iters} iterations, relative distance to FP64 solution {ex:.3e}",
+          flush=True)
+    assert ex <= 5e-3
+
+    # CG in both precisions on the FP32-rounded system at x32
+    g32 = torch.empty_like(x32)
+    m32.upper_value_grad(th, y32, x32, g32)
+    xr, gr = x32.double(), g32.double()
+    tol = 1e-5 * float(gr.norm())
+    q32 = torch.zeros_like(x32)
+    c32 = m32.adjoint_solve(th, x32, g32, q32, tol, max_iter=20000)
+    q64 = torch.zeros_like(xr)
+    c64 = m64.adjoint_solve(th, xr, gr, q64, tol, max_iter=20000)
+    eq = rel(q32.double().cpu().numpy(), q64.cpu().numpy())
+    print(f"[prec] CG at rel tol 1e-5: FP32 {c32.iters} / FP64 {c64.iters} iterations, q rel diff {eq:.3e}", flush=True)
+    assert c32.status == L.OK and c64.status == L.OK
+    assert abs(c32.iters - c64.iters) <= 2
+    assert eq <= 1e-4
+
+    # hypergradient: FP64 GPU vs oracle at full size; FP32 vs FP64 at the same point
+    z64, _ = m64.hypergrad(th, th, y64, xr, q64)
+    zo, _ = O.hypergrad(p, inst.a, inst.a, y_np, xr.cpu().numpy(), q64.cpu().numpy(), with_r=True)
+    e64 = rel(z64.cpu().numpy(), zo)
+    z32, _ = m32.hypergrad(th, th, y32, x32, q32)
+    e32 = rel(z32.cpu().numpy(), zo)
+    print(f"[prec] hypergradient vs oracle: FP64 {e64:.3e}, FP32 {e32:.3e}", flush=True)
+    assert e64 <= 1e-12
+    assert e32 <= 1e-4
+    m64.close()
+    m32.close()
