@@ -98,7 +98,7 @@ template <typename T> struct Inst {
     int32_t K;                   // kernel size
     int32_t nb, base;            // stencil blocks (tiles x channels) and first block within its group launch
     int32_t nbe, base_e;         // elementwise blocks and first block within the elementwise launch
-    int32_t pad;
+    int32_t cv_prev_slot;        // red slot for cv_prev_part's total
     int64_t N;                   // C*H*W
     // lower level (FISTA)
     T* X[3];                     // iterates (rotating: cur, prev, next)
@@ -119,6 +119,7 @@ template <typename T> struct Inst {
     T* Hp;
     const T* xt;                 // point the Hessian is taken at
     const T* b;                  // right-hand side
+    const T* q0;                 // the caller's starting point (read by the set-up passes)
     double* pR;                  // per-block partials of ||r||^2 (nbe entries)
     double* pK;                  // per-block partials of <p, Hp> (nb entries)
     // one convolution job: cv_out = cv_ker (x) cv_in [- cv_sub], partials of its square
@@ -126,10 +127,17 @@ template <typename T> struct Inst {
     const T* cv_in;
     const T* cv_sub;
     T* cv_out;
+    T* cv_out2;                  // nullable: a second copy of cv_out
+    T* cv_cp[2];                 // nullable: copies of cv_in
     double* cv_part;             // nullable
+    const double* cv_prev_part;  // nullable: partials of an earlier pass, summed by block 0 into red[cv_prev_slot]
     // kernel preparation: theta64 (K*K doubles) -> th / thf
     const double* theta64;       // nullable: nothing to prepare
     double* red;                 // per-instance reduction results (8 doubles)
+    // Sobolev term r(theta) of Eq. (2.5) for the finishing pass (sob_th nullable)
+    const double* sob_th;
+    const double* sob_a;
+    double beta, h1_w0;
 };
 
 }  // namespace maid

@@ -232,6 +232,30 @@ int run_chunk(maid_ctx* c, int kind, int chunk, hipStream_t s, F enqueue) {
     return MAID_OK;
 }
 
+// Launch `want` slots as power-of-two graph chunks back to back (no host
+// round trip between them).
+template <typename F>
+int run_slots(maid_ctx* c, int kind, long want, hipStream_t s, F enqueue) {
+    for (int p = 32; p >= 1; p >>= 1)
+        while (want >= p) {
+            int rc = run_chunk(c, kind, p, s, [&](hipStream_t st) { return enqueue(st, p); });
+            if (rc) return rc;
+            want -= p;
+        }
+    return MAID_OK;
+}
+
+// Slots to launch before the next look at the state: first three quarters
+// of the count the previous solve of this kind needed (warm-started solves
+// in Algorithm 2 need similar counts; a slot past the end costs an early-exit
+// launch, a look costs a host round trip with the GPU drained), then growing
+// steps from an eighth of it; with no history 1, 2, 4, ...
+long next_slots(long pred, long done_so_far, long last) {
+    if (done_so_far == 0) return pred > 0 ? std::max(1L, pred * 3 / 4) : 1;
+    if (pred > 0 && done_so_far == last) return std::max(1L, pred / 8);
+    return std::min(last * 2, 64L);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ set-up
@@ -467,7 +491,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
 template <typename T>
 int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
                 const std::vector<const T*>& y, const std::vector<T*>& x, const std::vector<double>& tol, int max_iter,
-                double* L_inout, maid_solve_info* info, int* codes, int32_t* trace_bt, hipStream_t s) {
+                double* L_inout, maid_solve_info* info, int* codes, int32_t* trace_bt, hipStream_t s,
+                int pred_role, const std::vector<const T*>* xin) {
     const int n = c->n;
     Inst<T>* tab = tab_host<T>(c, ROLE_APG);
     const Inst<T>* tabd = tab_dev<T>(c, ROLE_APG);
@@ -495,31 +520,27 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         I.y = y[i];
         I.xout = x[i];
         I.theta64 = theta[i];
+        // set-up: X0 = X1 = x_start, KX0 = KX1 = theta*x_start in one pass
         I.cv_ker = I.thf;
-        I.cv_in = I.X[0];
+        I.cv_in = xin ? (*xin)[i] : x[i];
         I.cv_out = I.KX[0];
+        I.cv_out2 = I.KX[1];
+        I.cv_cp[0] = I.X[0];
+        I.cv_cp[1] = I.X[1];
     }
     TRY(push(c, s, c->apg[0], n * sizeof(ApgState)));
     TRY(upload<T>(c, ROLE_APG, s));
     LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, c->apg[0], -1, s));
-    for (int i = 0; i < n; ++i)
-        if (act[i]) {
-            const size_t bytes = (size_t)c->m[i].N * sizeof(T);
-            HIP_TRY(hipMemcpyAsync(c->m[i].X[0], x[i], bytes, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(c->m[i].X[1], x[i], bytes, hipMemcpyDeviceToDevice, s));
-        }
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, tabd, s));
-    for (int i = 0; i < n; ++i)
-        if (act[i])
-            HIP_TRY(hipMemcpyAsync(c->m[i].KX[1], c->m[i].KX[0], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
     // each slot is one gradient pass and one trial pass; a slot advances every
     // unfinished solve by one iteration or by one backtracking step
     const long slot_cap = (long)max_iter + 256 + 1;
-    long slots = 0;
-    int chunk = 1;
+    const long pred = std::min(c->pred_slots[pred_role], (long)max_iter + 1);
+    long slots = 0, chunk = 0;
     for (;;) {
-        int rc = run_chunk(c, G_APG, chunk, s, [&](hipStream_t s) {
-            for (int k = 0; k < chunk; ++k) {
+        chunk = next_slots(pred, slots, chunk);
+        int rc = run_slots(c, G_APG, chunk, s, [&](hipStream_t s, int cnt) {
+            for (int k = 0; k < cnt; ++k) {
                 for (auto& lg : c->groups)
                     LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(lg.g, tabd, c->apg[0], c->apg[1], s));
                 for (auto& lg : c->groups)
@@ -534,7 +555,12 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         for (int i = 0; i < n; ++i) done = done && c->apg_h[i].done;
         if (done) break;
         if (slots > slot_cap) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
-        chunk = std::min(chunk * 2, 16);
+    }
+    {
+        long need = 1;
+        for (int i = 0; i < n; ++i)
+            if (act[i]) need = std::max<long>(need, (long)c->apg_h[i].iters + c->apg_h[i].bt + 1);
+        c->pred_slots[pred_role] = need;
     }
     if (c->prof_on) {
         // passes that did work: a gradient at the start and after every
@@ -595,27 +621,23 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         h.first = 1;
         tab[i].xt = xt[i];
         tab[i].b = rhs[i];
+        tab[i].q0 = q[i];
         tab[i].theta64 = theta[i];
     }
     TRY(push(c, s, c->cg[0], n * sizeof(CgState)));
     TRY(upload<T>(c, ROLE_CG, s));
     LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, nullptr, -1, s));
-    for (int i = 0; i < n; ++i)
-        if (act[i]) {
-            const size_t bytes = (size_t)c->m[i].N * sizeof(T);
-            HIP_TRY(hipMemcpyAsync(c->m[i].cq, q[i], bytes, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(c->m[i].cr, q[i], bytes, hipMemcpyDeviceToDevice, s));
-        }
-    // r = rhs - H q0 (the direction pass in set-up mode copies q0 into p)
+    // r = rhs - H q0 (the direction pass in set-up mode copies q0 into q and p)
     CgState** S = c->cg;
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
     LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->grid_e, c->blk_e, c->only_e, tabd, S[0], s));
-    int chunk = 1;
-    long slots = 0;
+    const long pred = std::min(c->pred_slots[3], (long)max_iter + 1);
+    long slots = 0, chunk = 0;
     for (;;) {
-        int rc = run_chunk(c, G_CG, chunk, s, [&](hipStream_t s) {
-            for (int k = 0; k < chunk; ++k) {
+        chunk = next_slots(pred, slots, chunk);
+        int rc = run_slots(c, G_CG, chunk, s, [&](hipStream_t s, int cnt) {
+            for (int k = 0; k < cnt; ++k) {
                 for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
                 for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
                 LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
@@ -629,7 +651,12 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         for (int i = 0; i < n; ++i) done = done && c->cg_h[i].done;
         if (done) break;
         if (slots > (long)max_iter + 2) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
-        chunk = std::min(chunk * 2, 16);
+    }
+    {
+        long need = 1;
+        for (int i = 0; i < n; ++i)
+            if (act[i]) need = std::max<long>(need, (long)c->cg_h[i].iters + 1);
+        c->pred_slots[3] = need;
     }
     if (c->prof_on) {
         // the set-up direction and Hessian passes, then one of each per iteration
@@ -662,10 +689,16 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
 
 // ------------------------------------------------------------------ upper level at x
 // rho = a*x - y, g = 1/2 ||rho||^2, grad = a . rho, ||grad||.
+// With sob_theta, also r(theta_i) of the Sobolev term (Eq. 2.5) into r_out,
+// read back with the same host round trip.
+namespace {
 template <typename T>
-int upper_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& a,
-                const std::vector<const T*>& y, const std::vector<const T*>& x, const std::vector<T*>& grad,
-                double* g_out, double* gn_out, hipStream_t s) {
+int upper_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& a,
+               const std::vector<const T*>& y, const std::vector<const T*>& x, const std::vector<T*>& grad,
+               double* g_out, double* gn_out, const std::vector<const double*>* sob_theta, double* r_out,
+               hipStream_t s) {
+    // prep(a) [+ ||a||_1] -> rho = a*x - y (partials in pC) -> grad = a.rho
+    // (partials in pA; its block 0 sums pC) -> finish: sum pA [+ r(theta)]
     const int n = c->n;
     Inst<T>* t0 = tab_host<T>(c, ROLE_CV0);
     Inst<T>* t1 = tab_host<T>(c, ROLE_CV1);
@@ -685,32 +718,51 @@ int upper_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         t1[i].cv_ker = (T*)M.a_c;
         t1[i].cv_in = (T*)M.tmp0;
         t1[i].cv_out = grad[i] ? grad[i] : (T*)M.gradg;
-        t1[i].cv_part = M.pC;
+        t1[i].cv_part = M.pA;
+        t1[i].cv_prev_part = M.pC;
+        t1[i].cv_prev_slot = kRedG;
+        if (sob_theta && M.d.beta != 0.0) {
+            t1[i].sob_th = (*sob_theta)[i];
+            t1[i].sob_a = a[i];
+            t1[i].beta = M.d.beta;
+            t1[i].h1_w0 = M.d.h1_w0;
+        }
     }
     TRY(upload<T>(c, ROLE_CV0, s));
     TRY(upload<T>(c, ROLE_CV1, s));
     const Inst<T>* d0 = tab_dev<T>(c, ROLE_CV0);
     const Inst<T>* d1 = tab_dev<T>(c, ROLE_CV1);
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, kRedAbs, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d0, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::reduce(d0, n, kRedG, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d1, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::reduce(d1, n, kRedGrad, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::finish(d1, n, kRedGrad, kRedSob, s));
     TRY(pull_red(c, s));
     for (int i = 0; i < n; ++i)
         if (act[i]) {
             if (g_out) g_out[i] = 0.5 * c->red_h[i * kRedSlots + kRedG];
             if (gn_out) gn_out[i] = std::sqrt(c->red_h[i * kRedSlots + kRedGrad]);
+            if (sob_theta) r_out[i] = c->m[i].d.beta != 0.0 ? c->red_h[i * kRedSlots + kRedSob] : 0.0;
         }
     return MAID_OK;
 }
+}  // namespace
+
+template <typename T>
+int upper_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& a,
+                const std::vector<const T*>& y, const std::vector<const T*>& x, const std::vector<T*>& grad,
+                double* g_out, double* gn_out, hipStream_t s) {
+    return upper_impl<T>(c, act, a, y, x, grad, g_out, gn_out, nullptr, nullptr, s);
+}
 
 // ------------------------------------------------------------------ hypergradient (Eq. 3.2)
+// znorm_out == nullptr: ||z||^2 stays in the reduction slots (no host
+// round trip; the next read-back of the slots brings it).
+namespace {
 template <typename T>
-int hypergrad_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
-                    const std::vector<const double*>& a, const std::vector<const T*>& y, const std::vector<const T*>& xt,
-                    const std::vector<const T*>& q, int with_r, const std::vector<double*>& z, double* znorm_out,
-                    hipStream_t s) {
+int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                   const std::vector<const double*>& a, const std::vector<const T*>& y, const std::vector<const T*>& xt,
+                   const std::vector<const T*>& q, int with_r, const std::vector<double*>& z, double* znorm_out,
+                   hipStream_t s) {
     const int n = c->n;
     Inst<T>* t2 = tab_host<T>(c, ROLE_CV2);
     Inst<T>* t3 = tab_host<T>(c, ROLE_CV3);
@@ -745,9 +797,24 @@ int hypergrad_batch(maid_ctx* c, const std::vector<char>& act, const std::vector
         LAUNCH(MAID_PROF_OTHER, launch_hg_final(M.shape, M.d.beta, M.d.h1_w0, M.hg_part, nblk, theta[i],
                                                 wr ? a[i] : nullptr, wr, z[i], c->red + (size_t)i * kRedSlots + kRedZ, s));
     }
+    if (!znorm_out) return MAID_OK;
     TRY(pull_red(c, s));
     for (int i = 0; i < n; ++i)
-        if (act[i] && znorm_out) znorm_out[i] = std::sqrt(c->red_h[i * kRedSlots + kRedZ]);
+        if (act[i]) znorm_out[i] = std::sqrt(c->red_h[i * kRedSlots + kRedZ]);
+    return MAID_OK;
+}
+}  // namespace
+
+template <typename T>
+int hypergrad_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
+                    const std::vector<const double*>& a, const std::vector<const T*>& y, const std::vector<const T*>& xt,
+                    const std::vector<const T*>& q, int with_r, const std::vector<double*>& z, double* znorm_out,
+                    hipStream_t s) {
+    std::vector<double> zn(c->n, 0.0);
+    TRY(hypergrad_impl<T>(c, act, theta, a, y, xt, q, with_r, z, zn.data(), s));
+    if (znorm_out)
+        for (int i = 0; i < c->n; ++i)
+            if (act[i]) znorm_out[i] = zn[i];
     return MAID_OK;
 }
 
@@ -891,20 +958,10 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
     const int n = c->n;
     std::vector<maid_step_info> I(n);
     std::memset(I.data(), 0, n * sizeof(maid_step_info));
+    // L_g <= 0: ||a||_1^2, from the first upper-level read-back (its prep of a
+    // leaves ||a||_1 in the reduction slots)
     std::vector<double> Lg(n, hp->L_g);
-    if (!(hp->L_g > 0)) {
-        Inst<T>* t0 = tab_host<T>(c, ROLE_CV0);
-        for (int i = 0; i < n; ++i) {
-            fill_base(c, i, t0[i]);
-            t0[i].th = (T*)c->m[i].a_c;
-            t0[i].thf = (T*)c->m[i].af_c;
-            t0[i].theta64 = a[i];
-        }
-        TRY(upload<T>(c, ROLE_CV0, s));
-        LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tab_dev<T>(c, ROLE_CV0), n, nullptr, kRedAbs, s));
-        TRY(pull_red(c, s));
-        for (int i = 0; i < n; ++i) Lg[i] = c->red_h[i * kRedSlots + kRedAbs] * c->red_h[i * kRedSlots + kRedAbs];
-    }
+    bool have_Lg = hp->L_g > 0;
     std::vector<const double*> theta(n), th2c(n);
     std::vector<double*> th2(n), z(n);
     std::vector<T*> x(n), q(n), xs(n), grad(n), none(n, nullptr);
@@ -935,7 +992,7 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
             dtol[i] = st[i].delta;
             L[i] = st[i].L;
         }
-        TRY(lower_batch<T>(c, need, theta, y, x, tol, hp->max_lower_iter, L.data(), li.data(), rc.data(), nullptr, s));
+        TRY(lower_batch<T>(c, need, theta, y, x, tol, hp->max_lower_iter, L.data(), li.data(), rc.data(), nullptr, s, 1));
         for (int i = 0; i < n; ++i) {
             if (!need[i]) continue;
             if (rc[i] < 0) {
@@ -946,8 +1003,12 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
             st[i].L = L[i];
             I[i].lower_iters += li[i].iters;
         }
-        TRY(upper_batch<T>(c, need, a, y, xc, grad, g_k.data(), n_k.data(), s));
-        TRY(sobolev_batch(c, need, theta, a, r_k.data(), s));
+        TRY(upper_impl<T>(c, need, a, y, xc, grad, g_k.data(), n_k.data(), &theta, r_k.data(), s));
+        if (!have_Lg) {
+            for (int i = 0; i < n; ++i)
+                if (need[i]) Lg[i] = c->red_h[i * kRedSlots + kRedAbs] * c->red_h[i * kRedSlots + kRedAbs];
+            have_Lg = true;
+        }
         TRY(adjoint_batch<T>(c, need, theta, xc, gradc, q, dtol, hp->max_cg_iter, ci.data(), rc.data(), s));
         for (int i = 0; i < n; ++i) {
             if (!need[i]) continue;
@@ -957,12 +1018,13 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                 need[i] = 0;
             }
         }
-        TRY(hypergrad_batch<T>(c, need, theta, a, y, xc, qc, 1, z, znorm.data(), s));
+        // ||z|| comes back with the first trial's read-back
+        TRY(hypergrad_impl<T>(c, need, theta, a, y, xc, qc, 1, z, nullptr, s));
+        bool have_znorm = false;
         for (int i = 0; i < n; ++i)
             if (need[i]) {
                 ell_k[i] = g_k[i] + r_k[i];
                 I[i].ell_k = ell_k[i];
-                I[i].znorm = znorm[i];
             }
         // the psi trials
         std::vector<char> tr = need;
@@ -972,10 +1034,11 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                 if (!tr[i]) continue;
                 const int KK = c->m[i].d.K * c->m[i].d.K;
                 LAUNCH(MAID_PROF_OTHER, launch_theta_step(theta[i], z[i], st[i].step, th2[i], KK, s));
-                HIP_TRY(hipMemcpyAsync(xs[i], x[i], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
                 L[i] = st[i].L;
             }
-            TRY(lower_batch<T>(c, tr, th2c, y, xs, tol, hp->max_lower_iter, L.data(), li.data(), rc.data(), nullptr, s));
+            // the trial solve starts from x and returns in xs
+            TRY(lower_batch<T>(c, tr, th2c, y, xs, tol, hp->max_lower_iter, L.data(), li.data(), rc.data(), nullptr, s,
+                               2, &xc));
             for (int i = 0; i < n; ++i) {
                 if (!tr[i]) continue;
                 if (rc[i] < 0) {
@@ -987,8 +1050,15 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                 st[i].L = L[i];
                 I[i].lower_iters += li[i].iters;
             }
-            TRY(upper_batch<T>(c, tr, a, y, xsc, none, g_n.data(), n_n.data(), s));
-            TRY(sobolev_batch(c, tr, th2c, a, r_n.data(), s));
+            TRY(upper_impl<T>(c, tr, a, y, xsc, none, g_n.data(), n_n.data(), &th2c, r_n.data(), s));
+            if (!have_znorm) {
+                for (int i = 0; i < n; ++i)
+                    if (need[i]) {
+                        znorm[i] = std::sqrt(c->red_h[i * kRedSlots + kRedZ]);
+                        I[i].znorm = znorm[i];
+                    }
+                have_znorm = true;
+            }
             bool copied = false;
             for (int i = 0; i < n; ++i) {
                 if (!tr[i]) continue;
@@ -1040,7 +1110,8 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
 #define MAID_ENGINE_INSTANTIATE(T)                                                                                       \
     template int lower_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,                 \
                                 const std::vector<const T*>&, const std::vector<T*>&, const std::vector<double>&, int,  \
-                                double*, maid_solve_info*, int*, int32_t*, hipStream_t);                                 \
+                                double*, maid_solve_info*, int*, int32_t*, hipStream_t, int,                            \
+                                const std::vector<const T*>*);                                                           \
     template int adjoint_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,               \
                                   const std::vector<const T*>&, const std::vector<const T*>&, const std::vector<T*>&,   \
                                   const std::vector<double>&, int, maid_solve_info*, int*, hipStream_t);                 \

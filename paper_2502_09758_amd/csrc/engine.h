@@ -111,6 +111,11 @@ struct maid_ctx {
     hipStream_t cap = nullptr;        // private stream for graph capture
     bool use_graphs = true;
     int kx_resync = 16;               // exact theta*x every kx_resync iterations (twice in a row)
+    // slots the last solve of each kind needed (sizes the first chunk of the
+    // next): lower level for callers, for Algorithm 2's InexactGradient and
+    // for its psi trials (their counts differ: the first starts from the
+    // accepted trial's solution, the second from a new theta); CG
+    long pred_slots[4] = {0, 0, 0, 0};
     struct Graph { int kind; int chunk; int gen; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
     std::string err;
@@ -139,7 +144,8 @@ void prof_harvest(maid_ctx* c);
 template <typename T>
 int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
                 const std::vector<const T*>& y, const std::vector<T*>& x, const std::vector<double>& tol, int max_iter,
-                double* L_inout, maid_solve_info* info, int* codes, int32_t* trace_bt, hipStream_t s);
+                double* L_inout, maid_solve_info* info, int* codes, int32_t* trace_bt, hipStream_t s,
+                int pred_role = 0, const std::vector<const T*>* xin = nullptr);
 template <typename T>
 int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<const double*>& theta,
                   const std::vector<const T*>& xt, const std::vector<const T*>& rhs, const std::vector<T*>& q,

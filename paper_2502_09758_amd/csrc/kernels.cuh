@@ -262,11 +262,17 @@ __device__ __forceinline__ void tile_pos(const Params& pr, int lb, int nb, int& 
 // ------------------------------------------------------------------ generic convolution pass
 // cv_out = cv_ker (x) cv_in  [- cv_sub]   (correlation with cv_ker; the
 // flipped kernel gives the true convolution); with cv_part, per-block
-// partials of sum cv_out^2.  Instances without cv_out take no part.
+// partials of sum cv_out^2; optionally a second copy of the result and up to
+// two copies of the input (the set-up of a solve).  Instances without cv_out
+// take no part.
 template <typename T, int K, int R>
 __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only) {
     MAID_STENCIL_PROLOGUE
     if (!I.cv_out) return;
+    if (I.cv_prev_part && lb == 0) {
+        const double t = reduce_partials(I.cv_prev_part, I.nb);
+        if (threadIdx.x == 0) I.red[I.cv_prev_slot] = t;
+    }
     constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
@@ -294,6 +300,12 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
             T val = acc[o];
             if (sub) val -= sub[e];
             out[e] = val;
+            if (I.cv_out2) I.cv_out2[e] = val;
+            if (I.cv_cp[0]) {
+                const T xin = s[(li0 + o + c0) * CP + tx + c0];
+                I.cv_cp[0][e] = xin;
+                if (I.cv_cp[1]) I.cv_cp[1][e] = xin;
+            }
             sq += (double)val * (double)val;
         }
     }
@@ -645,7 +657,7 @@ __global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ i
 // p_new = r + beta p_old (p_new = r on the first iteration, beta =
 // gamma / gamma_prev) and Kp = theta*p_new.  r and p_old are staged while the
 // partials are in flight and combined once beta is known.  init = 1: the
-// set-up call that only copies r (holding q0) into p and forms theta*q0,
+// set-up call that copies the caller's q0 into q and p and forms theta*q0,
 // without touching the state.
 template <typename T, int K, int R>
 __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
@@ -672,7 +684,7 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     const int gj = tj0 + tx;
     const T* __restrict__ Pold = pick(I.P[0], I.P[1], st.pc) + ch * HW;
     T* __restrict__ Pnew = pick(I.P[0], I.P[1], st.pc ^ 1) + ch * HW;
-    const T* __restrict__ rc = I.r + ch * HW;
+    const T* __restrict__ rc = (init ? I.q0 : I.r) + ch * HW;
     const bool with_p = !init && !st.first;
     if (!SEQ) {
         load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return rc[g]; });
@@ -722,8 +734,10 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
         const int li = li0 + o, gi = ti0 + li;
         if (gi < H && gj < W) {
             const int64_t e = (int64_t)gi * W + gj;
-            Pnew[e] = s[(li + c0) * CP + tx + c0];
+            const T pv = s[(li + c0) * CP + tx + c0];
+            Pnew[e] = pv;
             Kp[e] = acc[o];
+            if (init) I.q[ch * HW + e] = pv;
         }
     }
 }
@@ -969,13 +983,31 @@ __global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* __restrict_
     }
 }
 
-// One block per instance: red[slot] = sum of the instance's cv_part partials.
+// One block per instance: red[slot] = sum of the instance's cv_part partials;
+// with sob_th, also red[sob_slot] = r(theta) = beta (w0 ||e||^2 + ||D_h e||^2
+// + ||D_v e||^2), e = theta - a, Neumann forward differences on the KxK grid.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_reduce(const Inst<T>* __restrict__ insts, int slot) {
+__global__ __launch_bounds__(kNT) void k_finish(const Inst<T>* __restrict__ insts, int slot, int sob_slot) {
     const Inst<T>& I = insts[blockIdx.x];
-    if (!I.cv_part) return;
-    const double s = reduce_partials(I.cv_part, I.nb);
-    if (threadIdx.x == 0) I.red[slot] = s;
+    if (I.cv_part) {
+        const double s = reduce_partials(I.cv_part, I.nb);
+        if (threadIdx.x == 0) I.red[slot] = s;
+    }
+    if (I.sob_th) {
+        const int K = I.K, KK = K * K;
+        const double* th = I.sob_th;
+        const double* a = I.sob_a;
+        double v = 0.0;
+        for (int t = threadIdx.x; t < KK; t += kNT) {
+            const int u = t / K, w = t - u * K;
+            const double e = th[t] - a[t];
+            const double dh = w < K - 1 ? (th[t + 1] - a[t + 1]) - e : 0.0;
+            const double dv = u < K - 1 ? (th[t + K] - a[t + K]) - e : 0.0;
+            v += I.h1_w0 * e * e + dh * dh + dv * dv;
+        }
+        const double s = block_sum(v);
+        if (threadIdx.x == 0) I.red[sob_slot] = I.beta * s;
+    }
 }
 
 // ------------------------------------------------------------------ hypergradient

@@ -55,8 +55,8 @@ hipError_t Ops<T>::prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, int s
 }
 
 template <typename T>
-hipError_t Ops<T>::reduce(const Inst<T>* insts, int n, int slot, hipStream_t s) {
-    return launch(k_reduce<T>, dim3(n), dim3(kNT), 0, s, insts, slot);
+hipError_t Ops<T>::finish(const Inst<T>* insts, int n, int slot, int sob_slot, hipStream_t s) {
+    return launch(k_finish<T>, dim3(n), dim3(kNT), 0, s, insts, slot, sob_slot);
 }
 
 template <typename T>
