@@ -46,7 +46,8 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [hipcc(), *FLAGS, "-x", "hip", "-c", src, "-o", obj]
+        # host-side units (no device code): one host pass
+        cmd = [hipcc(), *FLAGS, "-x", "hip", "--offload-host-only", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -93,6 +93,18 @@ __host__ __device__ constexpr int lds_cg_hvp(int K, int R, int C, int nw) {
 __host__ __device__ constexpr int lds_cg_dir(int K, int R) { return seq_lds(K) ? lds_conv(K, R) : 2 * lds_conv(K, R); }
 
 // ------------------------------------------------------------------ instance table
+// Every table pointer is a global-memory pointer: in the device pass it
+// carries the global address space, so loads and stores through it (and
+// through pointers derived from it) compile to global (not flat) memory
+// instructions, and uniform loads of read-only data to scalar loads.  The
+// host pass sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MAID_GLOBAL __attribute__((address_space(1)))
+#else
+#define MAID_GLOBAL
+#endif
+template <typename T> using gp = T MAID_GLOBAL*;
+
 template <typename T> struct Inst {
     Params pr;                   // C, H, W, reg, alpha, eps_tv
     int32_t K;                   // kernel size
@@ -101,42 +113,42 @@ template <typename T> struct Inst {
     int32_t cv_prev_slot;        // red slot for cv_prev_part's total
     int64_t N;                   // C*H*W
     // lower level (FISTA)
-    T* X[3];                     // iterates (rotating: cur, prev, next)
-    T* KX[3];                    // theta * x, kept by linearity
-    T* G;                        // gradient at the extrapolated point
-    const T* y;
-    T* th;                       // theta in the compute type, correlation form, column-major
-    T* thf;                      // the flipped kernel (convolution form), column-major
-    double* pA;                  // per-block partials, gradient pass (nb entries)
-    double* pB;                  // per-block partials, trial pass (nb entries)
-    int* trace;                  // rejected trials per iteration
-    T* xout;                     // where the returned point is written
+    gp<T> X[3];                     // iterates (rotating: cur, prev, next)
+    gp<T> KX[3];                    // theta * x, kept by linearity
+    gp<T> G;                        // gradient at the extrapolated point
+    gp<const T> y;
+    gp<T> th;                       // theta in the compute type, correlation form, column-major
+    gp<T> thf;                      // the flipped kernel (convolution form), column-major
+    gp<double> pA;                  // per-block partials, gradient pass (nb entries)
+    gp<double> pB;                  // per-block partials, trial pass (nb entries)
+    gp<int> trace;                  // rejected trials per iteration
+    gp<T> xout;                     // where the returned point is written
     // conjugate gradients
-    T* q;
-    T* r;
-    T* P[2];                     // search direction (ping-pong)
-    T* Kp;                       // theta * p
-    T* Hp;
-    const T* xt;                 // point the Hessian is taken at
-    const T* b;                  // right-hand side
-    const T* q0;                 // the caller's starting point (read by the set-up passes)
-    double* pR;                  // per-block partials of ||r||^2 (nbe entries)
-    double* pK;                  // per-block partials of <p, Hp> (nb entries)
+    gp<T> q;
+    gp<T> r;
+    gp<T> P[2];                     // search direction (ping-pong)
+    gp<T> Kp;                       // theta * p
+    gp<T> Hp;
+    gp<const T> xt;                 // point the Hessian is taken at
+    gp<const T> b;                  // right-hand side
+    gp<const T> q0;                 // the caller's starting point (read by the set-up passes)
+    gp<double> pR;                  // per-block partials of ||r||^2 (nbe entries)
+    gp<double> pK;                  // per-block partials of <p, Hp> (nb entries)
     // one convolution job: cv_out = cv_ker (x) cv_in [- cv_sub], partials of its square
-    const T* cv_ker;
-    const T* cv_in;
-    const T* cv_sub;
-    T* cv_out;
-    T* cv_out2;                  // nullable: a second copy of cv_out
-    T* cv_cp[2];                 // nullable: copies of cv_in
-    double* cv_part;             // nullable
-    const double* cv_prev_part;  // nullable: partials of an earlier pass, summed by block 0 into red[cv_prev_slot]
+    gp<const T> cv_ker;
+    gp<const T> cv_in;
+    gp<const T> cv_sub;
+    gp<T> cv_out;
+    gp<T> cv_out2;                  // nullable: a second copy of cv_out
+    gp<T> cv_cp[2];                 // nullable: copies of cv_in
+    gp<double> cv_part;             // nullable
+    gp<const double> cv_prev_part;  // nullable: partials of an earlier pass, summed by block 0 into red[cv_prev_slot]
     // kernel preparation: theta64 (K*K doubles) -> th / thf
-    const double* theta64;       // nullable: nothing to prepare
-    double* red;                 // per-instance reduction results (8 doubles)
+    gp<const double> theta64;       // nullable: nothing to prepare
+    gp<double> red;                 // per-instance reduction results (8 doubles)
     // Sobolev term r(theta) of Eq. (2.5) for the finishing pass (sob_th nullable)
-    const double* sob_th;
-    const double* sob_a;
+    gp<const double> sob_th;
+    gp<const double> sob_a;
     double beta, h1_w0;
 };
 

@@ -133,15 +133,29 @@ template <typename P>
 __device__ __forceinline__ P pick(P a0, P a1, int i) { return i == 0 ? a0 : a1; }
 
 // Stage f(global flat index) into an LDS tile s[ROWS][PITCH] covering rows
-// gi0.., columns gj0..; zero outside [0,H) x [0,W).
+// gi0.., columns gj0..; zero outside [0,H) x [0,W).  Each thread issues the
+// global loads of up to eight of its elements before it writes any of them
+// to LDS, so their latencies overlap instead of adding up.
 template <int ROWS, int COLS, int PITCH, typename T, typename F>
 __device__ __forceinline__ void load_tile(T* s, int gi0, int gj0, int H, int W, F f) {
-    for (int idx = threadIdx.x; idx < ROWS * COLS; idx += kNT) {
-        const int r = idx / COLS, cc = idx - r * COLS;
-        const int gi = gi0 + r, gj = gj0 + cc;
-        T val = T(0);
-        if (gi >= 0 && gi < H && gj >= 0 && gj < W) val = f((int64_t)gi * W + gj);
-        s[r * PITCH + cc] = val;
+    constexpr int NE = ROWS * COLS, IT = (NE + kNT - 1) / kNT, B = IT < 8 ? IT : 8;
+#pragma unroll 1
+    for (int k0 = 0; k0 < IT; k0 += B) {
+        T val[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int idx = threadIdx.x + (k0 + k) * kNT;
+            const int r = idx / COLS, cc = idx - r * COLS;
+            const int gi = gi0 + r, gj = gj0 + cc;
+            val[k] = T(0);
+            if (idx < NE && gi >= 0 && gi < H && gj >= 0 && gj < W) val[k] = f((int64_t)gi * W + gj);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int idx = threadIdx.x + (k0 + k) * kNT;
+            const int r = idx / COLS, cc = idx - r * COLS;
+            if (idx < NE) s[r * PITCH + cc] = val[k];
+        }
     }
 }
 
@@ -151,14 +165,22 @@ __device__ __forceinline__ void load_tile(T* s, int gi0, int gj0, int H, int W, 
 // column arrive in a few wide scalar loads.  The column loop stays rolled
 // for large K to bound register pressure (R+K-1 staged values, R
 // accumulators, K taps in SGPRs per iteration).
+// The taps are read through the constant address space: they are uniform and
+// nothing in the kernel writes them, so they arrive by scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MAID_CONST __attribute__((address_space(4)))
+#else
+#define MAID_CONST
+#endif
 template <typename T, int K, int R>
 __device__ __forceinline__ void correlate_col(const T* s, int pitch, const T* __restrict__ kT, int li0, int tx, int v, T (&acc)[R]) {
+    const T MAID_CONST* kc = (const T MAID_CONST*)kT;
     T col[R + K - 1];
 #pragma unroll
     for (int t = 0; t < R + K - 1; ++t) col[t] = s[(li0 + t) * pitch + tx + v];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-        const T w = kT[v * K + u];
+        const T w = kc[v * K + u];
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = dfma(w, col[o + u], acc[o]);
     }
