@@ -139,16 +139,19 @@ def traffic_for(workload: str, kernel: str, launches_per_work: float):
 
 
 def calibrate_copy(mib: int = 512, reps: int = 5):
-    """A plain device-to-device copy kernel (torch's elementwise copy) of
-    known size: reads and writes `mib` MiB per launch."""
+    """A plain streaming kernel of known size (torch's vectorised elementwise
+    kernel computing dst = 1 * src): reads and writes `mib` MiB per launch.
+    Serves as the scale of the PMC byte counters and as the measured
+    copy ceiling."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.arange(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     print(json.dumps({"calibration": "copy", "bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4,
