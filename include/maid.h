@@ -121,14 +121,15 @@ const char* maid_last_error(const maid_ctx* ctx);
    instances. */
 const char* maid_config_string(const maid_ctx* ctx);
 /* Override the rows-per-thread tile parameter of the stencil kernels for
-   every instance (1, 2 or 4; 0 = back to the autotuner's choice, else the
-   size rule). */
+   every instance (1, 2, 4 or 8; 8 applies to K >= 13, smaller kernels use 4;
+   0 = back to the autotuner's choice, else the size rule). */
 int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
 /* Autotuner: for each group of instances with the same K, time a short
    lower-level solve and a short CG solve (probe_iters iterations each,
-   1..1000, tolerance 0) with every rows-per-thread candidate (1, 2, 4) on
+   1..1000, tolerance 0) with every rows-per-thread candidate on
    the caller's data (theta[i], y[i]: HOST arrays of n DEVICE pointers, as
-   for the batched calls; only workspace is written) and keep the fastest.
+   for the batched calls; only workspace is written) and keep the fastest
+   (candidates 1, 2, 4, and 8 for K >= 13).
    rows_out (HOST, n, nullable): the choice per instance.  A later
    maid_set_tile_rows(ctx, r != 0) overrides the choice. */
 int maid_autotune(maid_ctx* ctx, const void* const* theta, const void* const* y, int32_t probe_iters,

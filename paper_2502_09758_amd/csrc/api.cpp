@@ -112,7 +112,7 @@ const char* maid_config_string(const maid_ctx* c) {
 
 int maid_set_tile_rows(maid_ctx* c, int32_t rows) {
     if (!c) return MAID_EINVAL;
-    if (rows != 0 && !valid_rows(rows)) return fail(c, MAID_EINVAL, "rows per thread must be 0, 1, 2 or 4");
+    if (rows != 0 && !valid_rows(rows)) return fail(c, MAID_EINVAL, "rows per thread must be 0, 1, 2, 4 or 8");
     c->R_override = rows;
     return relayout(c);
 }

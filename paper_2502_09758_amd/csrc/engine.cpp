@@ -284,7 +284,7 @@ int relayout(maid_ctx* c) {
     std::vector<int> host;
     for (int i = 0; i < c->n; ++i) {
         Member& M = c->m[i];
-        M.R = c->R_override ? c->R_override : (M.R_tuned ? M.R_tuned : M.R_auto);
+        M.R = c->R_override ? std::min(c->R_override, max_rows(M.d.K)) : (M.R_tuned ? M.R_tuned : M.R_auto);
         M.nb = stencil_blocks(M.shape, M.R);
     }
     std::vector<char> placed(c->n, 0);
@@ -856,7 +856,8 @@ int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, in
 }
 
 // ------------------------------------------------------------------ autotuner
-// For every candidate tile height (rows per thread 1, 2, 4) all instances
+// For every candidate tile height (rows per thread 1, 2, 4, and 8 for
+// K >= 13) all instances
 // take that candidate; a short lower-level solve and a short CG solve (fixed
 // iteration counts, tolerance 0, on the caller's data, writing only
 // workspace) run with per-launch timing, and the GPU time of the solver
@@ -866,7 +867,7 @@ template <typename T>
 int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const std::vector<const T*>& y, int probe_iters,
                    int32_t* rows_out, hipStream_t s) {
     const int n = c->n;
-    const int cands[3] = {1, 2, 4};
+    const int cands[4] = {1, 2, 4, 8};
     std::vector<int> Ks;
     for (int i = 0; i < n; ++i)
         if (std::find(Ks.begin(), Ks.end(), c->m[i].d.K) == Ks.end()) Ks.push_back(c->m[i].d.K);
@@ -896,7 +897,8 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
     for (int k = 0; k < (int)Ks.size() && rc == MAID_OK; ++k) {
         std::vector<char> act(n, 0);
         for (int i = 0; i < n; ++i) act[i] = c->m[i].d.K == Ks[k];
-        for (int ci = 0; ci < 3 && rc == MAID_OK; ++ci) {
+        for (int ci = 0; ci < 4 && rc == MAID_OK; ++ci) {
+            if (cands[ci] > max_rows(Ks[k])) continue;
             c->R_override = cands[ci];
             if ((rc = relayout(c))) break;
             for (int i = 0; i < n; ++i)

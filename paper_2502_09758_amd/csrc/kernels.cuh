@@ -253,7 +253,9 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
 // large-kernel passes need enough waves to hide their LDS latency, so their
 // register budget is capped at that of the plain convolution.
 // (FP32 storage only; the FP64 instantiations keep the compiler's choice).
-template <typename T> __host__ __device__ constexpr int min_waves(int K) { return sizeof(T) == 4 && seq_lds(K) ? 6 : 1; }
+template <typename T> __host__ __device__ constexpr int min_waves(int K, int R) {
+    return sizeof(T) == 4 && seq_lds(K) ? (R == 8 ? 5 : 6) : 1;
+}
 
 // ------------------------------------------------------------------ instance lookup
 // Block -> (instance, local block).  Padding blocks (lb >= nb) return at once.
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
 // an acceptance would move to is computed while the partials are in flight;
 // a rejection drops it before any store.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                   const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
     MAID_STENCIL_PROLOGUE
     ApgState st = sin[ii];
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 // the convolution of the stored x+ (two consecutive, so that both theta*x
 // and theta*x_prev, i.e. the momentum term, are exact again).
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                    const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
     MAID_STENCIL_PROLOGUE
     ApgState st = sin[ii];
@@ -769,7 +771,7 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
 // grad^2 R(x)[p] = D^T (w Dp - w^3 m Dx), m = <Dx, Dp> over the coupled
 // channels.  init = 1 computes H q0 only.
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K)))) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                 const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
     MAID_STENCIL_PROLOGUE
     const CgState st = sin[ii];

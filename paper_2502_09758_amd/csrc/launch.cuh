@@ -66,6 +66,9 @@ static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState*
         case 1: return FN<T, K, 1>(__VA_ARGS__);                   \
         case 2: return FN<T, K, 2>(__VA_ARGS__);                   \
         case 4: return FN<T, K, 4>(__VA_ARGS__);                   \
+        case 8:                                                    \
+            if constexpr (seq_lds(K)) return FN<T, K, 8>(__VA_ARGS__); \
+            else return hipErrorInvalidValue;                      \
         default: return hipErrorInvalidValue;                      \
     }
 

@@ -21,7 +21,10 @@ inline int stencil_blocks(const Shape& d, int R) {
     return ((d.W + kTW - 1) / kTW) * ((d.H + tile_h(R) - 1) / tile_h(R)) * d.C;
 }
 
-inline bool valid_rows(int R) { return R == 1 || R == 2 || R == 4; }
+// Rows per thread: 1, 2, 4, and 8 for the large kernels (K >= 13), whose
+// convolution reuses each staged column value over more outputs.
+inline bool valid_rows(int R) { return R == 1 || R == 2 || R == 4 || R == 8; }
+inline int max_rows(int K) { return seq_lds(K) ? 8 : 4; }
 
 // Kernel timing: while a pair of events is set (per host thread), every
 // launch hands them to the dispatch, which stamps them with the kernel's own

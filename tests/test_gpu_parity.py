@@ -51,7 +51,7 @@ SHAPES = [(1, 16, 16, 3), (1, 37, 70, 7), (3, 45, 130, 9), (2, 64, 64, 15), (1, 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("C,H,W,K", SHAPES)
-@pytest.mark.parametrize("rows", [1, 2, 4])
+@pytest.mark.parametrize("rows", [1, 2, 4, 8])
 def test_upper_value_grad(dt, C, H, W, K, rows):
     print(f"[case] upper_value_grad {dt} C={C} H={H} W={W} K={K} rows={rows}", flush=True)
     inst, p = problem(C, H, W, K)
@@ -214,3 +214,29 @@ def test_deterministic_bitwise():
         outs.append((x.clone(), q.clone(), z.clone()))
     for a, b in zip(outs[0], outs[1]):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("C,H,W,K,dt", [(3, 48, 100, 15, "f32"), (2, 70, 50, 31, "f32"), (1, 70, 90, 13, "f64")])
+def test_tall_tiles_solver_parity(C, H, W, K, dt):
+    """The 8-rows-per-thread tiles of the large kernels (64x32 outputs per
+    block, ragged in both directions here): lower-level replay and CG."""
+    print(f"[case] rows=8 solvers {dt} C={C} H={H} W={W} K={K}", flush=True)
+    inst, p = problem(C, H, W, K, seed=6)
+    y = stored(inst.y, dt)
+    m = Maid(C, H, W, K, DT[dt], alpha=p.alpha, eps_tv=p.eps_tv)
+    m.set_tile_rows(8)
+    assert "rows_per_thread=8" in m.config()
+    tol = 1e-4 if dt == "f64" else 3e-3
+    x = dev(y, DT[dt])
+    info = m.lower_solve(dev(inst.a, torch.float64), dev(y, DT[dt]), x, tol, max_iter=3000, trace=True)
+    assert info.status == L.OK and info.iters > 3
+    xr, _, _ = O.lower_solve(p, inst.a, y, y, tol=0.0, max_iter=info.iters, L=0.0, replay_bt=info.trace)
+    assert rel(host(x), xr) <= (1e-10 if dt == "f64" else 1e-5)
+    xt = host(x)
+    b, _, _ = O.upper_value_grad(p, inst.a, y, xt)
+    b = stored(b, dt)
+    q = torch.zeros((C, H, W), dtype=DT[dt], device="cuda")
+    ci = m.adjoint_solve(dev(inst.a, torch.float64), x, dev(b, DT[dt]), q, 1e-3 * np.linalg.norm(b), max_iter=2000)
+    assert ci.status == L.OK
+    qr, _ = O.adjoint_solve(p, inst.a, xt, b, tol=0.0, max_iter=ci.iters)
+    assert rel(host(q), qr) <= (1e-6 if dt == "f64" else 1e-5)
