@@ -257,6 +257,40 @@ template <typename T> __host__ __device__ constexpr int min_waves(int K, int R) 
     return sizeof(T) == 4 && seq_lds(K) ? (R == 8 ? 5 : 6) : 1;
 }
 
+// Several tiles staged together: every tile's global loads are issued (held
+// in registers) before any of them is written to LDS, so a pass that needs a
+// few small tiles pays one memory latency instead of one per tile.
+template <int ROWS, int COLS, int PITCH, typename T, typename F>
+struct Stage {
+    static constexpr int NE = ROWS * COLS, IT = (NE + kNT - 1) / kNT;
+    T* s;
+    int gi0, gj0;
+    F f;
+    T val[IT];
+    __device__ __forceinline__ void fetch(int H, int W) {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int idx = threadIdx.x + k * kNT;
+            const int r = idx / COLS, cc = idx - r * COLS;
+            const int gi = gi0 + r, gj = gj0 + cc;
+            val[k] = T(0);
+            if (idx < NE && gi >= 0 && gi < H && gj >= 0 && gj < W) val[k] = f((int64_t)gi * W + gj);
+        }
+    }
+    __device__ __forceinline__ void put() const {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int idx = threadIdx.x + k * kNT;
+            const int r = idx / COLS, cc = idx - r * COLS;
+            if (idx < NE) s[r * PITCH + cc] = val[k];
+        }
+    }
+};
+template <int ROWS, int COLS, int PITCH, typename T, typename F>
+__device__ __forceinline__ Stage<ROWS, COLS, PITCH, T, F> stage(T* s, int gi0, int gj0, F f) {
+    return Stage<ROWS, COLS, PITCH, T, F>{s, gi0, gj0, f, {}};
+}
+
 // ------------------------------------------------------------------ instance lookup
 // Block -> (instance, local block).  Padding blocks (lb >= nb) return at once.
 #define MAID_STENCIL_PROLOGUE                                         \
@@ -401,11 +435,30 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
             return dfma(m, kx - KXP[g], kx) - Yc[g];
         });
     };
-    for (int c = 0; c < C; ++c) {
+    auto vfun = [&](int c) {
         const T* Xc = X + c * HW;
         const T* XPc = XP + c * HW;
-        load_tile<VR, VP, VP>(s_v + c * VR * VP, ti0 - 1, tj0 - 1, H, W,
-                              [&](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); });
+        return [=](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); };
+    };
+    if constexpr (!SEQ) {
+        // all of this pass's tiles in one round of loads
+        auto v0 = stage<VR, VP, VP>(s_v, ti0 - 1, tj0 - 1, vfun(0));
+        auto v1 = stage<VR, VP, VP>(s_v + VR * VP, ti0 - 1, tj0 - 1, vfun(C > 1 ? 1 : 0));
+        auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, vfun(C > 2 ? 2 : 0));
+        auto rs = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int64_t g) {
+            const T kx = KX[g];
+            return dfma(m, kx - KXP[g], kx) - Yc[g];
+        });
+        v0.fetch(H, W);
+        if (C > 1) v1.fetch(H, W);
+        if (C > 2) v2.fetch(H, W);
+        rs.fetch(H, W);
+        v0.put();
+        if (C > 1) v1.put();
+        if (C > 2) v2.put();
+        rs.put();
+    } else {
+        for (int c = 0; c < C; ++c) load_tile<VR, VP, VP>(s_v + c * VR * VP, ti0 - 1, tj0 - 1, H, W, vfun(c));
     }
     // the backtracking decision; large kernels take it before their
     // convolution (occupancy first), small ones after it (latency first)
@@ -444,7 +497,6 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         }
         if (writer) put_state(&sout[ii], st);
     };
-    if (!SEQ) stage_residual();
     __syncthreads();
     if (SEQ) {
         decide();
@@ -710,9 +762,13 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     T* __restrict__ Pnew = pick(I.P[0], I.P[1], st.pc ^ 1) + ch * HW;
     const T* __restrict__ rc = (init ? I.q0 : I.r) + ch * HW;
     const bool with_p = !init && !st.first;
-    if (!SEQ) {
-        load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return rc[g]; });
-        if (with_p) load_tile<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return Pold[g]; });
+    if constexpr (!SEQ) {
+        auto sr = stage<CR, CP, CP>(s, ti0 - c0, tj0 - c0, [&](int64_t g) { return rc[g]; });
+        auto sp = stage<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, [&](int64_t g) { return Pold[g]; });
+        sr.fetch(H, W);
+        if (with_p) sp.fetch(H, W);
+        sr.put();
+        if (with_p) sp.put();
     }
     double beta = 0.0;
     if (!init) {
@@ -802,12 +858,25 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     T* s_mw = s_w + WR * WP;
     const T* kc = I.Kp + ch * HW;
     auto stage_kp = [&]() { load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return kc[g]; }); };
-    if (!SEQ) stage_kp();
     {
         const T* xc = I.xt + ch * HW;
         const T* pc = P + ch * HW;
-        load_tile<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return xc[g]; });
-        load_tile<VR, VP, VP>(s_p, ti0 - 1, tj0 - 1, H, W, [&](int64_t g) { return pc[g]; });
+        auto sx = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, [&](int64_t g) { return xc[g]; });
+        auto sp = stage<VR, VP, VP>(s_p, ti0 - 1, tj0 - 1, [&](int64_t g) { return pc[g]; });
+        if constexpr (!SEQ) {
+            auto sk = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int64_t g) { return kc[g]; });
+            sx.fetch(H, W);
+            sp.fetch(H, W);
+            sk.fetch(H, W);
+            sx.put();
+            sp.put();
+            sk.put();
+        } else {
+            sx.fetch(H, W);
+            sp.fetch(H, W);
+            sx.put();
+            sp.put();
+        }
     }
     const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
     for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
