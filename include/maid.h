@@ -59,7 +59,8 @@ enum {
     MAID_NONFINITE = -5
 };
 
-/* Problem description.  C in 1..3, K odd with 1 <= K <= 31 and K <= min(H,W).
+/* Problem description.  C in 1..3, K odd with 1 <= K <= 31 and K <= min(H,W),
+   H*W < 2^31.
    reg: MAID_REG_TV (smoothed TV, one gradient magnitude per pixel over all
    channels), MAID_REG_TV_CHANNELWISE (one per channel and pixel) or
    MAID_REG_QUADRATIC (R = 1/2 ||Dx||^2, the Tikhonov case).  alpha >= 0,

@@ -83,12 +83,17 @@ __host__ __device__ constexpr int lds_apg_grad(int K, int R, int C, int nw) {
     return lds_side(seq_lds(K), C * tv_rows(R) * tv_pitch() + nw * fx_rows(R) * fx_pitch(), lds_conv(K, R)) +
            (seq_lds(K) ? R * 256 : 0);
 }
-__host__ __device__ constexpr int lds_apg_trial(int K, int R, int C) { return lds_conv(K, R); }
+__host__ __device__ constexpr int lds_apg_trial(int K, int R, int C) {
+    // small kernels also stage v and the step of every channel for the TV decrease
+    return seq_lds(K) ? lds_conv(K, R) : lds_conv(K, R) + 2 * C * tv_rows(R) * tv_pitch();
+}
 __host__ __device__ constexpr int lds_cg_hvp(int K, int R, int C, int nw) {
-    // sequential staging parks the TV Hessian term and p of each output in LDS
-    // across the convolution (2 R values per thread)
-    return lds_side(seq_lds(K), 2 * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch(), lds_conv(K, R)) +
-           (seq_lds(K) ? 2 * R * 256 : 0);
+    // small kernels: the Kp tile, x and p of every channel, two weight planes;
+    // large kernels: x, p of one channel and the weight planes, then the Kp
+    // tile in the same region, plus a park for the TV term and p of each
+    // output (2 R values per thread)
+    return seq_lds(K) ? cmax(2 * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch(), lds_conv(K, R)) + 2 * R * 256
+                      : lds_conv(K, R) + 2 * C * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch();
 }
 __host__ __device__ constexpr int lds_cg_dir(int K, int R) { return seq_lds(K) ? lds_conv(K, R) : 2 * lds_conv(K, R); }
 

@@ -271,8 +271,8 @@ int validate_desc(const maid_desc* d, std::string& why) {
     if (d->reg != MAID_REG_QUADRATIC && !(d->eps_tv > 0 && finite(d->eps_tv))) { why = "eps_tv must be > 0"; return MAID_EINVAL; }
     if (!finite(d->beta) || d->beta < 0) { why = "beta must be finite and >= 0"; return MAID_EINVAL; }
     if (!finite(d->h1_w0) || d->h1_w0 < 0) { why = "h1_w0 must be finite and >= 0"; return MAID_EINVAL; }
-    const double n = (double)d->H * d->W * d->C;
-    if (n > 4.0e9) { why = "image too large"; return MAID_EINVAL; }
+    // one channel plane is indexed with 32-bit offsets in the kernels
+    if ((double)d->H * d->W >= 2147483648.0) { why = "H*W must be below 2^31"; return MAID_EINVAL; }
     return MAID_OK;
 }
 

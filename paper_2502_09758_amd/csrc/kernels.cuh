@@ -47,6 +47,11 @@ template <> __device__ __forceinline__ double dfma<double>(double a, double b, d
 template <typename T> __device__ __forceinline__ T dsqrt(T v);
 template <> __device__ __forceinline__ float dsqrt<float>(float v) { return sqrtf(v); }
 template <> __device__ __forceinline__ double dsqrt<double>(double v) { return sqrt(v); }
+// 1/sqrt: the hardware reciprocal square root for FP32 (1 ulp), the
+// correctly rounded quotient for FP64
+template <typename T> __device__ __forceinline__ T drsqrt(T v);
+template <> __device__ __forceinline__ float drsqrt<float>(float v) { return rsqrtf(v); }
+template <> __device__ __forceinline__ double drsqrt<double>(double v) { return 1.0 / sqrt(v); }
 
 // blockIdx -> tile id, XCD-major: the hardware hands block b to XCD b % 8;
 // this bijection gives every XCD a contiguous run of tile ids.
@@ -132,6 +137,19 @@ __device__ __forceinline__ P pick(P a0, P a1, P a2, int i) { return i == 0 ? a0 
 template <typename P>
 __device__ __forceinline__ P pick(P a0, P a1, int i) { return i == 0 ? a0 : a1; }
 
+// Element i of a channel plane: the byte offset is formed in 32 bits (a
+// plane holds < 4 GiB), so global loads and stores take the uniform 64-bit
+// plane base in SGPRs plus a 32-bit VGPR offset.
+template <typename T> __device__ __forceinline__ T& at(T* p, unsigned i) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (size_t)(i * (unsigned)sizeof(T)));
+}
+template <typename T> __device__ __forceinline__ const T& at(const T* p, unsigned i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (size_t)(i * (unsigned)sizeof(T)));
+}
+// inside [0,H) x [0,W), with one unsigned compare per axis
+__device__ __forceinline__ bool inside(int gi, int gj, int H, int W) { return (unsigned)gi < (unsigned)H && (unsigned)gj < (unsigned)W; }
+__device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+
 // Stage f(global flat index) into an LDS tile s[ROWS][PITCH] covering rows
 // gi0.., columns gj0..; zero outside [0,H) x [0,W).  Each thread issues the
 // global loads of up to eight of its elements before it writes any of them
@@ -147,8 +165,11 @@ __device__ __forceinline__ void load_tile(T* s, int gi0, int gj0, int H, int W, 
             const int idx = threadIdx.x + (k0 + k) * kNT;
             const int r = idx / COLS, cc = idx - r * COLS;
             const int gi = gi0 + r, gj = gj0 + cc;
-            val[k] = T(0);
-            if (idx < NE && gi >= 0 && gi < H && gj >= 0 && gj < W) val[k] = f((int64_t)gi * W + gj);
+            // every lane loads from a valid (clamped) address and zeroes what
+            // lies outside afterwards: no branch around the loads, so all of
+            // them are in flight before the first is used
+            const T v = f(clampi(gi, H - 1) * W + clampi(gj, W - 1));
+            val[k] = (idx < NE && inside(gi, gj, H, W)) ? v : T(0);
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -223,12 +244,12 @@ __device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg,
             const T dh = hx ? V[r * VP + cc + 1] - v0 : T(0);
             const T dv = vx ? V[(r + 1) * VP + cc] - v0 : T(0);
             if (reg == 1) {
-                s_w[ch * WR * WP + idx] = in ? T(1) / dsqrt(dh * dh + dv * dv + eps2) : T(0);
+                s_w[ch * WR * WP + idx] = in ? drsqrt(dh * dh + dv * dv + eps2) : T(0);
             } else {
                 s2 += dh * dh + dv * dv;
             }
         }
-        if (reg != 1) s_w[idx] = in ? (reg == 2 ? T(1) : T(1) / dsqrt(s2 + eps2)) : T(0);
+        if (reg != 1) s_w[idx] = in ? (reg == 2 ? T(1) : drsqrt(s2 + eps2)) : T(0);
     }
 }
 
@@ -250,11 +271,12 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
 }
 
 // Occupancy floor (waves per SIMD) the compiler must keep: the ALU-bound
-// large-kernel passes need enough waves to hide their LDS latency, so their
-// register budget is capped at that of the plain convolution.
+// large-kernel passes with tall tiles need enough waves to hide their LDS
+// latency, so their register budget is capped near that of the plain
+// convolution.
 // (FP32 storage only; the FP64 instantiations keep the compiler's choice).
 template <typename T> __host__ __device__ constexpr int min_waves(int K, int R) {
-    return sizeof(T) == 4 && seq_lds(K) ? (R == 8 ? 5 : 6) : 1;
+    return sizeof(T) == 4 && seq_lds(K) && R >= 4 ? (R == 8 ? 5 : 6) : 1;
 }
 
 // Several tiles staged together: every tile's global loads are issued (held
@@ -273,8 +295,11 @@ struct Stage {
             const int idx = threadIdx.x + k * kNT;
             const int r = idx / COLS, cc = idx - r * COLS;
             const int gi = gi0 + r, gj = gj0 + cc;
-            val[k] = T(0);
-            if (idx < NE && gi >= 0 && gi < H && gj >= 0 && gj < W) val[k] = f((int64_t)gi * W + gj);
+            // every lane loads from a valid (clamped) address and zeroes what
+            // lies outside afterwards: no branch around the loads, so all of
+            // them are in flight before the first is used
+            const T v = f(clampi(gi, H - 1) * W + clampi(gj, W - 1));
+            val[k] = (idx < NE && inside(gi, gj, H, W)) ? v : T(0);
         }
     }
     __device__ __forceinline__ void put() const {
@@ -340,9 +365,13 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
     tile_pos<R>(I.pr, lb, I.nb, ti0, tj0, ch);
     const int tx = threadIdx.x & 63, li0 = (threadIdx.x >> 6) * R;
     const T* __restrict__ src = I.cv_in + ch * HW;
-    const T* __restrict__ sub = I.cv_sub;
-    T* __restrict__ out = I.cv_out;
-    load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return src[g]; });
+    // channel planes (64-bit base once per block; 32-bit offsets inside)
+    const T* __restrict__ sub = I.cv_sub ? I.cv_sub + ch * HW : nullptr;
+    T* __restrict__ out = I.cv_out + ch * HW;
+    T* __restrict__ out2 = I.cv_out2 ? I.cv_out2 + ch * HW : nullptr;
+    T* __restrict__ cp0 = I.cv_cp[0] ? I.cv_cp[0] + ch * HW : nullptr;
+    T* __restrict__ cp1 = I.cv_cp[1] ? I.cv_cp[1] + ch * HW : nullptr;
+    load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(src, g); });
     __syncthreads();
     T acc[R];
 #pragma unroll
@@ -354,15 +383,15 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
     for (int o = 0; o < R; ++o) {
         const int gi = ti0 + li0 + o;
         if (gi < H && gj < W) {
-            const int64_t e = ch * HW + (int64_t)gi * W + gj;
+            const int e = gi * W + gj;
             T val = acc[o];
-            if (sub) val -= sub[e];
-            out[e] = val;
-            if (I.cv_out2) I.cv_out2[e] = val;
-            if (I.cv_cp[0]) {
+            if (sub) val -= at(sub, e);
+            at(out, e) = val;
+            if (out2) at(out2, e) = val;
+            if (cp0) {
                 const T xin = s[(li0 + o + c0) * CP + tx + c0];
-                I.cv_cp[0][e] = xin;
-                if (I.cv_cp[1]) I.cv_cp[1][e] = xin;
+                at(cp0, e) = xin;
+                if (cp1) at(cp1, e) = xin;
             }
             sq += (double)val * (double)val;
         }
@@ -430,24 +459,24 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     T* s_w = s_v + C * VR * VP;
     T* s_c = SEQ ? sm : s_w + nw * WR * WP;
     auto stage_residual = [&]() {
-        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) {
-            const T kx = KX[g];
-            return dfma(m, kx - KXP[g], kx) - Yc[g];
+        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
+            const T kx = at(KX, g);
+            return dfma(m, kx - at(KXP, g), kx) - at(Yc, g);
         });
     };
     auto vfun = [&](int c) {
         const T* Xc = X + c * HW;
         const T* XPc = XP + c * HW;
-        return [=](int64_t g) { const T xv = Xc[g]; return dfma(m, xv - XPc[g], xv); };
+        return [=](int g) { const T xv = at(Xc, g); return dfma(m, xv - at(XPc, g), xv); };
     };
     if constexpr (!SEQ) {
         // all of this pass's tiles in one round of loads
         auto v0 = stage<VR, VP, VP>(s_v, ti0 - 1, tj0 - 1, vfun(0));
         auto v1 = stage<VR, VP, VP>(s_v + VR * VP, ti0 - 1, tj0 - 1, vfun(C > 1 ? 1 : 0));
         auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, vfun(C > 2 ? 2 : 0));
-        auto rs = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int64_t g) {
-            const T kx = KX[g];
-            return dfma(m, kx - KXP[g], kx) - Yc[g];
+        auto rs = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) {
+            const T kx = at(KX, g);
+            return dfma(m, kx - at(KXP, g), kx) - at(Yc, g);
         });
         v0.fetch(H, W);
         if (C > 1) v1.fetch(H, W);
@@ -539,7 +568,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     for (int o = 0; o < R; ++o) {
         const int gi = ti0 + li0 + o;
         if (gi < H && gj < W) {
-            G[(int64_t)gi * W + gj] = gv[o];
+            at(G, gi * W + gj) = gv[o];
             gsq += (double)gv[o] * (double)gv[o];
         }
     }
@@ -597,9 +626,42 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     const T* __restrict__ G = I.G;
     const T* __restrict__ Y = I.y;
 
+    constexpr bool SEQ = seq_lds(K);
+    constexpr int VP = tv_pitch(), VR = tv_rows(R);
     T* s_c = sm;
+    T* s_v = sm + lds_conv(K, R);       // small kernels: v and dl of every channel, one-pixel halo
+    T* s_d = s_v + C * VR * VP;
     const T* Gc = G + ch * HW;
-    load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return Gc[g] * ninvL; });
+    auto sfun_v = [&](int c) {
+        const T* Xc = X + c * HW;
+        const T* XPc = XP + c * HW;
+        return [=](int g) { const T xv = at(Xc, g); return dfma(m, xv - at(XPc, g), xv); };
+    };
+    auto sfun_d = [&](int c) {
+        const T* Gcc = G + c * HW;
+        return [=](int g) { return at(Gcc, g) * ninvL; };
+    };
+    if constexpr (!SEQ) {
+        auto sg = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) { return at(Gc, g) * ninvL; });
+        auto v0 = stage<VR, VP, VP>(s_v, ti0 - 1, tj0 - 1, sfun_v(0));
+        auto v1 = stage<VR, VP, VP>(s_v + VR * VP, ti0 - 1, tj0 - 1, sfun_v(C > 1 ? 1 : 0));
+        auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, sfun_v(C > 2 ? 2 : 0));
+        auto d0 = stage<VR, VP, VP>(s_d, ti0 - 1, tj0 - 1, sfun_d(0));
+        auto d1 = stage<VR, VP, VP>(s_d + VR * VP, ti0 - 1, tj0 - 1, sfun_d(C > 1 ? 1 : 0));
+        auto d2 = stage<VR, VP, VP>(s_d + 2 * VR * VP, ti0 - 1, tj0 - 1, sfun_d(C > 2 ? 2 : 0));
+        sg.fetch(H, W);
+        v0.fetch(H, W);
+        d0.fetch(H, W);
+        if (C > 1) { v1.fetch(H, W); d1.fetch(H, W); }
+        if (C > 2) { v2.fetch(H, W); d2.fetch(H, W); }
+        sg.put();
+        v0.put();
+        d0.put();
+        if (C > 1) { v1.put(); d1.put(); }
+        if (C > 2) { v2.put(); d2.put(); }
+    } else {
+        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(Gc, g) * ninvL; });
+    }
     __syncthreads();
 
     bool trial = true;
@@ -626,27 +688,61 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     if (!trial) return;
 
     // ---- TV part of the decrease, per site: the tile's rows are dealt to its
-    // channel blocks in turn; v and dl come from global memory (L1/L2)
+    // channel blocks in turn; v and dl come from LDS (small kernels) or from
+    // global memory (L1/L2; large kernels keep their LDS for the convolution)
     const double e2 = I.pr.eps_tv * I.pr.eps_tv;
     double dtv = 0.0;
-    {
+    auto tv_site = [&](double bh, double bv, double ah, double av, double& ds2, double& s2) {
+        if (reg == 2) {
+            ds2 += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
+        } else if (reg == 1) {
+            const double d2 = ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
+            const double q2 = bh * bh + bv * bv;
+            dtv += d2 / (sqrt(q2 + d2 + e2) + sqrt(q2 + e2));
+        } else {
+            ds2 += ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
+            s2 += bh * bh + bv * bv;
+        }
+    };
+    if constexpr (!SEQ) {
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int li = li0 + o, gi = ti0 + li;
             if (li % C == ch && gi < H && gj < W) {
-                const int64_t e = (int64_t)gi * W + gj;
+                const int idx = (li + 1) * VP + tx + 1;
+                const bool hx = gj < W - 1, vx = gi < H - 1;
+                double ds2 = 0.0, s2 = 0.0;
+                for (int c = 0; c < C; ++c) {
+                    const T* V = s_v + c * VR * VP;
+                    const T* D = s_d + c * VR * VP;
+                    const double bh = hx ? (double)(V[idx + 1] - V[idx]) : 0.0;
+                    const double bv = vx ? (double)(V[idx + VP] - V[idx]) : 0.0;
+                    const double ah = hx ? (double)(D[idx + 1] - D[idx]) : 0.0;
+                    const double av = vx ? (double)(D[idx + VP] - D[idx]) : 0.0;
+                    tv_site(bh, bv, ah, av, ds2, s2);
+                }
+                if (reg == 2) dtv += ds2;
+                else if (reg == 0) dtv += ds2 / (sqrt(s2 + ds2 + e2) + sqrt(s2 + e2));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < R; ++o) {
+            const int li = li0 + o, gi = ti0 + li;
+            if (li % C == ch && gi < H && gj < W) {
+                const int e = gi * W + gj;
                 const bool hx = gj < W - 1, vx = gi < H - 1;
                 double ds2 = 0.0, s2 = 0.0;
                 for (int c = 0; c < C; ++c) {
                     const T* Xc = X + c * HW;
                     const T* XPc = XP + c * HW;
                     const T* Gcc = G + c * HW;
-                    auto vat = [&](int64_t f) { const T xv = Xc[f]; return dfma(m, xv - XPc[f], xv); };
-                    const T v0 = vat(e), d0 = Gcc[e] * ninvL;
+                    auto vat = [&](int f) { const T xv = at(Xc, f); return dfma(m, xv - at(XPc, f), xv); };
+                    const T v0 = vat(e), d0 = at(Gcc, e) * ninvL;
                     const double bh = hx ? (double)(vat(e + 1) - v0) : 0.0;
                     const double bv = vx ? (double)(vat(e + W) - v0) : 0.0;
-                    const double ah = hx ? (double)(Gcc[e + 1] * ninvL - d0) : 0.0;
-                    const double av = vx ? (double)(Gcc[e + W] * ninvL - d0) : 0.0;
+                    const double ah = hx ? (double)(at(Gcc, e + 1) * ninvL - d0) : 0.0;
+                    const double av = vx ? (double)(at(Gcc, e + W) * ninvL - d0) : 0.0;
                     if (reg == 2) {
                         ds2 += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
                     } else if (reg == 1) {
@@ -666,24 +762,52 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 
     // ---- data part of this block's channel, and the new iterate
     const bool exact = st.resync > 0 && (st.iters % st.resync) < 2;
+    const T* __restrict__ KXc = KX + ch * HW;
+    const T* __restrict__ KXPc = KXP + ch * HW;
+    const T* __restrict__ Yc = Y + ch * HW;
+    const T* __restrict__ Xc0 = X + ch * HW;
+    const T* __restrict__ XPc0 = XP + ch * HW;
+    T* __restrict__ XNc = XN + ch * HW;
+    T* __restrict__ KXNc = KXN + ch * HW;
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
     correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
     double ddat = 0.0;
+    // small kernels: every row's loads in flight before any is used (clamped
+    // addresses, no branch); large kernels keep their registers
+    constexpr int RL = SEQ ? 1 : R;
+    T kxr[RL], kxpr[RL], yr[RL], xr[RL], xpr[RL];
+    if constexpr (!SEQ) {
+#pragma unroll
+        for (int o = 0; o < R; ++o) {
+            const int e = clampi(ti0 + li0 + o, H - 1) * W + clampi(gj, W - 1);
+            kxr[o] = at(KXc, e);
+            kxpr[o] = at(KXPc, e);
+            yr[o] = at(Yc, e);
+            xr[o] = at(Xc0, e);
+            xpr[o] = at(XPc0, e);
+        }
+    }
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int li = li0 + o, gi = ti0 + li;
         if (gi < H && gj < W) {
-            const int64_t e = ch * HW + (int64_t)gi * W + gj;
-            const T kx = KX[e];
-            const T kv = dfma(m, kx - KXP[e], kx);
+            const int e = gi * W + gj;
+            const int q = SEQ ? 0 : o;
+            if constexpr (SEQ) {
+                kxr[0] = at(KXc, e);
+                kxpr[0] = at(KXPc, e);
+                yr[0] = at(Yc, e);
+                xr[0] = at(Xc0, e);
+                xpr[0] = at(XPc0, e);
+            }
+            const T kv = dfma(m, kxr[q] - kxpr[q], kxr[q]);
             const T d = acc[o];
-            const double rv = (double)kv - (double)Y[e];
+            const double rv = (double)kv - (double)yr[q];
             ddat += (double)d * (rv + 0.5 * (double)d);
-            const T xv = X[e];
-            XN[e] = dfma(m, xv - XP[e], xv) + s_c[(li + c0) * CP + tx + c0];
-            if (!exact) KXN[e] = kv + d;
+            at(XNc, e) = dfma(m, xr[q] - xpr[q], xr[q]) + s_c[(li + c0) * CP + tx + c0];
+            if (!exact) at(KXNc, e) = kv + d;
         }
     }
     if (exact) {
@@ -691,9 +815,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         const T* Xc = X + ch * HW;
         const T* XPc = XP + ch * HW;
         __syncthreads();
-        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) {
-            const T xv = Xc[g];
-            return dfma(m, xv - XPc[g], xv) + Gc[g] * ninvL;
+        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
+            const T xv = at(Xc, g);
+            return dfma(m, xv - at(XPc, g), xv) + at(Gc, g) * ninvL;
         });
         __syncthreads();
 #pragma unroll
@@ -702,7 +826,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int gi = ti0 + li0 + o;
-            if (gi < H && gj < W) KXN[ch * HW + (int64_t)gi * W + gj] = acc[o];
+            if (gi < H && gj < W) at(KXNc, gi * W + gj) = acc[o];
         }
     }
     block_partial(ddat + I.pr.alpha * dtv, I.pB, lb);
@@ -763,8 +887,8 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     const T* __restrict__ rc = (init ? I.q0 : I.r) + ch * HW;
     const bool with_p = !init && !st.first;
     if constexpr (!SEQ) {
-        auto sr = stage<CR, CP, CP>(s, ti0 - c0, tj0 - c0, [&](int64_t g) { return rc[g]; });
-        auto sp = stage<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, [&](int64_t g) { return Pold[g]; });
+        auto sr = stage<CR, CP, CP>(s, ti0 - c0, tj0 - c0, [&](int g) { return at(rc, g); });
+        auto sp = stage<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, [&](int g) { return at(Pold, g); });
         sr.fetch(H, W);
         if (with_p) sp.fetch(H, W);
         sr.put();
@@ -795,9 +919,9 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     if (SEQ) {
         const T bT = (T)beta;
         if (with_p)
-            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return dfma(bT, Pold[g], rc[g]); });
+            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return dfma(bT, at(Pold, g), at(rc, g)); });
         else
-            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return rc[g]; });
+            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(rc, g); });
     } else if (with_p) {
         __syncthreads();
         const T bT = (T)beta;
@@ -809,15 +933,16 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     for (int o = 0; o < R; ++o) acc[o] = T(0);
     correlate<T, K, R>(s, CP, I.thf, li0, tx, acc);
     T* __restrict__ Kp = I.Kp + ch * HW;
+    T* __restrict__ qc = I.q + ch * HW;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int li = li0 + o, gi = ti0 + li;
         if (gi < H && gj < W) {
-            const int64_t e = (int64_t)gi * W + gj;
+            const int e = gi * W + gj;
             const T pv = s[(li + c0) * CP + tx + c0];
-            Pnew[e] = pv;
-            Kp[e] = acc[o];
-            if (init) I.q[ch * HW + e] = pv;
+            at(Pnew, e) = pv;
+            at(Kp, e) = acc[o];
+            if (init) at(qc, e) = pv;
         }
     }
 }
@@ -846,67 +971,105 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     const T alpha = (T)I.pr.alpha;
     const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
 
-    // LDS: x and p of this block's channel with a one-pixel halo, and the
-    // weight planes w, w^3 m of the flux sites; the weights couple the
-    // channels and are formed from global memory (L1/L2-resident neighbours),
-    // which keeps the footprint independent of C.
+    // LDS: x and p with a one-pixel halo (small kernels: every channel, all
+    // staged with the Kp tile in one round; large kernels: this block's
+    // channel only, the coupled weights then formed from global memory, so
+    // the footprint does not grow with C), and the weight planes w, w^3 m of
+    // the flux sites (one each: reg 1 needs only this channel's).
     constexpr bool SEQ = seq_lds(K);
+    const int nx = SEQ ? 1 : C;
     T* s_c = sm;
     T* s_x = SEQ ? sm : s_c + lds_conv(K, R);
-    T* s_p = s_x + VR * VP;
-    T* s_w = s_p + VR * VP;
+    T* s_p = s_x + nx * VR * VP;
+    T* s_w = s_p + nx * VR * VP;
     T* s_mw = s_w + WR * WP;
     const T* kc = I.Kp + ch * HW;
-    auto stage_kp = [&]() { load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int64_t g) { return kc[g]; }); };
-    {
-        const T* xc = I.xt + ch * HW;
-        const T* pc = P + ch * HW;
-        auto sx = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, [&](int64_t g) { return xc[g]; });
-        auto sp = stage<VR, VP, VP>(s_p, ti0 - 1, tj0 - 1, [&](int64_t g) { return pc[g]; });
-        if constexpr (!SEQ) {
-            auto sk = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int64_t g) { return kc[g]; });
-            sx.fetch(H, W);
-            sp.fetch(H, W);
-            sk.fetch(H, W);
-            sx.put();
-            sp.put();
-            sk.put();
-        } else {
-            sx.fetch(H, W);
-            sp.fetch(H, W);
-            sx.put();
-            sp.put();
-        }
-    }
+    auto stage_kp = [&]() { load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(kc, g); }); };
+    auto xfun = [&](int c) { const T* xc = I.xt + c * HW; return [=](int g) { return at(xc, g); }; };
+    auto pfun = [&](int c) { const T* pc = P + c * HW; return [=](int g) { return at(pc, g); }; };
     const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
-    for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
-        const int r = idx / WP, cc = idx - r * WP;
-        const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
-        const bool in = (gi >= 0 && gi < H && gj2 >= 0 && gj2 < W);
-        const bool hx = gj2 < W - 1, vx = gi < H - 1;
-        T s2 = T(0), mm = T(0);
-        if (in && reg != 2) {
-            const int64_t e = (int64_t)gi * W + gj2;
+    if constexpr (!SEQ) {
+        auto sk = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) { return at(kc, g); });
+        auto x0 = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, xfun(0));
+        auto x1 = stage<VR, VP, VP>(s_x + VR * VP, ti0 - 1, tj0 - 1, xfun(C > 1 ? 1 : 0));
+        auto x2 = stage<VR, VP, VP>(s_x + 2 * VR * VP, ti0 - 1, tj0 - 1, xfun(C > 2 ? 2 : 0));
+        auto p0 = stage<VR, VP, VP>(s_p, ti0 - 1, tj0 - 1, pfun(0));
+        auto p1 = stage<VR, VP, VP>(s_p + VR * VP, ti0 - 1, tj0 - 1, pfun(C > 1 ? 1 : 0));
+        auto p2 = stage<VR, VP, VP>(s_p + 2 * VR * VP, ti0 - 1, tj0 - 1, pfun(C > 2 ? 2 : 0));
+        sk.fetch(H, W);
+        x0.fetch(H, W);
+        p0.fetch(H, W);
+        if (C > 1) { x1.fetch(H, W); p1.fetch(H, W); }
+        if (C > 2) { x2.fetch(H, W); p2.fetch(H, W); }
+        sk.put();
+        x0.put();
+        p0.put();
+        if (C > 1) { x1.put(); p1.put(); }
+        if (C > 2) { x2.put(); p2.put(); }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
+            const int r = idx / WP, cc = idx - r * WP;
+            const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
+            const bool in = inside(gi, gj2, H, W);
+            const bool hx = gj2 < W - 1, vx = gi < H - 1;
+            const int i0 = r * VP + cc;
+            T s2 = T(0), mm = T(0);
             const int c_lo = reg == 1 ? ch : 0, c_hi = reg == 1 ? ch + 1 : C;
             for (int c = c_lo; c < c_hi; ++c) {
-                const T* xc = I.xt + c * HW;
-                const T* pc = P + c * HW;
-                const T x0 = xc[e], p0 = pc[e];
-                const T xh = hx ? xc[e + 1] - x0 : T(0);
-                const T xv = vx ? xc[e + W] - x0 : T(0);
-                const T ph = hx ? pc[e + 1] - p0 : T(0);
-                const T pv = vx ? pc[e + W] - p0 : T(0);
+                const T* Xv = s_x + c * VR * VP;
+                const T* Pv = s_p + c * VR * VP;
+                const T xh = hx ? Xv[i0 + 1] - Xv[i0] : T(0);
+                const T xv = vx ? Xv[i0 + VP] - Xv[i0] : T(0);
+                const T ph = hx ? Pv[i0 + 1] - Pv[i0] : T(0);
+                const T pv = vx ? Pv[i0 + VP] - Pv[i0] : T(0);
                 s2 += xh * xh + xv * xv;
                 mm += xh * ph + xv * pv;
             }
+            if (reg == 2) {
+                s_w[idx] = in ? T(1) : T(0);
+                s_mw[idx] = T(0);
+            } else {
+                const T w = in ? drsqrt(s2 + eps2) : T(0);
+                s_w[idx] = w;
+                s_mw[idx] = w * w * w * mm;
+            }
         }
-        if (reg == 2) {
-            s_w[idx] = in ? T(1) : T(0);
-            s_mw[idx] = T(0);
-        } else {
-            const T w = in ? T(1) / dsqrt(s2 + eps2) : T(0);
-            s_w[idx] = w;
-            s_mw[idx] = w * w * w * mm;
+    } else {
+        auto sx = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, xfun(ch));
+        auto sp = stage<VR, VP, VP>(s_p, ti0 - 1, tj0 - 1, pfun(ch));
+        sx.fetch(H, W);
+        sp.fetch(H, W);
+        sx.put();
+        sp.put();
+        for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
+            const int r = idx / WP, cc = idx - r * WP;
+            const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
+            const bool in = inside(gi, gj2, H, W);
+            // clamped neighbours: outside the image a difference reads zero
+            const int gic = clampi(gi, H - 1), gjc = clampi(gj2, W - 1);
+            const int e = gic * W + gjc;
+            const int eh = gjc < W - 1 ? e + 1 : e, ev = gic < H - 1 ? e + W : e;
+            T s2 = T(0), mm = T(0);
+            if (reg != 2) {
+                const int c_lo = reg == 1 ? ch : 0, c_hi = reg == 1 ? ch + 1 : C;
+                for (int c = c_lo; c < c_hi; ++c) {
+                    const T* xc = I.xt + c * HW;
+                    const T* pc = P + c * HW;
+                    const T x0 = at(xc, e), p0 = at(pc, e);
+                    const T xh = at(xc, eh) - x0, xv = at(xc, ev) - x0;
+                    const T ph = at(pc, eh) - p0, pv = at(pc, ev) - p0;
+                    s2 += xh * xh + xv * xv;
+                    mm += xh * ph + xv * pv;
+                }
+            }
+            if (reg == 2) {
+                s_w[idx] = in ? T(1) : T(0);
+                s_mw[idx] = T(0);
+            } else {
+                const T w = in ? drsqrt(s2 + eps2) : T(0);
+                s_w[idx] = w;
+                s_mw[idx] = w * w * w * mm;
+            }
         }
     }
     __syncthreads();
@@ -914,8 +1077,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
     if (!SEQ) correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
-    const T* Xv = s_x;
-    const T* Pv = s_p;
+    const T* Xv = s_x + (SEQ ? 0 : ch) * VR * VP;
+    const T* Pv = s_p + (SEQ ? 0 : ch) * VR * VP;
     const T* Wt = s_w;
     const T* Mw = s_mw;
     // SEQ: the TV term and p of each output wait in LDS past the tile region
@@ -962,7 +1125,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
             const T hv = SEQ ? s_park[o * kNT + threadIdx.x] : hvv[SEQ ? 0 : o];
             const T pp = SEQ ? s_park[(R + o) * kNT + threadIdx.x] : pc[SEQ ? 0 : o];
             const T hp = dfma(alpha, hv, acc[o]);
-            Hp[(int64_t)gi * W + gj] = hp;
+            at(Hp, gi * W + gj) = hp;
             kap += (double)pp * (double)hp;
         }
     }
@@ -1016,12 +1179,28 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
         r[e0] = rv;
         rs += (double)rv * (double)rv;
     }
-    for (int64_t e = e0 + stride; e < I.N; e += stride) {
-        const T pe = P[e];
-        q[e] = dfma(a, pe, q[e]);
-        const T rv = dfma(-a, Hp[e], r[e]);
-        r[e] = rv;
-        rs += (double)rv * (double)rv;
+    // the rest four at a time, every load in flight before any is used
+    for (int64_t e = e0 + stride; e < I.N; e += 4 * stride) {
+        T pv[4], qv[4], rv[4], hv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t ek = e + k * stride;
+            const int64_t el = ek < I.N ? ek : 0;
+            pv[k] = P[el];
+            qv[k] = q[el];
+            rv[k] = r[el];
+            hv[k] = Hp[el];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t ek = e + k * stride;
+            if (ek < I.N) {
+                q[ek] = dfma(a, pv[k], qv[k]);
+                const T rn = dfma(-a, hv[k], rv[k]);
+                r[ek] = rn;
+                rs += (double)rn * (double)rn;
+            }
+        }
     }
     block_partial(rs, I.pR, lb);
 }
@@ -1147,12 +1326,12 @@ __global__ __launch_bounds__(kNT) void k_hg_corr(int C, int H, int W, int K, con
         for (int idx = threadIdx.x; idx < arows * kHgTJ; idx += kNT) {
             const int r = idx / kHgTJ, cc = idx - r * kHgTJ;
             const int gi = ti0 - c0 + r, gj = tj0 + cc;
-            sA[r * AP + cc] = (gi >= 0 && gi < H && gj < W) ? Asrc[(int64_t)gi * W + gj] : T(0);
+            sA[r * AP + cc] = (gi >= 0 && gi < H && gj < W) ? Asrc[gi * W + gj] : T(0);
         }
         for (int idx = threadIdx.x; idx < kHgTI * bcols; idx += kNT) {
             const int r = idx / bcols, cc = idx - r * bcols;
             const int gi = ti0 + r, gj = tj0 - c0 + cc;
-            sB[r * BP + cc] = (gi < H && gj >= 0 && gj < W) ? Bsrc[(int64_t)gi * W + gj] : T(0);
+            sB[r * BP + cc] = (gi < H && gj >= 0 && gj < W) ? Bsrc[gi * W + gj] : T(0);
         }
         __syncthreads();
         for (int li = wid; li < kHgTI; li += 4) {
