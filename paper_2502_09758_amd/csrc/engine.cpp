@@ -5,6 +5,8 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -86,6 +88,29 @@ template <typename T> int upload(maid_ctx* c, int role, hipStream_t s) {
     return MAID_OK;
 }
 int pull_red(maid_ctx* c, hipStream_t s) { return pull(c, s, c->red, sizeof(double) * kRedSlots * c->n); }
+
+// Like pull, without synchronising the stream: a one-block kernel copies
+// the range into host-visible memory and raises a flag, which the host
+// waits for (with the stream synchronisation as the fallback after a long
+// wait).  The state lands in the same mirror as with pull.
+int publish(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n) {
+    const size_t off = (const char*)dev_ptr - c->st_dev;
+    volatile unsigned* flag = c->pub_flag;
+    *flag = 0u;
+    HIP_TRY(launch_publish(c->st_dev + off, n, c->pub + off, c->pub_flag, s));
+    const auto t0 = std::chrono::steady_clock::now();
+    long spins = 0;
+    while (*flag == 0u) {
+        if ((++spins & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
+            HIP_TRY(hipStreamSynchronize(s));
+            if (*flag == 0u) return fail(c, MAID_EHIP, "state publication did not arrive");
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    std::memcpy(c->st_host + off, c->pub + off, n);
+    return MAID_OK;
+}
 
 // Table entry of instance i with every workspace pointer set; the caller
 // adds the per-call pointers.
@@ -362,6 +387,7 @@ void destroy_ctx(maid_ctx* c) {
     if (c->ws) (void)hipFree(c->ws);
     if (c->st_dev) (void)hipFree(c->st_dev);
     if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->pub) (void)hipHostFree(c->pub);
     if (c->tab_dev) (void)hipFree(c->tab_dev);
     if (c->tab_host) (void)hipHostFree(c->tab_host);
     if (c->maps) (void)hipFree(c->maps);
@@ -411,6 +437,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->st_dev, c->st_bytes);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->st_host, c->st_bytes, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&c->pub, c->st_bytes + 256, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) c->pub_flag = (unsigned*)(c->pub + c->st_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->tab_dev, tab_bytes);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->tab_host, tab_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&c->maps, maps * sizeof(int));
@@ -550,7 +579,7 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         });
         if (rc) return rc;
         slots += chunk;
-        TRY(pull(c, s, c->apg[0], n * sizeof(ApgState)));
+        TRY(publish(c, s, c->apg[0], n * sizeof(ApgState)));
         bool done = true;
         for (int i = 0; i < n; ++i) done = done && c->apg_h[i].done;
         if (done) break;
@@ -646,7 +675,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         });
         if (rc) return rc;
         slots += chunk;
-        TRY(pull(c, s, c->cg[0], n * sizeof(CgState)));
+        TRY(publish(c, s, c->cg[0], n * sizeof(CgState)));
         bool done = true;
         for (int i = 0; i < n; ++i) done = done && c->cg_h[i].done;
         if (done) break;

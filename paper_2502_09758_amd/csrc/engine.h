@@ -95,6 +95,10 @@ struct maid_ctx {
     // device-resident solver states (+ pinned host mirror of the same layout)
     char* st_dev = nullptr;
     char* st_host = nullptr;
+    // host-visible, GPU-writable copy of the state block and its ready flag:
+    // the solver loops learn the state without a stream synchronisation
+    char* pub = nullptr;
+    unsigned* pub_flag = nullptr;
     size_t st_bytes = 0;
     maid::ApgState* apg[2] = {};      // device arrays of n
     maid::CgState* cg[3] = {};

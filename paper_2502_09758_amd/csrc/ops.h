@@ -73,6 +73,7 @@ template <typename T> struct Ops {
 
 hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
                            const double* a, int with_r, double* z, double* znorm2, hipStream_t s);
+hipError_t launch_publish(const void* src, size_t bytes, void* dst_host, unsigned* flag_host, hipStream_t s);
 hipError_t launch_theta_step(const double* th, const double* z, double step, double* out, int KK, hipStream_t s);
 hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s);
 int hg_items(const Shape& d);

@@ -125,6 +125,22 @@ hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w,
     return launch((k_hg_corr<T, 32>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
 }
 
+// Copy `words` 32-bit words of solver state into host-visible memory and
+// then raise *flag: every thread's stores are made visible system-wide before
+// the flag is written, so a host that sees the flag reads complete state.
+__global__ __launch_bounds__(kNT) void k_publish(const unsigned* __restrict__ src, int words, unsigned* dst,
+                                                 unsigned* flag) {
+    for (int i = threadIdx.x; i < words; i += kNT) dst[i] = src[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) *(volatile unsigned*)flag = 1u;
+}
+
+hipError_t launch_publish(const void* src, size_t bytes, void* dst_host, unsigned* flag_host, hipStream_t s) {
+    return launch(k_publish, dim3(1), dim3(kNT), 0, s, (const unsigned*)src, (int)(bytes / 4), (unsigned*)dst_host,
+                  flag_host);
+}
+
 template struct Ops<float>;
 template struct Ops<double>;
 
