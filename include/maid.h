@@ -125,6 +125,20 @@ const char* maid_config_string(const maid_ctx* ctx);
    every instance (1, 2, 4 or 8; 8 applies to K >= 13, smaller kernels use 4;
    0 = back to the autotuner's choice, else the size rule). */
 int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
+/* Persistent loops for small instances.  The lower-level and CG loops of a
+   group of instances with at most 64 tiles each (and tile rows 1, 2 or 4)
+   run inside one kernel per solve on teams of blocks, one team per XCD,
+   which meet at barriers through the XCD's L2 instead of at kernel
+   boundaries; a batch runs up to eight instances at once.  Results are
+   bitwise those of the multi-kernel passes (same passes, same sums).
+   members: -1 = size rule (one member per tile of the group's largest
+   instance, capped by occupancy and by the tiles of the smallest instance),
+   0 = never, 1..128 = that many (capped the same way; larger instances
+   then take the team path too).  If a team cannot assemble (its blocks not
+   resident together), the solve is repeated on the multi-kernel passes
+   and the context stays on them.  The choice shows in
+   maid_config_string ("team=P"). */
+int maid_set_team(maid_ctx* ctx, int32_t members);
 /* Autotuner: for each group of instances with the same K, time a short
    lower-level solve and a short CG solve (probe_iters iterations each,
    1..1000, tolerance 0) with every rows-per-thread candidate on
@@ -262,7 +276,9 @@ enum {
     MAID_PROF_CG_UPDATE = 5,  /* CG: q, r update and residual norm */
     MAID_PROF_HG_CORR = 6,    /* hypergradient correlation (FP64 MFMA) */
     MAID_PROF_OTHER = 7,      /* small kernels */
-    MAID_PROF_KINDS = 8
+    MAID_PROF_APG_TEAM = 8,   /* lower-level loop of small instances on one team per XCD (work: slots) */
+    MAID_PROF_CG_TEAM = 9,    /* CG loop of small instances on one team per XCD (work: iterations) */
+    MAID_PROF_KINDS = 10
 };
 int maid_profile(maid_ctx* ctx, int32_t enable);
 int maid_profile_read(maid_ctx* ctx, int32_t kind, int64_t* launches, int64_t* work_launches, double* total_ms);

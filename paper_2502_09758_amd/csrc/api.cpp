@@ -117,6 +117,14 @@ int maid_set_tile_rows(maid_ctx* c, int32_t rows) {
     return relayout(c);
 }
 
+int maid_set_team(maid_ctx* c, int32_t members) {
+    if (!c) return MAID_EINVAL;
+    if (members < -1 || members > kTeamMax)
+        return fail(c, MAID_EINVAL, "members per team must be -1 (size rule), 0 (off) or 1..128");
+    c->team_req = members;
+    return relayout(c);
+}
+
 int maid_profile(maid_ctx* c, int32_t enable) {
     if (!c) return MAID_EINVAL;
     prof_harvest(c);
@@ -139,8 +147,8 @@ int maid_profile_read(maid_ctx* c, int32_t kind, int64_t* launches, int64_t* wor
 }
 
 const char* maid_profile_name(int32_t kind) {
-    static const char* names[MAID_PROF_KINDS] = {"conv", "apg_grad", "apg_trial", "cg_dir", "cg_hvp",
-                                                  "cg_update", "hg_corr", "other"};
+    static const char* names[MAID_PROF_KINDS] = {"conv",    "apg_grad", "apg_trial", "cg_dir",   "cg_hvp",
+                                                  "cg_update", "hg_corr", "other",    "apg_team", "cg_team"};
     if (kind < 0 || kind >= MAID_PROF_KINDS) return "";
     return names[kind];
 }

@@ -51,6 +51,18 @@ struct CgState {
     int32_t max, iters, status, done, pc, first;
 };
 
+// Control block of a team launch (the persistent solver loops for small
+// instances): one team of P blocks per XCD.
+constexpr int kTeamMax = 128;    // members per team
+constexpr int kTeamXcd = 8;      // teams per launch (XCDs)
+struct TeamCtl {
+    uint64_t* arrive;     // kTeamXcd x kTeamMax arrival words, never reset
+    unsigned* err;        // nonzero once a member gave up waiting
+    uint64_t epoch;       // (launch number) << 32: arrival words only grow
+    int32_t P;            // members per team
+    int64_t wait;         // wall-clock ticks a member waits at most
+};
+
 // Problem parameters the kernels need (part of the instance table, which
 // kernels only read, so they come in through scalar loads).
 struct Params {

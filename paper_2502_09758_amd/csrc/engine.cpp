@@ -201,7 +201,8 @@ void prof_harvest(maid_ctx* c) {
             c->prof_ms[r.kind] += ms;
             // kinds without early exits: every launch works
             if (r.kind != MAID_PROF_APG_GRAD && r.kind != MAID_PROF_APG_TRIAL && r.kind != MAID_PROF_CG_DIR &&
-                r.kind != MAID_PROF_CG_HVP && r.kind != MAID_PROF_CG_UPDATE)
+                r.kind != MAID_PROF_CG_HVP && r.kind != MAID_PROF_CG_UPDATE && r.kind != MAID_PROF_APG_TEAM &&
+                r.kind != MAID_PROF_CG_TEAM)
                 c->prof_work[r.kind] += 1;
         }
         c->prof_pool.push_back(r.a);
@@ -301,6 +302,33 @@ int validate_desc(const maid_desc* d, std::string& why) {
     return MAID_OK;
 }
 
+// Members per team of a group's persistent loops, 0 for the multi-kernel
+// passes.  Every member must hold at least one tile and one elementwise
+// block of each instance (each member takes the solver decisions itself), and
+// a team must fit on its XCD at once.  Size rule: the team path for groups
+// whose instances have at most kTeamTiles tiles, one tile per member.  A pass
+// on one XCD is bound by that XCD's vector ALUs once each member holds more
+// than one tile (measured: 128x128 at one row per thread, 64 tiles, runs
+// lower + CG iterations ~17% faster on teams than as kernels; 256x256, 256
+// tiles, 2.4x slower), so larger instances stay on the multi-kernel passes.
+constexpr int kTeamTiles = 64;
+int team_members(maid_ctx* c, const LaunchGroup& lg) {
+    if (!c->team_ok || c->team_req == 0 || lg.g.R > 4) return 0;
+    int most_tiles = 0, cap = kTeamMax;
+    for (int i : lg.members) {
+        most_tiles = std::max(most_tiles, c->m[i].nb);
+        cap = std::min(cap, std::min(c->m[i].nb, c->m[i].nbe));
+    }
+    if (c->team_req < 0 && most_tiles > kTeamTiles) return 0;
+    int bpc = 0;
+    const hipError_t e = c->dtype == MAID_F64 ? Ops<double>::team_occupancy(lg.g, &bpc)
+                                              : Ops<float>::team_occupancy(lg.g, &bpc);
+    if (e != hipSuccess || bpc < 1) return 0;
+    cap = std::min(cap, bpc * c->cus_per_xcd);
+    const int want = c->team_req > 0 ? c->team_req : most_tiles;
+    return std::max(0, std::min(want, cap));
+}
+
 // Group the instances by (K, tile rows), give each instance a block range
 // starting at a multiple of 8 (so that the XCD-major tile order holds within
 // every instance), build the block -> instance maps and upload them.
@@ -357,6 +385,11 @@ int relayout(maid_ctx* c) {
         const int end = i + 1 < c->n ? c->m[i + 1].base_e : c->grid_e;
         for (int b = c->m[i].base_e; b < end; ++b) host[off_e + b] = i;
     }
+    std::vector<size_t> offs_l;
+    for (auto& lg : c->groups) {
+        offs_l.push_back(host.size());
+        host.insert(host.end(), lg.members.begin(), lg.members.end());
+    }
     if (host.size() > c->maps_cap) return fail(c, MAID_EHIP, "relayout: block maps exceed their allocation");
     HIP_TRY(hipMemcpy(c->maps, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
     for (size_t g = 0; g < c->groups.size(); ++g) {
@@ -365,6 +398,11 @@ int relayout(maid_ctx* c) {
     }
     c->blk_e = c->maps + off_e;
     c->only_e = c->n == 1 ? 0 : -1;
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        LaunchGroup& lg = c->groups[g];
+        lg.list = c->maps + offs_l[g];
+        lg.team = team_members(c, lg);
+    }
     c->layout_gen += 1;
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
@@ -374,8 +412,44 @@ int relayout(maid_ctx* c) {
         std::snprintf(buf, sizeof(buf), "%sK=%d rows_per_thread=%d tile=64x%d instances=%zu", c->cfg.empty() ? "" : "; ",
                       lg.g.K, lg.g.R, tile_h(lg.g.R), lg.members.size());
         c->cfg += buf;
+        if (lg.team > 0) {
+            std::snprintf(buf, sizeof(buf), " team=%d", lg.team);
+            c->cfg += buf;
+        }
     }
     return MAID_OK;
+}
+
+// The team loops need every XCD's blocks to be the ones the XCC_ID register
+// names and the hardware to deal blocks to the XCDs round-robin (block b to
+// XCD (b + b0) mod 8); a map of one grid checks both.  Without it (another
+// partitioning of the device, another dispatch order) the team path stays
+// off.
+hipError_t team_setup(maid_ctx* c) {
+    int dev = 0, cus = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    c->cus_per_xcd = cus / kTeamXcd;
+    // a member waits at most ~200 ms at a barrier
+    c->team_wait = (int64_t)(khz > 0 ? khz : 100000) * 200;
+    c->team_ok = false;
+    if (cus % kTeamXcd != 0 || c->cus_per_xcd < 1) return hipSuccess;
+    const int nblk = kTeamXcd * kTeamMax;
+    int* d = nullptr;
+    e = hipMalloc((void**)&d, nblk * sizeof(int));
+    if (e != hipSuccess) return e;
+    std::vector<int> h(nblk, -1);
+    e = launch_team_map(d, c->cap);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, nblk * sizeof(int), hipMemcpyDeviceToHost, c->cap);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->cap);
+    (void)hipFree(d);
+    if (e != hipSuccess) return e;
+    bool ok = h[0] >= 0 && h[0] < kTeamXcd;
+    for (int b = 0; b < nblk && ok; ++b) ok = h[b] == (b + h[0]) % kTeamXcd;
+    c->team_ok = ok;
+    return hipSuccess;
 }
 
 void destroy_ctx(maid_ctx* c) {
@@ -391,6 +465,7 @@ void destroy_ctx(maid_ctx* c) {
     if (c->tab_dev) (void)hipFree(c->tab_dev);
     if (c->tab_host) (void)hipHostFree(c->tab_host);
     if (c->maps) (void)hipFree(c->maps);
+    if (c->team_arrive) (void)hipFree(c->team_arrive);
     delete c;
 }
 
@@ -431,8 +506,10 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe);
     }
     c->ws_bytes = total;
+    maps += n;   // the groups' instance lists
     c->maps_cap = maps;
-    c->st_bytes = al(2 * n * sizeof(ApgState)) + al(3 * n * sizeof(CgState)) + al(n * kRedSlots * sizeof(double));
+    c->st_bytes = 256 + al(2 * n * sizeof(ApgState)) + 256 + al(3 * n * sizeof(CgState)) +
+                  al(n * kRedSlots * sizeof(double));
     const size_t tab_bytes = (size_t)kRoles * n * sizeof(Inst<double>);
     hipError_t e = hipMalloc((void**)&c->ws, c->ws_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->st_dev, c->st_bytes);
@@ -446,6 +523,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     if (e == hipSuccess) e = hipMemset(c->ws, 0, c->ws_bytes);
     if (e == hipSuccess) e = hipMemset(c->st_dev, 0, c->st_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->team_arrive, kTeamXcd * kTeamMax * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(c->team_arrive, 0, kTeamXcd * kTeamMax * sizeof(uint64_t));
+    if (e == hipSuccess) e = team_setup(c);
     if (e != hipSuccess) {
         why = std::string("allocation failed: ") + hipGetErrorString(e);
         const int code = e == hipErrorOutOfMemory ? MAID_ENOMEM : MAID_EHIP;
@@ -453,6 +533,10 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         return code;
     }
     if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
+    if (const char* t = std::getenv("MAID_TEAM")) c->team_req = std::max(-1, std::atoi(t));
+    // longest wait at a team barrier, in wall-clock ticks (0 forces the
+    // multi-kernel fallback, for tests)
+    if (const char* w = std::getenv("MAID_TEAM_WAIT")) c->team_wait = std::max(0LL, std::atoll(w));
     // period of the exact recomputation of theta*x in the lower-level solve
     c->kx_resync = c->dtype == MAID_F64 ? 32 : 8;
     if (const char* r = std::getenv("MAID_KX_RESYNC")) c->kx_resync = std::max(0, std::atoi(r));
@@ -460,9 +544,13 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     std::memset(c->tab_host, 0, tab_bytes);
     {
         char* p = c->st_dev;
+        c->team_err_apg = (unsigned*)p;
+        p += 256;
         c->apg[0] = (ApgState*)p;
         c->apg[1] = c->apg[0] + n;
         p += al(2 * n * sizeof(ApgState));
+        c->team_err_cg = (unsigned*)p;
+        p += 256;
         c->cg[0] = (CgState*)p;
         c->cg[1] = c->cg[0] + n;
         c->cg[2] = c->cg[1] + n;
@@ -564,27 +652,58 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
     // each slot is one gradient pass and one trial pass; a slot advances every
     // unfinished solve by one iteration or by one backtracking step
     const long slot_cap = (long)max_iter + 256 + 1;
-    const long pred = std::min(c->pred_slots[pred_role], (long)max_iter + 1);
-    long slots = 0, chunk = 0;
-    for (;;) {
-        chunk = next_slots(pred, slots, chunk);
-        int rc = run_slots(c, G_APG, chunk, s, [&](hipStream_t s, int cnt) {
-            for (int k = 0; k < cnt; ++k) {
-                for (auto& lg : c->groups)
-                    LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(lg.g, tabd, c->apg[0], c->apg[1], s));
-                for (auto& lg : c->groups)
-                    LAUNCH(MAID_PROF_APG_TRIAL, Ops<T>::apg_trial(lg.g, tabd, c->apg[1], c->apg[0], s));
-            }
-            return (int)MAID_OK;
-        });
-        if (rc) return rc;
-        slots += chunk;
-        TRY(publish(c, s, c->apg[0], n * sizeof(ApgState)));
-        bool done = true;
-        for (int i = 0; i < n; ++i) done = done && c->apg_h[i].done;
-        if (done) break;
-        if (slots > slot_cap) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
+    // groups of small instances: the whole loop in one launch per group
+    std::vector<char> in_team(n, 0);
+    bool graph_any = false;
+    for (auto& lg : c->groups) {
+        if (lg.team == 0) {
+            graph_any = true;
+            continue;
+        }
+        for (int i : lg.members) in_team[i] = 1;
+        const TeamCtl ctl{c->team_arrive, c->team_err_apg, (++c->team_epoch) << 32, lg.team, c->team_wait};
+        LAUNCH(MAID_PROF_APG_TEAM,
+               Ops<T>::apg_team(lg.g, tabd, lg.list, (int)lg.members.size(), c->apg[0], ctl, slot_cap, s));
     }
+    const size_t pub_bytes = 256 + n * sizeof(ApgState);
+    if (graph_any) {
+        const long pred = std::min(c->pred_slots[pred_role], (long)max_iter + 1);
+        long slots = 0, chunk = 0;
+        for (;;) {
+            chunk = next_slots(pred, slots, chunk);
+            int rc = run_slots(c, G_APG, chunk, s, [&](hipStream_t s, int cnt) {
+                for (int k = 0; k < cnt; ++k) {
+                    for (auto& lg : c->groups)
+                        if (lg.team == 0)
+                            LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(lg.g, tabd, c->apg[0], c->apg[1], s));
+                    for (auto& lg : c->groups)
+                        if (lg.team == 0)
+                            LAUNCH(MAID_PROF_APG_TRIAL, Ops<T>::apg_trial(lg.g, tabd, c->apg[1], c->apg[0], s));
+                }
+                return (int)MAID_OK;
+            });
+            if (rc) return rc;
+            slots += chunk;
+            TRY(publish(c, s, c->team_err_apg, pub_bytes));
+            bool done = true;
+            for (int i = 0; i < n; ++i) done = done && (c->apg_h[i].done || in_team[i]);
+            if (done) break;
+            if (slots > slot_cap) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
+        }
+    } else {
+        TRY(publish(c, s, c->team_err_apg, pub_bytes));
+    }
+    if (*(const unsigned*)(c->st_host + ((const char*)c->team_err_apg - c->st_dev)) != 0u) {
+        // a team did not assemble (its blocks were not resident together):
+        // repeat the solve on the multi-kernel passes, which the context
+        // keeps using from now on
+        HIP_TRY(hipMemsetAsync(c->team_err_apg, 0, sizeof(unsigned), s));
+        c->team_ok = false;
+        TRY(relayout(c));
+        return lower_batch<T>(c, act, theta, y, x, tol, max_iter, L_inout, info, codes, trace_bt, s, pred_role, xin);
+    }
+    for (int i = 0; i < n; ++i)
+        if (act[i] && !c->apg_h[i].done) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
     {
         long need = 1;
         for (int i = 0; i < n; ++i)
@@ -594,15 +713,19 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
     if (c->prof_on) {
         // passes that did work: a gradient at the start and after every
         // accepted step, a trial for every accepted or rejected step (the
-        // busiest instance of the batch)
-        int64_t wg = 0, wt = 0;
+        // busiest instance of the batch); team loops: the slots of every
+        // instance (each slot one trial pass and one gradient pass)
+        int64_t wg = 0, wt = 0, wteam = 0;
         for (int i = 0; i < n; ++i)
-            if (act[i]) {
+            if (act[i] && in_team[i]) {
+                wteam += c->apg_h[i].iters + c->apg_h[i].bt;
+            } else if (act[i]) {
                 wg = std::max<int64_t>(wg, c->apg_h[i].iters + 1);
                 wt = std::max<int64_t>(wt, c->apg_h[i].iters + c->apg_h[i].bt);
             }
         c->prof_work[MAID_PROF_APG_GRAD] += wg;
         c->prof_work[MAID_PROF_APG_TRIAL] += wt;
+        c->prof_work[MAID_PROF_APG_TEAM] += wteam;
     }
     LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, c->only_e, tabd, c->apg[0], s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -661,26 +784,56 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
     LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->grid_e, c->blk_e, c->only_e, tabd, S[0], s));
-    const long pred = std::min(c->pred_slots[3], (long)max_iter + 1);
-    long slots = 0, chunk = 0;
-    for (;;) {
-        chunk = next_slots(pred, slots, chunk);
-        int rc = run_slots(c, G_CG, chunk, s, [&](hipStream_t s, int cnt) {
-            for (int k = 0; k < cnt; ++k) {
-                for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
-                for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
-                LAUNCH(MAID_PROF_CG_UPDATE, Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
-            }
-            return (int)MAID_OK;
-        });
-        if (rc) return rc;
-        slots += chunk;
-        TRY(publish(c, s, c->cg[0], n * sizeof(CgState)));
-        bool done = true;
-        for (int i = 0; i < n; ++i) done = done && c->cg_h[i].done;
-        if (done) break;
-        if (slots > (long)max_iter + 2) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
+    // groups of small instances: the whole loop in one launch per group
+    std::vector<char> in_team(n, 0);
+    bool graph_any = false;
+    for (auto& lg : c->groups) {
+        if (lg.team == 0) {
+            graph_any = true;
+            continue;
+        }
+        for (int i : lg.members) in_team[i] = 1;
+        const TeamCtl ctl{c->team_arrive, c->team_err_cg, (++c->team_epoch) << 32, lg.team, c->team_wait};
+        LAUNCH(MAID_PROF_CG_TEAM,
+               Ops<T>::cg_team(lg.g, tabd, lg.list, (int)lg.members.size(), S[0], n, ctl, (long)max_iter + 2, s));
     }
+    const size_t pub_bytes = 256 + n * sizeof(CgState);
+    if (graph_any) {
+        const long pred = std::min(c->pred_slots[3], (long)max_iter + 1);
+        long slots = 0, chunk = 0;
+        for (;;) {
+            chunk = next_slots(pred, slots, chunk);
+            int rc = run_slots(c, G_CG, chunk, s, [&](hipStream_t s, int cnt) {
+                for (int k = 0; k < cnt; ++k) {
+                    for (auto& lg : c->groups)
+                        if (lg.team == 0) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
+                    for (auto& lg : c->groups)
+                        if (lg.team == 0) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
+                    LAUNCH(MAID_PROF_CG_UPDATE,
+                           Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
+                }
+                return (int)MAID_OK;
+            });
+            if (rc) return rc;
+            slots += chunk;
+            TRY(publish(c, s, c->team_err_cg, pub_bytes));
+            bool done = true;
+            for (int i = 0; i < n; ++i) done = done && (c->cg_h[i].done || in_team[i]);
+            if (done) break;
+            if (slots > (long)max_iter + 2) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
+        }
+    } else {
+        TRY(publish(c, s, c->team_err_cg, pub_bytes));
+    }
+    if (*(const unsigned*)(c->st_host + ((const char*)c->team_err_cg - c->st_dev)) != 0u) {
+        // a team did not assemble: repeat on the multi-kernel passes
+        HIP_TRY(hipMemsetAsync(c->team_err_cg, 0, sizeof(unsigned), s));
+        c->team_ok = false;
+        TRY(relayout(c));
+        return adjoint_batch<T>(c, act, theta, xt, rhs, q, tol, max_iter, info, codes, s);
+    }
+    for (int i = 0; i < n; ++i)
+        if (act[i] && !c->cg_h[i].done) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
     {
         long need = 1;
         for (int i = 0; i < n; ++i)
@@ -688,13 +841,16 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         c->pred_slots[3] = need;
     }
     if (c->prof_on) {
-        // the set-up direction and Hessian passes, then one of each per iteration
-        int64_t w = 0;
+        // the set-up direction and Hessian passes, then one of each per
+        // iteration; team loops: the iterations of every instance
+        int64_t w = 0, wteam = 0;
         for (int i = 0; i < n; ++i)
-            if (act[i]) w = std::max<int64_t>(w, c->cg_h[i].iters);
+            if (act[i] && in_team[i]) wteam += c->cg_h[i].iters;
+            else if (act[i]) w = std::max<int64_t>(w, c->cg_h[i].iters);
         c->prof_work[MAID_PROF_CG_DIR] += w + 1;
         c->prof_work[MAID_PROF_CG_HVP] += w + 1;
         c->prof_work[MAID_PROF_CG_UPDATE] += w;
+        c->prof_work[MAID_PROF_CG_TEAM] += wteam;
     }
     for (int i = 0; i < n; ++i) {
         codes[i] = MAID_OK;

@@ -74,6 +74,8 @@ struct Member {
 struct LaunchGroup {
     Group g;
     std::vector<int> members;
+    int team = 0;               // members per team of the persistent loops (0: multi-kernel passes)
+    const int* list = nullptr;  // device copy of `members` (the team launches' instance list)
 };
 
 }  // namespace maid
@@ -102,6 +104,10 @@ struct maid_ctx {
     size_t st_bytes = 0;
     maid::ApgState* apg[2] = {};      // device arrays of n
     maid::CgState* cg[3] = {};
+    // error words of the team loops, just before apg[0] and cg[0] in the
+    // state block so that one publication brings back word and states
+    unsigned* team_err_apg = nullptr;
+    unsigned* team_err_cg = nullptr;
     double* red = nullptr;            // n x kRedSlots
     maid::ApgState* apg_h = nullptr;  // host mirror of apg[0]
     maid::CgState* cg_h = nullptr;    // host mirror of cg[0]
@@ -112,6 +118,13 @@ struct maid_ctx {
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    // persistent team loops for small instances (one team per XCD)
+    int team_req = -1;                // members per team: -1 size rule, 0 never, > 0 that many (capped)
+    bool team_ok = false;             // blocks reach the XCDs round-robin and XCC_ID reads them
+    int cus_per_xcd = 0;
+    uint64_t* team_arrive = nullptr;  // kTeamXcd x kTeamMax arrival words
+    uint64_t team_epoch = 0;
+    int64_t team_wait = 0;            // wall-clock ticks of the longest wait at a team barrier
     hipStream_t cap = nullptr;        // private stream for graph capture
     bool use_graphs = true;
     int kx_resync = 16;               // exact theta*x every kx_resync iterations (twice in a row)

@@ -53,6 +53,29 @@ template <typename T> __device__ __forceinline__ T drsqrt(T v);
 template <> __device__ __forceinline__ float drsqrt<float>(float v) { return rsqrtf(v); }
 template <> __device__ __forceinline__ double drsqrt<double>(double v) { return 1.0 / sqrt(v); }
 
+// Element i of a channel plane: the byte offset is formed in 32 bits (a
+// plane holds < 4 GiB), so global loads and stores take the uniform 64-bit
+// plane base in SGPRs plus a 32-bit VGPR offset.
+template <typename T> __device__ __forceinline__ T& at(T* p, unsigned i) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (size_t)(i * (unsigned)sizeof(T)));
+}
+template <typename T> __device__ __forceinline__ const T& at(const T* p, unsigned i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (size_t)(i * (unsigned)sizeof(T)));
+}
+// Load of element i under a load policy: CO = false is a plain load; CO =
+// true (the team loops, where the data were written by other blocks of the
+// same XCD during the kernel) is a relaxed device-scope atomic load, which
+// misses in the CU's L1 and so reads what the writers left in the XCD's L2.
+template <bool CO, typename T> __device__ __forceinline__ T ld(const T* p, unsigned i) {
+    if constexpr (CO) return __hip_atomic_load(&at(p, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return at(p, i);
+}
+
+template <bool CO, typename T> __device__ __forceinline__ T ld64(const T* p, int64_t e) {
+    if constexpr (CO) return __hip_atomic_load(p + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return p[e];
+}
+
 // blockIdx -> tile id, XCD-major: the hardware hands block b to XCD b % 8;
 // this bijection gives every XCD a contiguous run of tile ids.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -102,18 +125,20 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
 struct Partials {
     double v[4];
 };
+template <bool CO = false>
 __device__ __forceinline__ Partials partials_issue(const double* __restrict__ part, int nb) {
     Partials p;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int b = threadIdx.x + k * kNT;
-        p.v[k] = b < nb ? part[b] : 0.0;
+        p.v[k] = b < nb ? ld<CO>(part, b) : 0.0;
     }
     return p;
 }
+template <bool CO = false>
 __device__ __forceinline__ double partials_finish(const double* __restrict__ part, int nb, const Partials& p) {
     double s = ((p.v[0] + p.v[1]) + p.v[2]) + p.v[3];
-    for (int b = threadIdx.x + 4 * kNT; b < nb; b += kNT) s += part[b];
+    for (int b = threadIdx.x + 4 * kNT; b < nb; b += kNT) s += ld<CO>(part, b);
     return block_sum(s);
 }
 
@@ -137,15 +162,6 @@ __device__ __forceinline__ P pick(P a0, P a1, P a2, int i) { return i == 0 ? a0 
 template <typename P>
 __device__ __forceinline__ P pick(P a0, P a1, int i) { return i == 0 ? a0 : a1; }
 
-// Element i of a channel plane: the byte offset is formed in 32 bits (a
-// plane holds < 4 GiB), so global loads and stores take the uniform 64-bit
-// plane base in SGPRs plus a 32-bit VGPR offset.
-template <typename T> __device__ __forceinline__ T& at(T* p, unsigned i) {
-    return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (size_t)(i * (unsigned)sizeof(T)));
-}
-template <typename T> __device__ __forceinline__ const T& at(const T* p, unsigned i) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (size_t)(i * (unsigned)sizeof(T)));
-}
 // inside [0,H) x [0,W), with one unsigned compare per axis
 __device__ __forceinline__ bool inside(int gi, int gj, int H, int W) { return (unsigned)gi < (unsigned)H && (unsigned)gj < (unsigned)W; }
 __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
@@ -410,19 +426,12 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
 // and its per-block partials of ||G||^2 go to pA.  The gradient at the point
 // an acceptance would move to is computed while the partials are in flight;
 // a rejection drops it before any store.
-template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
-                                                  const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
-    MAID_STENCIL_PROLOGUE
-    ApgState st = sin[ii];
-    const bool writer = lb == 0 && threadIdx.x == 0;
-    if (st.done) {
-        if (writer) put_state(&sout[ii], st);
-        return;
-    }
+template <typename T, int K, int R, bool CO>
+__device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState& st, ApgState* __restrict__ sout,
+                                              bool writer) {
     const bool trialed = st.phase == PH_TRIALED;
     Partials pv;
-    if (trialed) pv = partials_issue(I.pB, I.nb);
+    if (trialed) pv = partials_issue<CO>(I.pB, I.nb);
     // the point of the next gradient if the trial is accepted (at the start: the current one)
     int cur = st.cur, prev = st.prev;
     double mnext = st.m, tnext = st.t;
@@ -460,14 +469,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     T* s_c = SEQ ? sm : s_w + nw * WR * WP;
     auto stage_residual = [&]() {
         load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
-            const T kx = at(KX, g);
-            return dfma(m, kx - at(KXP, g), kx) - at(Yc, g);
+            const T kx = ld<CO>(KX, g);
+            return dfma(m, kx - ld<CO>(KXP, g), kx) - ld<CO>(Yc, g);
         });
     };
     auto vfun = [&](int c) {
         const T* Xc = X + c * HW;
         const T* XPc = XP + c * HW;
-        return [=](int g) { const T xv = at(Xc, g); return dfma(m, xv - at(XPc, g), xv); };
+        return [=](int g) { const T xv = ld<CO>(Xc, g); return dfma(m, xv - ld<CO>(XPc, g), xv); };
     };
     if constexpr (!SEQ) {
         // all of this pass's tiles in one round of loads
@@ -475,8 +484,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         auto v1 = stage<VR, VP, VP>(s_v + VR * VP, ti0 - 1, tj0 - 1, vfun(C > 1 ? 1 : 0));
         auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, vfun(C > 2 ? 2 : 0));
         auto rs = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) {
-            const T kx = at(KX, g);
-            return dfma(m, kx - at(KXP, g), kx) - at(Yc, g);
+            const T kx = ld<CO>(KX, g);
+            return dfma(m, kx - ld<CO>(KXP, g), kx) - ld<CO>(Yc, g);
         });
         v0.fetch(H, W);
         if (C > 1) v1.fetch(H, W);
@@ -494,7 +503,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     bool compute = true;
     auto decide = [&]() {
         if (trialed) {
-            const double delta = partials_finish(I.pB, I.nb, pv);
+            const double delta = partials_finish<CO>(I.pB, I.nb, pv);
             st.delta_last = delta;
             if (!finite_d(delta)) {
                 st.done = 1;
@@ -524,7 +533,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         } else {
             st.phase = PH_GRAD_READY;
         }
-        if (writer) put_state(&sout[ii], st);
+        if (writer && sout) put_state(sout, st);
     };
     __syncthreads();
     if (SEQ) {
@@ -575,6 +584,19 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     block_partial(gsq, I.pA, lb);
 }
 
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_grad(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                  const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
+    MAID_STENCIL_PROLOGUE
+    ApgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(&sout[ii], st);
+        return;
+    }
+    apg_grad_body<T, K, R, false>(I, lb, st, &sout[ii], writer);
+}
+
 // Trial pass.  Per instance: reads sin, block 0 writes sout.  After a fresh
 // gradient it finishes ||G||^2 and applies the stop tests (||G|| <= tol:
 // done, the point is v; iteration cap: done with MAXITER); otherwise (or on
@@ -592,19 +614,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 // two consecutive iterations of every `resync` it is recomputed exactly as
 // the convolution of the stored x+ (two consecutive, so that both theta*x
 // and theta*x_prev, i.e. the momentum term, are exact again).
-template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
-                                                   const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
-    MAID_STENCIL_PROLOGUE
-    ApgState st = sin[ii];
-    const bool writer = lb == 0 && threadIdx.x == 0;
-    if (st.done) {
-        if (writer) put_state(&sout[ii], st);
-        return;
-    }
+template <typename T, int K, int R, bool CO>
+__device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgState& st, ApgState* __restrict__ sout,
+                                               bool writer) {
     const bool fresh = st.phase == PH_GRAD_READY;
     Partials pv;
-    if (fresh) pv = partials_issue(I.pA, I.nb);
+    if (fresh) pv = partials_issue<CO>(I.pA, I.nb);
 
     constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -635,14 +650,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     auto sfun_v = [&](int c) {
         const T* Xc = X + c * HW;
         const T* XPc = XP + c * HW;
-        return [=](int g) { const T xv = at(Xc, g); return dfma(m, xv - at(XPc, g), xv); };
+        return [=](int g) { const T xv = ld<CO>(Xc, g); return dfma(m, xv - ld<CO>(XPc, g), xv); };
     };
     auto sfun_d = [&](int c) {
         const T* Gcc = G + c * HW;
-        return [=](int g) { return at(Gcc, g) * ninvL; };
+        return [=](int g) { return ld<CO>(Gcc, g) * ninvL; };
     };
     if constexpr (!SEQ) {
-        auto sg = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) { return at(Gc, g) * ninvL; });
+        auto sg = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) { return ld<CO>(Gc, g) * ninvL; });
         auto v0 = stage<VR, VP, VP>(s_v, ti0 - 1, tj0 - 1, sfun_v(0));
         auto v1 = stage<VR, VP, VP>(s_v + VR * VP, ti0 - 1, tj0 - 1, sfun_v(C > 1 ? 1 : 0));
         auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, sfun_v(C > 2 ? 2 : 0));
@@ -660,13 +675,13 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         if (C > 1) { v1.put(); d1.put(); }
         if (C > 2) { v2.put(); d2.put(); }
     } else {
-        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(Gc, g) * ninvL; });
+        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) { return ld<CO>(Gc, g) * ninvL; });
     }
     __syncthreads();
 
     bool trial = true;
     if (fresh) {
-        const double gn2 = partials_finish(I.pA, I.nb, pv);
+        const double gn2 = partials_finish<CO>(I.pA, I.nb, pv);
         st.gn2 = gn2;
         st.nb_iter = 0;
         if (!finite_d(gn2)) {
@@ -684,7 +699,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         }
     }
     if (trial) st.phase = PH_TRIALED;
-    if (writer) put_state(&sout[ii], st);
+    if (writer && sout) put_state(sout, st);
     if (!trial) return;
 
     // ---- TV part of the decrease, per site: the tile's rows are dealt to its
@@ -737,12 +752,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
                     const T* Xc = X + c * HW;
                     const T* XPc = XP + c * HW;
                     const T* Gcc = G + c * HW;
-                    auto vat = [&](int f) { const T xv = at(Xc, f); return dfma(m, xv - at(XPc, f), xv); };
-                    const T v0 = vat(e), d0 = at(Gcc, e) * ninvL;
+                    auto vat = [&](int f) { const T xv = ld<CO>(Xc, f); return dfma(m, xv - ld<CO>(XPc, f), xv); };
+                    const T v0 = vat(e), d0 = ld<CO>(Gcc, e) * ninvL;
                     const double bh = hx ? (double)(vat(e + 1) - v0) : 0.0;
                     const double bv = vx ? (double)(vat(e + W) - v0) : 0.0;
-                    const double ah = hx ? (double)(at(Gcc, e + 1) * ninvL - d0) : 0.0;
-                    const double av = vx ? (double)(at(Gcc, e + W) * ninvL - d0) : 0.0;
+                    const double ah = hx ? (double)(ld<CO>(Gcc, e + 1) * ninvL - d0) : 0.0;
+                    const double av = vx ? (double)(ld<CO>(Gcc, e + W) * ninvL - d0) : 0.0;
                     if (reg == 2) {
                         ds2 += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
                     } else if (reg == 1) {
@@ -782,11 +797,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int e = clampi(ti0 + li0 + o, H - 1) * W + clampi(gj, W - 1);
-            kxr[o] = at(KXc, e);
-            kxpr[o] = at(KXPc, e);
-            yr[o] = at(Yc, e);
-            xr[o] = at(Xc0, e);
-            xpr[o] = at(XPc0, e);
+            kxr[o] = ld<CO>(KXc, e);
+            kxpr[o] = ld<CO>(KXPc, e);
+            yr[o] = ld<CO>(Yc, e);
+            xr[o] = ld<CO>(Xc0, e);
+            xpr[o] = ld<CO>(XPc0, e);
         }
     }
 #pragma unroll
@@ -796,11 +811,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
             const int e = gi * W + gj;
             const int q = SEQ ? 0 : o;
             if constexpr (SEQ) {
-                kxr[0] = at(KXc, e);
-                kxpr[0] = at(KXPc, e);
-                yr[0] = at(Yc, e);
-                xr[0] = at(Xc0, e);
-                xpr[0] = at(XPc0, e);
+                kxr[0] = ld<CO>(KXc, e);
+                kxpr[0] = ld<CO>(KXPc, e);
+                yr[0] = ld<CO>(Yc, e);
+                xr[0] = ld<CO>(Xc0, e);
+                xpr[0] = ld<CO>(XPc0, e);
             }
             const T kv = dfma(m, kxr[q] - kxpr[q], kxr[q]);
             const T d = acc[o];
@@ -816,8 +831,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         const T* XPc = XP + ch * HW;
         __syncthreads();
         load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
-            const T xv = at(Xc, g);
-            return dfma(m, xv - at(XPc, g), xv) + at(Gc, g) * ninvL;
+            const T xv = ld<CO>(Xc, g);
+            return dfma(m, xv - ld<CO>(XPc, g), xv) + ld<CO>(Gc, g) * ninvL;
         });
         __syncthreads();
 #pragma unroll
@@ -832,22 +847,39 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     block_partial(ddat + I.pr.alpha * dtv, I.pB, lb);
 }
 
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_trial(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                   const ApgState* __restrict__ sin, ApgState* __restrict__ sout) {
+    MAID_STENCIL_PROLOGUE
+    ApgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(&sout[ii], st);
+        return;
+    }
+    apg_trial_body<T, K, R, false>(I, lb, st, &sout[ii], writer);
+}
+
 // xout = v = x + m (x - x_prev): the point that passed the stop test
 // (instances whose solve failed are left untouched).
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
-                                                   const ApgState* __restrict__ sin) {
-    MAID_EW_PROLOGUE
-    const ApgState st = sin[ii];
+template <typename T, bool CO>
+__device__ __forceinline__ void apg_final_body(const Inst<T>& I, int lb, const ApgState& st) {
     if (st.status < 0 || !I.xout) return;
     const T* X = pick(I.X[0], I.X[1], I.X[2], st.cur);
     const T* XP = pick(I.X[0], I.X[1], I.X[2], st.prev);
     const T m = (T)st.m;
     T* out = I.xout;
     for (int64_t e = (int64_t)lb * kNT + threadIdx.x; e < I.N; e += (int64_t)I.nbe * kNT) {
-        const T xv = X[e];
-        out[e] = dfma(m, xv - XP[e], xv);
+        const T xv = ld64<CO>(X, e);
+        out[e] = dfma(m, xv - ld64<CO>(XP, e), xv);
     }
+}
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                   const ApgState* __restrict__ sin) {
+    MAID_EW_PROLOGUE
+    const ApgState st = sin[ii];
+    apg_final_body<T, false>(I, lb, st);
 }
 
 // ------------------------------------------------------------------ conjugate gradients
@@ -859,18 +891,11 @@ __global__ __launch_bounds__(kNT) void k_apg_final(const Inst<T>* __restrict__ i
 // partials are in flight and combined once beta is known.  init = 1: the
 // set-up call that copies the caller's q0 into q and p and forms theta*q0,
 // without touching the state.
-template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
-                                                const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
-    MAID_STENCIL_PROLOGUE
-    CgState st = sin[ii];
-    const bool writer = lb == 0 && threadIdx.x == 0;
-    if (st.done) {
-        if (writer && !init) put_state(&sout[ii], st);
-        return;
-    }
+template <typename T, int K, int R, bool CO>
+__device__ __forceinline__ void cg_dir_body(const Inst<T>& I, int lb, CgState& st, CgState* __restrict__ sout, bool writer,
+                                            int init) {
     Partials pv;
-    if (!init) pv = partials_issue(I.pR, I.nbe);
+    if (!init) pv = partials_issue<CO>(I.pR, I.nbe);
     constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
@@ -887,8 +912,8 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     const T* __restrict__ rc = (init ? I.q0 : I.r) + ch * HW;
     const bool with_p = !init && !st.first;
     if constexpr (!SEQ) {
-        auto sr = stage<CR, CP, CP>(s, ti0 - c0, tj0 - c0, [&](int g) { return at(rc, g); });
-        auto sp = stage<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, [&](int g) { return at(Pold, g); });
+        auto sr = stage<CR, CP, CP>(s, ti0 - c0, tj0 - c0, [&](int g) { return ld<CO>(rc, g); });
+        auto sp = stage<CR, CP, CP>(s_p, ti0 - c0, tj0 - c0, [&](int g) { return ld<CO>(Pold, g); });
         sr.fetch(H, W);
         if (with_p) sp.fetch(H, W);
         sr.put();
@@ -896,7 +921,7 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     }
     double beta = 0.0;
     if (!init) {
-        const double g = partials_finish(I.pR, I.nbe, pv);
+        const double g = partials_finish<CO>(I.pR, I.nbe, pv);
         if (st.first) {
             st.first = 0;
         } else {
@@ -913,15 +938,15 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
             st.done = 1;
             st.status = ST_MAXITER;
         }
-        if (writer) put_state(&sout[ii], st);
+        if (writer && sout) put_state(sout, st);
         if (st.done) return;
     }
     if (SEQ) {
         const T bT = (T)beta;
         if (with_p)
-            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return dfma(bT, at(Pold, g), at(rc, g)); });
+            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return dfma(bT, ld<CO>(Pold, g), ld<CO>(rc, g)); });
         else
-            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(rc, g); });
+            load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return ld<CO>(rc, g); });
     } else if (with_p) {
         __syncthreads();
         const T bT = (T)beta;
@@ -947,17 +972,25 @@ __global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ inst
     }
 }
 
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kNT) void k_cg_dir(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
+    MAID_STENCIL_PROLOGUE
+    CgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer && !init) put_state(&sout[ii], st);
+        return;
+    }
+    cg_dir_body<T, K, R, false>(I, lb, st, &sout[ii], writer, init);
+}
+
 // Hessian pass.  Per instance: reads sin, block 0 writes sout.
 // Hp = theta . Kp + alpha grad^2 R(xt)[p] and per-block partials of <p,Hp>;
 // grad^2 R(x)[p] = D^T (w Dp - w^3 m Dx), m = <Dx, Dp> over the coupled
 // channels.  init = 1 computes H q0 only.
-template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
-                                                const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
-    MAID_STENCIL_PROLOGUE
-    const CgState st = sin[ii];
-    if (!init && lb == 0 && threadIdx.x == 0) put_state(&sout[ii], st);
-    if (st.done) return;
+template <typename T, int K, int R, bool CO>
+__device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgState& st, int init) {
     constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
     constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -984,12 +1017,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     T* s_w = s_p + nx * VR * VP;
     T* s_mw = s_w + WR * WP;
     const T* kc = I.Kp + ch * HW;
-    auto stage_kp = [&]() { load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(kc, g); }); };
-    auto xfun = [&](int c) { const T* xc = I.xt + c * HW; return [=](int g) { return at(xc, g); }; };
-    auto pfun = [&](int c) { const T* pc = P + c * HW; return [=](int g) { return at(pc, g); }; };
+    auto stage_kp = [&]() { load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) { return ld<CO>(kc, g); }); };
+    auto xfun = [&](int c) { const T* xc = I.xt + c * HW; return [=](int g) { return ld<CO>(xc, g); }; };
+    auto pfun = [&](int c) { const T* pc = P + c * HW; return [=](int g) { return ld<CO>(pc, g); }; };
     const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
     if constexpr (!SEQ) {
-        auto sk = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) { return at(kc, g); });
+        auto sk = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) { return ld<CO>(kc, g); });
         auto x0 = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, xfun(0));
         auto x1 = stage<VR, VP, VP>(s_x + VR * VP, ti0 - 1, tj0 - 1, xfun(C > 1 ? 1 : 0));
         auto x2 = stage<VR, VP, VP>(s_x + 2 * VR * VP, ti0 - 1, tj0 - 1, xfun(C > 2 ? 2 : 0));
@@ -1055,9 +1088,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
                 for (int c = c_lo; c < c_hi; ++c) {
                     const T* xc = I.xt + c * HW;
                     const T* pc = P + c * HW;
-                    const T x0 = at(xc, e), p0 = at(pc, e);
-                    const T xh = at(xc, eh) - x0, xv = at(xc, ev) - x0;
-                    const T ph = at(pc, eh) - p0, pv = at(pc, ev) - p0;
+                    const T x0 = ld<CO>(xc, e), p0 = ld<CO>(pc, e);
+                    const T xh = ld<CO>(xc, eh) - x0, xv = ld<CO>(xc, ev) - x0;
+                    const T ph = ld<CO>(pc, eh) - p0, pv = ld<CO>(pc, ev) - p0;
                     s2 += xh * xh + xv * xv;
                     mm += xh * ph + xv * pv;
                 }
@@ -1132,21 +1165,24 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
     if (!init) block_partial(kap, I.pK, lb);
 }
 
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_cg_hvp(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                const CgState* __restrict__ sin, CgState* __restrict__ sout, int init) {
+    MAID_STENCIL_PROLOGUE
+    const CgState st = sin[ii];
+    if (!init && lb == 0 && threadIdx.x == 0) put_state(&sout[ii], st);
+    if (st.done) return;
+    cg_hvp_body<T, K, R, false>(I, lb, st, init);
+}
+
 // Update pass.  Per instance: reads sin, block 0 writes sout.  Finishes the
 // curvature kappa = <p,Hp> (not positive: MAID_NOT_SPD), a = gamma/kappa,
 // then q += a p, r -= a Hp and per-block partials of ||r||^2.  The first
 // element of every thread is loaded while the partials are in flight.
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
-                                                   const CgState* __restrict__ sin, CgState* __restrict__ sout) {
-    MAID_EW_PROLOGUE
-    CgState st = sin[ii];
-    const bool writer = lb == 0 && threadIdx.x == 0;
-    if (st.done) {
-        if (writer) put_state(&sout[ii], st);
-        return;
-    }
-    const Partials pv = partials_issue(I.pK, I.nb);
+template <typename T, bool CO>
+__device__ __forceinline__ void cg_update_body(const Inst<T>& I, int lb, CgState& st, CgState* __restrict__ sout,
+                                               bool writer) {
+    const Partials pv = partials_issue<CO>(I.pK, I.nb);
     const T* __restrict__ P = pick(I.P[0], I.P[1], st.pc ^ 1);
     T* __restrict__ q = I.q;
     T* __restrict__ r = I.r;
@@ -1154,23 +1190,23 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
     const int64_t e0 = (int64_t)lb * kNT + threadIdx.x, stride = (int64_t)I.nbe * kNT;
     T p0 = T(0), q0 = T(0), r0 = T(0), h0 = T(0);
     if (e0 < I.N) {
-        p0 = P[e0];
-        q0 = q[e0];
-        r0 = r[e0];
-        h0 = Hp[e0];
+        p0 = ld64<CO>(P, e0);
+        q0 = ld64<CO>(q, e0);
+        r0 = ld64<CO>(r, e0);
+        h0 = ld64<CO>(Hp, e0);
     }
-    const double kappa = partials_finish(I.pK, I.nb, pv);
+    const double kappa = partials_finish<CO>(I.pK, I.nb, pv);
     st.kappa = kappa;
     if (!(kappa > 0.0) || !finite_d(kappa)) {
         st.done = 1;
         st.status = finite_d(kappa) ? ST_NOT_SPD : ST_NONFINITE;
-        if (writer) put_state(&sout[ii], st);
+        if (writer && sout) put_state(sout, st);
         return;
     }
     st.a = st.gamma / kappa;
     st.iters += 1;
     st.pc ^= 1;
-    if (writer) put_state(&sout[ii], st);
+    if (writer && sout) put_state(sout, st);
     const T a = (T)st.a;
     double rs = 0.0;
     if (e0 < I.N) {
@@ -1186,10 +1222,10 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
         for (int k = 0; k < 4; ++k) {
             const int64_t ek = e + k * stride;
             const int64_t el = ek < I.N ? ek : 0;
-            pv[k] = P[el];
-            qv[k] = q[el];
-            rv[k] = r[el];
-            hv[k] = Hp[el];
+            pv[k] = ld64<CO>(P, el);
+            qv[k] = ld64<CO>(q, el);
+            rv[k] = ld64<CO>(r, el);
+            hv[k] = ld64<CO>(Hp, el);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -1203,6 +1239,19 @@ __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ i
         }
     }
     block_partial(rs, I.pR, lb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                   const CgState* __restrict__ sin, CgState* __restrict__ sout) {
+    MAID_EW_PROLOGUE
+    CgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(&sout[ii], st);
+        return;
+    }
+    cg_update_body<T, false>(I, lb, st, &sout[ii], writer);
 }
 
 // r = b - H q0 (Hp holds H q0) and per-block partials of ||r||^2.

@@ -3,6 +3,7 @@
 // largest instance.  Included by the per-K instantiation units.
 #pragma once
 #include "kernels.cuh"
+#include "team.cuh"
 #include "stencil_decl.h"
 
 namespace maid {
@@ -61,6 +62,61 @@ static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState*
     return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout, init);
 }
 
+// Team launches (persistent loops for small instances): 8 P blocks; their
+// LDS is the larger of the two passes each loop alternates.
+template <typename T, int K, int R>
+static size_t apg_team_lds(const Group& g) {
+    return sizeof(T) * cmax(lds_apg_grad(K, R, g.C, g.nw), lds_apg_trial(K, R, g.C));
+}
+template <typename T, int K, int R>
+static size_t cg_team_lds(const Group& g) {
+    return sizeof(T) * cmax(lds_cg_dir(K, R), lds_cg_hvp(K, R, g.C, g.nw));
+}
+
+template <typename T, int K, int R>
+static hipError_t apg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st,
+                              const TeamCtl& ctl, long max_slots, hipStream_t s) {
+    const size_t lds = apg_team_lds<T, K, R>(g);
+    auto kern = k_apg_team<T, K, R>;
+    hipError_t e = ensure_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    return launch(kern, dim3(kTeamXcd * ctl.P), dim3(kNT), lds, s, insts, list, nlist, st, ctl, max_slots);
+}
+
+template <typename T, int K, int R>
+static hipError_t cg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                             const TeamCtl& ctl, long max_slots, hipStream_t s) {
+    const size_t lds = cg_team_lds<T, K, R>(g);
+    auto kern = k_cg_team<T, K, R>;
+    hipError_t e = ensure_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    return launch(kern, dim3(kTeamXcd * ctl.P), dim3(kNT), lds, s, insts, list, nlist, st, n, ctl, max_slots);
+}
+
+// Blocks of the group's two team kernels that fit on one CU at once (the
+// smaller of the two).
+template <typename T, int K, int R>
+static hipError_t team_occupancy_kr(const Group& g, int* blocks_per_cu) {
+    int a = 0, b = 0;
+    hipError_t e = ensure_lds(k_apg_team<T, K, R>, apg_team_lds<T, K, R>(g));
+    if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R>, cg_team_lds<T, K, R>(g));
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_apg_team<T, K, R>, kNT, apg_team_lds<T, K, R>(g));
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R>, kNT, cg_team_lds<T, K, R>(g));
+    *blocks_per_cu = e == hipSuccess ? (a < b ? a : b) : 0;
+    return e;
+}
+
+// Team loops exist for tile rows 1, 2 and 4.
+#define MAID_TEAM_R_DISPATCH(FN, ...)                              \
+    switch (g.R) {                                                 \
+        case 1: return FN<T, K, 1>(__VA_ARGS__);                   \
+        case 2: return FN<T, K, 2>(__VA_ARGS__);                   \
+        case 4: return FN<T, K, 4>(__VA_ARGS__);                   \
+        default: return hipErrorInvalidValue;                      \
+    }
+
 #define MAID_R_DISPATCH(FN, ...)                                   \
     switch (g.R) {                                                 \
         case 1: return FN<T, K, 1>(__VA_ARGS__);                   \
@@ -93,12 +149,32 @@ hipError_t cg_hvp_k(const Group& g, const Inst<T>* insts, const CgState* sin, Cg
     MAID_R_DISPATCH(cg_hvp_kr, g, insts, sin, sout, init, s)
 }
 
+template <typename T, int K>
+hipError_t apg_team_k(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st, const TeamCtl& ctl,
+                      long max_slots, hipStream_t s) {
+    MAID_TEAM_R_DISPATCH(apg_team_kr, g, insts, list, nlist, st, ctl, max_slots, s)
+}
+template <typename T, int K>
+hipError_t cg_team_k(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                     const TeamCtl& ctl, long max_slots, hipStream_t s) {
+    MAID_TEAM_R_DISPATCH(cg_team_kr, g, insts, list, nlist, st, n, ctl, max_slots, s)
+}
+template <typename T, int K>
+hipError_t team_occupancy_k(const Group& g, int* blocks_per_cu) {
+    MAID_TEAM_R_DISPATCH(team_occupancy_kr, g, blocks_per_cu)
+}
+
 #define MAID_INSTANTIATE_T(T, KV)                                                                                       \
     template hipError_t conv_k<T, KV>(const Group&, const Inst<T>*, hipStream_t);                                       \
     template hipError_t apg_grad_k<T, KV>(const Group&, const Inst<T>*, const ApgState*, ApgState*, hipStream_t);       \
     template hipError_t apg_trial_k<T, KV>(const Group&, const Inst<T>*, const ApgState*, ApgState*, hipStream_t);      \
     template hipError_t cg_dir_k<T, KV>(const Group&, const Inst<T>*, const CgState*, CgState*, int, hipStream_t);      \
-    template hipError_t cg_hvp_k<T, KV>(const Group&, const Inst<T>*, const CgState*, CgState*, int, hipStream_t);
+    template hipError_t cg_hvp_k<T, KV>(const Group&, const Inst<T>*, const CgState*, CgState*, int, hipStream_t);      \
+    template hipError_t apg_team_k<T, KV>(const Group&, const Inst<T>*, const int*, int, ApgState*, const TeamCtl&,      \
+                                          long, hipStream_t);                                                           \
+    template hipError_t cg_team_k<T, KV>(const Group&, const Inst<T>*, const int*, int, CgState*, int, const TeamCtl&,  \
+                                         long, hipStream_t);                                                            \
+    template hipError_t team_occupancy_k<T, KV>(const Group&, int*);
 
 // Instantiate every stencil launcher of both storage types for one K.
 #define MAID_INSTANTIATE_K(KV) MAID_INSTANTIATE_T(float, KV) MAID_INSTANTIATE_T(double, KV)

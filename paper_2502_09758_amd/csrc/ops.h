@@ -67,12 +67,21 @@ template <typename T> struct Ops {
                                 CgState* sout, hipStream_t s);
     static hipError_t cg_init(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const CgState* sin,
                               hipStream_t s);
+    // Persistent loops of a group on one team per XCD (ctl.P members each);
+    // list: device array of the nlist instance indices of the group.
+    static hipError_t apg_team(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st,
+                               const TeamCtl& ctl, long max_slots, hipStream_t s);
+    static hipError_t cg_team(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                              const TeamCtl& ctl, long max_slots, hipStream_t s);
+    static hipError_t team_occupancy(const Group& g, int* blocks_per_cu);
     static hipError_t hg_corr(const Shape& d, const T* rho, const T* q, const T* w, const T* xt, double* part, int nblk,
                               hipStream_t s);
 };
 
 hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
                            const double* a, int with_r, double* z, double* znorm2, hipStream_t s);
+// XCD of each block of a kTeamXcd x kTeamMax grid (out: that many ints).
+hipError_t launch_team_map(int* out, hipStream_t s);
 hipError_t launch_publish(const void* src, size_t bytes, void* dst_host, unsigned* flag_host, hipStream_t s);
 hipError_t launch_theta_step(const double* th, const double* z, double step, double* out, int KK, hipStream_t s);
 hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s);

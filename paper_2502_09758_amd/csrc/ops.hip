@@ -100,6 +100,32 @@ hipError_t Ops<T>::cg_hvp(const Group& g, const Inst<T>* insts, const CgState* s
 }
 
 template <typename T>
+hipError_t Ops<T>::apg_team(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st,
+                            const TeamCtl& ctl, long max_slots, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return apg_team_k<T, KV>(g, insts, list, nlist, st, ctl, max_slots, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
+hipError_t Ops<T>::cg_team(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                           const TeamCtl& ctl, long max_slots, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return cg_team_k<T, KV>(g, insts, list, nlist, st, n, ctl, max_slots, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
+hipError_t Ops<T>::team_occupancy(const Group& g, int* blocks_per_cu) {
+#define MAID_CASE(KV) \
+    case KV: return team_occupancy_k<T, KV>(g, blocks_per_cu);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
 hipError_t Ops<T>::apg_final(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const ApgState* sin,
                              hipStream_t s) {
     return launch(k_apg_final<T>, dim3(grid_e), dim3(kNT), 0, s, insts, blk_e, only, sin);
@@ -123,6 +149,15 @@ hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w,
     if (d.K <= 16)
         return launch((k_hg_corr<T, 16>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
     return launch((k_hg_corr<T, 32>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
+}
+
+// XCD (hardware XCC_ID) of every block of the grid.
+__global__ __launch_bounds__(64) void k_team_map(int* out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = (int)(__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 7u);
+}
+
+hipError_t launch_team_map(int* out, hipStream_t s) {
+    return launch(k_team_map, dim3(kTeamXcd * kTeamMax), dim3(64), 0, s, out);
 }
 
 // Copy `words` 32-bit words of solver state into host-visible memory and

@@ -15,4 +15,12 @@ template <typename T, int K>
 hipError_t cg_dir_k(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);
 template <typename T, int K>
 hipError_t cg_hvp_k(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);
+template <typename T, int K>
+hipError_t apg_team_k(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st, const TeamCtl& ctl,
+                      long max_slots, hipStream_t s);
+template <typename T, int K>
+hipError_t cg_team_k(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                     const TeamCtl& ctl, long max_slots, hipStream_t s);
+template <typename T, int K>
+hipError_t team_occupancy_k(const Group& g, int* blocks_per_cu);
 }  // namespace maid

@@ -115,6 +115,10 @@ class Maid:
     def set_tile_rows(self, rows: int):
         self._check(L.lib().maid_set_tile_rows(self.handle, int(rows)), "set_tile_rows")
 
+    def set_team(self, members: int):
+        """Members per team of the persistent loops: -1 size rule, 0 off."""
+        self._check(L.lib().maid_set_team(self.handle, int(members)), "set_team")
+
     def autotune(self, theta, y, probe_iters=6):
         """Pick the tile height by timing short probe solves; returns the rows
         per thread chosen."""
@@ -240,6 +244,7 @@ class MaidBatch:
     handle = Maid.handle
     config = Maid.config
     set_tile_rows = Maid.set_tile_rows
+    set_team = Maid.set_team
     profile = Maid.profile
     profile_read = Maid.profile_read
     _check = Maid._check
