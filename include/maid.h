@@ -144,7 +144,9 @@ int maid_set_team(maid_ctx* ctx, int32_t members);
    1..1000, tolerance 0) with every rows-per-thread candidate on
    the caller's data (theta[i], y[i]: HOST arrays of n DEVICE pointers, as
    for the batched calls; only workspace is written) and keep the fastest
-   (candidates 1, 2, 4, and 8 for K >= 13).
+   (candidates 1, 2, 4, and 8 for K >= 13; where every instance of the K
+   has one channel and 3 <= K <= 11, each with the two-pass and the
+   one-pass form of the lower-level iteration, see maid_lower_solve).
    rows_out (HOST, n, nullable): the choice per instance.  A later
    maid_set_tile_rows(ctx, r != 0) overrides the choice. */
 int maid_autotune(maid_ctx* ctx, const void* const* theta, const void* const* y, int32_t probe_iters,
@@ -157,7 +159,15 @@ int maid_autotune(maid_ctx* ctx, const void* const* theta, const void* const* y,
    it steps x+ = v - G/L and doubles L until h(x+) - h(v) <= -||G||^2/(2L).
    x: in = starting point, out = the returned point.  L_inout: Lipschitz
    estimate in/out (<= 0 on input: ||theta||_1^2).  trace_bt (HOST, nullable,
-   length >= max_iter): rejected trials per iteration.  info: nullable. */
+   length >= max_iter): rejected trials per iteration.  info: nullable.
+   Two forms of one iteration: two passes (gradient, then trial step), or
+   -- for one channel and 3 <= K <= 11 -- one pass in which every tile also
+   computes G on its convolution halo and takes the trial step at once (the
+   stop and decrease tests move to the start of the next pass; the same
+   decisions, iterates equal to rounding of the partial sums).  The
+   autotuner chooses per K; untuned, the one-pass form is used for instances
+   of at most 640 of its tiles (about 380 x 380 for K = 9 at one row per
+   thread). */
 int maid_lower_solve(maid_ctx* ctx, const void* theta, const void* y, void* x,
                      double tol, int32_t max_iter, double* L_inout,
                      maid_solve_info* info, int32_t* trace_bt, hipStream_t stream);
@@ -278,7 +288,8 @@ enum {
     MAID_PROF_OTHER = 7,      /* small kernels */
     MAID_PROF_APG_TEAM = 8,   /* lower-level loop of small instances on one team per XCD (work: slots) */
     MAID_PROF_CG_TEAM = 9,    /* CG loop of small instances on one team per XCD (work: iterations) */
-    MAID_PROF_KINDS = 10
+    MAID_PROF_APG_STEP = 10,  /* lower level, one-pass form: gradient and trial step in one pass */
+    MAID_PROF_KINDS = 11
 };
 int maid_profile(maid_ctx* ctx, int32_t enable);
 int maid_profile_read(maid_ctx* ctx, int32_t kind, int64_t* launches, int64_t* work_launches, double* total_ms);

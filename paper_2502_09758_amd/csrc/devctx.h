@@ -29,7 +29,11 @@ enum Status : int32_t { ST_OK = 0, ST_MAXITER = 1, ST_NOT_SPD = -4, ST_NONFINITE
 // gradient pass reads the first and its block 0 of each instance writes the
 // second; the trial pass reads the second and writes the first.  No kernel
 // writes the copy it reads, so every block of a launch sees the same state.
-enum ApgPhase : int32_t { PH_START = 0, PH_GRAD_READY = 1, PH_RETRY = 2, PH_TRIALED = 3 };
+// (PH_STEP_*: the one-pass form -- the last pass computed G and a trial at a
+// new point, or again at the same point after a rejection.)
+enum ApgPhase : int32_t {
+    PH_START = 0, PH_GRAD_READY = 1, PH_RETRY = 2, PH_TRIALED = 3, PH_STEP_NEW = 4, PH_STEP_RETRY = 5
+};
 
 struct ApgState {
     double L, t, t_prev, m;      // Lipschitz estimate, momentum sequence, m = (t_prev-1)/t
@@ -41,6 +45,7 @@ struct ApgState {
     int32_t cur, prev, nxt;      // rotation of the three x / Kx buffers
     int32_t trace_cap;
     int32_t resync;              // theta*x recomputed exactly when iters % resync < 2 (0: never)
+    int32_t pp;                  // one-pass form: half of pA / pB the last pass wrote its partials to
 };
 
 // CG state, one per instance, in three arrays: the direction pass reads the
@@ -127,6 +132,7 @@ template <typename T> struct Inst {
     int32_t K;                   // kernel size
     int32_t nb, base;            // stencil blocks (tiles x channels) and first block within its group launch
     int32_t nbe, base_e;         // elementwise blocks and first block within the elementwise launch
+    int32_t nbf, basef;          // blocks of the one-pass FISTA launch (0: not on that path)
     int32_t cv_prev_slot;        // red slot for cv_prev_part's total
     int64_t N;                   // C*H*W
     // lower level (FISTA)

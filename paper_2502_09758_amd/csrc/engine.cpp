@@ -123,6 +123,8 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
     I.base = M.base;
     I.nbe = M.nbe;
     I.base_e = M.base_e;
+    I.nbf = M.nbf;
+    I.basef = M.basef;
     I.N = M.N;
     for (int k = 0; k < 3; ++k) {
         I.X[k] = (T*)M.X[k];
@@ -202,7 +204,7 @@ void prof_harvest(maid_ctx* c) {
             // kinds without early exits: every launch works
             if (r.kind != MAID_PROF_APG_GRAD && r.kind != MAID_PROF_APG_TRIAL && r.kind != MAID_PROF_CG_DIR &&
                 r.kind != MAID_PROF_CG_HVP && r.kind != MAID_PROF_CG_UPDATE && r.kind != MAID_PROF_APG_TEAM &&
-                r.kind != MAID_PROF_CG_TEAM)
+                r.kind != MAID_PROF_CG_TEAM && r.kind != MAID_PROF_APG_STEP)
                 c->prof_work[r.kind] += 1;
         }
         c->prof_pool.push_back(r.a);
@@ -312,12 +314,14 @@ int validate_desc(const maid_desc* d, std::string& why) {
 // lower + CG iterations ~17% faster on teams than as kernels; 256x256, 256
 // tiles, 2.4x slower), so larger instances stay on the multi-kernel passes.
 constexpr int kTeamTiles = 64;
+constexpr int kStepTiles = 640;
 int team_members(maid_ctx* c, const LaunchGroup& lg) {
     if (!c->team_ok || c->team_req == 0 || lg.g.R > 4) return 0;
     int most_tiles = 0, cap = kTeamMax;
     for (int i : lg.members) {
-        most_tiles = std::max(most_tiles, c->m[i].nb);
-        cap = std::min(cap, std::min(c->m[i].nb, c->m[i].nbe));
+        const int tiles = lg.g.grid_f > 0 ? c->m[i].nbf : c->m[i].nb;
+        most_tiles = std::max(most_tiles, tiles);
+        cap = std::min(cap, std::min(tiles, c->m[i].nbe));
     }
     if (c->team_req < 0 && most_tiles > kTeamTiles) return 0;
     int bpc = 0;
@@ -339,14 +343,24 @@ int relayout(maid_ctx* c) {
         Member& M = c->m[i];
         M.R = c->R_override ? std::min(c->R_override, max_rows(M.d.K)) : (M.R_tuned ? M.R_tuned : M.R_auto);
         M.nb = stencil_blocks(M.shape, M.R);
+        // the one-pass FISTA form: one channel, 3 <= K <= 11, and the
+        // autotuner's choice (untuned: instances of at most kStepTiles
+        // tiles; larger ones are bound by the ALUs, which the recomputed
+        // halo gradient loads further)
+        bool fuse = c->fuse && step_ok(M.d.C, M.d.K, M.R);
+        if (c->fuse_force >= 0) fuse = fuse && c->fuse_force == 1;
+        else if (M.fuse_tuned >= 0) fuse = fuse && M.fuse_tuned == 1;
+        else fuse = fuse && step_blocks(M.d.H, M.d.W, M.d.K, M.R) <= kStepTiles;
+        M.nbf = fuse ? step_blocks(M.d.H, M.d.W, M.d.K, M.R) : 0;
     }
     std::vector<char> placed(c->n, 0);
     for (int i = 0; i < c->n; ++i) {
         if (placed[i]) continue;
         LaunchGroup lg;
-        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr, -1};
+        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr, -1, 0, nullptr};
         for (int k = i; k < c->n; ++k)
-            if (!placed[k] && c->m[k].d.K == lg.g.K && c->m[k].R == lg.g.R) {
+            if (!placed[k] && c->m[k].d.K == lg.g.K && c->m[k].R == lg.g.R &&
+                (c->m[k].nbf > 0) == (c->m[i].nbf > 0)) {
                 placed[k] = 1;
                 lg.members.push_back(k);
             }
@@ -360,6 +374,19 @@ int relayout(maid_ctx* c) {
             base = round8(base + M.nb);
         }
         c->groups.push_back(lg);
+    }
+    // one-pass block ranges, then team loops for groups of tiny instances
+    for (auto& lg : c->groups) {
+        int basef = 0;
+        for (int i : lg.members) {
+            Member& M = c->m[i];
+            M.basef = M.nbf > 0 ? basef : 0;
+            if (M.nbf > 0) {
+                lg.g.grid_f = basef + M.nbf;
+                basef = round8(basef + M.nbf);
+            }
+        }
+        lg.team = team_members(c, lg);
     }
     int base_e = 0;
     for (int i = 0; i < c->n; ++i) {
@@ -385,10 +412,20 @@ int relayout(maid_ctx* c) {
         const int end = i + 1 < c->n ? c->m[i + 1].base_e : c->grid_e;
         for (int b = c->m[i].base_e; b < end; ++b) host[off_e + b] = i;
     }
-    std::vector<size_t> offs_l;
+    std::vector<size_t> offs_l, offs_f;
     for (auto& lg : c->groups) {
         offs_l.push_back(host.size());
         host.insert(host.end(), lg.members.begin(), lg.members.end());
+    }
+    for (auto& lg : c->groups) {
+        offs_f.push_back(host.size());
+        host.resize(host.size() + lg.g.grid_f);
+        int* mp = host.data() + offs_f.back();
+        for (size_t t = 0; t < lg.members.size() && lg.g.grid_f > 0; ++t) {
+            const Member& M = c->m[lg.members[t]];
+            const int end = t + 1 < lg.members.size() ? c->m[lg.members[t + 1]].basef : lg.g.grid_f;
+            for (int b = M.basef; b < end; ++b) mp[b] = lg.members[t];
+        }
     }
     if (host.size() > c->maps_cap) return fail(c, MAID_EHIP, "relayout: block maps exceed their allocation");
     HIP_TRY(hipMemcpy(c->maps, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -401,7 +438,7 @@ int relayout(maid_ctx* c) {
     for (size_t g = 0; g < c->groups.size(); ++g) {
         LaunchGroup& lg = c->groups[g];
         lg.list = c->maps + offs_l[g];
-        lg.team = team_members(c, lg);
+        lg.g.blk_f = lg.g.grid_f > 0 ? c->maps + offs_f[g] : nullptr;
     }
     c->layout_gen += 1;
     for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -416,6 +453,7 @@ int relayout(maid_ctx* c) {
             std::snprintf(buf, sizeof(buf), " team=%d", lg.team);
             c->cfg += buf;
         }
+        if (lg.g.grid_f > 0) c->cfg += " one-pass";
     }
     return MAID_OK;
 }
@@ -497,13 +535,15 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.shape = Shape{M.d.C, M.d.H, M.d.W, M.d.K, M.d.reg};
         M.N = (int64_t)M.d.C * M.d.H * M.d.W;
         M.R_auto = auto_rows(M.shape);
+        M.fuse_tuned = -1;
         M.nbe = (int)std::min<int64_t>((M.N + kNT - 1) / kNT, kEwMaxBlocks);
         const size_t img = al((size_t)M.N * c->esz);
-        const size_t nblk = std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe);
+        const size_t nblk = std::max<size_t>(std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe),
+                                             (size_t)step_blocks(M.d.H, M.d.W, M.d.K, 1));
         const size_t part = al(nblk * sizeof(double));
-        total += 17 * img + 6 * kern + 5 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
+        total += 17 * img + 6 * kern + 7 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
                  al(kTraceCap * sizeof(int));
-        maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe);
+        maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe) + round8(step_blocks(M.d.H, M.d.W, M.d.K, 1));
     }
     c->ws_bytes = total;
     maps += n;   // the groups' instance lists
@@ -534,6 +574,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     }
     if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
     if (const char* t = std::getenv("MAID_TEAM")) c->team_req = std::max(-1, std::atoi(t));
+    if (const char* f = std::getenv("MAID_FUSE")) c->fuse = std::strcmp(f, "0") != 0;
     // longest wait at a team barrier, in wall-clock ticks (0 forces the
     // multi-kernel fallback, for tests)
     if (const char* w = std::getenv("MAID_TEAM_WAIT")) c->team_wait = std::max(0LL, std::atoll(w));
@@ -565,7 +606,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     for (int i = 0; i < n; ++i) {
         Member& M = c->m[i];
         const size_t img = al((size_t)M.N * c->esz);
-        const size_t nblk = std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe);
+        const size_t nblk = std::max<size_t>(std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe),
+                                             (size_t)step_blocks(M.d.H, M.d.W, M.d.K, 1));
         const size_t part = al(nblk * sizeof(double));
         for (int k = 0; k < 3; ++k) M.X[k] = take(img);
         for (int k = 0; k < 3; ++k) M.KX[k] = take(img);
@@ -586,8 +628,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.af_c = take(kern);
         M.th_trial = (double*)take(kern);
         M.zbuf = (double*)take(kern);
-        M.pA = (double*)take(part);
-        M.pB = (double*)take(part);
+        // pA, pB: two halves each for the one-pass form
+        M.pA = (double*)take(2 * part);
+        M.pB = (double*)take(2 * part);
         M.pR = (double*)take(part);
         M.pK = (double*)take(part);
         M.pC = (double*)take(part);
@@ -672,13 +715,22 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         for (;;) {
             chunk = next_slots(pred, slots, chunk);
             int rc = run_slots(c, G_APG, chunk, s, [&](hipStream_t s, int cnt) {
+                // one-pass groups take two iterations per slot (state there and back)
                 for (int k = 0; k < cnt; ++k) {
-                    for (auto& lg : c->groups)
-                        if (lg.team == 0)
+                    for (auto& lg : c->groups) {
+                        if (lg.team != 0) continue;
+                        if (lg.g.grid_f > 0)
+                            LAUNCH(MAID_PROF_APG_STEP, Ops<T>::apg_step(lg.g, tabd, c->apg[0], c->apg[1], s));
+                        else
                             LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(lg.g, tabd, c->apg[0], c->apg[1], s));
-                    for (auto& lg : c->groups)
-                        if (lg.team == 0)
+                    }
+                    for (auto& lg : c->groups) {
+                        if (lg.team != 0) continue;
+                        if (lg.g.grid_f > 0)
+                            LAUNCH(MAID_PROF_APG_STEP, Ops<T>::apg_step(lg.g, tabd, c->apg[1], c->apg[0], s));
+                        else
                             LAUNCH(MAID_PROF_APG_TRIAL, Ops<T>::apg_trial(lg.g, tabd, c->apg[1], c->apg[0], s));
+                    }
                 }
                 return (int)MAID_OK;
             });
@@ -705,9 +757,14 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
     for (int i = 0; i < n; ++i)
         if (act[i] && !c->apg_h[i].done) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
     {
+        // one-pass instances: a pass per iteration or backtracking step, one
+        // more at the start, two passes per slot
         long need = 1;
-        for (int i = 0; i < n; ++i)
-            if (act[i]) need = std::max<long>(need, (long)c->apg_h[i].iters + c->apg_h[i].bt + 1);
+        for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            const long steps = (long)c->apg_h[i].iters + c->apg_h[i].bt;
+            need = std::max<long>(need, c->m[i].nbf > 0 ? (steps + 3) / 2 : steps + 1);
+        }
         c->pred_slots[pred_role] = need;
     }
     if (c->prof_on) {
@@ -715,10 +772,13 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         // accepted step, a trial for every accepted or rejected step (the
         // busiest instance of the batch); team loops: the slots of every
         // instance (each slot one trial pass and one gradient pass)
-        int64_t wg = 0, wt = 0, wteam = 0;
+        // one-pass form: every pass but the one that finds the stop computes
+        int64_t wg = 0, wt = 0, wteam = 0, wstep = 0;
         for (int i = 0; i < n; ++i)
             if (act[i] && in_team[i]) {
                 wteam += c->apg_h[i].iters + c->apg_h[i].bt;
+            } else if (act[i] && c->m[i].nbf > 0) {
+                wstep = std::max<int64_t>(wstep, c->apg_h[i].iters + c->apg_h[i].bt + 1);
             } else if (act[i]) {
                 wg = std::max<int64_t>(wg, c->apg_h[i].iters + 1);
                 wt = std::max<int64_t>(wt, c->apg_h[i].iters + c->apg_h[i].bt);
@@ -726,6 +786,7 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         c->prof_work[MAID_PROF_APG_GRAD] += wg;
         c->prof_work[MAID_PROF_APG_TRIAL] += wt;
         c->prof_work[MAID_PROF_APG_TEAM] += wteam;
+        c->prof_work[MAID_PROF_APG_STEP] += wstep;
     }
     LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, c->only_e, tabd, c->apg[0], s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1042,12 +1103,13 @@ int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, in
 
 // ------------------------------------------------------------------ autotuner
 // For every candidate tile height (rows per thread 1, 2, 4, and 8 for
-// K >= 13) all instances
-// take that candidate; a short lower-level solve and a short CG solve (fixed
-// iteration counts, tolerance 0, on the caller's data, writing only
-// workspace) run with per-launch timing, and the GPU time of the solver
-// passes is summed per kernel size K.  Each K group keeps its fastest
-// candidate.  The caller's own timing state is restored.
+// K >= 13), and with each of the two forms of the lower-level iteration
+// where the one-pass form applies (one channel, 3 <= K <= 11, rows <= 4),
+// all instances take that candidate; a short lower-level solve and a short
+// CG solve (fixed iteration counts, tolerance 0, on the caller's data,
+// writing only workspace) run with per-launch timing, and the GPU time of
+// the solver passes is summed per kernel size K.  Each K group keeps its
+// fastest candidate.  The caller's own timing state is restored.
 template <typename T>
 int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const std::vector<const T*>& y, int probe_iters,
                    int32_t* rows_out, hipStream_t s) {
@@ -1057,7 +1119,7 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
     for (int i = 0; i < n; ++i)
         if (std::find(Ks.begin(), Ks.end(), c->m[i].d.K) == Ks.end()) Ks.push_back(c->m[i].d.K);
     std::vector<double> best(Ks.size(), 1e300);
-    std::vector<int> best_R(Ks.size(), 0);
+    std::vector<int> best_R(Ks.size(), 0), best_F(Ks.size(), 0);
     // keep the caller's timing state
     prof_harvest(c);
     const bool prof_was = c->prof_on;
@@ -1082,9 +1144,16 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
     for (int k = 0; k < (int)Ks.size() && rc == MAID_OK; ++k) {
         std::vector<char> act(n, 0);
         for (int i = 0; i < n; ++i) act[i] = c->m[i].d.K == Ks[k];
-        for (int ci = 0; ci < 4 && rc == MAID_OK; ++ci) {
+        // the one-pass FISTA form is a candidate where every instance of this K allows it
+        bool fuse_ok = c->fuse;
+        for (int i = 0; i < n; ++i)
+            if (act[i]) fuse_ok = fuse_ok && step_ok(c->m[i].d.C, c->m[i].d.K, 1);
+        for (int cj = 0; cj < 8 && rc == MAID_OK; ++cj) {
+            const int ci = cj >> 1, f = cj & 1;
             if (cands[ci] > max_rows(Ks[k])) continue;
+            if (f == 1 && !(fuse_ok && step_ok(1, Ks[k], cands[ci]))) continue;
             c->R_override = cands[ci];
+            c->fuse_force = f;
             if ((rc = relayout(c))) break;
             for (int i = 0; i < n; ++i)
                 if (act[i]) {
@@ -1107,10 +1176,13 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
             c->prof_on = false;
             if (rc) break;
             const double t = c->prof_ms[MAID_PROF_APG_GRAD] + c->prof_ms[MAID_PROF_APG_TRIAL] +
-                             c->prof_ms[MAID_PROF_CG_DIR] + c->prof_ms[MAID_PROF_CG_HVP];
+                             c->prof_ms[MAID_PROF_APG_STEP] + c->prof_ms[MAID_PROF_CG_DIR] +
+                             c->prof_ms[MAID_PROF_CG_HVP] + c->prof_ms[MAID_PROF_APG_TEAM] +
+                             c->prof_ms[MAID_PROF_CG_TEAM];
             if (t < best[k]) {
                 best[k] = t;
                 best_R[k] = cands[ci];
+                best_F[k] = f;
             }
         }
     }
@@ -1119,10 +1191,14 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
     std::memcpy(c->prof_ms, sv_ms, sizeof(sv_ms));
     c->prof_on = prof_was;
     c->R_override = R_over;
+    c->fuse_force = -1;
     if (rc == MAID_OK)
         for (int i = 0; i < n; ++i)
             for (size_t k = 0; k < Ks.size(); ++k)
-                if (c->m[i].d.K == Ks[k]) c->m[i].R_tuned = best_R[k];
+                if (c->m[i].d.K == Ks[k]) {
+                    c->m[i].R_tuned = best_R[k];
+                    c->m[i].fuse_tuned = best_F[k];
+                }
     const int rc2 = relayout(c);
     if (rc) return rc;
     if (rc2) return rc2;

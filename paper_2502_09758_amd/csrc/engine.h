@@ -40,9 +40,11 @@ struct Member {
     int64_t N;
     int R_auto;                 // rows per thread from the size rule
     int R_tuned;                // rows per thread chosen by the autotuner (0: none)
+    int fuse_tuned;             // one-pass FISTA chosen by the autotuner (-1: not tuned, 0 no, 1 yes)
     int nbe;                    // elementwise blocks
     // current layout (depends on the tile rows)
     int R, nb, base, base_e;
+    int nbf, basef;             // one-pass FISTA blocks and first block in the group's launch (0: two-pass)
     // device workspace, carved from the context's allocation
     void* X[3];
     void* KX[3];
@@ -119,6 +121,8 @@ struct maid_ctx {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     // persistent team loops for small instances (one team per XCD)
+    bool fuse = true;                 // one-pass FISTA where the group allows it
+    int fuse_force = -1;              // autotuner's candidate: -1 none, 0 two-pass, 1 one-pass
     int team_req = -1;                // members per team: -1 size rule, 0 never, > 0 that many (capped)
     bool team_ok = false;             // blocks reach the XCDs round-robin and XCC_ID reads them
     int cus_per_xcd = 0;

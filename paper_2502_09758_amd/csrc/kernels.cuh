@@ -151,7 +151,7 @@ __device__ __forceinline__ void put_state(ApgState* __restrict__ o, const ApgSta
     o->L = s.L; o->t = s.t; o->t_prev = s.t_prev; o->m = s.m; o->gn2 = s.gn2; o->tol = s.tol;
     o->delta_last = s.delta_last; o->max_iter = s.max_iter; o->iters = s.iters; o->bt = s.bt;
     o->nb_iter = s.nb_iter; o->status = s.status; o->done = s.done; o->phase = s.phase; o->cur = s.cur;
-    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->resync = s.resync;
+    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->resync = s.resync; o->pp = s.pp;
 }
 __device__ __forceinline__ void put_state(CgState* __restrict__ o, const CgState& s) {
     o->gamma = s.gamma; o->kappa = s.kappa; o->a = s.a; o->tol = s.tol; o->max = s.max; o->iters = s.iters;
@@ -223,9 +223,16 @@ __device__ __forceinline__ void correlate_col(const T* s, int pitch, const T* __
     }
 }
 
+// Small kernels with short columns unroll the column loop too, so that the
+// LDS reads of the next columns are in flight during this column's FMAs (a
+// pass of a small image has few waves per SIMD to hide that latency).
+template <typename T, int K, int R> __host__ __device__ constexpr bool corr_unrolled() {
+    return K <= 5 || (K <= 11 && K * (R + K - 1) <= (sizeof(T) == 4 ? 160 : 96));
+}
+
 template <typename T, int K, int R>
 __device__ __forceinline__ void correlate(const T* s, int pitch, const T* __restrict__ kT, int li0, int tx, T (&acc)[R]) {
-    if constexpr (K <= 5) {
+    if constexpr (corr_unrolled<T, K, R>()) {
 #pragma unroll
         for (int v = 0; v < K; ++v) correlate_col<T, K, R>(s, pitch, kT, li0, tx, v, acc);
     } else {

@@ -51,7 +51,17 @@ struct Group {
     int grid;          // blocks of one pass over the group
     const int* blk;    // device map, grid entries
     int only;          // the instance index if the group has one instance, else -1
+    int grid_f;        // blocks of a one-pass FISTA launch over the group (0: two-pass form)
+    const int* blk_f;  // its device map
 };
+
+// Whether a group can take the one-pass FISTA form: one channel and
+// 3 <= K <= 11 (tile rows 1, 2, 4).
+inline bool step_ok(int C, int K, int R) { return C == 1 && K >= 3 && K <= 11 && R <= 4; }
+inline int step_blocks(int H, int W, int K, int R) {
+    const int tw = kTW - (K - 1);
+    return ((W + tw - 1) / tw) * ((H + tile_h(R) - 1) / tile_h(R));
+}
 
 template <typename T> struct Ops {
     static hipError_t prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, int slot_abs, hipStream_t s);
@@ -59,6 +69,7 @@ template <typename T> struct Ops {
     static hipError_t conv(const Group& g, const Inst<T>* insts, hipStream_t s);
     static hipError_t apg_grad(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
     static hipError_t apg_trial(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
+    static hipError_t apg_step(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
     static hipError_t apg_final(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const ApgState* sin,
                                 hipStream_t s);
     static hipError_t cg_dir(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);

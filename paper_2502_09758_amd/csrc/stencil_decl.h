@@ -23,4 +23,6 @@ hipError_t cg_team_k(const Group& g, const Inst<T>* insts, const int* list, int 
                      const TeamCtl& ctl, long max_slots, hipStream_t s);
 template <typename T, int K>
 hipError_t team_occupancy_k(const Group& g, int* blocks_per_cu);
+template <typename T, int K>
+hipError_t apg_step_k(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
 }  // namespace maid

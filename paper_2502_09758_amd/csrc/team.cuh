@@ -32,6 +32,7 @@
 // after the other.
 #pragma once
 #include "kernels.cuh"
+#include "step.cuh"
 
 namespace maid {
 
@@ -85,11 +86,11 @@ struct Team {
 
 // FISTA loop (Algorithm 1, lower level) for the instances of a group: per
 // slot one gradient pass and one trial pass, as the multi-kernel path runs
-// them, until every solve has stopped or max_slots slots have run (the final
-// point is formed by the elementwise pass that follows, as on the
-// multi-kernel path).  st: the state array (read at the start, written at
-// the end).
-template <typename T, int K, int R>
+// them (STEP: one pass of the one-pass form), until every solve has stopped
+// or max_slots slots have run (the final point is formed by the elementwise
+// pass that follows, as on the multi-kernel path).  st: the state array
+// (read at the start, written at the end).
+template <typename T, int K, int R, bool STEP>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_team(
     const Inst<T>* __restrict__ insts, const int* __restrict__ list, int nlist, ApgState* __restrict__ st_arr,
     TeamCtl ctl, long max_slots) {
@@ -98,7 +99,21 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         const int ii = list[j];
         const Inst<T>& I = insts[ii];
         ApgState st = st_arr[ii];
-        if (!st.done) {
+        if (STEP && !st.done) {
+            // one-pass form: one pass (and one barrier) per iteration
+            for (long slot = 0;; ++slot) {
+                ApgState nx = st;
+                for (int lb = tm.me; lb < I.nbf; lb += tm.P) {
+                    nx = st;
+                    __syncthreads();
+                    if constexpr (STEP) apg_step_body<T, K, R, true>(I, lb, nx, nullptr, lb == 0 && threadIdx.x == 0);
+                }
+                st = nx;
+                if (st.done) break;
+                if (!tm.sync()) return;
+                if (slot + 1 >= max_slots) break;
+            }
+        } else if (!st.done) {
             for (long slot = 0;; ++slot) {
                 ApgState nx = st;
                 for (int lb = tm.me; lb < I.nb; lb += tm.P) {

@@ -1,0 +1,150 @@
+"""One-pass form of the lower-level iteration (gradient on the tile's
+convolution halo, trial step in the same pass) against the two-pass form,
+through the C ABI.
+
+Both forms take the same decisions in the same order (stop test on ||G_k||,
+then the decrease test of trial k) with the same per-pixel formulas; the
+partial sums run over different tiles, and the compiler may contract
+products into FMAs differently in the two kernels, so results agree to
+rounding.  Checked: iteration and
+backtracking counts, backtracking traces, Lipschitz estimates and iterates
+(to rounding) for K = 3..11, ragged tile tails, every tile height, both
+storage types, TV and quadratic regularisers, runs with many rejected
+trials, and MAID steps.  The oracle parity of the one-pass form is covered
+by the lower-level parity tests, which take it for every one-channel case
+with K <= 11."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2502_09758_amd import _lib as L
+from paper_2502_09758_amd import synth
+from paper_2502_09758_amd.maid import Maid, MaidBatch, MaidState
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def ctx(inst, dt, one_pass, rows=0, reg=L.MAID_REG_TV):
+    os.environ["MAID_FUSE"] = "1" if one_pass else "0"
+    try:
+        m = Maid(inst.C, inst.H, inst.W, inst.K, dt, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta, reg=reg)
+    finally:
+        del os.environ["MAID_FUSE"]
+    m.set_team(0)
+    if rows:
+        m.set_tile_rows(rows)
+    assert ("one-pass" in m.config()) == one_pass, m.config()
+    return m
+
+
+def solve(m, inst, dt, tol, L0=0.0, max_iter=400):
+    th = dev(inst.a, torch.float64)
+    y = dev(inst.y, dt)
+    x = y.clone()
+    info = m.lower_solve(th, y, x, tol, max_iter=max_iter, L_est=L0, trace=True)
+    return x, info
+
+
+def check_pair(inst, dt, rows, tol, L0=0.0, reg=L.MAID_REG_TV):
+    m0 = ctx(inst, dt, False, rows, reg)
+    x0, i0 = solve(m0, inst, dt, tol, L0)
+    m0.close()
+    m1 = ctx(inst, dt, True, rows, reg)
+    x1, i1 = solve(m1, inst, dt, tol, L0)
+    m1.close()
+    assert (i0.status, i0.iters, i0.backtracks) == (i1.status, i1.iters, i1.backtracks), (i0, i1)
+    assert i0.trace == i1.trace
+    assert i0.L == i1.L
+    rt = 1e-5 if dt == torch.float32 else 1e-12
+    # ||G|| is a small difference of large terms, so the rounding of the
+    # iterates (the two forms' kernels may contract products into FMAs
+    # differently) shows in it much more than in the iterates themselves
+    assert abs(i0.res_norm - i1.res_norm) <= (2e-2 if dt == torch.float32 else 1e-6) * i0.res_norm
+    err = float((x0 - x1).norm() / x0.norm())
+    assert err <= rt, err
+    return i1
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+@pytest.mark.parametrize("shape", [(40, 70, 5), (130, 96, 9), (64, 64, 3), (77, 201, 11), (100, 50, 7), (256, 256, 9)])
+def test_one_pass_matches_two_pass(dt, shape):
+    H, W, K = shape
+    print(f"[case] one-pass vs two-pass {shape} {dt}", flush=True)
+    inst = synth.make("cfg1", H=H, W=W, C=1, K=K, seed=300 + K)
+    tol = 1e-4 if dt == torch.float32 else 1e-7
+    for rows in (1, 2, 4):
+        check_pair(inst, dt, rows, tol)
+
+
+@pytest.mark.parametrize("reg", [L.MAID_REG_TV_CHANNELWISE, L.MAID_REG_QUADRATIC])
+def test_one_pass_other_regularisers(reg):
+    print(f"[case] one-pass regulariser {reg}", flush=True)
+    inst = synth.make("cfg1", H=90, W=120, C=1, K=7, seed=41)
+    check_pair(inst, torch.float64, 2, 1e-7, reg=reg)
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_one_pass_backtracking(dt):
+    """A start far below the Lipschitz constant: many rejected trials, each
+    recomputing G at the same point."""
+    print(f"[case] one-pass backtracking {dt}", flush=True)
+    inst = synth.make("cfg1", H=96, W=150, C=1, K=9, seed=77)
+    info = check_pair(inst, dt, 1, 1e-4 if dt == torch.float32 else 1e-7, L0=1e-4)
+    assert info.backtracks >= 5 and sum(info.trace) == info.backtracks
+
+
+def test_one_pass_maid_steps():
+    """Algorithm 2 iterations on the one-pass form agree with the two-pass
+    form (same accepted steps, trials and solve counts; iterates to
+    rounding)."""
+    print("[case] one-pass MAID steps", flush=True)
+    inst = synth.make("cfg1", H=96, W=128, C=1, K=9, seed=5)
+    out = []
+    for one_pass in (False, True):
+        m = ctx(inst, torch.float64, one_pass)
+        a = dev(inst.a, torch.float64)
+        y = dev(inst.y, torch.float64)
+        st = MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=1e-4, delta=1e-4, step=1e-3)
+        infos = []
+        for _ in range(4):
+            rc, info = m.maid_step(a, y, st)
+            assert rc >= 0
+            infos.append((info["accepted"], info["trials"], info["lower_iters"], info["cg_iters"]))
+        out.append((st.theta.clone(), st.x.clone(), infos))
+        m.close()
+    assert out[0][2] == out[1][2]
+    assert float((out[0][0] - out[1][0]).norm() / out[0][0].norm()) <= 1e-10
+    assert float((out[0][1] - out[1][1]).norm() / out[0][1].norm()) <= 1e-10
+
+
+def test_one_pass_batch_mixed_with_two_pass():
+    """A batch whose K groups take different forms (a 3-channel instance keeps
+    its group on two passes) equals solo runs of each instance."""
+    print("[case] one-pass in a mixed batch", flush=True)
+    shapes = [(1, 80, 90, 5), (1, 70, 130, 5), (3, 60, 60, 7), (1, 50, 200, 9), (1, 150, 40, 13)]
+    insts = [synth.make("cfg1", H=H, W=W, C=C, K=K, seed=500 + i) for i, (C, H, W, K) in enumerate(shapes)]
+    specs = [dict(C=i.C, H=i.H, W=i.W, K=i.K, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta) for i in insts]
+    mb = MaidBatch(specs, torch.float32)
+    mb.set_team(0)
+    cfg = mb.config()
+    assert "one-pass" in cfg, cfg
+    th = [dev(i.a, torch.float64) for i in insts]
+    ys = [dev(i.y, torch.float32) for i in insts]
+    xs = [y.clone() for y in ys]
+    rc, infos = mb.lower_solve(th, ys, xs, [1e-4] * len(insts), max_iter=400)
+    assert rc in (L.OK, L.MAXITER)
+    for k, inst in enumerate(insts):
+        m = Maid(inst.C, inst.H, inst.W, inst.K, torch.float32, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta)
+        m.set_team(0)
+        x = ys[k].clone()
+        info = m.lower_solve(th[k], ys[k], x, 1e-4, max_iter=400)
+        assert (info.iters, info.backtracks, info.L) == (infos[k].iters, infos[k].backtracks, infos[k].L)
+        assert torch.equal(x, xs[k]), f"instance {k}"
+        m.close()
+    mb.close()
