@@ -64,6 +64,12 @@ def kernel_model(kind: str, K: int, esz: int, C: int):
         return 6 * esz, k2 + 45
     if kind == "apg_trial":     # x, x_prev, G, Kx, Kx_prev, y -> x+, Kx+
         return 8 * esz, k2 + 50
+    if kind == "apg_step":      # one-pass iteration: x, x_prev, Kx, Kx_prev, y -> x+, Kx+ (G stays on chip)
+        return 7 * esz, 2 * k2 + 95
+    if kind == "apg_team":      # a gradient and a trial pass per slot
+        return 14 * esz, 2 * k2 + 95
+    if kind == "cg_team":       # direction, Hessian and update pass per iteration
+        return 14 * esz, 2 * k2 + 68
     if kind == "cg_dir":        # r, p_old -> p, Kp
         return 4 * esz, k2 + 2
     if kind == "cg_hvp":        # Kp, p, x -> Hp

@@ -146,7 +146,9 @@ int maid_set_team(maid_ctx* ctx, int32_t members);
    for the batched calls; only workspace is written) and keep the fastest
    (candidates 1, 2, 4, and 8 for K >= 13; where every instance of the K
    has one channel and 3 <= K <= 11, each with the two-pass and the
-   one-pass form of the lower-level iteration, see maid_lower_solve).
+   one-pass form of the lower-level iteration, see maid_lower_solve; each
+   candidate runs twice and the second run, with the launch predictors
+   set, is timed).
    rows_out (HOST, n, nullable): the choice per instance.  A later
    maid_set_tile_rows(ctx, r != 0) overrides the choice. */
 int maid_autotune(maid_ctx* ctx, const void* const* theta, const void* const* y, int32_t probe_iters,

@@ -1155,25 +1155,31 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
             c->R_override = cands[ci];
             c->fuse_force = f;
             if ((rc = relayout(c))) break;
-            for (int i = 0; i < n; ++i)
-                if (act[i]) {
-                    const size_t bytes = (size_t)c->m[i].N * sizeof(T);
-                    hipError_t e = hipMemcpyAsync(xs[i], y[i], bytes, hipMemcpyDeviceToDevice, s);
-                    if (e == hipSuccess) e = hipMemsetAsync(qs[i], 0, bytes, s);
-                    if (e != hipSuccess) {
-                        rc = fail(c, MAID_EHIP, std::string("autotune: ") + hipGetErrorString(e));
-                        break;
+            // twice: the first run sets the slot predictors of this layout
+            // (so that neither form pays for launches past the end), the
+            // second is timed
+            for (int rep = 0; rep < 2 && rc == MAID_OK; ++rep) {
+                for (int i = 0; i < n; ++i)
+                    if (act[i]) {
+                        const size_t bytes = (size_t)c->m[i].N * sizeof(T);
+                        hipError_t e = hipMemcpyAsync(xs[i], y[i], bytes, hipMemcpyDeviceToDevice, s);
+                        if (e == hipSuccess) e = hipMemsetAsync(qs[i], 0, bytes, s);
+                        if (e != hipSuccess) {
+                            rc = fail(c, MAID_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+                            break;
+                        }
+                        L[i] = 0.0;
                     }
-                    L[i] = 0.0;
-                }
-            if (rc) break;
-            c->prof_on = true;
-            for (int t = 0; t < MAID_PROF_KINDS; ++t) c->prof_ms[t] = 0.0;
-            rc = lower_batch<T>(c, act, theta, y, xs, tol, probe_iters, L.data(), nullptr, codes.data(), nullptr, s);
-            if (rc == MAID_OK)
-                rc = adjoint_batch<T>(c, act, theta, xsc, rhs, qs, tol, probe_iters, nullptr, codes.data(), s);
-            prof_harvest(c);
-            c->prof_on = false;
+                if (rc) break;
+                c->prof_on = true;
+                for (int t = 0; t < MAID_PROF_KINDS; ++t) c->prof_ms[t] = 0.0;
+                rc = lower_batch<T>(c, act, theta, y, xs, tol, probe_iters, L.data(), nullptr, codes.data(), nullptr,
+                                    s);
+                if (rc == MAID_OK)
+                    rc = adjoint_batch<T>(c, act, theta, xsc, rhs, qs, tol, probe_iters, nullptr, codes.data(), s);
+                prof_harvest(c);
+                c->prof_on = false;
+            }
             if (rc) break;
             const double t = c->prof_ms[MAID_PROF_APG_GRAD] + c->prof_ms[MAID_PROF_APG_TRIAL] +
                              c->prof_ms[MAID_PROF_APG_STEP] + c->prof_ms[MAID_PROF_CG_DIR] +

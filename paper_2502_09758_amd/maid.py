@@ -119,7 +119,7 @@ class Maid:
         """Members per team of the persistent loops: -1 size rule, 0 off."""
         self._check(L.lib().maid_set_team(self.handle, int(members)), "set_team")
 
-    def autotune(self, theta, y, probe_iters=6):
+    def autotune(self, theta, y, probe_iters=20):
         """Pick the tile height by timing short probe solves; returns the rows
         per thread chosen."""
         self._ker(theta, "theta"), self._img(y, "y")
@@ -275,7 +275,7 @@ class MaidBatch:
             raise L.MaidError(rc, f"{what}: {L.last_error(self.handle)}")
         return rc
 
-    def autotune(self, thetas, ys, probe_iters=6):
+    def autotune(self, thetas, ys, probe_iters=20):
         """Per K group, pick the tile height by timing short probe solves;
         returns the rows per thread chosen for each instance."""
         th, y = self._kers(thetas, "theta"), self._imgs(ys, "y")
