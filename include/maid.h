@@ -184,7 +184,11 @@ int maid_upper_value_grad(maid_ctx* ctx, const void* a, const void* y, const voi
    (theta.theta* + alpha grad^2 R(x_tilde)) q = rhs, stopping when the
    recursive residual satisfies ||r||_2 <= tol (the accuracy delta).
    q: in = starting point, out = solution.  MAID_NOT_SPD if a curvature
-   <p,Hp> <= 0 is met (q not written). */
+   <p,Hp> <= 0 is met (q not written).  Instances on the one-pass form (see
+   maid_lower_solve) run the Chronopoulos-Gear form of CG, which needs one
+   reduction per iteration (<r,r> and <r,Hr> together) and so one pass:
+   the same iterates in exact arithmetic, the same stop and curvature
+   tests. */
 int maid_adjoint_solve(maid_ctx* ctx, const void* theta, const void* x_tilde,
                        const void* rhs, void* q, double tol, int32_t max_iter,
                        maid_solve_info* info, hipStream_t stream);
@@ -291,7 +295,8 @@ enum {
     MAID_PROF_APG_TEAM = 8,   /* lower-level loop of small instances on one team per XCD (work: slots) */
     MAID_PROF_CG_TEAM = 9,    /* CG loop of small instances on one team per XCD (work: iterations) */
     MAID_PROF_APG_STEP = 10,  /* lower level, one-pass form: gradient and trial step in one pass */
-    MAID_PROF_KINDS = 11
+    MAID_PROF_CG_STEP = 11,   /* CG, one-pass form: update and Hessian product in one pass */
+    MAID_PROF_KINDS = 12
 };
 int maid_profile(maid_ctx* ctx, int32_t enable);
 int maid_profile_read(maid_ctx* ctx, int32_t kind, int64_t* launches, int64_t* work_launches, double* total_ms);

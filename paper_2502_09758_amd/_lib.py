@@ -28,7 +28,7 @@ EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string
            "maid_profile", "maid_profile_read", "maid_profile_name",
            "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
            "maid_batch_step", "maid_autotune", "maid_batch_upper_value_grad", "maid_batch_hypergrad")
-PROF_KINDS = 11
+PROF_KINDS = 12
 
 
 class maid_desc(ct.Structure):

@@ -149,7 +149,7 @@ int maid_profile_read(maid_ctx* c, int32_t kind, int64_t* launches, int64_t* wor
 const char* maid_profile_name(int32_t kind) {
     static const char* names[MAID_PROF_KINDS] = {"conv",    "apg_grad", "apg_trial", "cg_dir",   "cg_hvp",
                                                   "cg_update", "hg_corr", "other",    "apg_team", "cg_team",
-                                                  "apg_step"};
+                                                  "apg_step", "cg_step"};
     if (kind < 0 || kind >= MAID_PROF_KINDS) return "";
     return names[kind];
 }

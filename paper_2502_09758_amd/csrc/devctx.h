@@ -157,6 +157,7 @@ template <typename T> struct Inst {
     gp<const T> q0;                 // the caller's starting point (read by the set-up passes)
     gp<double> pR;                  // per-block partials of ||r||^2 (nbe entries)
     gp<double> pK;                  // per-block partials of <p, Hp> (nb entries)
+    gp<T> V[2];                     // one-pass CG: the second w buffer, and p
     // one convolution job: cv_out = cv_ker (x) cv_in [- cv_sub], partials of its square
     gp<const T> cv_ker;
     gp<const T> cv_in;

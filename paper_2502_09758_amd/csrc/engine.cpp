@@ -144,6 +144,8 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
     I.Hp = (T*)M.cHp;
     I.pR = M.pR;
     I.pK = M.pK;
+    I.V[0] = (T*)M.cV[0];
+    I.V[1] = (T*)M.cV[1];
     I.red = c->red + (size_t)i * kRedSlots;
 }
 
@@ -204,7 +206,7 @@ void prof_harvest(maid_ctx* c) {
             // kinds without early exits: every launch works
             if (r.kind != MAID_PROF_APG_GRAD && r.kind != MAID_PROF_APG_TRIAL && r.kind != MAID_PROF_CG_DIR &&
                 r.kind != MAID_PROF_CG_HVP && r.kind != MAID_PROF_CG_UPDATE && r.kind != MAID_PROF_APG_TEAM &&
-                r.kind != MAID_PROF_CG_TEAM && r.kind != MAID_PROF_APG_STEP)
+                r.kind != MAID_PROF_CG_TEAM && r.kind != MAID_PROF_APG_STEP && r.kind != MAID_PROF_CG_STEP)
                 c->prof_work[r.kind] += 1;
         }
         c->prof_pool.push_back(r.a);
@@ -541,7 +543,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         const size_t nblk = std::max<size_t>(std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe),
                                              (size_t)step_blocks(M.d.H, M.d.W, M.d.K, 1));
         const size_t part = al(nblk * sizeof(double));
-        total += 17 * img + 6 * kern + 7 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
+        total += 19 * img + 6 * kern + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
                  al(kTraceCap * sizeof(int));
         maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe) + round8(step_blocks(M.d.H, M.d.W, M.d.K, 1));
     }
@@ -618,6 +620,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.cP[1] = take(img);
         M.cKp = take(img);
         M.cHp = take(img);
+        M.cV[0] = take(img);
+        M.cV[1] = take(img);
         M.tmp0 = take(img);
         M.tmp1 = take(img);
         M.xtrial = take(img);
@@ -631,8 +635,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         // pA, pB: two halves each for the one-pass form
         M.pA = (double*)take(2 * part);
         M.pB = (double*)take(2 * part);
-        M.pR = (double*)take(part);
-        M.pK = (double*)take(part);
+        // pR, pK: two halves each for the one-pass CG form
+        M.pR = (double*)take(2 * part);
+        M.pK = (double*)take(2 * part);
         M.pC = (double*)take(part);
         M.hg_part = (double*)take(al((size_t)kHgMaxBlocks * 1024 * sizeof(double)));
         M.trace = (int*)take(al(kTraceCap * sizeof(int)));
@@ -831,7 +836,8 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         }
         h.tol = tol[i];
         h.max = max_iter;
-        h.first = 1;
+        // one-pass form: its priming pass first (w_0 = H r_0 and the sums)
+        h.first = c->m[i].nbf > 0 ? 2 : 1;
         tab[i].xt = xt[i];
         tab[i].b = rhs[i];
         tab[i].q0 = q[i];
@@ -860,16 +866,29 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
     }
     const size_t pub_bytes = 256 + n * sizeof(CgState);
     if (graph_any) {
+        // one-pass groups: the priming pass and the first iteration
+        for (auto& lg : c->groups)
+            if (lg.team == 0 && lg.g.grid_f > 0) {
+                LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
+                LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
+            }
         const long pred = std::min(c->pred_slots[3], (long)max_iter + 1);
         long slots = 0, chunk = 0;
         for (;;) {
             chunk = next_slots(pred, slots, chunk);
+            // one-pass groups take two iterations per slot (state there and back)
             int rc = run_slots(c, G_CG, chunk, s, [&](hipStream_t s, int cnt) {
                 for (int k = 0; k < cnt; ++k) {
-                    for (auto& lg : c->groups)
-                        if (lg.team == 0) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
-                    for (auto& lg : c->groups)
-                        if (lg.team == 0) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
+                    for (auto& lg : c->groups) {
+                        if (lg.team != 0) continue;
+                        if (lg.g.grid_f > 0) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
+                        else LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
+                    }
+                    for (auto& lg : c->groups) {
+                        if (lg.team != 0) continue;
+                        if (lg.g.grid_f > 0) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
+                        else LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
+                    }
                     LAUNCH(MAID_PROF_CG_UPDATE,
                            Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
                 }
@@ -896,22 +915,30 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
     for (int i = 0; i < n; ++i)
         if (act[i] && !c->cg_h[i].done) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
     {
+        // one-pass instances: a pass per iteration after the two set-up
+        // passes, two passes per slot
         long need = 1;
-        for (int i = 0; i < n; ++i)
-            if (act[i]) need = std::max<long>(need, (long)c->cg_h[i].iters + 1);
+        for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            const long it = c->cg_h[i].iters;
+            need = std::max<long>(need, c->m[i].nbf > 0 ? (it + 1) / 2 : it + 1);
+        }
         c->pred_slots[3] = need;
     }
     if (c->prof_on) {
         // the set-up direction and Hessian passes, then one of each per
-        // iteration; team loops: the iterations of every instance
-        int64_t w = 0, wteam = 0;
+        // iteration; team loops: the iterations of every instance; one-pass
+        // form: the priming pass and one per iteration
+        int64_t w = 0, wteam = 0, wstep = 0;
         for (int i = 0; i < n; ++i)
             if (act[i] && in_team[i]) wteam += c->cg_h[i].iters;
+            else if (act[i] && c->m[i].nbf > 0) wstep = std::max<int64_t>(wstep, c->cg_h[i].iters + 1);
             else if (act[i]) w = std::max<int64_t>(w, c->cg_h[i].iters);
         c->prof_work[MAID_PROF_CG_DIR] += w + 1;
         c->prof_work[MAID_PROF_CG_HVP] += w + 1;
         c->prof_work[MAID_PROF_CG_UPDATE] += w;
         c->prof_work[MAID_PROF_CG_TEAM] += wteam;
+        c->prof_work[MAID_PROF_CG_STEP] += wstep;
     }
     for (int i = 0; i < n; ++i) {
         codes[i] = MAID_OK;
@@ -1184,7 +1211,8 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
             const double t = c->prof_ms[MAID_PROF_APG_GRAD] + c->prof_ms[MAID_PROF_APG_TRIAL] +
                              c->prof_ms[MAID_PROF_APG_STEP] + c->prof_ms[MAID_PROF_CG_DIR] +
                              c->prof_ms[MAID_PROF_CG_HVP] + c->prof_ms[MAID_PROF_APG_TEAM] +
-                             c->prof_ms[MAID_PROF_CG_TEAM];
+                             c->prof_ms[MAID_PROF_CG_TEAM] + c->prof_ms[MAID_PROF_CG_STEP] +
+                             c->prof_ms[MAID_PROF_CG_UPDATE];
             if (t < best[k]) {
                 best[k] = t;
                 best_R[k] = cands[ci];

@@ -54,6 +54,7 @@ struct Member {
     void* cP[2];
     void* cKp;
     void* cHp;
+    void* cV[2];                // one-pass CG: second w buffer and p
     void* tmp0;
     void* tmp1;
     void* xtrial;

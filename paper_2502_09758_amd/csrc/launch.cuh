@@ -72,9 +72,10 @@ static size_t apg_team_lds(const Group& g) {
 }
 // one-pass team loops exist where the one-pass form does
 template <int K, int R> constexpr bool step_team() { return K >= 3 && K <= 11 && R <= 4; }
-template <typename T, int K, int R>
+template <typename T, int K, int R, bool STEP>
 static size_t cg_team_lds(const Group& g) {
-    return sizeof(T) * cmax(lds_cg_dir(K, R), lds_cg_hvp(K, R, g.C, g.nw));
+    if constexpr (STEP) return sizeof(T) * lds_cg_step<K, R>();
+    else return sizeof(T) * cmax(lds_cg_dir(K, R), lds_cg_hvp(K, R, g.C, g.nw));
 }
 
 template <typename T, int K, int R, bool STEP>
@@ -94,14 +95,21 @@ static hipError_t apg_team_kr(const Group& g, const Inst<T>* insts, const int* l
     return apg_team_krs<T, K, R, false>(g, insts, list, nlist, st, ctl, max_slots, s);
 }
 
-template <typename T, int K, int R>
-static hipError_t cg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
-                             const TeamCtl& ctl, long max_slots, hipStream_t s) {
-    const size_t lds = cg_team_lds<T, K, R>(g);
-    auto kern = k_cg_team<T, K, R>;
+template <typename T, int K, int R, bool STEP>
+static hipError_t cg_team_krs(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                              const TeamCtl& ctl, long max_slots, hipStream_t s) {
+    const size_t lds = cg_team_lds<T, K, R, STEP>(g);
+    auto kern = k_cg_team<T, K, R, STEP>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
     return launch(kern, dim3(kTeamXcd * ctl.P), dim3(kNT), lds, s, insts, list, nlist, st, n, ctl, max_slots);
+}
+template <typename T, int K, int R>
+static hipError_t cg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
+                             const TeamCtl& ctl, long max_slots, hipStream_t s) {
+    if constexpr (step_team<K, R>())
+        if (g.grid_f > 0) return cg_team_krs<T, K, R, true>(g, insts, list, nlist, st, n, ctl, max_slots, s);
+    return cg_team_krs<T, K, R, false>(g, insts, list, nlist, st, n, ctl, max_slots, s);
 }
 
 // Blocks of the group's two team kernels that fit on one CU at once (the
@@ -110,12 +118,12 @@ template <typename T, int K, int R, bool STEP>
 static hipError_t team_occupancy_krs(const Group& g, int* blocks_per_cu) {
     int a = 0, b = 0;
     hipError_t e = ensure_lds(k_apg_team<T, K, R, STEP>, apg_team_lds<T, K, R, STEP>(g));
-    if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R>, cg_team_lds<T, K, R>(g));
+    if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R, STEP>, cg_team_lds<T, K, R, STEP>(g));
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_apg_team<T, K, R, STEP>, kNT,
                                                          apg_team_lds<T, K, R, STEP>(g));
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R>, kNT, cg_team_lds<T, K, R>(g));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R, STEP>, kNT, cg_team_lds<T, K, R, STEP>(g));
     *blocks_per_cu = e == hipSuccess ? (a < b ? a : b) : 0;
     return e;
 }
@@ -133,6 +141,19 @@ static hipError_t apg_step_kr(const Group& g, const Inst<T>* insts, const ApgSta
     if constexpr (K >= 3 && K <= 11) {
         const size_t lds = sizeof(T) * lds_apg_step<K, R>();
         auto kern = k_apg_step<T, K, R>;
+        hipError_t e = ensure_lds(kern, lds);
+        if (e != hipSuccess) return e;
+        return launch(kern, dim3(g.grid_f), dim3(kNT), lds, s, insts, g.blk_f, g.only, sin, sout);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int K, int R>
+static hipError_t cg_step_kr(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, hipStream_t s) {
+    if constexpr (K >= 3 && K <= 11) {
+        const size_t lds = sizeof(T) * lds_cg_step<K, R>();
+        auto kern = k_cg_step<T, K, R>;
         hipError_t e = ensure_lds(kern, lds);
         if (e != hipSuccess) return e;
         return launch(kern, dim3(g.grid_f), dim3(kNT), lds, s, insts, g.blk_f, g.only, sin, sout);
@@ -197,6 +218,10 @@ hipError_t apg_step_k(const Group& g, const Inst<T>* insts, const ApgState* sin,
     MAID_TEAM_R_DISPATCH(apg_step_kr, g, insts, sin, sout, s)
 }
 template <typename T, int K>
+hipError_t cg_step_k(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, hipStream_t s) {
+    MAID_TEAM_R_DISPATCH(cg_step_kr, g, insts, sin, sout, s)
+}
+template <typename T, int K>
 hipError_t team_occupancy_k(const Group& g, int* blocks_per_cu) {
     MAID_TEAM_R_DISPATCH(team_occupancy_kr, g, blocks_per_cu)
 }
@@ -212,7 +237,8 @@ hipError_t team_occupancy_k(const Group& g, int* blocks_per_cu) {
     template hipError_t cg_team_k<T, KV>(const Group&, const Inst<T>*, const int*, int, CgState*, int, const TeamCtl&,  \
                                          long, hipStream_t);                                                            \
     template hipError_t team_occupancy_k<T, KV>(const Group&, int*);                                               \
-    template hipError_t apg_step_k<T, KV>(const Group&, const Inst<T>*, const ApgState*, ApgState*, hipStream_t);
+    template hipError_t apg_step_k<T, KV>(const Group&, const Inst<T>*, const ApgState*, ApgState*, hipStream_t);     \
+    template hipError_t cg_step_k<T, KV>(const Group&, const Inst<T>*, const CgState*, CgState*, hipStream_t);
 
 // Instantiate every stencil launcher of both storage types for one K.
 #define MAID_INSTANTIATE_K(KV) MAID_INSTANTIATE_T(float, KV) MAID_INSTANTIATE_T(double, KV)

@@ -70,6 +70,7 @@ template <typename T> struct Ops {
     static hipError_t apg_grad(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
     static hipError_t apg_trial(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
     static hipError_t apg_step(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
+    static hipError_t cg_step(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, hipStream_t s);
     static hipError_t apg_final(int grid_e, const int* blk_e, int only, const Inst<T>* insts, const ApgState* sin,
                                 hipStream_t s);
     static hipError_t cg_dir(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init, hipStream_t s);

@@ -108,6 +108,14 @@ hipError_t Ops<T>::apg_step(const Group& g, const Inst<T>* insts, const ApgState
 }
 
 template <typename T>
+hipError_t Ops<T>::cg_step(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, hipStream_t s) {
+#define MAID_CASE(KV) \
+    case KV: return cg_step_k<T, KV>(g, insts, sin, sout, s);
+    MAID_K_SWITCH(MAID_CASE)
+#undef MAID_CASE
+}
+
+template <typename T>
 hipError_t Ops<T>::apg_team(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st,
                             const TeamCtl& ctl, long max_slots, hipStream_t s) {
 #define MAID_CASE(KV) \

@@ -25,4 +25,6 @@ template <typename T, int K>
 hipError_t team_occupancy_k(const Group& g, int* blocks_per_cu);
 template <typename T, int K>
 hipError_t apg_step_k(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);
+template <typename T, int K>
+hipError_t cg_step_k(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, hipStream_t s);
 }  // namespace maid

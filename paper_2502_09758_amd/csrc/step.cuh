@@ -274,4 +274,239 @@ __global__ __launch_bounds__(kNT) void k_apg_step(const Inst<T>* __restrict__ in
     apg_step_body<T, K, R, false>(I, lb, st, &sout[ii], writer);
 }
 
+// ------------------------------------------------------------------ one-pass CG
+// The adjoint solve of Algorithm 1 in the Chronopoulos-Gear form of conjugate
+// gradients: with w = H r kept next to r, the two inner products of an
+// iteration (gamma = <r,r>, delta = <r,w>) come from one reduction, and
+//   beta_i = gamma_i / gamma_{i-1},  a_i = gamma_i / (delta_i - beta_i gamma_i / a_{i-1}),
+//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}  (s = H p),
+//   q += a_i p_i,  r_{i+1} = r_i - a_i s_i,  w_{i+1} = H r_{i+1};
+// in exact arithmetic these are the iterates of the Hestenes-Stiefel form
+// (the denominator of a_i is <p_i, H p_i>, tested for positivity as there).
+// One pass per iteration: every block forms r_{i+1} on its tile grown by 2 c0
+// from r_i, w_i, s_{i-1} (the same arithmetic as the block that owns those
+// pixels), the convolution u = theta*r_{i+1} on the tile grown by c0 (the
+// region E of the one-pass FISTA form), and then H r_{i+1} = theta.u +
+// alpha grad^2 R(xt)[r_{i+1}] on the tile.  r, w and s alternate between two
+// buffers (blocks read their neighbours' old values while writing new ones);
+// the partials of gamma and delta alternate between the halves of pR and pK.
+// st.first: 2 = the priming pass (w_0 = H r_0 and the first sums, nothing
+// else), 1 = the first iteration (beta = 0), 0 after; st.pc: the buffer set
+// the pass reads.
+template <int K, int R> __host__ __device__ constexpr int lds_cg_step() {
+    return lds_conv(K, step_re<K, R>()) + tile_h(step_re<K, R>()) * cv_pitch(K) + 2 * tv_rows(R) * tv_pitch() +
+           2 * fx_rows(R) * fx_pitch();
+}
+
+template <typename T, int K, int R, bool CO>
+__device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& st, CgState* __restrict__ sout,
+                                             bool writer) {
+    constexpr int c0 = step_c0<K>(), TWF = step_tw<K>(), RE = step_re<K, R>();
+    constexpr int CP = cv_pitch(K), CRE = cv_rows(K, RE);
+    constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    T* s_rn = sm;                         // r_{i+1} on the tile grown by 2 c0
+    T* s_u = s_rn + CRE * CP;             // u = theta * r_{i+1} on E
+    T* s_x = s_u + tile_h(RE) * CP;       // xt, tile grown by one pixel
+    T* s_p = s_x + VR * VP;               // r_{i+1}, tile grown by one pixel
+    T* s_w = s_p + VR * VP;               // TV weights w and w^3 <Dx, Dr> of the flux sites
+    T* s_mw = s_w + WR * WP;
+
+    const int H = I.pr.H, W = I.pr.W, reg = I.pr.reg;
+    const int nbf = I.nbf;
+    const int ntx = (W + TWF - 1) / TWF;
+    const int t = xcd_tile(lb, nbf);
+    const int ti0 = (t / ntx) * tile_h(R), tj0 = (t % ntx) * TWF;
+    const int ei0 = ti0 - c0, ej0 = tj0 - c0;
+    const int tx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+    const bool prime = st.first == 2, first = st.first == 1;
+    const int par = st.pc;
+    const T* __restrict__ Rb = pick(I.r, I.Kp, par);
+    const T* __restrict__ Wb = pick(I.Hp, I.V[0], par);
+    const T* __restrict__ Sb = pick(I.P[0], I.P[1], par);
+    T* __restrict__ Pv = I.V[1];
+    T* __restrict__ Qv = I.q;
+    const T* __restrict__ Xt = I.xt;
+    const double* __restrict__ rG = I.pR + (par ? nbf : 0);
+    const double* __restrict__ rD = I.pK + (par ? nbf : 0);
+    Partials pg, pd;
+    if (!prime) {
+        pg = partials_issue<CO>(rG, nbf);
+        pd = partials_issue<CO>(rD, nbf);
+    }
+    // the tile pixels' own values, loaded with the staging
+    T rr[R], wr[R], sr[R], pr_[R], qr[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) {
+        const int e = clampi(ti0 + wv * R + o, H - 1) * W + clampi(tj0 + tx, W - 1);
+        rr[o] = ld<CO>(Rb, e);
+        wr[o] = ld<CO>(Wb, e);
+        sr[o] = ld<CO>(Sb, e);
+        pr_[o] = ld<CO>((const T*)Pv, e);
+        qr[o] = ld<CO>((const T*)Qv, e);
+    }
+    auto xs = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, [&](int g) { return ld<CO>(Xt, g); });
+    xs.fetch(H, W);
+
+    double a = 0.0, beta = 0.0;
+    if (!prime) {
+        const double g = partials_finish<CO>(rG, nbf, pg);
+        const double d = partials_finish<CO>(rD, nbf, pd);
+        beta = first ? 0.0 : g / st.gamma;
+        st.gamma = g;
+        if (!finite_d(g)) {
+            st.done = 1;
+            st.status = ST_NONFINITE;
+        } else if (sqrt(g) <= st.tol) {
+            st.done = 1;
+            st.status = ST_OK;
+        } else if (st.iters >= st.max) {
+            st.done = 1;
+            st.status = ST_MAXITER;
+        } else {
+            const double den = first ? d : d - beta * g / st.a;
+            st.kappa = den;
+            if (!(den > 0.0) || !finite_d(den)) {
+                st.done = 1;
+                st.status = finite_d(den) ? ST_NOT_SPD : ST_NONFINITE;
+            } else {
+                a = g / den;
+                st.a = a;
+                st.iters += 1;
+                st.first = 0;
+                st.pc = par ^ 1;
+            }
+        }
+    } else {
+        st.first = 1;
+    }
+    if (writer && sout) put_state(sout, st);
+    if (st.done) return;
+
+    // r_{i+1} on the tile grown by 2 c0 (zero outside the image); s_i = w_i +
+    // beta s_{i-1} and r_{i+1} = r_i - a s_i by the same expressions as below
+    const T aT = (T)a, bT = (T)beta;
+    auto rnext = [&](T r, T w, T s) {
+        const T si = first ? w : dfma(bT, s, w);
+        return dfma(-aT, si, r);
+    };
+    if (prime) {
+        load_tile<CRE, CP, CP>(s_rn, ei0 - c0, ej0 - c0, H, W, [&](int g) { return ld<CO>(Rb, g); });
+    } else {
+        load_tile<CRE, CP, CP>(s_rn, ei0 - c0, ej0 - c0, H, W,
+                               [&](int g) { return rnext(ld<CO>(Rb, g), ld<CO>(Wb, g), ld<CO>(Sb, g)); });
+    }
+    xs.put();
+    __syncthreads();
+    // u = theta * r_{i+1} on E (the direction pass's convolution), r_{i+1} on
+    // the tile grown by one pixel for the TV term
+    T acc[RE];
+#pragma unroll
+    for (int o = 0; o < RE; ++o) acc[o] = T(0);
+    correlate<T, K, RE>(s_rn, CP, I.thf, wv * RE, tx, acc);
+#pragma unroll
+    for (int o = 0; o < RE; ++o) {
+        const int li = wv * RE + o;
+        s_u[li * CP + tx] = inside(ei0 + li, ej0 + tx, H, W) ? acc[o] : T(0);
+    }
+    for (int idx = threadIdx.x; idx < VR * VP; idx += kNT) {
+        const int r = idx / VP, cc = idx - r * VP;
+        s_p[idx] = s_rn[(r + 2 * c0 - 1) * CP + cc + 2 * c0 - 1];
+    }
+    __syncthreads();
+    // TV weights of the flux sites (the Hessian pass's arithmetic, one channel)
+    const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
+    for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
+        const int r = idx / WP, cc = idx - r * WP;
+        const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
+        const bool in = inside(gi, gj2, H, W);
+        const bool hx = gj2 < W - 1, vx = gi < H - 1;
+        const int i0 = r * VP + cc;
+        const T xh = hx ? s_x[i0 + 1] - s_x[i0] : T(0);
+        const T xv = vx ? s_x[i0 + VP] - s_x[i0] : T(0);
+        const T ph = hx ? s_p[i0 + 1] - s_p[i0] : T(0);
+        const T pv = vx ? s_p[i0 + VP] - s_p[i0] : T(0);
+        const T s2 = xh * xh + xv * xv, mm = xh * ph + xv * pv;
+        if (reg == 2) {
+            s_w[idx] = in ? T(1) : T(0);
+            s_mw[idx] = T(0);
+        } else {
+            const T w = in ? drsqrt(s2 + eps2) : T(0);
+            s_w[idx] = w;
+            s_mw[idx] = w * w * w * mm;
+        }
+    }
+    T hacc[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) hacc[o] = T(0);
+    correlate<T, K, R>(s_u, CP, I.th, wv * R, tx, hacc);
+    __syncthreads();
+
+    // w_{i+1} = theta.u + alpha grad^2 R(xt)[r_{i+1}] on the tile; the updates
+    const T alpha = (T)I.pr.alpha;
+    const int li0 = wv * R, oj = tj0 + tx;
+    const bool lane_in = tx < TWF;
+    const int wsel = prime ? par : par ^ 1;
+    T* __restrict__ Rn = pick(I.r, I.Kp, wsel);
+    T* __restrict__ Wn = pick(I.Hp, I.V[0], wsel);
+    T* __restrict__ Sn = pick(I.P[0], I.P[1], wsel);
+    double gs = 0.0, ds = 0.0;
+#pragma unroll
+    for (int o = 0; o < R; ++o) {
+        const int gi = ti0 + li0 + o;
+        if (lane_in && gi < H && oj < W) {
+            const int r = li0 + o + 1, cc = tx + 1;
+            const int i0 = r * VP + cc;
+            const T xh_h = (oj < W - 1) ? s_x[i0 + 1] - s_x[i0] : T(0);
+            const T ph_h = (oj < W - 1) ? s_p[i0 + 1] - s_p[i0] : T(0);
+            const T xv_h = (gi < H - 1) ? s_x[i0 + VP] - s_x[i0] : T(0);
+            const T pv_h = (gi < H - 1) ? s_p[i0 + VP] - s_p[i0] : T(0);
+            const T xh_l = s_x[i0] - s_x[i0 - 1], ph_l = s_p[i0] - s_p[i0 - 1];
+            const T xv_u = s_x[i0] - s_x[i0 - VP], pv_u = s_p[i0] - s_p[i0 - VP];
+            const int f0 = r * WP + cc, fl = f0 - 1, fu = f0 - WP;
+            const T fh_here = s_w[f0] * ph_h - s_mw[f0] * xh_h;
+            const T fv_here = s_w[f0] * pv_h - s_mw[f0] * xv_h;
+            const T fh_left = s_w[fl] * ph_l - s_mw[fl] * xh_l;
+            const T fv_up = s_w[fu] * pv_u - s_mw[fu] * xv_u;
+            const T hv = fh_left - fh_here + fv_up - fv_here;
+            const T wn = dfma(alpha, hv, hacc[o]);
+            const T rn = s_p[i0];
+            const int e = gi * W + oj;
+            at(Wn, e) = wn;
+            if (!prime) {
+                const T pi = first ? rr[o] : dfma(bT, pr_[o], rr[o]);
+                const T si = first ? wr[o] : dfma(bT, sr[o], wr[o]);
+                at(Pv, e) = pi;
+                at(Sn, e) = si;
+                at(Qv, e) = dfma(aT, pi, qr[o]);
+                at(Rn, e) = rn;
+            }
+            gs += (double)rn * (double)rn;
+            ds += (double)rn * (double)wn;
+        }
+    }
+    double* __restrict__ wG = I.pR + (wsel ? nbf : 0);
+    double* __restrict__ wD = I.pK + (wsel ? nbf : 0);
+    block_partial(gs, wG, lb);
+    block_partial(ds, wD, lb);
+}
+
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kNT) void k_cg_step(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+                                                 const CgState* __restrict__ sin, CgState* __restrict__ sout) {
+    const int ii = only >= 0 ? only : blk[blockIdx.x];
+    const Inst<T>& I = insts[ii];
+    const int lb = (int)blockIdx.x - I.basef;
+    if (lb >= I.nbf) return;
+    CgState st = sin[ii];
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (st.done) {
+        if (writer) put_state(&sout[ii], st);
+        return;
+    }
+    cg_step_body<T, K, R, false>(I, lb, st, &sout[ii], writer);
+}
+
 }  // namespace maid

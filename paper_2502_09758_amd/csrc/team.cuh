@@ -141,11 +141,11 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 
 // CG loop (the adjoint solve of Algorithm 1) after its set-up passes: per
 // slot a direction, a Hessian and an update pass, as the multi-kernel path
-// runs them.  st: the first of the three state arrays (n entries each; read
+// runs them (STEP: one pass of the one-pass form).  st: the first of the three state arrays (n entries each; read
 // at the start from the first).  The final state goes into all three: an
 // elementwise update pass of the multi-kernel path that covers the whole
 // batch then finds the instance finished and leaves it as it is.
-template <typename T, int K, int R>
+template <typename T, int K, int R, bool STEP>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_cg_team(
     const Inst<T>* __restrict__ insts, const int* __restrict__ list, int nlist, CgState* __restrict__ st_arr,
     int n, TeamCtl ctl, long max_slots) {
@@ -154,7 +154,21 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         const int ii = list[j];
         const Inst<T>& I = insts[ii];
         CgState st = st_arr[ii];
-        if (!st.done) {
+        if (STEP && !st.done) {
+            // one-pass form (its priming pass first): one pass per iteration
+            for (long slot = 0;; ++slot) {
+                CgState nx = st;
+                for (int lb = tm.me; lb < I.nbf; lb += tm.P) {
+                    nx = st;
+                    __syncthreads();
+                    if constexpr (STEP) cg_step_body<T, K, R, true>(I, lb, nx, nullptr, false);
+                }
+                st = nx;
+                if (st.done) break;
+                if (!tm.sync()) return;
+                if (slot + 1 >= max_slots) break;
+            }
+        } else if (!st.done) {
             for (long slot = 0;; ++slot) {
                 CgState nx = st;
                 for (int lb = tm.me; lb < I.nb; lb += tm.P) {

@@ -1,6 +1,7 @@
-"""One-pass form of the lower-level iteration (gradient on the tile's
-convolution halo, trial step in the same pass) against the two-pass form,
-through the C ABI.
+"""One-pass forms against the multi-pass forms, through the C ABI: the
+lower-level iteration (gradient on the tile's convolution halo, trial step in
+the same pass) and the CG iteration (Chronopoulos-Gear form: the update, the
+Hessian product on the halo and both inner products in one pass).
 
 Both forms take the same decisions in the same order (stop test on ||G_k||,
 then the decrease test of trial k) with the same per-pixel formulas; the
@@ -10,9 +11,10 @@ rounding.  Checked: iteration and
 backtracking counts, backtracking traces, Lipschitz estimates and iterates
 (to rounding) for K = 3..11, ragged tile tails, every tile height, both
 storage types, TV and quadratic regularisers, runs with many rejected
-trials, and MAID steps.  The oracle parity of the one-pass form is covered
-by the lower-level parity tests, which take it for every one-channel case
-with K <= 11."""
+trials, and MAID steps; for CG: iteration counts (to one), residual norms
+and solutions (to the loss-of-orthogonality level of the two recurrences).
+The oracle parity of the one-pass forms is covered by the lower-level and
+CG parity tests, which take them for every one-channel case with K <= 11."""
 import os
 
 import numpy as np
@@ -148,3 +150,36 @@ def test_one_pass_batch_mixed_with_two_pass():
         assert torch.equal(x, xs[k]), f"instance {k}"
         m.close()
     mb.close()
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+@pytest.mark.parametrize("shape", [(40, 70, 5), (130, 96, 9), (64, 64, 3), (77, 201, 11), (100, 50, 7)])
+@pytest.mark.parametrize("reg", [L.MAID_REG_TV, L.MAID_REG_QUADRATIC])
+def test_one_pass_cg_matches_hestenes_stiefel(dt, shape, reg):
+    H, W, K = shape
+    print(f"[case] one-pass CG vs three-pass {shape} {dt} reg={reg}", flush=True)
+    inst = synth.make("cfg1", H=H, W=W, C=1, K=K, seed=600 + K)
+    th = dev(inst.a, torch.float64)
+    y = dev(inst.y, dt)
+    x = y.clone()
+    m = ctx(inst, dt, False, 0, reg)
+    m.lower_solve(th, y, x, 1e-3, max_iter=300)
+    b = dev(np.cos(np.arange(y.numel()).reshape(y.shape) * 0.11), dt) * 0.1
+    tol = 1e-4 * float(b.norm())
+    res = []
+    for one_pass in (False, True):
+        mm = ctx(inst, dt, one_pass, 0, reg)
+        for rows in (1, 2, 4):
+            mm.set_tile_rows(rows)
+            q = torch.zeros_like(y)
+            ci = mm.adjoint_solve(th, x, b, q, tol, max_iter=2000)
+            assert ci.status == L.OK
+            res.append((one_pass, rows, ci, q))
+        mm.close()
+    m.close()
+    ref = res[0]
+    for one_pass, rows, ci, q in res[1:]:
+        assert abs(ci.iters - ref[2].iters) <= 1, (one_pass, rows, ci.iters, ref[2].iters)
+        assert ci.res_norm <= tol
+        err = float((q - ref[3]).norm() / ref[3].norm())
+        assert err <= (1e-3 if dt == torch.float32 else 1e-5), (one_pass, rows, err)
