@@ -126,7 +126,7 @@ const char* maid_config_string(const maid_ctx* ctx);
    0 = back to the autotuner's choice, else the size rule). */
 int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
 /* Persistent loops for small instances.  The lower-level and CG loops of a
-   group of instances with at most 64 tiles each (and tile rows 1, 2 or 4)
+   group of instances with at most 16384 pixels each (and tile rows 1, 2 or 4)
    run inside one kernel per solve on teams of blocks, one team per XCD,
    which meet at barriers through the XCD's L2 instead of at kernel
    boundaries; a batch runs up to eight instances at once.  Results are

@@ -310,7 +310,8 @@ int validate_desc(const maid_desc* d, std::string& why) {
 // passes.  Every member must hold at least one tile and one elementwise
 // block of each instance (each member takes the solver decisions itself), and
 // a team must fit on its XCD at once.  Size rule: the team path for groups
-// whose instances have at most kTeamTiles tiles, one tile per member.  A pass
+// whose instances have at most kTeamTiles x 256 pixels (kTeamTiles tiles of
+// one row per thread), one tile per member.  A pass
 // on one XCD is bound by that XCD's vector ALUs once each member holds more
 // than one tile (measured: 128x128 at one row per thread, 64 tiles, runs
 // lower + CG iterations ~17% faster on teams than as kernels; 256x256, 256
@@ -325,7 +326,10 @@ int team_members(maid_ctx* c, const LaunchGroup& lg) {
         most_tiles = std::max(most_tiles, tiles);
         cap = std::min(cap, std::min(tiles, c->m[i].nbe));
     }
-    if (c->team_req < 0 && most_tiles > kTeamTiles) return 0;
+    // the size rule counts pixels (tiles of one row per thread), whatever the tile height
+    int64_t most_px = 0;
+    for (int i : lg.members) most_px = std::max<int64_t>(most_px, c->m[i].N);
+    if (c->team_req < 0 && most_px > (int64_t)kTeamTiles * kTW * tile_h(1)) return 0;
     int bpc = 0;
     const hipError_t e = c->dtype == MAID_F64 ? Ops<double>::team_occupancy(lg.g, &bpc)
                                               : Ops<float>::team_occupancy(lg.g, &bpc);
