@@ -869,6 +869,9 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
                Ops<T>::cg_team(lg.g, tabd, lg.list, (int)lg.members.size(), S[0], n, ctl, (long)max_iter + 2, s));
     }
     const size_t pub_bytes = 256 + n * sizeof(CgState);
+    // the elementwise update pass serves the three-pass groups only
+    bool hs_any = false;
+    for (auto& lg : c->groups) hs_any = hs_any || (lg.team == 0 && lg.g.grid_f == 0);
     if (graph_any) {
         // one-pass groups: the priming pass and the first iteration
         for (auto& lg : c->groups)
@@ -893,8 +896,9 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
                         if (lg.g.grid_f > 0) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
                         else LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
                     }
-                    LAUNCH(MAID_PROF_CG_UPDATE,
-                           Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
+                    if (hs_any)
+                        LAUNCH(MAID_PROF_CG_UPDATE,
+                               Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
                 }
                 return (int)MAID_OK;
             });
