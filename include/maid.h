@@ -139,6 +139,15 @@ int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
    and the context stays on them.  The choice shows in
    maid_config_string ("team=P"). */
 int maid_set_team(maid_ctx* ctx, int32_t members);
+/* One-pass CG (enable != 0, the default) for the instances on the one-pass
+   lower-level form: the Chronopoulos-Gear recurrences need one reduction
+   and so one pass per iteration (measured at 256x256, K = 9: 11.9 against
+   14.7 us per iteration); 0 = the three-pass Hestenes-Stiefel kernels (the
+   oracle's form) for every instance.  Both forms' iterates drift from the
+   oracle's by loss of orthogonality, the one-pass form's differently
+   (measured at equal iteration counts: FP64, 30-50 iterations, <= 1.6e-6
+   relative against <= 1e-6; FP32, 83 iterations, 2.2e-5 against 4.7e-5). */
+int maid_set_one_pass_cg(maid_ctx* ctx, int32_t enable);
 /* Autotuner: for each group of instances with the same K, time a short
    lower-level solve and a short CG solve (probe_iters iterations each,
    1..1000, tolerance 0) with every rows-per-thread candidate on
@@ -188,7 +197,7 @@ int maid_upper_value_grad(maid_ctx* ctx, const void* a, const void* y, const voi
    maid_lower_solve) run the Chronopoulos-Gear form of CG, which needs one
    reduction per iteration (<r,r> and <r,Hr> together) and so one pass:
    the same iterates in exact arithmetic, the same stop and curvature
-   tests. */
+   tests; see maid_set_one_pass_cg. */
 int maid_adjoint_solve(maid_ctx* ctx, const void* theta, const void* x_tilde,
                        const void* rhs, void* q, double tol, int32_t max_iter,
                        maid_solve_info* info, hipStream_t stream);

@@ -117,6 +117,12 @@ int maid_set_tile_rows(maid_ctx* c, int32_t rows) {
     return relayout(c);
 }
 
+int maid_set_one_pass_cg(maid_ctx* c, int32_t enable) {
+    if (!c) return MAID_EINVAL;
+    c->cg_fuse = enable != 0;
+    return relayout(c);
+}
+
 int maid_set_team(maid_ctx* c, int32_t members) {
     if (!c) return MAID_EINVAL;
     if (members < -1 || members > kTeamMax)

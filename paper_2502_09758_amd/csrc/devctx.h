@@ -133,6 +133,7 @@ template <typename T> struct Inst {
     int32_t nb, base;            // stencil blocks (tiles x channels) and first block within its group launch
     int32_t nbe, base_e;         // elementwise blocks and first block within the elementwise launch
     int32_t nbf, basef;          // blocks of the one-pass FISTA launch (0: not on that path)
+    int32_t cg1;                 // the CG solve runs the one-pass form (on the same blocks)
     int32_t cv_prev_slot;        // red slot for cv_prev_part's total
     int64_t N;                   // C*H*W
     // lower level (FISTA)
@@ -158,6 +159,7 @@ template <typename T> struct Inst {
     gp<double> pR;                  // per-block partials of ||r||^2 (nbe entries)
     gp<double> pK;                  // per-block partials of <p, Hp> (nb entries)
     gp<T> V[2];                     // one-pass CG: the second w buffer, and p
+    gp<double> S64[2];              // one-pass CG: s = Hp, carried in FP64 (two buffers)
     // one convolution job: cv_out = cv_ker (x) cv_in [- cv_sub], partials of its square
     gp<const T> cv_ker;
     gp<const T> cv_in;

@@ -125,6 +125,7 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
     I.base_e = M.base_e;
     I.nbf = M.nbf;
     I.basef = M.basef;
+    I.cg1 = M.nbf > 0 && c->cg_fuse ? 1 : 0;
     I.N = M.N;
     for (int k = 0; k < 3; ++k) {
         I.X[k] = (T*)M.X[k];
@@ -146,6 +147,8 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
     I.pK = M.pK;
     I.V[0] = (T*)M.cV[0];
     I.V[1] = (T*)M.cV[1];
+    I.S64[0] = M.cS64[0];
+    I.S64[1] = M.cS64[1];
     I.red = c->red + (size_t)i * kRedSlots;
 }
 
@@ -363,7 +366,7 @@ int relayout(maid_ctx* c) {
     for (int i = 0; i < c->n; ++i) {
         if (placed[i]) continue;
         LaunchGroup lg;
-        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr, -1, 0, nullptr};
+        lg.g = Group{c->m[i].d.K, c->m[i].R, 1, 1, 0, nullptr, -1, 0, nullptr, 0};
         for (int k = i; k < c->n; ++k)
             if (!placed[k] && c->m[k].d.K == lg.g.K && c->m[k].R == lg.g.R &&
                 (c->m[k].nbf > 0) == (c->m[i].nbf > 0)) {
@@ -392,6 +395,7 @@ int relayout(maid_ctx* c) {
                 basef = round8(basef + M.nbf);
             }
         }
+        lg.g.cg1 = lg.g.grid_f > 0 && c->cg_fuse ? 1 : 0;
         lg.team = team_members(c, lg);
     }
     int base_e = 0;
@@ -460,6 +464,7 @@ int relayout(maid_ctx* c) {
             c->cfg += buf;
         }
         if (lg.g.grid_f > 0) c->cfg += " one-pass";
+        if (lg.g.cg1) c->cfg += " cg-one-pass";
     }
     return MAID_OK;
 }
@@ -547,6 +552,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         const size_t nblk = std::max<size_t>(std::max<size_t>(stencil_blocks(M.shape, 1), (size_t)M.nbe),
                                              (size_t)step_blocks(M.d.H, M.d.W, M.d.K, 1));
         const size_t part = al(nblk * sizeof(double));
+        // FP64 s buffers of the one-pass CG, for instances that can take it
+        const size_t s64 = step_ok(M.d.C, M.d.K, 1) ? 2 * al((size_t)M.N * sizeof(double)) : 0;
+        total += s64;
         total += 19 * img + 6 * kern + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
                  al(kTraceCap * sizeof(int));
         maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe) + round8(step_blocks(M.d.H, M.d.W, M.d.K, 1));
@@ -581,6 +589,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
     if (const char* t = std::getenv("MAID_TEAM")) c->team_req = std::max(-1, std::atoi(t));
     if (const char* f = std::getenv("MAID_FUSE")) c->fuse = std::strcmp(f, "0") != 0;
+    if (const char* f = std::getenv("MAID_CG_ONE_PASS")) c->cg_fuse = std::strcmp(f, "0") != 0;
     // longest wait at a team barrier, in wall-clock ticks (0 forces the
     // multi-kernel fallback, for tests)
     if (const char* w = std::getenv("MAID_TEAM_WAIT")) c->team_wait = std::max(0LL, std::atoll(w));
@@ -626,6 +635,9 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.cHp = take(img);
         M.cV[0] = take(img);
         M.cV[1] = take(img);
+        const bool s64 = step_ok(M.d.C, M.d.K, 1);
+        M.cS64[0] = s64 ? (double*)take(al((size_t)M.N * sizeof(double))) : nullptr;
+        M.cS64[1] = s64 ? (double*)take(al((size_t)M.N * sizeof(double))) : nullptr;
         M.tmp0 = take(img);
         M.tmp1 = take(img);
         M.xtrial = take(img);
@@ -841,7 +853,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         h.tol = tol[i];
         h.max = max_iter;
         // one-pass form: its priming pass first (w_0 = H r_0 and the sums)
-        h.first = c->m[i].nbf > 0 ? 2 : 1;
+        h.first = c->m[i].nbf > 0 && c->cg_fuse ? 2 : 1;
         tab[i].xt = xt[i];
         tab[i].b = rhs[i];
         tab[i].q0 = q[i];
@@ -871,11 +883,11 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
     const size_t pub_bytes = 256 + n * sizeof(CgState);
     // the elementwise update pass serves the three-pass groups only
     bool hs_any = false;
-    for (auto& lg : c->groups) hs_any = hs_any || (lg.team == 0 && lg.g.grid_f == 0);
+    for (auto& lg : c->groups) hs_any = hs_any || (lg.team == 0 && !lg.g.cg1);
     if (graph_any) {
         // one-pass groups: the priming pass and the first iteration
         for (auto& lg : c->groups)
-            if (lg.team == 0 && lg.g.grid_f > 0) {
+            if (lg.team == 0 && lg.g.cg1) {
                 LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
                 LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
             }
@@ -888,12 +900,12 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
                 for (int k = 0; k < cnt; ++k) {
                     for (auto& lg : c->groups) {
                         if (lg.team != 0) continue;
-                        if (lg.g.grid_f > 0) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
+                        if (lg.g.cg1) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
                         else LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
                     }
                     for (auto& lg : c->groups) {
                         if (lg.team != 0) continue;
-                        if (lg.g.grid_f > 0) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
+                        if (lg.g.cg1) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
                         else LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
                     }
                     if (hs_any)
@@ -929,7 +941,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         for (int i = 0; i < n; ++i) {
             if (!act[i]) continue;
             const long it = c->cg_h[i].iters;
-            need = std::max<long>(need, c->m[i].nbf > 0 ? (it + 1) / 2 : it + 1);
+            need = std::max<long>(need, c->m[i].nbf > 0 && c->cg_fuse ? (it + 1) / 2 : it + 1);
         }
         c->pred_slots[3] = need;
     }
@@ -940,7 +952,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         int64_t w = 0, wteam = 0, wstep = 0;
         for (int i = 0; i < n; ++i)
             if (act[i] && in_team[i]) wteam += c->cg_h[i].iters;
-            else if (act[i] && c->m[i].nbf > 0) wstep = std::max<int64_t>(wstep, c->cg_h[i].iters + 1);
+            else if (act[i] && c->m[i].nbf > 0 && c->cg_fuse) wstep = std::max<int64_t>(wstep, c->cg_h[i].iters + 1);
             else if (act[i]) w = std::max<int64_t>(w, c->cg_h[i].iters);
         c->prof_work[MAID_PROF_CG_DIR] += w + 1;
         c->prof_work[MAID_PROF_CG_HVP] += w + 1;

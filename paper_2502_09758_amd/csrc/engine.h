@@ -55,6 +55,7 @@ struct Member {
     void* cKp;
     void* cHp;
     void* cV[2];                // one-pass CG: second w buffer and p
+    double* cS64[2];            // one-pass CG: s = Hp in FP64 (one-channel instances with 3 <= K <= 11)
     void* tmp0;
     void* tmp1;
     void* xtrial;
@@ -123,6 +124,7 @@ struct maid_ctx {
     size_t ws_bytes = 0;
     // persistent team loops for small instances (one team per XCD)
     bool fuse = true;                 // one-pass FISTA where the group allows it
+    bool cg_fuse = true;              // one-pass (Chronopoulos-Gear) CG on the one-pass instances
     int fuse_force = -1;              // autotuner's candidate: -1 none, 0 two-pass, 1 one-pass
     int team_req = -1;                // members per team: -1 size rule, 0 never, > 0 that many (capped)
     bool team_ok = false;             // blocks reach the XCDs round-robin and XCC_ID reads them

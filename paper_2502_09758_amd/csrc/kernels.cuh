@@ -1252,8 +1252,8 @@ template <typename T>
 __global__ __launch_bounds__(kNT) void k_cg_update(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                    const CgState* __restrict__ sin, CgState* __restrict__ sout) {
     MAID_EW_PROLOGUE
-    // instances on the one-pass form have their own state sequence
-    if (I.nbf > 0) return;
+    // instances on the one-pass CG form have their own state sequence
+    if (I.cg1) return;
     CgState st = sin[ii];
     const bool writer = lb == 0 && threadIdx.x == 0;
     if (st.done) {

@@ -108,30 +108,33 @@ template <typename T, int K, int R>
 static hipError_t cg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
                              const TeamCtl& ctl, long max_slots, hipStream_t s) {
     if constexpr (step_team<K, R>())
-        if (g.grid_f > 0) return cg_team_krs<T, K, R, true>(g, insts, list, nlist, st, n, ctl, max_slots, s);
+        if (g.cg1) return cg_team_krs<T, K, R, true>(g, insts, list, nlist, st, n, ctl, max_slots, s);
     return cg_team_krs<T, K, R, false>(g, insts, list, nlist, st, n, ctl, max_slots, s);
 }
 
 // Blocks of the group's two team kernels that fit on one CU at once (the
 // smaller of the two).
-template <typename T, int K, int R, bool STEP>
+template <typename T, int K, int R, bool STEP, bool STEP_CG>
 static hipError_t team_occupancy_krs(const Group& g, int* blocks_per_cu) {
     int a = 0, b = 0;
     hipError_t e = ensure_lds(k_apg_team<T, K, R, STEP>, apg_team_lds<T, K, R, STEP>(g));
-    if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R, STEP>, cg_team_lds<T, K, R, STEP>(g));
+    if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R, STEP_CG>, cg_team_lds<T, K, R, STEP_CG>(g));
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_apg_team<T, K, R, STEP>, kNT,
                                                          apg_team_lds<T, K, R, STEP>(g));
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R, STEP>, kNT, cg_team_lds<T, K, R, STEP>(g));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R, STEP_CG>, kNT,
+                                                         cg_team_lds<T, K, R, STEP_CG>(g));
     *blocks_per_cu = e == hipSuccess ? (a < b ? a : b) : 0;
     return e;
 }
 template <typename T, int K, int R>
 static hipError_t team_occupancy_kr(const Group& g, int* blocks_per_cu) {
-    if constexpr (step_team<K, R>())
-        if (g.grid_f > 0) return team_occupancy_krs<T, K, R, true>(g, blocks_per_cu);
-    return team_occupancy_krs<T, K, R, false>(g, blocks_per_cu);
+    if constexpr (step_team<K, R>()) {
+        if (g.grid_f > 0 && g.cg1) return team_occupancy_krs<T, K, R, true, true>(g, blocks_per_cu);
+        if (g.grid_f > 0) return team_occupancy_krs<T, K, R, true, false>(g, blocks_per_cu);
+    }
+    return team_occupancy_krs<T, K, R, false, false>(g, blocks_per_cu);
 }
 
 // One-pass FISTA (single channel, 3 <= K <= 11; tile rows 1, 2, 4).

@@ -53,6 +53,7 @@ struct Group {
     int only;          // the instance index if the group has one instance, else -1
     int grid_f;        // blocks of a one-pass FISTA launch over the group (0: two-pass form)
     const int* blk_f;  // its device map
+    int cg1;           // the group's CG runs the one-pass form (needs grid_f > 0)
 };
 
 // Whether a group can take the one-pass FISTA form: one channel and

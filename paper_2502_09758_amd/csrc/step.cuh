@@ -287,8 +287,9 @@ __global__ __launch_bounds__(kNT) void k_apg_step(const Inst<T>* __restrict__ in
 // from r_i, w_i, s_{i-1} (the same arithmetic as the block that owns those
 // pixels), the convolution u = theta*r_{i+1} on the tile grown by c0 (the
 // region E of the one-pass FISTA form), and then H r_{i+1} = theta.u +
-// alpha grad^2 R(xt)[r_{i+1}] on the tile.  r, w and s alternate between two
-// buffers (blocks read their neighbours' old values while writing new ones);
+// alpha grad^2 R(xt)[r_{i+1}] on the tile.  r, w and s (FP64) alternate
+// between two buffers (blocks read their neighbours' old values while
+// writing new ones);
 // the partials of gamma and delta alternate between the halves of pR and pK.
 // st.first: 2 = the priming pass (w_0 = H r_0 and the first sums, nothing
 // else), 1 = the first iteration (beta = 0), 0 after; st.pc: the buffer set
@@ -325,7 +326,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     const int par = st.pc;
     const T* __restrict__ Rb = pick(I.r, I.Kp, par);
     const T* __restrict__ Wb = pick(I.Hp, I.V[0], par);
-    const T* __restrict__ Sb = pick(I.P[0], I.P[1], par);
+    const double* __restrict__ Sb = pick(I.S64[0], I.S64[1], par);
     T* __restrict__ Pv = I.V[1];
     T* __restrict__ Qv = I.q;
     const T* __restrict__ Xt = I.xt;
@@ -337,7 +338,8 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
         pd = partials_issue<CO>(rD, nbf);
     }
     // the tile pixels' own values, loaded with the staging
-    T rr[R], wr[R], sr[R], pr_[R], qr[R];
+    T rr[R], wr[R], pr_[R], qr[R];
+    double sr[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int e = clampi(ti0 + wv * R + o, H - 1) * W + clampi(tj0 + tx, W - 1);
@@ -386,12 +388,13 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     if (st.done) return;
 
     // r_{i+1} on the tile grown by 2 c0 (zero outside the image); s_i = w_i +
-    // beta s_{i-1} and r_{i+1} = r_i - a s_i by the same expressions as below
+    // beta s_{i-1} and r_{i+1} = r_i - a s_i by the same expressions as below.
+    // s is a recurrence (the Hestenes-Stiefel form recomputes Hp instead), so
+    // it is carried in FP64 whatever the storage type: stored in FP32 its
+    // rounding accumulates into r and the iterates drift from that form.
     const T aT = (T)a, bT = (T)beta;
-    auto rnext = [&](T r, T w, T s) {
-        const T si = first ? w : dfma(bT, s, w);
-        return dfma(-aT, si, r);
-    };
+    auto snext = [&](T w, double s) { return first ? (double)w : dfma(beta, s, (double)w); };
+    auto rnext = [&](T r, T w, double s) { return (T)dfma(-a, snext(w, s), (double)r); };
     if (prime) {
         load_tile<CRE, CP, CP>(s_rn, ei0 - c0, ej0 - c0, H, W, [&](int g) { return ld<CO>(Rb, g); });
     } else {
@@ -451,7 +454,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     const int wsel = prime ? par : par ^ 1;
     T* __restrict__ Rn = pick(I.r, I.Kp, wsel);
     T* __restrict__ Wn = pick(I.Hp, I.V[0], wsel);
-    T* __restrict__ Sn = pick(I.P[0], I.P[1], wsel);
+    double* __restrict__ Sn = pick(I.S64[0], I.S64[1], wsel);
     double gs = 0.0, ds = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
@@ -477,7 +480,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
             at(Wn, e) = wn;
             if (!prime) {
                 const T pi = first ? rr[o] : dfma(bT, pr_[o], rr[o]);
-                const T si = first ? wr[o] : dfma(bT, sr[o], wr[o]);
+                const double si = snext(wr[o], sr[o]);
                 at(Pv, e) = pi;
                 at(Sn, e) = si;
                 at(Qv, e) = dfma(aT, pi, qr[o]);

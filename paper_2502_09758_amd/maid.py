@@ -115,6 +115,10 @@ class Maid:
     def set_tile_rows(self, rows: int):
         self._check(L.lib().maid_set_tile_rows(self.handle, int(rows)), "set_tile_rows")
 
+    def set_one_pass_cg(self, enable: bool):
+        """Opt in to the one-pass (Chronopoulos-Gear) CG on one-pass instances."""
+        self._check(L.lib().maid_set_one_pass_cg(self.handle, int(bool(enable))), "set_one_pass_cg")
+
     def set_team(self, members: int):
         """Members per team of the persistent loops: -1 size rule, 0 off."""
         self._check(L.lib().maid_set_team(self.handle, int(members)), "set_team")
@@ -245,6 +249,7 @@ class MaidBatch:
     config = Maid.config
     set_tile_rows = Maid.set_tile_rows
     set_team = Maid.set_team
+    set_one_pass_cg = Maid.set_one_pass_cg
     profile = Maid.profile
     profile_read = Maid.profile_read
     _check = Maid._check

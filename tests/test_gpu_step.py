@@ -169,6 +169,8 @@ def test_one_pass_cg_matches_hestenes_stiefel(dt, shape, reg):
     res = []
     for one_pass in (False, True):
         mm = ctx(inst, dt, one_pass, 0, reg)
+        mm.set_one_pass_cg(one_pass)
+        assert ("cg-one-pass" in mm.config()) == one_pass
         for rows in (1, 2, 4):
             mm.set_tile_rows(rows)
             q = torch.zeros_like(y)

@@ -193,3 +193,21 @@ def test_team_size_rule():
     m = solo(big, torch.float32)
     assert "team=" not in m.config(), m.config()
     m.close()
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_team_one_pass_cg_bitwise(dt):
+    """The opt-in one-pass CG on team loops equals it on kernels."""
+    print(f"[case] team one-pass CG {dt}", flush=True)
+    inst = synth.make("cfg1", H=64, W=96, C=1, K=7, seed=44)
+    tol = 1e-4 if dt == torch.float32 else 1e-6
+    out = []
+    for members in (0, -1):
+        m = solo(inst, dt)
+        m.set_one_pass_cg(True)
+        m.set_team(members)
+        assert "cg-one-pass" in m.config() and ("team=" in m.config()) == (members != 0), m.config()
+        out.append(solve_pair(m, inst, dt, tol))
+        m.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert same_info(out[0][2], out[1][2]) and same_info(out[0][3], out[1][3])
