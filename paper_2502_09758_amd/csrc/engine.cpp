@@ -87,7 +87,8 @@ template <typename T> int upload(maid_ctx* c, int role, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(c->tab_dev + role * bytes, c->tab_host + role * bytes, bytes, hipMemcpyHostToDevice, s));
     return MAID_OK;
 }
-int pull_red(maid_ctx* c, hipStream_t s) { return pull(c, s, c->red, sizeof(double) * kRedSlots * c->n); }
+int publish(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n);
+int pull_red(maid_ctx* c, hipStream_t s) { return publish(c, s, c->red, sizeof(double) * kRedSlots * c->n); }
 
 // Like pull, without synchronising the stream: a one-block kernel copies
 // the range into host-visible memory and raises a flag, which the host
@@ -810,7 +811,10 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         c->prof_work[MAID_PROF_APG_STEP] += wstep;
     }
     LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, c->only_e, tabd, c->apg[0], s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // (inside a MAID step the next work is stream-ordered after this pass,
+    // and no host buffer it reads is still being copied: the last state
+    // publication drained everything before it)
+    if (!c->in_step) HIP_TRY(hipStreamSynchronize(s));
     for (int i = 0; i < n; ++i) {
         codes[i] = MAID_OK;
         if (!act[i]) continue;
@@ -976,7 +980,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
             info[i].L = 0.0;
         }
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!c->in_step) HIP_TRY(hipStreamSynchronize(s));
     return MAID_OK;
 }
 
@@ -1272,6 +1276,11 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
 template <typename T>
 int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
                const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s) {
+    struct InStep {
+        maid_ctx* c;
+        InStep(maid_ctx* cc) : c(cc) { c->in_step = true; }
+        ~InStep() { c->in_step = false; }
+    } in_step_guard(c);
     const int n = c->n;
     std::vector<maid_step_info> I(n);
     std::memset(I.data(), 0, n * sizeof(maid_step_info));
@@ -1376,7 +1385,6 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                     }
                 have_znorm = true;
             }
-            bool copied = false;
             for (int i = 0; i < n; ++i) {
                 if (!tr[i]) continue;
                 const double ell_n = g_n[i] + r_n[i];
@@ -1390,7 +1398,6 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                     const int KK = c->m[i].d.K * c->m[i].d.K;
                     HIP_TRY(hipMemcpyAsync(st[i].theta, th2[i], KK * sizeof(double), hipMemcpyDeviceToDevice, s));
                     HIP_TRY(hipMemcpyAsync(x[i], xs[i], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
-                    copied = true;
                     st[i].eps *= hp->nu_hi;
                     st[i].delta *= hp->nu_hi;
                     st[i].step *= hp->rho_hi;
@@ -1403,7 +1410,6 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                 st[i].step *= hp->rho_lo;
                 if (++cnt[i] >= j[i]) tr[i] = 0;
             }
-            if (copied) HIP_TRY(hipStreamSynchronize(s));
         }
         for (int i = 0; i < n; ++i) {
             if (!need[i]) continue;
@@ -1421,6 +1427,8 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
         I[i].status = codes[i];
         if (out) out[i] = I[i];
     }
+    // the step's array outputs (theta, x, q) are complete when it returns
+    HIP_TRY(hipStreamSynchronize(s));
     return MAID_OK;
 }
 
