@@ -176,6 +176,10 @@ template <typename T> struct Inst {
     gp<const double> sob_th;
     gp<const double> sob_a;
     double beta, h1_w0;
+    // initial solver states, copied into the state arrays by the preparation
+    // pass at the start of a solve (one upload per solve carries both)
+    ApgState st0;
+    CgState cg0;
 };
 
 }  // namespace maid

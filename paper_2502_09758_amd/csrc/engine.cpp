@@ -710,9 +710,10 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         I.cv_cp[0] = I.X[0];
         I.cv_cp[1] = I.X[1];
     }
-    TRY(push(c, s, c->apg[0], n * sizeof(ApgState)));
+    // the initial states travel in the table; the preparation pass copies them
+    for (int i = 0; i < n; ++i) tab[i].st0 = c->apg_h[i];
     TRY(upload<T>(c, ROLE_APG, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, c->apg[0], -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, c->apg[0], nullptr, -1, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, tabd, s));
     // each slot is one gradient pass and one trial pass; a slot advances every
     // unfinished solve by one iteration or by one backtracking step
@@ -863,9 +864,9 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         tab[i].q0 = q[i];
         tab[i].theta64 = theta[i];
     }
-    TRY(push(c, s, c->cg[0], n * sizeof(CgState)));
+    for (int i = 0; i < n; ++i) tab[i].cg0 = c->cg_h[i];
     TRY(upload<T>(c, ROLE_CG, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, nullptr, -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, nullptr, c->cg[0], -1, s));
     // r = rhs - H q0 (the direction pass in set-up mode copies q0 into q and p)
     CgState** S = c->cg;
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
@@ -1029,7 +1030,7 @@ int upper_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<cons
     TRY(upload<T>(c, ROLE_CV1, s));
     const Inst<T>* d0 = tab_dev<T>(c, ROLE_CV0);
     const Inst<T>* d1 = tab_dev<T>(c, ROLE_CV1);
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, kRedAbs, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, nullptr, kRedAbs, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d0, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d1, s));
     LAUNCH(MAID_PROF_OTHER, Ops<T>::finish(d1, n, kRedGrad, kRedSob, s));
@@ -1081,7 +1082,7 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
     TRY(upload<T>(c, ROLE_CV3, s));
     const Inst<T>* d2 = tab_dev<T>(c, ROLE_CV2);
     const Inst<T>* d3 = tab_dev<T>(c, ROLE_CV3);
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d2, n, nullptr, -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d2, n, nullptr, nullptr, -1, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d2, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d3, s));
     for (int i = 0; i < n; ++i) {
@@ -1146,7 +1147,7 @@ int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, in
     t[0].cv_out = out;
     TRY(upload<T>(c, ROLE_CV0, s));
     const Inst<T>* d = tab_dev<T>(c, ROLE_CV0);
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d, 1, nullptr, -1, s));
+    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d, 1, nullptr, nullptr, -1, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MAID_OK;

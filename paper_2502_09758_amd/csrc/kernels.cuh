@@ -1282,15 +1282,21 @@ __global__ __launch_bounds__(kNT) void k_cg_init(const Inst<T>* __restrict__ ins
 }
 
 // ------------------------------------------------------------------ small kernels
-// One block per instance: theta64 (double, KxK) -> th (correlation form) and
-// thf (flipped, convolution form), both column-major in the compute type;
-// with L_io, the l1 norm squared becomes the starting Lipschitz estimate
-// when that is <= 0; red[slot_abs] receives the l1 norm when slot_abs >= 0.
+// One block per instance: the initial solver states of the table entry go
+// into the state arrays (Lst, Cst: nullable), then theta64 (double, KxK) ->
+// th (correlation form) and thf (flipped, convolution form), both
+// column-major in the compute type; with Lst, the l1 norm squared becomes the
+// starting Lipschitz estimate when the initial one is <= 0; red[slot_abs]
+// receives the l1 norm when slot_abs >= 0.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* __restrict__ insts, ApgState* __restrict__ Lst,
-                                                      int slot_abs) {
+                                                      CgState* __restrict__ Cst, int slot_abs) {
     __shared__ double s_abs[1024];
     const Inst<T>& I = insts[blockIdx.x];
+    if (threadIdx.x == 0) {
+        if (Lst) put_state(&Lst[blockIdx.x], I.st0);
+        if (Cst) put_state(&Cst[blockIdx.x], I.cg0);
+    }
     if (!I.theta64) return;
     const int K = I.K, KK = K * K;
     const int t = threadIdx.x;
@@ -1308,7 +1314,7 @@ __global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* __restrict_
     if (t == 0) {
         double s = 0.0;
         for (int i = 0; i < KK; ++i) s += s_abs[i];
-        if (Lst && !(Lst[blockIdx.x].L > 0.0)) Lst[blockIdx.x].L = s * s;
+        if (Lst && !(I.st0.L > 0.0)) Lst[blockIdx.x].L = s * s;
         if (slot_abs >= 0) I.red[slot_abs] = s;
     }
 }

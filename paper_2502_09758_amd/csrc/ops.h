@@ -65,7 +65,8 @@ inline int step_blocks(int H, int W, int K, int R) {
 }
 
 template <typename T> struct Ops {
-    static hipError_t prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, int slot_abs, hipStream_t s);
+    static hipError_t prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, CgState* Cst, int slot_abs,
+                                  hipStream_t s);
     static hipError_t finish(const Inst<T>* insts, int n, int slot, int sob_slot, hipStream_t s);
     static hipError_t conv(const Group& g, const Inst<T>* insts, hipStream_t s);
     static hipError_t apg_grad(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);

@@ -50,8 +50,9 @@ __global__ __launch_bounds__(1024) void k_sobolev(double beta, double h1_w0, con
     }
 
 template <typename T>
-hipError_t Ops<T>::prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, int slot_abs, hipStream_t s) {
-    return launch(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, slot_abs);
+hipError_t Ops<T>::prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, CgState* Cst, int slot_abs,
+                               hipStream_t s) {
+    return launch(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, Cst, slot_abs);
 }
 
 template <typename T>
