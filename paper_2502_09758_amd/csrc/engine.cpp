@@ -82,9 +82,14 @@ int push(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n) {
     HIP_TRY(hipMemcpyAsync(c->st_dev + off, c->st_host + off, n, hipMemcpyHostToDevice, s));
     return MAID_OK;
 }
-template <typename T> int upload(maid_ctx* c, int role, hipStream_t s) {
+// copy `roles` adjacent role tables, starting at `role`, in one transfer
+template <typename T> int upload(maid_ctx* c, int role, hipStream_t s, int roles = 1) {
     const size_t bytes = sizeof(Inst<T>) * c->n;
-    HIP_TRY(hipMemcpyAsync(c->tab_dev + role * bytes, c->tab_host + role * bytes, bytes, hipMemcpyHostToDevice, s));
+    if (c->upload_kernel)
+        HIP_TRY(launch_upload(c->tab_host + role * bytes, roles * bytes, c->tab_dev + role * bytes, s));
+    else
+        HIP_TRY(hipMemcpyAsync(c->tab_dev + role * bytes, c->tab_host + role * bytes, roles * bytes,
+                               hipMemcpyHostToDevice, s));
     return MAID_OK;
 }
 int publish(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n);
@@ -573,7 +578,10 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         e = hipHostMalloc((void**)&c->pub, c->st_bytes + 256, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) c->pub_flag = (unsigned*)(c->pub + c->st_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->tab_dev, tab_bytes);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->tab_host, tab_bytes, hipHostMallocDefault);
+    // mapped and coherent: the upload kernel reads it (the host rewrites it
+    // only after the solve that read it has been waited for)
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&c->tab_host, tab_bytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipMalloc((void**)&c->maps, maps * sizeof(int));
     if (e == hipSuccess) e = hipMemset(c->ws, 0, c->ws_bytes);
     if (e == hipSuccess) e = hipMemset(c->st_dev, 0, c->st_bytes);
@@ -591,6 +599,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     if (const char* t = std::getenv("MAID_TEAM")) c->team_req = std::max(-1, std::atoi(t));
     if (const char* f = std::getenv("MAID_FUSE")) c->fuse = std::strcmp(f, "0") != 0;
     if (const char* f = std::getenv("MAID_CG_ONE_PASS")) c->cg_fuse = std::strcmp(f, "0") != 0;
+    if (const char* u = std::getenv("MAID_UPLOAD_KERNEL")) c->upload_kernel = std::strcmp(u, "0") != 0;
     // longest wait at a team barrier, in wall-clock ticks (0 forces the
     // multi-kernel fallback, for tests)
     if (const char* w = std::getenv("MAID_TEAM_WAIT")) c->team_wait = std::max(0LL, std::atoll(w));
@@ -1026,8 +1035,7 @@ int upper_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<cons
             t1[i].h1_w0 = M.d.h1_w0;
         }
     }
-    TRY(upload<T>(c, ROLE_CV0, s));
-    TRY(upload<T>(c, ROLE_CV1, s));
+    TRY(upload<T>(c, ROLE_CV0, s, 2));   // ROLE_CV0 and ROLE_CV1
     const Inst<T>* d0 = tab_dev<T>(c, ROLE_CV0);
     const Inst<T>* d1 = tab_dev<T>(c, ROLE_CV1);
     LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, nullptr, kRedAbs, s));
@@ -1078,8 +1086,7 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
         t3[i].cv_in = q[i];
         t3[i].cv_out = (T*)M.tmp1;
     }
-    TRY(upload<T>(c, ROLE_CV2, s));
-    TRY(upload<T>(c, ROLE_CV3, s));
+    TRY(upload<T>(c, ROLE_CV2, s, 2));   // ROLE_CV2 and ROLE_CV3
     const Inst<T>* d2 = tab_dev<T>(c, ROLE_CV2);
     const Inst<T>* d3 = tab_dev<T>(c, ROLE_CV3);
     LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d2, n, nullptr, nullptr, -1, s));

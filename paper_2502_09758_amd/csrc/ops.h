@@ -94,6 +94,8 @@ template <typename T> struct Ops {
 
 hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
                            const double* a, int with_r, double* z, double* znorm2, hipStream_t s);
+// Copy bytes (a multiple of 4) from device-mapped host memory to the device.
+hipError_t launch_upload(const void* src_host, size_t bytes, void* dst, hipStream_t s);
 // XCD of each block of a kTeamXcd x kTeamMax grid (out: that many ints).
 hipError_t launch_team_map(int* out, hipStream_t s);
 hipError_t launch_publish(const void* src, size_t bytes, void* dst_host, unsigned* flag_host, hipStream_t s);

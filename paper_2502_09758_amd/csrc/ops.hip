@@ -1,5 +1,7 @@
 // ops.hip -- Ops<T>: runtime dispatch of K to the per-K launchers, and the
 // kernels that do not depend on K.
+#include <algorithm>
+
 #include "kernels.cuh"
 #include "stencil_decl.h"
 
@@ -166,6 +168,26 @@ hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w,
     if (d.K <= 16)
         return launch((k_hg_corr<T, 16>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
     return launch((k_hg_corr<T, 32>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
+}
+
+// dst[i] = src[i] for `words` 32-bit words, src in host memory mapped for the
+// device: the instance tables' upload as a kernel (no copy-engine call).
+__global__ __launch_bounds__(kNT) void k_upload(const unsigned* __restrict__ src, int words, unsigned* __restrict__ dst) {
+    const int stride = (int)gridDim.x * kNT * 4;
+    for (int i0 = ((int)blockIdx.x * kNT + (int)threadIdx.x) * 4; i0 < words; i0 += stride) {
+        unsigned v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k < words ? src[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k < words) dst[i0 + k] = v[k];
+    }
+}
+
+hipError_t launch_upload(const void* src_host, size_t bytes, void* dst, hipStream_t s) {
+    const int words = (int)(bytes / 4);
+    const int blocks = std::max(1, std::min(64, (words + 4 * kNT - 1) / (4 * kNT)));
+    return launch(k_upload, dim3(blocks), dim3(kNT), 0, s, (const unsigned*)src_host, words, (unsigned*)dst);
 }
 
 // XCD (hardware XCC_ID) of every block of the grid.
