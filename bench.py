@@ -66,8 +66,8 @@ def kernel_model(kind: str, K: int, esz: int, C: int):
         return 8 * esz, k2 + 50
     if kind == "apg_step":      # one-pass iteration: x, x_prev, Kx, Kx_prev, y -> x+, Kx+ (G stays on chip)
         return 7 * esz, 2 * k2 + 95
-    if kind == "cg_step":       # one-pass CG: r, w, s, p, q, x -> r, w, s, p, q (Kr stays on chip)
-        return 11 * esz, 2 * k2 + 70
+    if kind == "cg_step":       # one-pass CG: r, w, s, p, q, x -> r, w, s, p, q (Kr stays on chip; s in FP64)
+        return 9 * esz + 16, 2 * k2 + 70
     if kind == "apg_team":      # a gradient and a trial pass per slot
         return 14 * esz, 2 * k2 + 95
     if kind == "cg_team":       # direction, Hessian and update pass per iteration
