@@ -83,14 +83,38 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// A lane permutation of a double through the DPP crossbar (two 32-bit
+// moves; CTRL is a pattern in which every lane reads an active lane).
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the wave (all 64 lanes active), the same value in every lane:
+// butterflies within each row of 16 lanes on the DPP crossbar (partners
+// lane^1 and lane^2, then the half-row and the row mirror, each of which
+// pairs two lanes holding sums over disjoint lane sets, so both partners
+// form the same sum), then the four row sums in a fixed order.  The lane
+// crossbar takes a few cycles per step where a shuffle through the LDS
+// unit takes a round trip.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
 }
 
 // Sum of one double per thread over the block, returned to every thread
-// (wave butterflies, then the four waves in a fixed order).
+// (wave sums, then the four waves in a fixed order).
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double s_w[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -100,12 +124,35 @@ __device__ __forceinline__ double block_sum(double v) {
     __syncthreads();
     return ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
+// Two such sums with one pair of barriers (each summed as block_sum does).
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+    __shared__ double s_w2[8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+        s_w2[wid] = a;
+        s_w2[4 + wid] = b;
+    }
+    __syncthreads();
+    a = ((s_w2[0] + s_w2[1]) + s_w2[2]) + s_w2[3];
+    b = ((s_w2[4] + s_w2[5]) + s_w2[6]) + s_w2[7];
+}
 
 // Producer side of a grid-wide sum: one partial per block (index lb within
 // its instance), plain store.
 __device__ __forceinline__ void block_partial(double v, double* part, int lb) {
     const double s = block_sum(v);
     if (threadIdx.x == 0) part[lb] = s;
+}
+// Two partials of the same block.
+__device__ __forceinline__ void block_partial2(double va, double* pa, double vb, double* pb, int lb) {
+    block_sum2(va, vb);
+    if (threadIdx.x == 0) {
+        pa[lb] = va;
+        pb[lb] = vb;
+    }
 }
 
 // Consumer side, at the start of the next kernel: every block sums the nb
@@ -135,11 +182,16 @@ __device__ __forceinline__ Partials partials_issue(const double* __restrict__ pa
     }
     return p;
 }
+// The thread's share of partials_finish (before the sum over the block).
 template <bool CO = false>
-__device__ __forceinline__ double partials_finish(const double* __restrict__ part, int nb, const Partials& p) {
+__device__ __forceinline__ double partials_local(const double* __restrict__ part, int nb, const Partials& p) {
     double s = ((p.v[0] + p.v[1]) + p.v[2]) + p.v[3];
     for (int b = threadIdx.x + 4 * kNT; b < nb; b += kNT) s += ld<CO>(part, b);
-    return block_sum(s);
+    return s;
+}
+template <bool CO = false>
+__device__ __forceinline__ double partials_finish(const double* __restrict__ part, int nb, const Partials& p) {
+    return block_sum(partials_local<CO>(part, nb, p));
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v <= 1.0e300 && v >= -1.0e300; }

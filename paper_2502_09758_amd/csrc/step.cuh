@@ -108,8 +108,11 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     };
     stage_point(cur, prev, (T)mnext);
 
+    // both sums of the previous pass with one pair of barriers
+    double gn2 = fresh ? partials_local<CO>(rA, nbf, pa) : 0.0;
+    double delta = start ? 0.0 : partials_local<CO>(rB, nbf, pb);
+    block_sum2(gn2, delta);
     if (fresh) {
-        const double gn2 = partials_finish<CO>(rA, nbf, pa);
         st.gn2 = gn2;
         st.nb_iter = 0;
         if (!finite_d(gn2)) {
@@ -125,7 +128,6 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     }
     bool moved = start;
     if (!st.done && !start) {
-        const double delta = partials_finish<CO>(rB, nbf, pb);
         st.delta_last = delta;
         if (!finite_d(delta)) {
             st.done = 1;
@@ -251,8 +253,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
             if (lane_in && gi < H && oj < W) at(KXN, gi * W + oj) = dacc[o];
         }
     }
-    block_partial(gsq, wA, lb);
-    block_partial(ddat + I.pr.alpha * dtv, wB, lb);
+    block_partial2(gsq, wA, ddat + I.pr.alpha * dtv, wB, lb);
 }
 
 // One-pass FISTA launch over a group: block b -> (instance, local block) via
@@ -354,8 +355,9 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
 
     double a = 0.0, beta = 0.0;
     if (!prime) {
-        const double g = partials_finish<CO>(rG, nbf, pg);
-        const double d = partials_finish<CO>(rD, nbf, pd);
+        double g = partials_local<CO>(rG, nbf, pg);
+        double d = partials_local<CO>(rD, nbf, pd);
+        block_sum2(g, d);
         beta = first ? 0.0 : g / st.gamma;
         st.gamma = g;
         if (!finite_d(g)) {
@@ -492,8 +494,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     }
     double* __restrict__ wG = I.pR + (wsel ? nbf : 0);
     double* __restrict__ wD = I.pK + (wsel ? nbf : 0);
-    block_partial(gs, wG, lb);
-    block_partial(ds, wD, lb);
+    block_partial2(gs, wG, ds, wD, lb);
 }
 
 template <typename T, int K, int R>
