@@ -49,6 +49,11 @@ template <> __device__ __forceinline__ float dsqrt<float>(float v) { return sqrt
 template <> __device__ __forceinline__ double dsqrt<double>(double v) { return sqrt(v); }
 // 1/sqrt: the hardware reciprocal square root for FP32 (1 ulp), the
 // correctly rounded quotient for FP64
+// c ? v : 0 with v evaluated whatever c is: where v reads LDS at addresses
+// that lie inside the tile for every lane, the reads are then issued
+// together instead of each under a branch of its own.
+template <typename T> __device__ __forceinline__ T keep(bool c, T v) { return c ? v : T(0); }
+
 template <typename T> __device__ __forceinline__ T drsqrt(T v);
 template <> __device__ __forceinline__ float drsqrt<float>(float v) { return rsqrtf(v); }
 template <> __device__ __forceinline__ double drsqrt<double>(double v) { return 1.0 / sqrt(v); }
@@ -307,8 +312,34 @@ __device__ __forceinline__ T pick3(const T (&a)[R], const T (&b)[R], const T (&c
 template <typename T, int R>
 __device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg, T eps2, int ti0, int tj0, int H, int W) {
     constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
-    for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
-        const int r = idx / WP, cc = idx - r * WP;
+    constexpr int NS = WR * WP, IT = (NS + kNT - 1) / kNT;
+    if (reg == 1 && C > 1) {
+        // channelwise weights, one set per channel
+        for (int idx = threadIdx.x; idx < NS; idx += kNT) {
+            const int r = idx / WP, cc = idx - r * WP;
+            const int gi = ti0 - 1 + r, gj = tj0 - 1 + cc;
+            const bool in = (gi >= 0 && gi < H && gj >= 0 && gj < W);
+            const bool hx = gj < W - 1, vx = gi < H - 1;
+            for (int ch = 0; ch < C; ++ch) {
+                const T* V = s_v + ch * VR * VP;
+                const T v0 = V[r * VP + cc];
+                const T dh = keep(hx, V[r * VP + cc + 1] - v0);
+                const T dv = keep(vx, V[(r + 1) * VP + cc] - v0);
+                s_w[ch * WR * WP + idx] = in ? drsqrt(dh * dh + dv * dv + eps2) : T(0);
+            }
+        }
+        return;
+    }
+    // one weight per site (coupled channels; with one channel the
+    // channelwise weight is the same number): the thread's sites unrolled,
+    // all reads (at a clamped site index) before all stores, so that no LDS
+    // read waits behind an LDS store the compiler cannot tell apart from it
+    T wk[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int idx = threadIdx.x + k * kNT;
+        const int ic = idx < NS ? idx : NS - 1;
+        const int r = ic / WP, cc = ic - r * WP;
         const int gi = ti0 - 1 + r, gj = tj0 - 1 + cc;
         const bool in = (gi >= 0 && gi < H && gj >= 0 && gj < W);
         const bool hx = gj < W - 1, vx = gi < H - 1;
@@ -316,15 +347,16 @@ __device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg,
         for (int ch = 0; ch < C; ++ch) {
             const T* V = s_v + ch * VR * VP;
             const T v0 = V[r * VP + cc];
-            const T dh = hx ? V[r * VP + cc + 1] - v0 : T(0);
-            const T dv = vx ? V[(r + 1) * VP + cc] - v0 : T(0);
-            if (reg == 1) {
-                s_w[ch * WR * WP + idx] = in ? drsqrt(dh * dh + dv * dv + eps2) : T(0);
-            } else {
-                s2 += dh * dh + dv * dv;
-            }
+            const T dh = keep(hx, V[r * VP + cc + 1] - v0);
+            const T dv = keep(vx, V[(r + 1) * VP + cc] - v0);
+            s2 += dh * dh + dv * dv;
         }
-        if (reg != 1) s_w[idx] = in ? (reg == 2 ? T(1) : drsqrt(s2 + eps2)) : T(0);
+        wk[k] = in ? (reg == 2 ? T(1) : drsqrt(s2 + eps2)) : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int idx = threadIdx.x + k * kNT;
+        if (idx < NS) s_w[idx] = wk[k];
     }
 }
 
@@ -337,8 +369,8 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
     const T* Wt = s_w + (reg == 1 ? ch * WR * WP : 0);
     const int r = li + 1, cc = tx + 1;
     const T v0 = V[r * VP + cc];
-    const T dh_here = (gj < W - 1) ? V[r * VP + cc + 1] - v0 : T(0);
-    const T dv_here = (gi < H - 1) ? V[(r + 1) * VP + cc] - v0 : T(0);
+    const T dh_here = keep(gj < W - 1, V[r * VP + cc + 1] - v0);
+    const T dv_here = keep(gi < H - 1, V[(r + 1) * VP + cc] - v0);
     const T dh_left = v0 - V[r * VP + cc - 1];
     const T dv_up = v0 - V[(r - 1) * VP + cc];
     const T w0 = Wt[r * WP + cc];

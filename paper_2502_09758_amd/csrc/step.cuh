@@ -176,10 +176,17 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     __syncthreads();
     double gsq = 0.0;
     const int gj = ej0 + tx;
+    // all rows' LDS reads before the first LDS store
+    T gv[RE];
 #pragma unroll
     for (int o = 0; o < RE; ++o) {
         const int li = wv * RE + o, gi = ei0 + li;
-        const T g = dfma(alpha, tv_grad_px<T, RE>(s_v, s_w, 0, reg, li, tx, gi, gj, H, W), acc[o]);
+        gv[o] = dfma(alpha, tv_grad_px<T, RE>(s_v, s_w, 0, reg, li, tx, gi, gj, H, W), acc[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < RE; ++o) {
+        const int li = wv * RE + o, gi = ei0 + li;
+        const T g = gv[o];
         const bool in = inside(gi, gj, H, W);
         s_g[li * CP + tx] = in ? g * ninvL : T(0);
         // ||G||^2 over the output tile only (every pixel in exactly one tile)
@@ -195,24 +202,27 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     double dtv = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
+        // every lane reads (inside the staged tiles) and computes; lanes
+        // outside the output tile or the image add nothing
         const int gi = ti0 + li0 + o;
-        if (lane_in && gi < H && oj < W) {
-            const int iv = (li0 + o + c0 + 1) * VP + tx + c0 + 1;
-            const int ig = (li0 + o + c0) * CP + tx + c0;
-            const bool hx = oj < W - 1, vx = gi < H - 1;
-            const double bh = hx ? (double)(s_v[iv + 1] - s_v[iv]) : 0.0;
-            const double bv = vx ? (double)(s_v[iv + VP] - s_v[iv]) : 0.0;
-            const double ah = hx ? (double)(s_g[ig + 1] - s_g[ig]) : 0.0;
-            const double av = vx ? (double)(s_g[ig + CP] - s_g[ig]) : 0.0;
-            if (reg == 2) {
-                dtv += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
-            } else {
-                // one channel: the coupled and the channelwise magnitudes agree
-                const double d2 = ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
-                const double q2 = bh * bh + bv * bv;
-                dtv += d2 / (sqrt(q2 + d2 + e2) + sqrt(q2 + e2));
-            }
+        const bool px = lane_in && gi < H && oj < W;
+        const int iv = (li0 + o + c0 + 1) * VP + tx + c0 + 1;
+        const int ig = (li0 + o + c0) * CP + tx + c0;
+        const bool hx = oj < W - 1, vx = gi < H - 1;
+        const double bh = keep(hx, (double)(s_v[iv + 1] - s_v[iv]));
+        const double bv = keep(vx, (double)(s_v[iv + VP] - s_v[iv]));
+        const double ah = keep(hx, (double)(s_g[ig + 1] - s_g[ig]));
+        const double av = keep(vx, (double)(s_g[ig + CP] - s_g[ig]));
+        double term;
+        if (reg == 2) {
+            term = ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
+        } else {
+            // one channel: the coupled and the channelwise magnitudes agree
+            const double d2 = ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
+            const double q2 = bh * bh + bv * bv;
+            term = d2 / (sqrt(q2 + d2 + e2) + sqrt(q2 + e2));
         }
+        dtv = px ? dtv + term : dtv;
     }
     T dacc[R];
 #pragma unroll
@@ -423,24 +433,39 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     __syncthreads();
     // TV weights of the flux sites (the Hessian pass's arithmetic, one channel)
     const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
-    for (int idx = threadIdx.x; idx < WR * WP; idx += kNT) {
-        const int r = idx / WP, cc = idx - r * WP;
+    constexpr int NS = WR * WP, ITS = (NS + kNT - 1) / kNT;
+    // unrolled over the thread's sites with a clamped site index for the
+    // reads, all reads before all stores
+    T wk[ITS], mk[ITS];
+#pragma unroll
+    for (int k = 0; k < ITS; ++k) {
+        const int idx = threadIdx.x + k * kNT;
+        const int ic = idx < NS ? idx : NS - 1;
+        const int r = ic / WP, cc = ic - r * WP;
         const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
         const bool in = inside(gi, gj2, H, W);
         const bool hx = gj2 < W - 1, vx = gi < H - 1;
         const int i0 = r * VP + cc;
-        const T xh = hx ? s_x[i0 + 1] - s_x[i0] : T(0);
-        const T xv = vx ? s_x[i0 + VP] - s_x[i0] : T(0);
-        const T ph = hx ? s_p[i0 + 1] - s_p[i0] : T(0);
-        const T pv = vx ? s_p[i0 + VP] - s_p[i0] : T(0);
+        const T xh = keep(hx, s_x[i0 + 1] - s_x[i0]);
+        const T xv = keep(vx, s_x[i0 + VP] - s_x[i0]);
+        const T ph = keep(hx, s_p[i0 + 1] - s_p[i0]);
+        const T pv = keep(vx, s_p[i0 + VP] - s_p[i0]);
         const T s2 = xh * xh + xv * xv, mm = xh * ph + xv * pv;
         if (reg == 2) {
-            s_w[idx] = in ? T(1) : T(0);
-            s_mw[idx] = T(0);
+            wk[k] = in ? T(1) : T(0);
+            mk[k] = T(0);
         } else {
             const T w = in ? drsqrt(s2 + eps2) : T(0);
-            s_w[idx] = w;
-            s_mw[idx] = w * w * w * mm;
+            wk[k] = w;
+            mk[k] = w * w * w * mm;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ITS; ++k) {
+        const int idx = threadIdx.x + k * kNT;
+        if (idx < NS) {
+            s_w[idx] = wk[k];
+            s_mw[idx] = mk[k];
         }
     }
     T hacc[R];
@@ -461,23 +486,25 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int gi = ti0 + li0 + o;
+        // the Hessian term from LDS for every lane (the reads stay inside
+        // the staged tiles), the stores for the output pixels only
+        const int r = li0 + o + 1, cc = tx + 1;
+        const int i0 = r * VP + cc;
+        const T xh_h = keep(oj < W - 1, s_x[i0 + 1] - s_x[i0]);
+        const T ph_h = keep(oj < W - 1, s_p[i0 + 1] - s_p[i0]);
+        const T xv_h = keep(gi < H - 1, s_x[i0 + VP] - s_x[i0]);
+        const T pv_h = keep(gi < H - 1, s_p[i0 + VP] - s_p[i0]);
+        const T xh_l = s_x[i0] - s_x[i0 - 1], ph_l = s_p[i0] - s_p[i0 - 1];
+        const T xv_u = s_x[i0] - s_x[i0 - VP], pv_u = s_p[i0] - s_p[i0 - VP];
+        const int f0 = r * WP + cc, fl = f0 - 1, fu = f0 - WP;
+        const T fh_here = s_w[f0] * ph_h - s_mw[f0] * xh_h;
+        const T fv_here = s_w[f0] * pv_h - s_mw[f0] * xv_h;
+        const T fh_left = s_w[fl] * ph_l - s_mw[fl] * xh_l;
+        const T fv_up = s_w[fu] * pv_u - s_mw[fu] * xv_u;
+        const T hv = fh_left - fh_here + fv_up - fv_here;
+        const T rn = s_p[i0];
         if (lane_in && gi < H && oj < W) {
-            const int r = li0 + o + 1, cc = tx + 1;
-            const int i0 = r * VP + cc;
-            const T xh_h = (oj < W - 1) ? s_x[i0 + 1] - s_x[i0] : T(0);
-            const T ph_h = (oj < W - 1) ? s_p[i0 + 1] - s_p[i0] : T(0);
-            const T xv_h = (gi < H - 1) ? s_x[i0 + VP] - s_x[i0] : T(0);
-            const T pv_h = (gi < H - 1) ? s_p[i0 + VP] - s_p[i0] : T(0);
-            const T xh_l = s_x[i0] - s_x[i0 - 1], ph_l = s_p[i0] - s_p[i0 - 1];
-            const T xv_u = s_x[i0] - s_x[i0 - VP], pv_u = s_p[i0] - s_p[i0 - VP];
-            const int f0 = r * WP + cc, fl = f0 - 1, fu = f0 - WP;
-            const T fh_here = s_w[f0] * ph_h - s_mw[f0] * xh_h;
-            const T fv_here = s_w[f0] * pv_h - s_mw[f0] * xv_h;
-            const T fh_left = s_w[fl] * ph_l - s_mw[fl] * xh_l;
-            const T fv_up = s_w[fu] * pv_u - s_mw[fu] * xv_u;
-            const T hv = fh_left - fh_here + fv_up - fv_here;
             const T wn = dfma(alpha, hv, hacc[o]);
-            const T rn = s_p[i0];
             const int e = gi * W + oj;
             at(Wn, e) = wn;
             if (!prime) {
