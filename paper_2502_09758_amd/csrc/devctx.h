@@ -22,6 +22,8 @@ constexpr int kMaxC = 3;       // colour channels supported by the LDS tiles
 constexpr int kMaxK = 31;      // largest odd kernel size
 constexpr int kTW = 64;        // tile width: one wave64 spans a tile row
 constexpr int kNT = 256;       // threads per block (4 waves)
+constexpr int kStepNW = 8;     // waves per block of the one-pass forms (a tile row per wave)
+constexpr int kStepNT = 64 * kStepNW;
 
 enum Status : int32_t { ST_OK = 0, ST_MAXITER = 1, ST_NOT_SPD = -4, ST_NONFINITE = -5 };
 

@@ -326,7 +326,7 @@ int validate_desc(const maid_desc* d, std::string& why) {
 // lower + CG iterations ~17% faster on teams than as kernels; 256x256, 256
 // tiles, 2.4x slower), so larger instances stay on the multi-kernel passes.
 constexpr int kTeamTiles = 64;
-constexpr int kStepTiles = 640;
+constexpr int kStepTiles = 320;
 int team_members(maid_ctx* c, const LaunchGroup& lg) {
     if (!c->team_ok || c->team_req == 0 || lg.g.R > 4) return 0;
     int most_tiles = 0, cap = kTeamMax;

@@ -129,20 +129,26 @@ __device__ __forceinline__ double block_sum(double v) {
     __syncthreads();
     return ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
-// Two such sums with one pair of barriers (each summed as block_sum does).
-__device__ __forceinline__ void block_sum2(double& a, double& b) {
-    __shared__ double s_w2[8];
+// Two such sums with one pair of barriers, for blocks of NW waves (the wave
+// sums added in wave order).
+template <int NW = 4> __device__ __forceinline__ void block_sum2(double& a, double& b) {
+    __shared__ double s_w2[2 * NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
     __syncthreads();
     if (lane == 0) {
         s_w2[wid] = a;
-        s_w2[4 + wid] = b;
+        s_w2[NW + wid] = b;
     }
     __syncthreads();
-    a = ((s_w2[0] + s_w2[1]) + s_w2[2]) + s_w2[3];
-    b = ((s_w2[4] + s_w2[5]) + s_w2[6]) + s_w2[7];
+    a = s_w2[0];
+    b = s_w2[NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        a += s_w2[w];
+        b += s_w2[NW + w];
+    }
 }
 
 // Producer side of a grid-wide sum: one partial per block (index lb within
@@ -152,8 +158,9 @@ __device__ __forceinline__ void block_partial(double v, double* part, int lb) {
     if (threadIdx.x == 0) part[lb] = s;
 }
 // Two partials of the same block.
+template <int NW = 4>
 __device__ __forceinline__ void block_partial2(double va, double* pa, double vb, double* pb, int lb) {
-    block_sum2(va, vb);
+    block_sum2<NW>(va, vb);
     if (threadIdx.x == 0) {
         pa[lb] = va;
         pb[lb] = vb;
@@ -177,21 +184,21 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
 struct Partials {
     double v[4];
 };
-template <bool CO = false>
+template <bool CO = false, int NT = kNT>
 __device__ __forceinline__ Partials partials_issue(const double* __restrict__ part, int nb) {
     Partials p;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int b = threadIdx.x + k * kNT;
+        const int b = threadIdx.x + k * NT;
         p.v[k] = b < nb ? ld<CO>(part, b) : 0.0;
     }
     return p;
 }
 // The thread's share of partials_finish (before the sum over the block).
-template <bool CO = false>
+template <bool CO = false, int NT = kNT>
 __device__ __forceinline__ double partials_local(const double* __restrict__ part, int nb, const Partials& p) {
     double s = ((p.v[0] + p.v[1]) + p.v[2]) + p.v[3];
-    for (int b = threadIdx.x + 4 * kNT; b < nb; b += kNT) s += ld<CO>(part, b);
+    for (int b = threadIdx.x + 4 * NT; b < nb; b += NT) s += ld<CO>(part, b);
     return s;
 }
 template <bool CO = false>
@@ -227,15 +234,15 @@ __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > h
 // gi0.., columns gj0..; zero outside [0,H) x [0,W).  Each thread issues the
 // global loads of up to eight of its elements before it writes any of them
 // to LDS, so their latencies overlap instead of adding up.
-template <int ROWS, int COLS, int PITCH, typename T, typename F>
+template <int ROWS, int COLS, int PITCH, int NT = kNT, typename T, typename F>
 __device__ __forceinline__ void load_tile(T* s, int gi0, int gj0, int H, int W, F f) {
-    constexpr int NE = ROWS * COLS, IT = (NE + kNT - 1) / kNT, B = IT < 8 ? IT : 8;
+    constexpr int NE = ROWS * COLS, IT = (NE + NT - 1) / NT, B = IT < 8 ? IT : 8;
 #pragma unroll 1
     for (int k0 = 0; k0 < IT; k0 += B) {
         T val[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            const int idx = threadIdx.x + (k0 + k) * kNT;
+            const int idx = threadIdx.x + (k0 + k) * NT;
             const int r = idx / COLS, cc = idx - r * COLS;
             const int gi = gi0 + r, gj = gj0 + cc;
             // every lane loads from a valid (clamped) address and zeroes what
@@ -246,7 +253,7 @@ __device__ __forceinline__ void load_tile(T* s, int gi0, int gj0, int H, int W, 
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            const int idx = threadIdx.x + (k0 + k) * kNT;
+            const int idx = threadIdx.x + (k0 + k) * NT;
             const int r = idx / COLS, cc = idx - r * COLS;
             if (idx < NE) s[r * PITCH + cc] = val[k];
         }
@@ -266,6 +273,25 @@ __device__ __forceinline__ void load_tile(T* s, int gi0, int gj0, int H, int W, 
 #else
 #define MAID_CONST
 #endif
+// Warms the scalar cache with the lines of two tap arrays (K*K taps each):
+// scalar loads of one word per 64-byte line, folded into one value that only
+// an empty asm statement consumes (so all loads are issued before the one
+// wait).  Called while a pass's global loads are in flight, it takes the
+// taps' memory latency off the correlations, whose scalar loads of the taps
+// then hit the cache.
+template <typename T, int K> __device__ __forceinline__ void warm_taps(const T* ka, const T* kb) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using U = unsigned;
+    const U MAID_CONST* a = (const U MAID_CONST*)ka;
+    const U MAID_CONST* b = (const U MAID_CONST*)kb;
+    constexpr int NW = K * K * (int)(sizeof(T) / sizeof(U)), L = 16;
+    U x = a[NW - 1] ^ b[NW - 1];
+#pragma unroll
+    for (int i = 0; i < NW - 1; i += L) x ^= a[i] ^ b[i];
+    asm volatile("" ::"s"(x));
+#endif
+}
+
 template <typename T, int K, int R>
 __device__ __forceinline__ void correlate_col(const T* s, int pitch, const T* __restrict__ kT, int li0, int tx, int v, T (&acc)[R]) {
     const T MAID_CONST* kc = (const T MAID_CONST*)kT;
@@ -309,13 +335,15 @@ __device__ __forceinline__ T pick3(const T (&a)[R], const T (&b)[R], const T (&c
 // from a staged halo tile of v (C planes).  reg 0: one s over all channels;
 // reg 1: one per channel (nw = C planes); reg 2 (quadratic): w = 1.  Zero
 // at positions outside the image, so every flux there vanishes.
-template <typename T, int R>
-__device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg, T eps2, int ti0, int tj0, int H, int W) {
-    constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
-    constexpr int NS = WR * WP, IT = (NS + kNT - 1) / kNT;
+// TH: rows of the tile the weights serve (flux sites of TH + 1 rows from a
+// v tile of TH + 2 rows); NT: threads of the block.
+template <typename T, int TH, int NT>
+__device__ __forceinline__ void tv_weights_h(const T* s_v, T* s_w, int C, int reg, T eps2, int ti0, int tj0, int H, int W) {
+    constexpr int VP = tv_pitch(), VR = TH + 2, WP = fx_pitch(), WR = TH + 1;
+    constexpr int NS = WR * WP, IT = (NS + NT - 1) / NT;
     if (reg == 1 && C > 1) {
         // channelwise weights, one set per channel
-        for (int idx = threadIdx.x; idx < NS; idx += kNT) {
+        for (int idx = threadIdx.x; idx < NS; idx += NT) {
             const int r = idx / WP, cc = idx - r * WP;
             const int gi = ti0 - 1 + r, gj = tj0 - 1 + cc;
             const bool in = (gi >= 0 && gi < H && gj >= 0 && gj < W);
@@ -337,7 +365,7 @@ __device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg,
     T wk[IT];
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-        const int idx = threadIdx.x + k * kNT;
+        const int idx = threadIdx.x + k * NT;
         const int ic = idx < NS ? idx : NS - 1;
         const int r = ic / WP, cc = ic - r * WP;
         const int gi = ti0 - 1 + r, gj = tj0 - 1 + cc;
@@ -355,16 +383,20 @@ __device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg,
     }
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-        const int idx = threadIdx.x + k * kNT;
+        const int idx = threadIdx.x + k * NT;
         if (idx < NS) s_w[idx] = wk[k];
     }
+}
+template <typename T, int R>
+__device__ __forceinline__ void tv_weights(const T* s_v, T* s_w, int C, int reg, T eps2, int ti0, int tj0, int H, int W) {
+    tv_weights_h<T, tile_h(R), kNT>(s_v, s_w, C, reg, eps2, ti0, tj0, H, W);
 }
 
 // grad R at the thread's pixel (li, tx) of channel ch:
 // fh(i,j-1) - fh(i,j) + fv(i-1,j) - fv(i,j), flux f = w * (forward difference)
-template <typename T, int R>
-__device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int reg, int li, int tx, int gi, int gj, int H, int W) {
-    constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
+template <typename T, int TH>
+__device__ __forceinline__ T tv_grad_px_h(const T* s_v, const T* s_w, int ch, int reg, int li, int tx, int gi, int gj, int H, int W) {
+    constexpr int VP = tv_pitch(), VR = TH + 2, WP = fx_pitch(), WR = TH + 1;
     const T* V = s_v + ch * VR * VP;
     const T* Wt = s_w + (reg == 1 ? ch * WR * WP : 0);
     const int r = li + 1, cc = tx + 1;
@@ -375,6 +407,10 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
     const T dv_up = v0 - V[(r - 1) * VP + cc];
     const T w0 = Wt[r * WP + cc];
     return Wt[r * WP + cc - 1] * dh_left - w0 * dh_here + Wt[(r - 1) * WP + cc] * dv_up - w0 * dv_here;
+}
+template <typename T, int R>
+__device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int reg, int li, int tx, int gi, int gj, int H, int W) {
+    return tv_grad_px_h<T, tile_h(R)>(s_v, s_w, ch, reg, li, tx, gi, gj, H, W);
 }
 
 // Occupancy floor (waves per SIMD) the compiler must keep: the ALU-bound
@@ -389,9 +425,9 @@ template <typename T> __host__ __device__ constexpr int min_waves(int K, int R) 
 // Several tiles staged together: every tile's global loads are issued (held
 // in registers) before any of them is written to LDS, so a pass that needs a
 // few small tiles pays one memory latency instead of one per tile.
-template <int ROWS, int COLS, int PITCH, typename T, typename F>
+template <int ROWS, int COLS, int PITCH, typename T, typename F, int NT = kNT>
 struct Stage {
-    static constexpr int NE = ROWS * COLS, IT = (NE + kNT - 1) / kNT;
+    static constexpr int NE = ROWS * COLS, IT = (NE + NT - 1) / NT;
     T* s;
     int gi0, gj0;
     F f;
@@ -399,7 +435,7 @@ struct Stage {
     __device__ __forceinline__ void fetch(int H, int W) {
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            const int idx = threadIdx.x + k * kNT;
+            const int idx = threadIdx.x + k * NT;
             const int r = idx / COLS, cc = idx - r * COLS;
             const int gi = gi0 + r, gj = gj0 + cc;
             // every lane loads from a valid (clamped) address and zeroes what
@@ -412,15 +448,15 @@ struct Stage {
     __device__ __forceinline__ void put() const {
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            const int idx = threadIdx.x + k * kNT;
+            const int idx = threadIdx.x + k * NT;
             const int r = idx / COLS, cc = idx - r * COLS;
             if (idx < NE) s[r * PITCH + cc] = val[k];
         }
     }
 };
-template <int ROWS, int COLS, int PITCH, typename T, typename F>
-__device__ __forceinline__ Stage<ROWS, COLS, PITCH, T, F> stage(T* s, int gi0, int gj0, F f) {
-    return Stage<ROWS, COLS, PITCH, T, F>{s, gi0, gj0, f, {}};
+template <int ROWS, int COLS, int PITCH, int NT = kNT, typename T, typename F>
+__device__ __forceinline__ Stage<ROWS, COLS, PITCH, T, F, NT> stage(T* s, int gi0, int gj0, F f) {
+    return Stage<ROWS, COLS, PITCH, T, F, NT>{s, gi0, gj0, f, {}};
 }
 
 // ------------------------------------------------------------------ instance lookup

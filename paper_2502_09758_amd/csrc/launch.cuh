@@ -85,7 +85,8 @@ static hipError_t apg_team_krs(const Group& g, const Inst<T>* insts, const int* 
     auto kern = k_apg_team<T, K, R, STEP>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(kTeamXcd * ctl.P), dim3(kNT), lds, s, insts, list, nlist, st, ctl, max_slots);
+    return launch(kern, dim3(kTeamXcd * ctl.P), dim3(STEP ? kStepNT : kNT), lds, s, insts, list, nlist, st, ctl,
+                  max_slots);
 }
 template <typename T, int K, int R>
 static hipError_t apg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, ApgState* st,
@@ -102,7 +103,8 @@ static hipError_t cg_team_krs(const Group& g, const Inst<T>* insts, const int* l
     auto kern = k_cg_team<T, K, R, STEP>;
     hipError_t e = ensure_lds(kern, lds);
     if (e != hipSuccess) return e;
-    return launch(kern, dim3(kTeamXcd * ctl.P), dim3(kNT), lds, s, insts, list, nlist, st, n, ctl, max_slots);
+    return launch(kern, dim3(kTeamXcd * ctl.P), dim3(STEP ? kStepNT : kNT), lds, s, insts, list, nlist, st, n, ctl,
+                  max_slots);
 }
 template <typename T, int K, int R>
 static hipError_t cg_team_kr(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
@@ -120,10 +122,10 @@ static hipError_t team_occupancy_krs(const Group& g, int* blocks_per_cu) {
     hipError_t e = ensure_lds(k_apg_team<T, K, R, STEP>, apg_team_lds<T, K, R, STEP>(g));
     if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R, STEP_CG>, cg_team_lds<T, K, R, STEP_CG>(g));
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_apg_team<T, K, R, STEP>, kNT,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_apg_team<T, K, R, STEP>, STEP ? kStepNT : kNT,
                                                          apg_team_lds<T, K, R, STEP>(g));
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R, STEP_CG>, kNT,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cg_team<T, K, R, STEP_CG>, STEP_CG ? kStepNT : kNT,
                                                          cg_team_lds<T, K, R, STEP_CG>(g));
     *blocks_per_cu = e == hipSuccess ? (a < b ? a : b) : 0;
     return e;
@@ -146,7 +148,7 @@ static hipError_t apg_step_kr(const Group& g, const Inst<T>* insts, const ApgSta
         auto kern = k_apg_step<T, K, R>;
         hipError_t e = ensure_lds(kern, lds);
         if (e != hipSuccess) return e;
-        return launch(kern, dim3(g.grid_f), dim3(kNT), lds, s, insts, g.blk_f, g.only, sin, sout);
+        return launch(kern, dim3(g.grid_f), dim3(kStepNT), lds, s, insts, g.blk_f, g.only, sin, sout);
     } else {
         return hipErrorInvalidValue;
     }
@@ -159,7 +161,7 @@ static hipError_t cg_step_kr(const Group& g, const Inst<T>* insts, const CgState
         auto kern = k_cg_step<T, K, R>;
         hipError_t e = ensure_lds(kern, lds);
         if (e != hipSuccess) return e;
-        return launch(kern, dim3(g.grid_f), dim3(kNT), lds, s, insts, g.blk_f, g.only, sin, sout);
+        return launch(kern, dim3(g.grid_f), dim3(kStepNT), lds, s, insts, g.blk_f, g.only, sin, sout);
     } else {
         return hipErrorInvalidValue;
     }

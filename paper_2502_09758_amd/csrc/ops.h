@@ -59,9 +59,10 @@ struct Group {
 // Whether a group can take the one-pass FISTA form: one channel and
 // 3 <= K <= 11 (tile rows 1, 2, 4).
 inline bool step_ok(int C, int K, int R) { return C == 1 && K >= 3 && K <= 11 && R <= 4; }
+// Tiles of the one-pass forms: 64 - (K - 1) columns by kStepNW R rows.
 inline int step_blocks(int H, int W, int K, int R) {
-    const int tw = kTW - (K - 1);
-    return ((W + tw - 1) / tw) * ((H + tile_h(R) - 1) / tile_h(R));
+    const int tw = kTW - (K - 1), th = kStepNW * R;
+    return ((W + tw - 1) / tw) * ((H + th - 1) / th);
 }
 
 template <typename T> struct Ops {

@@ -13,6 +13,12 @@
 // two-pass form takes them; a rejected trial recomputes G at the same point
 // (the same values) with the doubled L.
 //
+// Blocks have kStepNW = 8 waves, one tile row per wave and row of a thread:
+// an output tile of 8 R rows needs 8 R + 2 c0 rows of G, so the recomputed
+// halo costs less per output pixel than with the 4-wave blocks of the
+// two-pass kernels, and a 256 x 256 image takes 160 blocks (one per CU)
+// instead of 320 (where a CU holding two blocks finishes last).
+//
 // Per-pixel formulas are those of the two-pass kernels (the same staging,
 // correlation order, TV terms and trial increments), so the iterates agree
 // with the two-pass form to rounding: the partial sums run over this pass's
@@ -23,12 +29,21 @@
 namespace maid {
 
 template <int K> __host__ __device__ constexpr int step_c0() { return (K - 1) / 2; }
+// Blocks of kStepNW waves: a tile of r rows per thread is kStepNW r rows tall
+// (the v tile two rows more, the flux sites one row more, a convolution
+// input K - 1 rows more).
+__host__ __device__ constexpr int step_th(int r) { return kStepNW * r; }
+__host__ __device__ constexpr int step_tv_rows(int r) { return step_th(r) + 2; }
+__host__ __device__ constexpr int step_fx_rows(int r) { return step_th(r) + 1; }
+__host__ __device__ constexpr int step_cv_rows(int K, int r) { return step_th(r) + K - 1; }
 // output tile width and the rows per thread of the extended region
 template <int K> __host__ __device__ constexpr int step_tw() { return kTW - 2 * step_c0<K>(); }
-template <int K, int R> __host__ __device__ constexpr int step_re() { return R + (2 * step_c0<K>() + 3) / 4; }
+template <int K, int R> __host__ __device__ constexpr int step_re() {
+    return R + (2 * step_c0<K>() + kStepNW - 1) / kStepNW;
+}
 template <int K, int R> __host__ __device__ constexpr int lds_apg_step() {
-    return tv_rows(step_re<K, R>()) * tv_pitch() + fx_rows(step_re<K, R>()) * fx_pitch() +
-           lds_conv(K, step_re<K, R>()) + tile_h(step_re<K, R>()) * cv_pitch(K);
+    return step_tv_rows(step_re<K, R>()) * tv_pitch() + step_fx_rows(step_re<K, R>()) * fx_pitch() +
+           step_cv_rows(K, step_re<K, R>()) * cv_pitch(K) + step_th(step_re<K, R>()) * cv_pitch(K);
 }
 
 // One FISTA iteration on the output tile of local block lb (see above).
@@ -39,8 +54,8 @@ template <typename T, int K, int R, bool CO>
 __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState& st, ApgState* __restrict__ sout,
                                               bool writer) {
     constexpr int c0 = step_c0<K>(), TWF = step_tw<K>(), RE = step_re<K, R>();
-    constexpr int CP = cv_pitch(K), CRE = cv_rows(K, RE);
-    constexpr int VP = tv_pitch(), VRE = tv_rows(RE), WP = fx_pitch(), WRE = fx_rows(RE);
+    constexpr int CP = cv_pitch(K), CRE = step_cv_rows(K, RE);
+    constexpr int VP = tv_pitch(), VRE = step_tv_rows(RE), WP = fx_pitch(), WRE = step_fx_rows(RE);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     T* s_v = sm;                          // v on E grown by one pixel
@@ -52,7 +67,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     const int nbf = I.nbf;
     const int ntx = (W + TWF - 1) / TWF;
     const int t = xcd_tile(lb, nbf);
-    const int ti0 = (t / ntx) * tile_h(R), tj0 = (t % ntx) * TWF;
+    const int ti0 = (t / ntx) * step_th(R), tj0 = (t % ntx) * TWF;
     const int ei0 = ti0 - c0, ej0 = tj0 - c0;          // origin of E
     const int tx = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
@@ -68,8 +83,8 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     double* __restrict__ wA = I.pA + (st.pp ? 0 : nbf);
     double* __restrict__ wB = I.pB + (st.pp ? 0 : nbf);
     Partials pa, pb;
-    if (fresh) pa = partials_issue<CO>(rA, nbf);
-    if (!start) pb = partials_issue<CO>(rB, nbf);
+    if (fresh) pa = partials_issue<CO, kStepNT>(rA, nbf);
+    if (!start) pb = partials_issue<CO, kStepNT>(rB, nbf);
     int cur = st.cur, prev = st.prev;
     double mnext = st.m, tnext = st.t;
     if (!start) {
@@ -86,11 +101,11 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
         const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], ci);
         const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], pi);
         const T* __restrict__ Y = I.y;
-        auto rs = stage<CRE, CP, CP>(s_r, ei0 - c0, ej0 - c0, [&](int g) {
+        auto rs = stage<CRE, CP, CP, kStepNT>(s_r, ei0 - c0, ej0 - c0, [&](int g) {
             const T kx = ld<CO>(KX, g);
             return dfma(m, kx - ld<CO>(KXP, g), kx) - ld<CO>(Y, g);
         });
-        auto vs = stage<VRE, VP, VP>(s_v, ei0 - 1, ej0 - 1, [&](int g) {
+        auto vs = stage<VRE, VP, VP, kStepNT>(s_v, ei0 - 1, ej0 - 1, [&](int g) {
             const T xv = ld<CO>(X, g);
             return dfma(m, xv - ld<CO>(XP, g), xv);
         });
@@ -103,15 +118,16 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
             kxpr[o] = ld<CO>(KXP, e);
             yr[o] = ld<CO>(Y, e);
         }
+        warm_taps<T, K>(I.th, I.thf);
         rs.put();
         vs.put();
     };
     stage_point(cur, prev, (T)mnext);
 
     // both sums of the previous pass with one pair of barriers
-    double gn2 = fresh ? partials_local<CO>(rA, nbf, pa) : 0.0;
-    double delta = start ? 0.0 : partials_local<CO>(rB, nbf, pb);
-    block_sum2(gn2, delta);
+    double gn2 = fresh ? partials_local<CO, kStepNT>(rA, nbf, pa) : 0.0;
+    double delta = start ? 0.0 : partials_local<CO, kStepNT>(rB, nbf, pb);
+    block_sum2<kStepNW>(gn2, delta);
     if (fresh) {
         st.gn2 = gn2;
         st.nb_iter = 0;
@@ -165,10 +181,10 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     }
     __syncthreads();
 
-    // ---- G on E: the gradient pass's arithmetic on a 64 x 4 RE tile at E
+    // ---- G on E: the gradient pass's arithmetic on a 64 x (kStepNW RE) tile at E
     const T alpha = (T)I.pr.alpha;
     const T ninvL = (T)(-1.0 / st.L);
-    tv_weights<T, RE>(s_v, s_w, 1, reg, (T)(I.pr.eps_tv * I.pr.eps_tv), ei0, ej0, H, W);
+    tv_weights_h<T, step_th(RE), kStepNT>(s_v, s_w, 1, reg, (T)(I.pr.eps_tv * I.pr.eps_tv), ei0, ej0, H, W);
     T acc[RE];
 #pragma unroll
     for (int o = 0; o < RE; ++o) acc[o] = T(0);
@@ -181,7 +197,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
 #pragma unroll
     for (int o = 0; o < RE; ++o) {
         const int li = wv * RE + o, gi = ei0 + li;
-        gv[o] = dfma(alpha, tv_grad_px<T, RE>(s_v, s_w, 0, reg, li, tx, gi, gj, H, W), acc[o]);
+        gv[o] = dfma(alpha, tv_grad_px_h<T, step_th(RE)>(s_v, s_w, 0, reg, li, tx, gi, gj, H, W), acc[o]);
     }
 #pragma unroll
     for (int o = 0; o < RE; ++o) {
@@ -190,7 +206,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
         const bool in = inside(gi, gj, H, W);
         s_g[li * CP + tx] = in ? g * ninvL : T(0);
         // ||G||^2 over the output tile only (every pixel in exactly one tile)
-        if (in && li >= c0 && li < c0 + tile_h(R) && tx >= c0 && tx < c0 + TWF) gsq += (double)g * (double)g;
+        if (in && li >= c0 && li < c0 + step_th(R) && tx >= c0 && tx < c0 + TWF) gsq += (double)g * (double)g;
     }
     __syncthreads();
 
@@ -249,7 +265,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
         // theta*x+ from x+ = v + dl on E (zero outside the image)
         T* s_x = s_r;
         __syncthreads();
-        for (int idx = threadIdx.x; idx < tile_h(RE) * kTW; idx += kNT) {
+        for (int idx = threadIdx.x; idx < step_th(RE) * kTW; idx += kStepNT) {
             const int r = idx / kTW, cc = idx - r * kTW;
             s_x[r * CP + cc] = s_v[(r + 1) * VP + cc + 1] + s_g[r * CP + cc];
         }
@@ -263,13 +279,13 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
             if (lane_in && gi < H && oj < W) at(KXN, gi * W + oj) = dacc[o];
         }
     }
-    block_partial2(gsq, wA, ddat + I.pr.alpha * dtv, wB, lb);
+    block_partial2<kStepNW>(gsq, wA, ddat + I.pr.alpha * dtv, wB, lb);
 }
 
 // One-pass FISTA launch over a group: block b -> (instance, local block) via
 // the group's step map (blocks of an instance start at a multiple of 8).
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_apg_step(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
+__global__ __launch_bounds__(kStepNT) void k_apg_step(const Inst<T>* __restrict__ insts, const int* __restrict__ blk,
                                                   int only, const ApgState* __restrict__ sin,
                                                   ApgState* __restrict__ sout) {
     const int ii = only >= 0 ? only : blk[blockIdx.x];
@@ -306,21 +322,21 @@ __global__ __launch_bounds__(kNT) void k_apg_step(const Inst<T>* __restrict__ in
 // else), 1 = the first iteration (beta = 0), 0 after; st.pc: the buffer set
 // the pass reads.
 template <int K, int R> __host__ __device__ constexpr int lds_cg_step() {
-    return lds_conv(K, step_re<K, R>()) + tile_h(step_re<K, R>()) * cv_pitch(K) + 2 * tv_rows(R) * tv_pitch() +
-           2 * fx_rows(R) * fx_pitch();
+    return step_cv_rows(K, step_re<K, R>()) * cv_pitch(K) + step_th(step_re<K, R>()) * cv_pitch(K) +
+           2 * step_tv_rows(R) * tv_pitch() + 2 * step_fx_rows(R) * fx_pitch();
 }
 
 template <typename T, int K, int R, bool CO>
 __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& st, CgState* __restrict__ sout,
                                              bool writer) {
     constexpr int c0 = step_c0<K>(), TWF = step_tw<K>(), RE = step_re<K, R>();
-    constexpr int CP = cv_pitch(K), CRE = cv_rows(K, RE);
-    constexpr int VP = tv_pitch(), VR = tv_rows(R), WP = fx_pitch(), WR = fx_rows(R);
+    constexpr int CP = cv_pitch(K), CRE = step_cv_rows(K, RE);
+    constexpr int VP = tv_pitch(), VR = step_tv_rows(R), WP = fx_pitch(), WR = step_fx_rows(R);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     T* s_rn = sm;                         // r_{i+1} on the tile grown by 2 c0
     T* s_u = s_rn + CRE * CP;             // u = theta * r_{i+1} on E
-    T* s_x = s_u + tile_h(RE) * CP;       // xt, tile grown by one pixel
+    T* s_x = s_u + step_th(RE) * CP;       // xt, tile grown by one pixel
     T* s_p = s_x + VR * VP;               // r_{i+1}, tile grown by one pixel
     T* s_w = s_p + VR * VP;               // TV weights w and w^3 <Dx, Dr> of the flux sites
     T* s_mw = s_w + WR * WP;
@@ -329,7 +345,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     const int nbf = I.nbf;
     const int ntx = (W + TWF - 1) / TWF;
     const int t = xcd_tile(lb, nbf);
-    const int ti0 = (t / ntx) * tile_h(R), tj0 = (t % ntx) * TWF;
+    const int ti0 = (t / ntx) * step_th(R), tj0 = (t % ntx) * TWF;
     const int ei0 = ti0 - c0, ej0 = tj0 - c0;
     const int tx = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
@@ -345,8 +361,8 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     const double* __restrict__ rD = I.pK + (par ? nbf : 0);
     Partials pg, pd;
     if (!prime) {
-        pg = partials_issue<CO>(rG, nbf);
-        pd = partials_issue<CO>(rD, nbf);
+        pg = partials_issue<CO, kStepNT>(rG, nbf);
+        pd = partials_issue<CO, kStepNT>(rD, nbf);
     }
     // the tile pixels' own values, loaded with the staging
     T rr[R], wr[R], pr_[R], qr[R];
@@ -360,14 +376,15 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
         pr_[o] = ld<CO>((const T*)Pv, e);
         qr[o] = ld<CO>((const T*)Qv, e);
     }
-    auto xs = stage<VR, VP, VP>(s_x, ti0 - 1, tj0 - 1, [&](int g) { return ld<CO>(Xt, g); });
+    auto xs = stage<VR, VP, VP, kStepNT>(s_x, ti0 - 1, tj0 - 1, [&](int g) { return ld<CO>(Xt, g); });
     xs.fetch(H, W);
+    warm_taps<T, K>(I.th, I.thf);
 
     double a = 0.0, beta = 0.0;
     if (!prime) {
-        double g = partials_local<CO>(rG, nbf, pg);
-        double d = partials_local<CO>(rD, nbf, pd);
-        block_sum2(g, d);
+        double g = partials_local<CO, kStepNT>(rG, nbf, pg);
+        double d = partials_local<CO, kStepNT>(rD, nbf, pd);
+        block_sum2<kStepNW>(g, d);
         beta = first ? 0.0 : g / st.gamma;
         st.gamma = g;
         if (!finite_d(g)) {
@@ -408,9 +425,9 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     auto snext = [&](T w, double s) { return first ? (double)w : dfma(beta, s, (double)w); };
     auto rnext = [&](T r, T w, double s) { return (T)dfma(-a, snext(w, s), (double)r); };
     if (prime) {
-        load_tile<CRE, CP, CP>(s_rn, ei0 - c0, ej0 - c0, H, W, [&](int g) { return ld<CO>(Rb, g); });
+        load_tile<CRE, CP, CP, kStepNT>(s_rn, ei0 - c0, ej0 - c0, H, W, [&](int g) { return ld<CO>(Rb, g); });
     } else {
-        load_tile<CRE, CP, CP>(s_rn, ei0 - c0, ej0 - c0, H, W,
+        load_tile<CRE, CP, CP, kStepNT>(s_rn, ei0 - c0, ej0 - c0, H, W,
                                [&](int g) { return rnext(ld<CO>(Rb, g), ld<CO>(Wb, g), ld<CO>(Sb, g)); });
     }
     xs.put();
@@ -426,20 +443,20 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
         const int li = wv * RE + o;
         s_u[li * CP + tx] = inside(ei0 + li, ej0 + tx, H, W) ? acc[o] : T(0);
     }
-    for (int idx = threadIdx.x; idx < VR * VP; idx += kNT) {
+    for (int idx = threadIdx.x; idx < VR * VP; idx += kStepNT) {
         const int r = idx / VP, cc = idx - r * VP;
         s_p[idx] = s_rn[(r + 2 * c0 - 1) * CP + cc + 2 * c0 - 1];
     }
     __syncthreads();
     // TV weights of the flux sites (the Hessian pass's arithmetic, one channel)
     const T eps2 = (T)(I.pr.eps_tv * I.pr.eps_tv);
-    constexpr int NS = WR * WP, ITS = (NS + kNT - 1) / kNT;
+    constexpr int NS = WR * WP, ITS = (NS + kStepNT - 1) / kStepNT;
     // unrolled over the thread's sites with a clamped site index for the
     // reads, all reads before all stores
     T wk[ITS], mk[ITS];
 #pragma unroll
     for (int k = 0; k < ITS; ++k) {
-        const int idx = threadIdx.x + k * kNT;
+        const int idx = threadIdx.x + k * kStepNT;
         const int ic = idx < NS ? idx : NS - 1;
         const int r = ic / WP, cc = ic - r * WP;
         const int gi = ti0 - 1 + r, gj2 = tj0 - 1 + cc;
@@ -462,7 +479,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     }
 #pragma unroll
     for (int k = 0; k < ITS; ++k) {
-        const int idx = threadIdx.x + k * kNT;
+        const int idx = threadIdx.x + k * kStepNT;
         if (idx < NS) {
             s_w[idx] = wk[k];
             s_mw[idx] = mk[k];
@@ -521,11 +538,11 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     }
     double* __restrict__ wG = I.pR + (wsel ? nbf : 0);
     double* __restrict__ wD = I.pK + (wsel ? nbf : 0);
-    block_partial2(gs, wG, ds, wD, lb);
+    block_partial2<kStepNW>(gs, wG, ds, wD, lb);
 }
 
 template <typename T, int K, int R>
-__global__ __launch_bounds__(kNT) void k_cg_step(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
+__global__ __launch_bounds__(kStepNT) void k_cg_step(const Inst<T>* __restrict__ insts, const int* __restrict__ blk, int only,
                                                  const CgState* __restrict__ sin, CgState* __restrict__ sout) {
     const int ii = only >= 0 ? only : blk[blockIdx.x];
     const Inst<T>& I = insts[ii];

@@ -91,7 +91,7 @@ struct Team {
 // pass that follows, as on the multi-kernel path).  st: the state array
 // (read at the start, written at the end).
 template <typename T, int K, int R, bool STEP>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_team(
+__global__ __launch_bounds__(STEP ? kStepNT : kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_apg_team(
     const Inst<T>* __restrict__ insts, const int* __restrict__ list, int nlist, ApgState* __restrict__ st_arr,
     TeamCtl ctl, long max_slots) {
     Team tm(ctl);
@@ -99,14 +99,15 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         const int ii = list[j];
         const Inst<T>& I = insts[ii];
         ApgState st = st_arr[ii];
-        if (STEP && !st.done) {
-            // one-pass form: one pass (and one barrier) per iteration
-            for (long slot = 0;; ++slot) {
+        if constexpr (STEP) {
+            // one-pass form (blocks of kStepNT threads): one pass (and one
+            // barrier) per iteration
+            for (long slot = 0; !st.done; ++slot) {
                 ApgState nx = st;
                 for (int lb = tm.me; lb < I.nbf; lb += tm.P) {
                     nx = st;
                     __syncthreads();
-                    if constexpr (STEP) apg_step_body<T, K, R, true>(I, lb, nx, nullptr, lb == 0 && threadIdx.x == 0);
+                    apg_step_body<T, K, R, true>(I, lb, nx, nullptr, lb == 0 && threadIdx.x == 0);
                 }
                 st = nx;
                 if (st.done) break;
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
 // elementwise update pass of the multi-kernel path that covers the whole
 // batch then finds the instance finished and leaves it as it is.
 template <typename T, int K, int R, bool STEP>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_cg_team(
+__global__ __launch_bounds__(STEP ? kStepNT : kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T>(K, R)))) void k_cg_team(
     const Inst<T>* __restrict__ insts, const int* __restrict__ list, int nlist, CgState* __restrict__ st_arr,
     int n, TeamCtl ctl, long max_slots) {
     Team tm(ctl);
@@ -154,14 +155,15 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(min_waves<T
         const int ii = list[j];
         const Inst<T>& I = insts[ii];
         CgState st = st_arr[ii];
-        if (STEP && !st.done) {
-            // one-pass form (its priming pass first): one pass per iteration
-            for (long slot = 0;; ++slot) {
+        if constexpr (STEP) {
+            // one-pass form (its priming pass first; blocks of kStepNT
+            // threads): one pass per iteration
+            for (long slot = 0; !st.done; ++slot) {
                 CgState nx = st;
                 for (int lb = tm.me; lb < I.nbf; lb += tm.P) {
                     nx = st;
                     __syncthreads();
-                    if constexpr (STEP) cg_step_body<T, K, R, true>(I, lb, nx, nullptr, false);
+                    cg_step_body<T, K, R, true>(I, lb, nx, nullptr, false);
                 }
                 st = nx;
                 if (st.done) break;
