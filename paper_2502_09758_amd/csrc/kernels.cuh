@@ -151,6 +151,50 @@ template <int NW = 4> __device__ __forceinline__ void block_sum2(double& a, doub
     }
 }
 
+// Two grid-wide sums at the consumer, for blocks of any number of waves:
+// wave 0 alone has loaded and added the partials (lane l those at l, l + 64,
+// ..., with partials_issue / partials_local at 64 threads) and passes a, b
+// here; the wave sums go to every thread through LDS (one barrier).
+__device__ __forceinline__ void wave0_share2(double& a, double& b) {
+    __shared__ double s_sh[2];
+    if ((threadIdx.x >> 6) == 0) {
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (threadIdx.x == 0) {
+            s_sh[0] = a;
+            s_sh[1] = b;
+        }
+    }
+    __syncthreads();
+    a = s_sh[0];
+    b = s_sh[1];
+}
+// Two partials of a block of NW waves; only thread 0 needs the totals (it
+// stores them), so one barrier: the wave sums meet in LDS and thread 0 adds
+// them in wave order.
+template <int NW>
+__device__ __forceinline__ void block_partial2_1(double va, double* pa, double vb, double* pb, int lb) {
+    __shared__ double s_p2[2 * NW];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    va = wave_sum(va);
+    vb = wave_sum(vb);
+    if (lane == 0) {
+        s_p2[wid] = va;
+        s_p2[NW + wid] = vb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = s_p2[0], b = s_p2[NW];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            a += s_p2[w];
+            b += s_p2[NW + w];
+        }
+        pa[lb] = a;
+        pb[lb] = b;
+    }
+}
+
 // Producer side of a grid-wide sum: one partial per block (index lb within
 // its instance), plain store.
 __device__ __forceinline__ void block_partial(double v, double* part, int lb) {

@@ -82,9 +82,12 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     const double* __restrict__ rB = I.pB + (st.pp ? nbf : 0);
     double* __restrict__ wA = I.pA + (st.pp ? 0 : nbf);
     double* __restrict__ wB = I.pB + (st.pp ? 0 : nbf);
+    // wave 0 alone reads and adds the partials
     Partials pa, pb;
-    if (fresh) pa = partials_issue<CO, kStepNT>(rA, nbf);
-    if (!start) pb = partials_issue<CO, kStepNT>(rB, nbf);
+    if (wv == 0) {
+        if (fresh) pa = partials_issue<CO, 64>(rA, nbf);
+        if (!start) pb = partials_issue<CO, 64>(rB, nbf);
+    }
     int cur = st.cur, prev = st.prev;
     double mnext = st.m, tnext = st.t;
     if (!start) {
@@ -125,9 +128,12 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     stage_point(cur, prev, (T)mnext);
 
     // both sums of the previous pass with one pair of barriers
-    double gn2 = fresh ? partials_local<CO, kStepNT>(rA, nbf, pa) : 0.0;
-    double delta = start ? 0.0 : partials_local<CO, kStepNT>(rB, nbf, pb);
-    block_sum2<kStepNW>(gn2, delta);
+    double gn2 = 0.0, delta = 0.0;
+    if (wv == 0) {
+        gn2 = fresh ? partials_local<CO, 64>(rA, nbf, pa) : 0.0;
+        delta = start ? 0.0 : partials_local<CO, 64>(rB, nbf, pb);
+    }
+    wave0_share2(gn2, delta);
     if (fresh) {
         st.gn2 = gn2;
         st.nb_iter = 0;
@@ -279,7 +285,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
             if (lane_in && gi < H && oj < W) at(KXN, gi * W + oj) = dacc[o];
         }
     }
-    block_partial2<kStepNW>(gsq, wA, ddat + I.pr.alpha * dtv, wB, lb);
+    block_partial2_1<kStepNW>(gsq, wA, ddat + I.pr.alpha * dtv, wB, lb);
 }
 
 // One-pass FISTA launch over a group: block b -> (instance, local block) via
@@ -361,8 +367,10 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     const double* __restrict__ rD = I.pK + (par ? nbf : 0);
     Partials pg, pd;
     if (!prime) {
-        pg = partials_issue<CO, kStepNT>(rG, nbf);
-        pd = partials_issue<CO, kStepNT>(rD, nbf);
+        if (wv == 0) {
+            pg = partials_issue<CO, 64>(rG, nbf);
+            pd = partials_issue<CO, 64>(rD, nbf);
+        }
     }
     // the tile pixels' own values, loaded with the staging
     T rr[R], wr[R], pr_[R], qr[R];
@@ -382,9 +390,12 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
 
     double a = 0.0, beta = 0.0;
     if (!prime) {
-        double g = partials_local<CO, kStepNT>(rG, nbf, pg);
-        double d = partials_local<CO, kStepNT>(rD, nbf, pd);
-        block_sum2<kStepNW>(g, d);
+        double g = 0.0, d = 0.0;
+        if (wv == 0) {
+            g = partials_local<CO, 64>(rG, nbf, pg);
+            d = partials_local<CO, 64>(rD, nbf, pd);
+        }
+        wave0_share2(g, d);
         beta = first ? 0.0 : g / st.gamma;
         st.gamma = g;
         if (!finite_d(g)) {
@@ -538,7 +549,7 @@ __device__ __forceinline__ void cg_step_body(const Inst<T>& I, int lb, CgState& 
     }
     double* __restrict__ wG = I.pR + (wsel ? nbf : 0);
     double* __restrict__ wD = I.pK + (wsel ? nbf : 0);
-    block_partial2<kStepNW>(gs, wG, ds, wD, lb);
+    block_partial2_1<kStepNW>(gs, wG, ds, wD, lb);
 }
 
 template <typename T, int K, int R>
