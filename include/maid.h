@@ -177,8 +177,8 @@ int maid_autotune(maid_ctx* ctx, const void* const* theta, const void* const* y,
    stop and decrease tests move to the start of the next pass; the same
    decisions, iterates equal to rounding of the partial sums).  The
    autotuner chooses per K; untuned, the one-pass form is used for instances
-   of at most 640 of its tiles (about 380 x 380 for K = 9 at one row per
-   thread). */
+   of at most 320 of its tiles of 64 - (K - 1) columns by 8 rows (about
+   380 x 380 for K = 9 at one row per thread). */
 int maid_lower_solve(maid_ctx* ctx, const void* theta, const void* y, void* x,
                      double tol, int32_t max_iter, double* L_inout,
                      maid_solve_info* info, int32_t* trace_bt, hipStream_t stream);
