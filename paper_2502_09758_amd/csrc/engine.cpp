@@ -92,6 +92,20 @@ template <typename T> int upload(maid_ctx* c, int role, hipStream_t s, int roles
                                hipMemcpyHostToDevice, s));
     return MAID_OK;
 }
+// upload `roles` adjacent role tables starting at `role` and run the
+// preparation pass over the first of them (one launch with the upload kernel)
+template <typename T>
+int upload_prep(maid_ctx* c, int role, int roles, ApgState* Lst, CgState* Cst, int slot_abs, hipStream_t s) {
+    const size_t bytes = sizeof(Inst<T>) * c->n;
+    if (!c->upload_kernel) {
+        TRY(upload<T>(c, role, s, roles));
+        HIP_TRY(Ops<T>::prep_kernel(tab_dev<T>(c, role), c->n, Lst, Cst, slot_abs, s));
+        return MAID_OK;
+    }
+    HIP_TRY(Ops<T>::prep_upload(c->tab_host + role * bytes, c->tab_dev + role * bytes, roles, c->n, Lst, Cst,
+                                slot_abs, s));
+    return MAID_OK;
+}
 int publish(maid_ctx* c, hipStream_t s, const void* dev_ptr, size_t n);
 int pull_red(maid_ctx* c, hipStream_t s) { return publish(c, s, c->red, sizeof(double) * kRedSlots * c->n); }
 
@@ -724,8 +738,10 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
     }
     // the initial states travel in the table; the preparation pass copies them
     for (int i = 0; i < n; ++i) tab[i].st0 = c->apg_h[i];
-    TRY(upload<T>(c, ROLE_APG, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, c->apg[0], nullptr, -1, s));
+    {
+        ProfScope ps_(c, MAID_PROF_OTHER, s);
+        TRY(upload_prep<T>(c, ROLE_APG, 1, c->apg[0], nullptr, -1, s));
+    }
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, tabd, s));
     // each slot is one gradient pass and one trial pass; a slot advances every
     // unfinished solve by one iteration or by one backtracking step
@@ -877,8 +893,10 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         tab[i].theta64 = theta[i];
     }
     for (int i = 0; i < n; ++i) tab[i].cg0 = c->cg_h[i];
-    TRY(upload<T>(c, ROLE_CG, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(tabd, n, nullptr, c->cg[0], -1, s));
+    {
+        ProfScope ps_(c, MAID_PROF_OTHER, s);
+        TRY(upload_prep<T>(c, ROLE_CG, 1, nullptr, c->cg[0], -1, s));
+    }
     // r = rhs - H q0 (the direction pass in set-up mode copies q0 into q and p)
     CgState** S = c->cg;
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
@@ -1038,10 +1056,13 @@ int upper_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<cons
             t1[i].h1_w0 = M.d.h1_w0;
         }
     }
-    TRY(upload<T>(c, ROLE_CV0, s, 2));   // ROLE_CV0 and ROLE_CV1
     const Inst<T>* d0 = tab_dev<T>(c, ROLE_CV0);
     const Inst<T>* d1 = tab_dev<T>(c, ROLE_CV1);
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d0, n, nullptr, nullptr, kRedAbs, s));
+    {
+        // ROLE_CV0 and ROLE_CV1 go up; the first is prepared
+        ProfScope ps_(c, MAID_PROF_OTHER, s);
+        TRY(upload_prep<T>(c, ROLE_CV0, 2, nullptr, nullptr, kRedAbs, s));
+    }
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d0, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d1, s));
     LAUNCH(MAID_PROF_OTHER, Ops<T>::finish(d1, n, kRedGrad, kRedSob, s));
@@ -1089,10 +1110,13 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
         t3[i].cv_in = q[i];
         t3[i].cv_out = (T*)M.tmp1;
     }
-    TRY(upload<T>(c, ROLE_CV2, s, 2));   // ROLE_CV2 and ROLE_CV3
     const Inst<T>* d2 = tab_dev<T>(c, ROLE_CV2);
     const Inst<T>* d3 = tab_dev<T>(c, ROLE_CV3);
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::prep_kernel(d2, n, nullptr, nullptr, -1, s));
+    {
+        // ROLE_CV2 and ROLE_CV3 go up; the first is prepared
+        ProfScope ps_(c, MAID_PROF_OTHER, s);
+        TRY(upload_prep<T>(c, ROLE_CV2, 2, nullptr, nullptr, -1, s));
+    }
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d2, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d3, s));
     for (int i = 0; i < n; ++i) {

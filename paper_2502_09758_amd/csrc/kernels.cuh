@@ -1453,9 +1453,24 @@ __global__ __launch_bounds__(kNT) void k_cg_init(const Inst<T>* __restrict__ ins
 // starting Lipschitz estimate when the initial one is <= 0; red[slot_abs]
 // receives the l1 norm when slot_abs >= 0.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* __restrict__ insts, ApgState* __restrict__ Lst,
-                                                      CgState* __restrict__ Cst, int slot_abs) {
+__global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* insts, ApgState* __restrict__ Lst,
+                                                      CgState* __restrict__ Cst, int slot_abs,
+                                                      const unsigned* __restrict__ up_src, unsigned* up_dst,
+                                                      int up_roles) {
     __shared__ double s_abs[1024];
+    if (up_src) {
+        // the table upload: block b copies entry b of each of up_roles
+        // adjacent role tables (gridDim.x entries each) from mapped host
+        // memory; insts is the first of those tables on the device
+        constexpr int IW = (int)(sizeof(Inst<T>) / 4);
+        static_assert(sizeof(Inst<T>) % 4 == 0, "instance entries are whole words");
+        for (int w = threadIdx.x; w < up_roles * IW; w += 1024) {
+            const int r = w / IW, k = w - r * IW;
+            const size_t o = ((size_t)r * gridDim.x + blockIdx.x) * IW + k;
+            up_dst[o] = up_src[o];
+        }
+        __syncthreads();
+    }
     const Inst<T>& I = insts[blockIdx.x];
     if (threadIdx.x == 0) {
         if (Lst) put_state(&Lst[blockIdx.x], I.st0);

@@ -68,6 +68,11 @@ inline int step_blocks(int H, int W, int K, int R) {
 template <typename T> struct Ops {
     static hipError_t prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, CgState* Cst, int slot_abs,
                                   hipStream_t s);
+    // the same, with the upload of `roles` adjacent role tables (n entries
+    // each) from mapped host memory src_host to dst folded in; the pass
+    // prepares the instances of the first of them
+    static hipError_t prep_upload(const void* src_host, void* dst, int roles, int n, ApgState* Lst, CgState* Cst,
+                                  int slot_abs, hipStream_t s);
     static hipError_t finish(const Inst<T>* insts, int n, int slot, int sob_slot, hipStream_t s);
     static hipError_t conv(const Group& g, const Inst<T>* insts, hipStream_t s);
     static hipError_t apg_grad(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s);

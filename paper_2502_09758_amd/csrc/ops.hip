@@ -54,7 +54,14 @@ __global__ __launch_bounds__(1024) void k_sobolev(double beta, double h1_w0, con
 template <typename T>
 hipError_t Ops<T>::prep_kernel(const Inst<T>* insts, int n, ApgState* Lst, CgState* Cst, int slot_abs,
                                hipStream_t s) {
-    return launch(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, Cst, slot_abs);
+    return launch(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, insts, Lst, Cst, slot_abs, (const unsigned*)nullptr,
+                  (unsigned*)nullptr, 0);
+}
+template <typename T>
+hipError_t Ops<T>::prep_upload(const void* src_host, void* dst, int roles, int n, ApgState* Lst, CgState* Cst,
+                               int slot_abs, hipStream_t s) {
+    return launch(k_prep_kernel<T>, dim3(n), dim3(1024), 0, s, (const Inst<T>*)dst, Lst, Cst, slot_abs,
+                  (const unsigned*)src_host, (unsigned*)dst, roles);
 }
 
 template <typename T>
