@@ -485,7 +485,11 @@ int relayout(maid_ctx* c) {
             std::snprintf(buf, sizeof(buf), " team=%d", lg.team);
             c->cfg += buf;
         }
-        if (lg.g.grid_f > 0) c->cfg += " one-pass";
+        if (lg.g.grid_f > 0) {
+            // the one-pass passes run on blocks of kStepNW waves
+            std::snprintf(buf, sizeof(buf), " one-pass(tile=%dx%d)", kTW, kStepNW * lg.g.R);
+            c->cfg += buf;
+        }
         if (lg.g.cg1) c->cfg += " cg-one-pass";
     }
     return MAID_OK;
