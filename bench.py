@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-vs-plain comparison")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="pin the tile height (rows per thread) instead of running the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs on a single MI355X (asked for --gpus {args.gpus}).",
@@ -351,7 +353,11 @@ def main():
         return MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=ms["eps0"], delta=ms["eps0"],
                          step=ms["step0"])
 
-    tuned_rows = m.autotune(a, y)
+    if args.rows:
+        m.set_tile_rows(args.rows)
+        tuned_rows = f"pinned {args.rows}"
+    else:
+        tuned_rows = m.autotune(a, y)
     hp = dict(eps_min=1e-6)
     state = fresh()
     restarts = 0
