@@ -1619,15 +1619,27 @@ __global__ __launch_bounds__(1024) void k_hg_final(double beta, double h1_w0, co
                                                    double* __restrict__ z, double* __restrict__ znorm2) {
     __shared__ double s_e[1024];
     __shared__ double s_z[1024];
+    __shared__ double s_g[1024];
     const int t = threadIdx.x, KK = K * K;
     if (t < KK) s_e[t] = (with_r && a) ? th[t] - a[t] : 0.0;
+    // the sum over the correlation blocks: G = 1024 / K^2 threads per tap,
+    // thread (g, tap) adds blocks g, g + G, ... in order, then the tap's
+    // thread adds the G sums in order (a fixed order for every launch)
+    const int G = KK <= 1024 ? 1024 / KK : 1;
+    if (t < G * KK) {
+        const int g = t / KK, tap = t - g * KK;
+        const int u = tap / K, v = tap - u * K;
+        double sg = 0.0;
+#pragma unroll 4
+        for (int bidx = g; bidx < nblk; bidx += G) sg += part[(size_t)bidx * KT * KT + u * KT + v];
+        s_g[t] = sg;
+    }
     __syncthreads();
     double zz = 0.0;
     if (t < KK) {
         const int u = t / K, v = t - u * K;
-        double s = 0.0;
-#pragma unroll 8
-        for (int bidx = 0; bidx < nblk; ++bidx) s += part[(size_t)bidx * KT * KT + u * KT + v];
+        double s = s_g[t];
+        for (int g = 1; g < G; ++g) s += s_g[g * KK + t];
         double gr = 0.0;
         if (with_r && a) {
             // D^T D e with Neumann differences = sum over in-grid neighbours of (e - e_nb)
