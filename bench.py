@@ -172,8 +172,8 @@ def inexact_gradient_work(insts, dt, tol_lower=1e-3, tol_cg=1e-3):
     InexactGradient (lower-level solve to tol_lower, upper-level gradient, CG
     to tol_cg, hypergradient) for every instance of a ragged batch, once
     through one batched context and once through one plain context per
-    instance (same tile heights, so the same iterations and bitwise the same
-    results).  Pixel-iterations count (lower + CG iterations) x C*H*W."""
+    instance (same tile heights and lower-level forms, so the same
+    iterations and bitwise the same results).  Pixel-iterations count (lower + CG iterations) x C*H*W."""
     import torch
     from paper_2502_09758_amd import _lib as L
     from paper_2502_09758_amd.maid import Maid, MaidBatch
@@ -183,10 +183,12 @@ def inexact_gradient_work(insts, dt, tol_lower=1e-3, tol_cg=1e-3):
     ys = [torch.tensor(i.y, dtype=dt, device="cuda") for i in insts]
     mb = MaidBatch(specs, dt)
     rows = mb.autotune(th, ys)
+    forms = mb.one_pass_forms()
     solos = []
     for k, i in enumerate(insts):
         m = Maid(i.C, i.H, i.W, i.K, dt, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta)
         m.set_tile_rows(rows[k])
+        m.set_one_pass(forms[k])
         solos.append(m)
     n = len(insts)
 

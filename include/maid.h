@@ -148,6 +148,16 @@ int maid_set_team(maid_ctx* ctx, int32_t members);
    (measured at equal iteration counts: FP64, 30-50 iterations, <= 1.6e-6
    relative against <= 1e-6; FP32, 83 iterations, 2.2e-5 against 4.7e-5). */
 int maid_set_one_pass_cg(maid_ctx* ctx, int32_t enable);
+/* Lower-level form of the instances that can take the one-pass form (one
+   channel, 3 <= K <= 11, tile rows <= 4): mode -1 (the default) = the
+   autotuner's choice where it ran, else the size rule; 0 = two passes per
+   iteration; 1 = one pass.  With the same tile rows and form, an instance
+   computes bitwise the same in any context (alone or in any batch).
+   MAID_EINVAL for another mode. */
+int maid_set_one_pass(maid_ctx* ctx, int32_t mode);
+/* out[i] (HOST, maid_batch_size entries) = 1 if instance i runs the
+   one-pass lower-level form under the context's current layout, else 0. */
+int maid_one_pass_forms(const maid_ctx* ctx, int32_t* out);
 /* Autotuner: for each group of instances with the same K, time a short
    lower-level solve and a short CG solve (probe_iters iterations each,
    1..1000, tolerance 0) with every rows-per-thread candidate on

@@ -117,6 +117,19 @@ int maid_set_tile_rows(maid_ctx* c, int32_t rows) {
     return relayout(c);
 }
 
+int maid_set_one_pass(maid_ctx* c, int32_t mode) {
+    if (!c) return MAID_EINVAL;
+    if (mode < -1 || mode > 1) return fail(c, MAID_EINVAL, "mode must be -1 (tuned or size rule), 0 or 1");
+    c->fuse_pin = mode;
+    return relayout(c);
+}
+
+int maid_one_pass_forms(const maid_ctx* c, int32_t* out) {
+    if (!c || !out) return MAID_EINVAL;
+    for (int i = 0; i < c->n; ++i) out[i] = c->m[i].nbf > 0 ? 1 : 0;
+    return MAID_OK;
+}
+
 int maid_set_one_pass_cg(maid_ctx* c, int32_t enable) {
     if (!c) return MAID_EINVAL;
     c->cg_fuse = enable != 0;

@@ -380,6 +380,7 @@ int relayout(maid_ctx* c) {
         // halo gradient loads further)
         bool fuse = c->fuse && step_ok(M.d.C, M.d.K, M.R);
         if (c->fuse_force >= 0) fuse = fuse && c->fuse_force == 1;
+        else if (c->fuse_pin >= 0) fuse = fuse && c->fuse_pin == 1;
         else if (M.fuse_tuned >= 0) fuse = fuse && M.fuse_tuned == 1;
         else fuse = fuse && step_blocks(M.d.H, M.d.W, M.d.K, M.R) <= kStepTiles;
         M.nbf = fuse ? step_blocks(M.d.H, M.d.W, M.d.K, M.R) : 0;

@@ -126,6 +126,7 @@ struct maid_ctx {
     bool fuse = true;                 // one-pass FISTA where the group allows it
     bool cg_fuse = true;              // one-pass (Chronopoulos-Gear) CG on the one-pass instances
     int fuse_force = -1;              // autotuner's candidate: -1 none, 0 two-pass, 1 one-pass
+    int fuse_pin = -1;                // the caller's choice (maid_set_one_pass): -1 none, 0, 1
     int team_req = -1;                // members per team: -1 size rule, 0 never, > 0 that many (capped)
     bool team_ok = false;             // blocks reach the XCDs round-robin and XCC_ID reads them
     int cus_per_xcd = 0;

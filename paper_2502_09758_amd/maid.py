@@ -119,6 +119,18 @@ class Maid:
         """Opt in to the one-pass (Chronopoulos-Gear) CG on one-pass instances."""
         self._check(L.lib().maid_set_one_pass_cg(self.handle, int(bool(enable))), "set_one_pass_cg")
 
+    def set_one_pass(self, mode: int):
+        """Lower-level form where the one-pass form applies: -1 tuned or size
+        rule (default), 0 two-pass, 1 one-pass."""
+        self._check(L.lib().maid_set_one_pass(self.handle, int(mode)), "set_one_pass")
+
+    def one_pass_forms(self):
+        """Per instance: 1 if it runs the one-pass lower-level form."""
+        n = int(L.lib().maid_batch_size(self.handle))
+        out = (ct.c_int32 * max(1, n))()
+        self._check(L.lib().maid_one_pass_forms(self.handle, out), "one_pass_forms")
+        return [int(out[i]) for i in range(n)]
+
     def set_team(self, members: int):
         """Members per team of the persistent loops: -1 size rule, 0 off."""
         self._check(L.lib().maid_set_team(self.handle, int(members)), "set_team")
@@ -250,6 +262,8 @@ class MaidBatch:
     set_tile_rows = Maid.set_tile_rows
     set_team = Maid.set_team
     set_one_pass_cg = Maid.set_one_pass_cg
+    set_one_pass = Maid.set_one_pass
+    one_pass_forms = Maid.one_pass_forms
     profile = Maid.profile
     profile_read = Maid.profile_read
     _check = Maid._check

@@ -185,3 +185,41 @@ def test_one_pass_cg_matches_hestenes_stiefel(dt, shape, reg):
         assert ci.res_norm <= tol
         err = float((q - ref[3]).norm() / ref[3].norm())
         assert err <= (1e-3 if dt == torch.float32 else 1e-5), (one_pass, rows, err)
+
+
+def test_form_pin_and_query_give_solo_equals_batch():
+    """maid_set_one_pass pins the lower-level form, maid_one_pass_forms reports
+    it per instance, and a solo context given a batch's tile rows and forms
+    computes bitwise what the batch computes, whatever the size rule says."""
+    print("[case] form pin and query", flush=True)
+    shapes = [(1, 80, 90, 5), (1, 200, 260, 9), (3, 60, 60, 7), (1, 50, 200, 9)]
+    insts = [synth.make("cfg1", H=H, W=W, C=C, K=K, seed=700 + i) for i, (C, H, W, K) in enumerate(shapes)]
+    specs = [dict(C=i.C, H=i.H, W=i.W, K=i.K, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta) for i in insts]
+    th = [dev(i.a, torch.float64) for i in insts]
+    ys = [dev(i.y, torch.float32) for i in insts]
+    for mode in (0, 1):
+        mb = MaidBatch(specs, torch.float32)
+        mb.set_tile_rows(2)
+        mb.set_one_pass(mode)
+        forms = mb.one_pass_forms()
+        # the 3-channel instance never takes the one-pass form
+        assert forms == ([0, 0, 0, 0] if mode == 0 else [1, 1, 0, 1]), forms
+        xs = [y.clone() for y in ys]
+        rc, infos = mb.lower_solve(th, ys, xs, [1e-4] * len(insts), max_iter=300)
+        assert rc in (L.OK, L.MAXITER)
+        for k, inst in enumerate(insts):
+            m = Maid(inst.C, inst.H, inst.W, inst.K, torch.float32, alpha=inst.alpha, eps_tv=inst.eps_tv,
+                     beta=inst.beta)
+            m.set_tile_rows(2)
+            m.set_one_pass(forms[k])
+            assert m.one_pass_forms() == [forms[k]]
+            x = ys[k].clone()
+            info = m.lower_solve(th[k], ys[k], x, 1e-4, max_iter=300)
+            assert (info.iters, info.backtracks, info.L) == (infos[k].iters, infos[k].backtracks, infos[k].L)
+            assert torch.equal(x, xs[k]), f"mode {mode}, instance {k}"
+            m.close()
+        mb.close()
+    m = Maid(1, 40, 40, 5, torch.float32)
+    with pytest.raises(L.MaidError):
+        m.set_one_pass(2)
+    m.close()
