@@ -303,7 +303,8 @@ int run_slots(maid_ctx* c, int kind, long want, hipStream_t s, F enqueue) {
 // Algorithm 2 need similar counts; a slot past the end costs two early-exit
 // launches, a few microseconds, while a look costs a host round trip with
 // the GPU drained; measured at 256 x 256, K = 9: 100 % beats 75 % by ~5 %
-// per MAID step and 50 % by ~12 %), then steps of an eighth of it; with no
+// per MAID step and 50 % by ~12 %; for the CG solves alone 100 % beats 75 %
+// by ~7 % and 125 % by ~5 %), then steps of an eighth of it; with no
 // history 1, 2, 4, ...
 long next_slots(long pred, long done_so_far, long last, int first_pct) {
     if (done_so_far == 0) return pred > 0 ? std::max(1L, pred * first_pct / 100) : 1;
@@ -622,6 +623,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     if (const char* f = std::getenv("MAID_CG_ONE_PASS")) c->cg_fuse = std::strcmp(f, "0") != 0;
     if (const char* u = std::getenv("MAID_UPLOAD_KERNEL")) c->upload_kernel = std::strcmp(u, "0") != 0;
     if (const char* u = std::getenv("MAID_PRED_FIRST")) c->pred_first = std::max(1, std::min(400, std::atoi(u)));
+    if (const char* u = std::getenv("MAID_PRED_FIRST_CG")) c->pred_first_cg = std::max(1, std::min(400, std::atoi(u)));
     // longest wait at a team barrier, in wall-clock ticks (0 forces the
     // multi-kernel fallback, for tests)
     if (const char* w = std::getenv("MAID_TEAM_WAIT")) c->team_wait = std::max(0LL, std::atoll(w));
@@ -934,7 +936,7 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         const long pred = std::min(c->pred_slots[3], (long)max_iter + 1);
         long slots = 0, chunk = 0;
         for (;;) {
-            chunk = next_slots(pred, slots, chunk, c->pred_first);
+            chunk = next_slots(pred, slots, chunk, c->pred_first_cg);
             // one-pass groups take two iterations per slot (state there and back)
             int rc = run_slots(c, G_CG, chunk, s, [&](hipStream_t s, int cnt) {
                 for (int k = 0; k < cnt; ++k) {

@@ -138,6 +138,7 @@ struct maid_ctx {
     bool in_step = false;             // inside a MAID step: solves need not drain the stream at their end
     bool upload_kernel = true;        // tables go up by a copy kernel reading mapped host memory
     int pred_first = 100;             // first chunk of a solve: this percentage of the predicted slots
+    int pred_first_cg = 100;          // the same for the CG solves
     int kx_resync = 16;               // exact theta*x every kx_resync iterations (twice in a row)
     // slots the last solve of each kind needed (sizes the first chunk of the
     // next): lower level for callers, for Algorithm 2's InexactGradient and
