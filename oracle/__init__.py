@@ -71,7 +71,14 @@ class om_step_info(ct.Structure):
     _fields_ = [("accepted", ct.c_int32), ("trials", ct.c_int32), ("retries", ct.c_int32),
                 ("lower_iters", ct.c_int32), ("cg_iters", ct.c_int32), ("status", ct.c_int32),
                 ("psi", ct.c_double), ("ell_k", ct.c_double), ("ell_next", ct.c_double),
-                ("znorm", ct.c_double)]
+                ("znorm", ct.c_double), ("lower_status", ct.c_int32), ("cg_status", ct.c_int32)]
+
+
+class om_trace(ct.Structure):
+    _fields_ = [("replay", ct.POINTER(ct.c_int32)), ("n_replay", ct.c_int32),
+                ("words", ct.POINTER(ct.c_int32)), ("values", ct.POINTER(ct.c_double)),
+                ("cap_words", ct.c_int32), ("cap_values", ct.c_int32),
+                ("n_words", ct.c_int32), ("n_values", ct.c_int32)]
 
 
 _lib = None
@@ -117,6 +124,9 @@ def lib():
         L.oracle_maid_step.argtypes = [P, d, d, ct.POINTER(om_state), ct.POINTER(om_hparams),
                                        ct.POINTER(om_step_info)]
         L.oracle_maid_step.restype = ct.c_int
+        L.oracle_maid_step_traced.argtypes = [P, d, d, ct.POINTER(om_state), ct.POINTER(om_hparams),
+                                              ct.POINTER(om_step_info), ct.POINTER(om_trace)]
+        L.oracle_maid_step_traced.restype = ct.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ct.c_int
         _lib = L
@@ -322,6 +332,60 @@ def maid_step(p: Problem, a, y, state: MaidState, **hp):
                                 ct.byref(st), ct.byref(hpc), ct.byref(info))
     state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
     return rc, {f: getattr(info, f) for f, _ in om_step_info._fields_}
+
+
+def maid_step_traced(p: Problem, a, y, state: MaidState, replay=None, cap=1 << 20, **hp):
+    """One Algorithm 2 step with its decision trace (record layout in
+    maid_oracle.h).  replay: None (free-running, the oracle's own decisions)
+    or the words of a trace to follow.  Returns (rc, info, words, values):
+    the trace written by this step (with the oracle's own values)."""
+    h = dict(DEFAULT_HPARAMS)
+    h.update(hp)
+    hpc = om_hparams(**h)
+    st = om_state(_d(state.theta), _d(state.x), _d(state.q), state.eps, state.delta, state.step,
+                  state.L, state.k)
+    info = om_step_info()
+    words = np.zeros(cap, dtype=np.int32)
+    values = np.zeros(cap, dtype=np.float64)
+    tr = om_trace(None, 0, words.ctypes.data_as(ct.POINTER(ct.c_int32)), _d(values), cap, cap, 0, 0)
+    if replay is not None:
+        rp = np.ascontiguousarray(replay, dtype=np.int32)
+        tr.replay = rp.ctypes.data_as(ct.POINTER(ct.c_int32))
+        tr.n_replay = len(rp)
+    rc = lib().oracle_maid_step_traced(ct.byref(p.c()), _d(_f64(a, (p.K, p.K))), _d(_f64(y, p.shape)),
+                                       ct.byref(st), ct.byref(hpc), ct.byref(info), ct.byref(tr))
+    state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
+    return (rc, {f: getattr(info, f) for f, _ in om_step_info._fields_},
+            words[:tr.n_words].copy(), values[:tr.n_values].copy())
+
+
+TRACE_RECORD_VALUES = {1: 2, 2: 3, 3: 1, 4: 1, 5: 1}
+
+
+def split_trace(words, values):
+    """Split a decision trace into records: a list of (words, values)
+    tuples, one per solve, evaluation or test, in order."""
+    out, wi, vi = [], 0, 0
+    words = list(words)
+    while wi < len(words):
+        kind = words[wi]
+        if kind == 1:
+            n = 4 + words[wi + 2]
+        elif kind == 2:
+            n = 2
+        elif kind == 3:
+            n = 3
+        elif kind == 4:
+            n = 1
+        elif kind == 5:
+            n = 2
+        else:
+            raise ValueError(f"bad trace record kind {kind} at word {wi}")
+        nv = TRACE_RECORD_VALUES[kind]
+        out.append((words[wi:wi + n], list(values[vi:vi + nv])))
+        wi += n
+        vi += nv
+    return out
 
 
 def _idx(idx):

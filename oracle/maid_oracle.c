@@ -539,10 +539,91 @@ void oracle_hypergrad(const om_problem* p, const double* th, const double* a, co
  *   psi = l(u') + ||grad_x l(u')|| e + L_g/2 e^2 - l(u_k) + ||grad_x l(u_k)|| e + lambda s ||z||^2
  * where l = g + r, grad_x l = grad g, and the trial lower-level solution u'
  * is solved at the current accuracy e = eps_k.
+ *
+ * Decision trace (om_trace, see the header): free-running, the step records
+ * what it decided; with a replay trace it takes every decision from there
+ * (iterations and rejected trials of each lower-level solve, iterations of
+ * each CG solve, acceptance of each psi test) and records its own values
+ * beside the same words.
  * ---------------------------------------------------------------------- */
-int oracle_maid_step(const om_problem* p, const double* a, const double* y, om_state* st,
-                     const om_hparams* hp, om_step_info* info) {
+typedef struct {
+    om_trace* t;
+    int32_t rp;        /* read position in t->replay */
+    int bad;           /* replay trace malformed or a buffer too small */
+} tracer;
+
+static void tr_word(tracer* T, int32_t w) {
+    if (!T->t || !T->t->words) return;
+    if (T->t->n_words >= T->t->cap_words) { T->bad = 1; return; }
+    T->t->words[T->t->n_words++] = w;
+}
+static void tr_value(tracer* T, double v) {
+    if (!T->t || !T->t->values) return;
+    if (T->t->n_values >= T->t->cap_values) { T->bad = 1; return; }
+    T->t->values[T->t->n_values++] = v;
+}
+static int replaying(const tracer* T) { return T->t && T->t->replay; }
+static int32_t rd(tracer* T) {
+    if (T->rp >= T->t->n_replay) { T->bad = 1; return 0; }
+    return T->t->replay[T->rp++];
+}
+
+/* one lower-level solve (role 0: InexactGradient at theta_k, 1: psi trial) */
+static int traced_lower(const om_problem* p, const double* th, const double* y, double* x, double tol,
+                        int32_t max_iter, double* L, om_solve_info* li, tracer* T, int role) {
+    int st;
+    if (replaying(T)) {
+        int32_t kind = rd(T), rl = rd(T), iters = rd(T), status = rd(T);
+        if (kind != 1 || rl != role || iters < 0 || T->rp + iters > T->t->n_replay) { T->bad = 1; return OM_EINVAL; }
+        const int32_t* bt = T->t->replay + T->rp;
+        T->rp += iters;
+        oracle_lower_solve(p, th, y, x, 0.0, iters, L, li, iters > 0 ? bt : NULL, NULL);
+        li->status = status;
+        st = status;
+        tr_word(T, 1); tr_word(T, role); tr_word(T, iters); tr_word(T, status);
+        for (int32_t n = 0; n < iters; ++n) tr_word(T, bt[n]);
+    } else {
+        int32_t* bt = (T->t && T->t->words) ? (int32_t*)calloc((size_t)max_iter + 1, sizeof(int32_t)) : NULL;
+        st = oracle_lower_solve(p, th, y, x, tol, max_iter, L, li, NULL, bt);
+        tr_word(T, 1); tr_word(T, role); tr_word(T, li->iters); tr_word(T, li->status);
+        if (bt) for (int32_t n = 0; n < li->iters; ++n) tr_word(T, bt[n]);
+        free(bt);
+    }
+    tr_value(T, li->res_norm);
+    tr_value(T, *L);
+    return st;
+}
+
+static int traced_cg(const om_problem* p, const double* th, const double* xt, const double* rhs, double* q,
+                     double tol, int32_t max_iter, om_solve_info* ci, tracer* T) {
+    int st;
+    if (replaying(T)) {
+        int32_t kind = rd(T), iters = rd(T), status = rd(T);
+        if (kind != 3 || iters < 0) { T->bad = 1; return OM_EINVAL; }
+        st = oracle_adjoint_solve(p, th, xt, rhs, q, 0.0, iters, ci, NULL);
+        if (st != OM_NOT_SPD) { st = status; ci->status = status; }
+    } else {
+        st = oracle_adjoint_solve(p, th, xt, rhs, q, tol, max_iter, ci, NULL);
+    }
+    tr_word(T, 3); tr_word(T, ci->iters); tr_word(T, ci->status);
+    tr_value(T, ci->res_norm);
+    return st;
+}
+
+static void traced_upper(tracer* T, int role, double g, double gn, double r) {
+    if (replaying(T)) {
+        int32_t kind = rd(T), rl = rd(T);
+        if (kind != 2 || rl != role) T->bad = 1;
+    }
+    tr_word(T, 2); tr_word(T, role);
+    tr_value(T, g); tr_value(T, gn); tr_value(T, r);
+}
+
+int oracle_maid_step_traced(const om_problem* p, const double* a, const double* y, om_state* st,
+                            const om_hparams* hp, om_step_info* info, om_trace* trace) {
     if (!p || !a || !y || !st || !hp || !st->theta || !st->x || !st->q) return OM_EINVAL;
+    tracer T = {trace, 0, 0};
+    if (trace) { trace->n_words = 0; trace->n_values = 0; }
     const int64_t N = npix(p);
     const int KK = p->K * p->K;
     double *xt = dalloc(N), *xs = dalloc(N), *G = dalloc(N), *q = dalloc(N);
@@ -557,16 +638,25 @@ int oracle_maid_step(const om_problem* p, const double* a, const double* y, om_s
     for (;;) {
         /* InexactGradient(theta_k, eps_k, delta_k) */
         om_solve_info li, ci;
-        oracle_lower_solve(p, st->theta, y, xt, st->eps * hp->mu, hp->max_lower_iter, &st->L, &li, NULL, NULL);
+        int ls = traced_lower(p, st->theta, y, xt, st->eps * hp->mu, hp->max_lower_iter, &st->L, &li, &T, 0);
+        if (T.bad) { status = OM_EINVAL; break; }
         I.lower_iters += li.iters;
+        if (ls == OM_MAXITER) I.lower_status = OM_MAXITER;
         double g_k, n_k;
         oracle_upper_value_grad(p, a, y, xt, G, &g_k, &n_k);
-        const double ell_k = g_k + oracle_sobolev_value(p, st->theta, a);
-        int cs = oracle_adjoint_solve(p, st->theta, xt, G, q, st->delta, hp->max_cg_iter, &ci, NULL);
+        const double r_k = oracle_sobolev_value(p, st->theta, a);
+        const double ell_k = g_k + r_k;
+        traced_upper(&T, 0, g_k, n_k, r_k);
+        int cs = traced_cg(p, st->theta, xt, G, q, st->delta, hp->max_cg_iter, &ci, &T);
+        if (T.bad) { status = OM_EINVAL; break; }
         I.cg_iters += ci.iters;
         if (cs == OM_NOT_SPD) { status = OM_NOT_SPD; break; }
+        if (cs == OM_MAXITER) I.cg_status = OM_MAXITER;
         double znorm;
         oracle_hypergrad(p, st->theta, a, y, xt, q, 1, z, &znorm);
+        if (replaying(&T) && rd(&T) != 4) { status = OM_EINVAL; break; }
+        tr_word(&T, 4);
+        tr_value(&T, znorm);
         I.ell_k = ell_k;
         I.znorm = znorm;
         /* backtracking on the step size */
@@ -574,18 +664,29 @@ int oracle_maid_step(const om_problem* p, const double* a, const double* y, om_s
         for (int i = 0; i < j; ++i) {
             for (int t = 0; t < KK; ++t) th2[t] = st->theta[t] - st->step * z[t];
             memcpy(xs, xt, N * sizeof(double));
-            oracle_lower_solve(p, th2, y, xs, st->eps * hp->mu, hp->max_lower_iter, &st->L, &li, NULL, NULL);
+            ls = traced_lower(p, th2, y, xs, st->eps * hp->mu, hp->max_lower_iter, &st->L, &li, &T, 1);
+            if (T.bad) break;
             I.lower_iters += li.iters;
+            if (ls == OM_MAXITER) I.lower_status = OM_MAXITER;
             double g_n, n_n;
             oracle_upper_value_grad(p, a, y, xs, NULL, &g_n, &n_n);
-            const double ell_n = g_n + oracle_sobolev_value(p, th2, a);
+            const double r_n = oracle_sobolev_value(p, th2, a);
+            const double ell_n = g_n + r_n;
+            traced_upper(&T, 1, g_n, n_n, r_n);
             const double e = st->eps;
             const double psi = ell_n + n_n * e + 0.5 * Lg * e * e - ell_k + n_k * e
                              + hp->lambda * st->step * znorm * znorm;
             I.trials += 1;
             I.psi = psi;
             I.ell_next = ell_n;
-            if (psi <= 0.0) {
+            int acc = psi <= 0.0;
+            if (replaying(&T)) {
+                if (rd(&T) != 5) { T.bad = 1; break; }
+                acc = rd(&T) != 0;
+            }
+            tr_word(&T, 5); tr_word(&T, acc);
+            tr_value(&T, psi);
+            if (acc) {
                 memcpy(st->theta, th2, KK * sizeof(double));
                 memcpy(xt, xs, N * sizeof(double));
                 st->eps *= hp->nu_hi;
@@ -597,6 +698,7 @@ int oracle_maid_step(const om_problem* p, const double* a, const double* y, om_s
             }
             st->step *= hp->rho_lo;
         }
+        if (T.bad) { status = OM_EINVAL; break; }
         if (accepted) { I.accepted = 1; break; }
         st->eps *= hp->nu_lo;
         st->delta *= hp->nu_lo;
@@ -606,10 +708,16 @@ int oracle_maid_step(const om_problem* p, const double* a, const double* y, om_s
     }
     memcpy(st->x, xt, N * sizeof(double));
     memcpy(st->q, q, N * sizeof(double));
+    if (status == OM_OK && (I.lower_status == OM_MAXITER || I.cg_status == OM_MAXITER)) status = OM_MAXITER;
     I.status = status;
     if (info) *info = I;
     free(xt); free(xs); free(G); free(q); free(z); free(th2);
     return status;
+}
+
+int oracle_maid_step(const om_problem* p, const double* a, const double* y, om_state* st,
+                     const om_hparams* hp, om_step_info* info) {
+    return oracle_maid_step_traced(p, a, y, st, hp, info, NULL);
 }
 
 /* ------------------------------------------------------------------------

@@ -65,6 +65,12 @@ typedef struct {
 typedef struct {
     int32_t accepted, trials, retries, lower_iters, cg_iters, status;
     double psi, ell_k, ell_next, znorm;
+    /* worst status (OM_OK or OM_MAXITER) of the step's lower-level solves and
+       of its CG solves: a solve that stops at its iteration cap is carried on
+       with (Section 4.1 reports the lower-level cap as never reached) and
+       flagged here, and the step then returns OM_MAXITER unless it ends in
+       another non-OK state */
+    int32_t lower_status, cg_status;
 } om_step_info;
 
 enum { OM_OK = 0, OM_MAXITER = 1, OM_ACCURACY_FLOOR = 2, OM_EINVAL = -1, OM_NOT_SPD = -4 };
@@ -101,6 +107,34 @@ void oracle_hypergrad(const om_problem*, const double* th, const double* a, cons
 /* Alg. 2: one outer step (the for-j retry loop and the accepted update). */
 int oracle_maid_step(const om_problem*, const double* a, const double* y, om_state* st,
                      const om_hparams* hp, om_step_info* info);
+
+/* Decision trace of one Algorithm 2 step, in the order the work happens.
+   Records (int32 words; FP64 values beside them):
+     lower-level solve  words 1, role, iters, status, rejected trials of each
+                        of the iters iterations;  values ||grad h||, L after
+                        (role 0: the InexactGradient solve at theta_k,
+                         role 1: a psi trial solve at theta')
+     upper level        words 2, role;            values g, ||grad g||, r(theta)
+     CG solve           words 3, iters, status;   values recursive residual norm
+     hypergradient      words 4;                  values ||z||
+     psi test           words 5, accepted;        values psi
+   Free-running (replay == NULL) the step records its own decisions.  With a
+   replay trace it takes every decision from there instead (each lower solve
+   runs exactly `iters` iterations rejecting the recorded trials, each CG
+   solve exactly `iters` iterations, each psi test takes the recorded
+   acceptance) and records the same words with its own values, so the two
+   traces can be compared value by value.  A malformed replay trace or a
+   full buffer makes the step return OM_EINVAL. */
+typedef struct {
+    const int32_t* replay;    /* nullable */
+    int32_t n_replay;
+    int32_t* words;           /* nullable: no recording */
+    double* values;
+    int32_t cap_words, cap_values;
+    int32_t n_words, n_values;   /* out */
+} om_trace;
+int oracle_maid_step_traced(const om_problem*, const double* a, const double* y, om_state* st,
+                            const om_hparams* hp, om_step_info* info, om_trace* trace);
 
 /* per-pixel evaluations, for sampled checks at sizes where whole-image
    oracle passes are too slow: out[n] = value at flat index idx[n] */

@@ -87,7 +87,7 @@ def test_schedule_arithmetic(step0, eps0):
     seen = 0
     for k in range(4):
         e0, d0, s0 = st.eps, st.delta, st.step
-        rc, info = O.maid_step(p, a, y, st, eps_min=1e-7)
+        rc, info = O.maid_step(p, a, y, st, eps_min=1e-7, max_lower_iter=100000, max_cg_iter=100000)
         if rc == O.ACCURACY_FLOOR:
             break
         assert rc == O.OK and info["accepted"] == 1
@@ -112,3 +112,77 @@ def test_accuracy_floor():
     assert rc == O.ACCURACY_FLOOR and info["accepted"] == 0
     np.testing.assert_array_equal(st.theta, inst.a)
     assert st.eps < 1e-3 and info["retries"] == 4
+
+
+def test_solve_cap_is_flagged_not_dropped():
+    """A lower-level or CG solve that stops at its iteration cap is carried on
+    with and flagged: the step reports which solve kind hit its cap and
+    returns MAXITER (a warning) where it would otherwise return OK."""
+    p, a, y, mu = _well_conditioned()
+    st = O.MaidState(a, y, np.zeros_like(y), eps=1e-6, delta=1e-6, step=0.3)
+    rc, info = O.maid_step(p, a, y, st, max_lower_iter=3, eps_min=1e-9)
+    assert info["lower_status"] == O.MAXITER
+    assert rc in (O.MAXITER, O.ACCURACY_FLOOR)
+    st = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-9, step=0.3)
+    rc, info = O.maid_step(p, a, y, st, max_cg_iter=2, max_lower_iter=100000, eps_min=1e-9)
+    assert info["cg_status"] == O.MAXITER and info["lower_status"] == O.OK
+    assert rc in (O.MAXITER, O.ACCURACY_FLOOR)
+    # uncapped: both flags clear and the step returns OK
+    st = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    rc, info = O.maid_step(p, a, y, st, max_lower_iter=100000, max_cg_iter=100000, eps_min=1e-7)
+    assert rc == O.OK and info["lower_status"] == O.OK and info["cg_status"] == O.OK
+
+
+def test_replay_of_own_trace_is_bitwise():
+    """The replay mode pinned to the free-running step: following the
+    oracle's own recorded decisions reproduces its result bit for bit, with
+    the same words and values."""
+    p, a, y, mu = _well_conditioned(C=2, seed=4)
+    s_free = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    s_rep = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    kinds = set()
+    for k in range(3):
+        rc, info, w, v = O.maid_step_traced(p, a, y, s_free, max_lower_iter=100000, eps_min=1e-7)
+        rc2, info2, w2, v2 = O.maid_step_traced(p, a, y, s_rep, replay=w, max_lower_iter=100000, eps_min=1e-7)
+        assert rc == rc2 and info == info2
+        np.testing.assert_array_equal(w, w2)
+        np.testing.assert_array_equal(v, v2)
+        np.testing.assert_array_equal(s_free.theta, s_rep.theta)
+        np.testing.assert_array_equal(s_free.x, s_rep.x)
+        np.testing.assert_array_equal(s_free.q, s_rep.q)
+        recs = O.split_trace(w, v)
+        kinds |= {r[0][0] for r in recs}
+        # the record counts agree with the step's own tallies
+        assert sum(r[0][2] for r in recs if r[0][0] == 1) == info["lower_iters"]
+        assert sum(r[0][1] for r in recs if r[0][0] == 3) == info["cg_iters"]
+        assert sum(1 for r in recs if r[0][0] == 5) == info["trials"]
+        psis = [r[1][0] for r in recs if r[0][0] == 5]
+        assert psis[-1] == info["psi"] and (psis[-1] <= 0) == bool(info["accepted"])
+        if rc != O.OK:
+            break
+    assert kinds == {1, 2, 3, 4, 5}
+
+
+def test_replay_follows_foreign_decisions():
+    """A replayed acceptance is taken even where the oracle's own psi says
+    otherwise, and a malformed trace is an error."""
+    p, a, y, mu = _well_conditioned(seed=5)
+    s0 = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    rc, info, w, v = O.maid_step_traced(p, a, y, s0, max_lower_iter=100000, eps_min=1e-7)
+    recs = O.split_trace(w, v)
+    assert info["accepted"] == 1 and info["trials"] < 3
+    # the accepted psi test turned into a rejection, followed by one more
+    # trial (replaying the last trial's lower-level decisions) that accepts
+    last = max(k for k, (rw, _) in enumerate(recs) if rw[0] == 5)
+    trial = [rw for rw, _ in recs if rw[0] == 1 and rw[1] == 1][-1]
+    out = []
+    for k, (rw, _) in enumerate(recs):
+        out += [5, 0] + list(trial) + [2, 1] + [5, 1] if k == last else list(rw)
+    s1 = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    rc1, info1, w1, v1 = O.maid_step_traced(p, a, y, s1, replay=out, max_lower_iter=100000, eps_min=1e-7)
+    assert rc1 == O.OK and info1["accepted"] == 1 and info1["trials"] == info["trials"] + 1
+    assert s1.step == pytest.approx(0.3 * 0.5 ** info["trials"] * 1.1, rel=1e-15)
+    np.testing.assert_array_equal(w1, out)
+    s2 = O.MaidState(a, y, np.zeros_like(y), eps=1e-4, delta=1e-4, step=0.3)
+    rc2, _, _, _ = O.maid_step_traced(p, a, y, s2, replay=[1, 0, 3], eps_min=1e-7)
+    assert rc2 == O.EINVAL
