@@ -102,9 +102,17 @@ typedef struct {
     int32_t k;
 } maid_state;
 
+/* One outer iteration's record: accepted (1 if theta moved), psi trials,
+   retries (accuracy reductions), lower-level and CG iterations, the step's
+   return code, the last psi of Eq. (3.4), ell(u_k), ell(u') of the last
+   trial, ||z||; lower_status / cg_status: MAID_MAXITER if any lower-level /
+   CG solve of the step stopped at its iteration cap (the step carries on
+   with that solve's result and then returns MAID_MAXITER, a warning, where
+   it would otherwise return MAID_OK), else MAID_OK. */
 typedef struct {
     int32_t accepted, trials, retries, lower_iters, cg_iters, status;
     double psi, ell_k, ell_next, znorm;
+    int32_t lower_status, cg_status;
 } maid_step_info;
 
 typedef struct maid_ctx maid_ctx;
@@ -240,6 +248,30 @@ int maid_sobolev_value(maid_ctx* ctx, const void* theta, const void* a, double* 
    MAID_ACCURACY_FLOOR (theta unchanged) once eps < eps_min. */
 int maid_step(maid_ctx* ctx, const void* a, const void* y, maid_state* state,
               const maid_hparams* hp, maid_step_info* info, hipStream_t stream);
+
+/* Decision trace of Algorithm 2, for a checker that replays the step's
+   decisions (the same solves with the same iteration counts, rejected trials
+   and acceptances, so that the two sides can be compared value by value
+   where a free-running comparison would diverge on rounding).  While
+   set, every maid_step / maid_batch_step call writes, for instance `inst`,
+   from the start of the caller's HOST buffers, in the order the work runs:
+     lower-level solve  words 1, role, iters, status, then the rejected trial
+                        steps of each of its iters iterations;
+                        values ||grad h|| at the returned point, L after
+                        (role 0: the InexactGradient solve at theta_k,
+                         role 1: the solve of a psi trial at theta')
+     upper level        words 2, role;           values g, ||grad g||, r(theta)
+     CG solve           words 3, iters, status;  values recursive residual
+     hypergradient      words 4;                 values ||z||
+     psi test           words 5, accepted;       values psi
+   Tracing reads the backtracking record of every traced solve back at once
+   (host round trips; the results are unchanged).  words == NULL turns it
+   off.  A step whose trace outgrows the buffers returns MAID_EINVAL after
+   completing.  maid_step_trace_length reports the words and values written
+   by the last step. */
+int maid_set_step_trace(maid_ctx* ctx, int32_t inst, int32_t* words, int32_t cap_words, double* values,
+                        int32_t cap_values);
+int maid_step_trace_length(const maid_ctx* ctx, int32_t* n_words, int32_t* n_values);
 
 /* ---------------------------------------------------------------- batched form
    One context over n independent problem instances of different sizes (a

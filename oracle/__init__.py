@@ -129,12 +129,18 @@ def lib():
         L.oracle_maid_step_traced.restype = ct.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ct.c_int
+        L.oracle_set_num_threads.argtypes = [ct.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

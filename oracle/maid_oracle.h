@@ -75,6 +75,10 @@ typedef struct {
 
 enum { OM_OK = 0, OM_MAXITER = 1, OM_ACCURACY_FLOOR = 2, OM_EINVAL = -1, OM_NOT_SPD = -4 };
 
+/* OpenMP threads of the whole-image loops (results do not depend on it) */
+int  oracle_num_threads(void);
+void oracle_set_num_threads(int n);
+
 /* operators */
 void   oracle_conv(const om_problem*, const double* th, const double* x, double* out);
 void   oracle_conv_adj(const om_problem*, const double* th, const double* r, double* out);

@@ -27,7 +27,8 @@ EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string
            "maid_adjoint_solve", "maid_hypergrad", "maid_apply_operator", "maid_sobolev_value", "maid_step",
            "maid_profile", "maid_profile_read", "maid_profile_name",
            "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
-           "maid_batch_step", "maid_autotune", "maid_batch_upper_value_grad", "maid_batch_hypergrad")
+           "maid_batch_step", "maid_autotune", "maid_batch_upper_value_grad", "maid_batch_hypergrad",
+           "maid_set_step_trace", "maid_step_trace_length")
 PROF_KINDS = 12
 
 
@@ -59,7 +60,7 @@ class maid_step_info(ct.Structure):
     _fields_ = [("accepted", ct.c_int32), ("trials", ct.c_int32), ("retries", ct.c_int32),
                 ("lower_iters", ct.c_int32), ("cg_iters", ct.c_int32), ("status", ct.c_int32),
                 ("psi", ct.c_double), ("ell_k", ct.c_double), ("ell_next", ct.c_double),
-                ("znorm", ct.c_double)]
+                ("znorm", ct.c_double), ("lower_status", ct.c_int32), ("cg_status", ct.c_int32)]
 
 
 _lib = None
@@ -138,6 +139,10 @@ def lib():
     L.maid_batch_upper_value_grad.restype = ct.c_int
     L.maid_batch_hypergrad.argtypes = [P, PP, PP, PP, PP, PP, i32, PP, dp, P]
     L.maid_batch_hypergrad.restype = ct.c_int
+    L.maid_set_step_trace.argtypes = [P, i32, ct.POINTER(i32), i32, dp, i32]
+    L.maid_set_step_trace.restype = ct.c_int
+    L.maid_step_trace_length.argtypes = [P, ct.POINTER(i32), ct.POINTER(i32)]
+    L.maid_step_trace_length.restype = ct.c_int
     L.maid_autotune.argtypes = [P, PP, PP, i32, ct.POINTER(i32), P]
     L.maid_autotune.restype = ct.c_int
     _lib = L

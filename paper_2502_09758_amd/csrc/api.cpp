@@ -289,6 +289,34 @@ int maid_step(maid_ctx* c, const void* a, const void* y, maid_state* st, const m
     return report(c, code, "maid_step");
 }
 
+int maid_set_step_trace(maid_ctx* c, int32_t inst, int32_t* words, int32_t cap_words, double* values,
+                        int32_t cap_values) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    auto& t = c->strace;
+    if (!words || !values) {
+        t = maid_ctx::StepTrace{};
+        return MAID_OK;
+    }
+    if (inst < 0 || inst >= c->n || cap_words < 1 || cap_values < 1)
+        return fail(c, MAID_EINVAL, "set_step_trace: bad instance or capacity");
+    t.inst = inst;
+    t.w = words;
+    t.v = values;
+    t.cap_w = cap_words;
+    t.cap_v = cap_values;
+    t.n_w = t.n_v = 0;
+    t.full = false;
+    return MAID_OK;
+}
+
+int maid_step_trace_length(const maid_ctx* c, int32_t* n_words, int32_t* n_values) {
+    if (!c || !n_words || !n_values) return MAID_EINVAL;
+    *n_words = c->strace.n_w;
+    *n_values = c->strace.n_v;
+    return MAID_OK;
+}
+
 int maid_autotune(maid_ctx* c, const void* const* theta, const void* const* y, int32_t probe_iters, int32_t* rows_out,
                   hipStream_t s) {
     if (!c) return MAID_EINVAL;

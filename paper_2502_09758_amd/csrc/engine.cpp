@@ -1315,6 +1315,36 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
 // sizes; an instance whose j trials all fail shrinks its accuracies and
 // joins the next round.  Each instance takes exactly the decisions, and
 // performs exactly the solves, it would take on its own.
+namespace {
+// Decision-trace records (layout declared with maid_set_step_trace).
+void tr_w(maid_ctx* c, int32_t w) {
+    auto& t = c->strace;
+    if (t.n_w >= t.cap_w) { t.full = true; return; }
+    t.w[t.n_w++] = w;
+}
+void tr_v(maid_ctx* c, double v) {
+    auto& t = c->strace;
+    if (t.n_v >= t.cap_v) { t.full = true; return; }
+    t.v[t.n_v++] = v;
+}
+// a lower-level solve of instance i that just finished on stream s
+int tr_lower(maid_ctx* c, int i, int role, const maid_solve_info& li, hipStream_t s) {
+    tr_w(c, 1);
+    tr_w(c, role);
+    tr_w(c, li.iters);
+    tr_w(c, li.status);
+    if (li.iters > 0) {
+        std::vector<int32_t> bt(std::min(li.iters, kTraceCap));
+        HIP_TRY(hipMemcpyAsync(bt.data(), c->m[i].trace, bt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int k = 0; k < li.iters; ++k) tr_w(c, k < (int)bt.size() ? bt[k] : -1);
+    }
+    tr_v(c, li.res_norm);
+    tr_v(c, li.L);
+    return MAID_OK;
+}
+}  // namespace
+
 template <typename T>
 int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
                const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s) {
@@ -1326,6 +1356,10 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
     const int n = c->n;
     std::vector<maid_step_info> I(n);
     std::memset(I.data(), 0, n * sizeof(maid_step_info));
+    // the decision trace (one instance): every call writes it from the start
+    const int ti = (c->strace.w && c->strace.v && c->strace.inst >= 0 && c->strace.inst < n) ? c->strace.inst : -1;
+    c->strace.n_w = c->strace.n_v = 0;
+    c->strace.full = false;
     // L_g <= 0: ||a||_1^2, from the first upper-level read-back (its prep of a
     // leaves ||a||_1 in the reduction slots)
     std::vector<double> Lg(n, hp->L_g);
@@ -1370,8 +1404,17 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
             }
             st[i].L = L[i];
             I[i].lower_iters += li[i].iters;
+            if (rc[i] == MAID_MAXITER) I[i].lower_status = MAID_MAXITER;
+            if (i == ti) TRY(tr_lower(c, i, 0, li[i], s));
         }
         TRY(upper_impl<T>(c, need, a, y, xc, grad, g_k.data(), n_k.data(), &theta, r_k.data(), s));
+        if (ti >= 0 && need[ti]) {
+            tr_w(c, 2);
+            tr_w(c, 0);
+            tr_v(c, g_k[ti]);
+            tr_v(c, n_k[ti]);
+            tr_v(c, r_k[ti]);
+        }
         if (!have_Lg) {
             for (int i = 0; i < n; ++i)
                 if (need[i]) Lg[i] = c->red_h[i * kRedSlots + kRedAbs] * c->red_h[i * kRedSlots + kRedAbs];
@@ -1381,14 +1424,35 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
         for (int i = 0; i < n; ++i) {
             if (!need[i]) continue;
             I[i].cg_iters += ci[i].iters;
+            if (i == ti) {
+                tr_w(c, 3);
+                tr_w(c, ci[i].iters);
+                tr_w(c, rc[i]);
+                tr_v(c, ci[i].res_norm);
+            }
             if (rc[i] < 0) {
                 codes[i] = rc[i];
                 need[i] = 0;
             }
+            if (rc[i] == MAID_MAXITER) I[i].cg_status = MAID_MAXITER;
         }
-        // ||z|| comes back with the first trial's read-back
-        TRY(hypergrad_impl<T>(c, need, theta, a, y, xc, qc, 1, z, nullptr, s));
+        // ||z|| comes back with the first trial's read-back (a traced step
+        // reads it back at once, for its record)
         bool have_znorm = false;
+        if (ti >= 0 && need[ti]) {
+            std::vector<double> zn(n, 0.0);
+            TRY(hypergrad_impl<T>(c, need, theta, a, y, xc, qc, 1, z, zn.data(), s));
+            for (int i = 0; i < n; ++i)
+                if (need[i]) {
+                    znorm[i] = zn[i];
+                    I[i].znorm = zn[i];
+                }
+            have_znorm = true;
+            tr_w(c, 4);
+            tr_v(c, znorm[ti]);
+        } else {
+            TRY(hypergrad_impl<T>(c, need, theta, a, y, xc, qc, 1, z, nullptr, s));
+        }
         for (int i = 0; i < n; ++i)
             if (need[i]) {
                 ell_k[i] = g_k[i] + r_k[i];
@@ -1417,8 +1481,17 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                 }
                 st[i].L = L[i];
                 I[i].lower_iters += li[i].iters;
+                if (rc[i] == MAID_MAXITER) I[i].lower_status = MAID_MAXITER;
+                if (i == ti) TRY(tr_lower(c, i, 1, li[i], s));
             }
             TRY(upper_impl<T>(c, tr, a, y, xsc, none, g_n.data(), n_n.data(), &th2c, r_n.data(), s));
+            if (ti >= 0 && tr[ti]) {
+                tr_w(c, 2);
+                tr_w(c, 1);
+                tr_v(c, g_n[ti]);
+                tr_v(c, n_n[ti]);
+                tr_v(c, r_n[ti]);
+            }
             if (!have_znorm) {
                 for (int i = 0; i < n; ++i)
                     if (need[i]) {
@@ -1436,6 +1509,11 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                 I[i].trials += 1;
                 I[i].psi = psi;
                 I[i].ell_next = ell_n;
+                if (i == ti) {
+                    tr_w(c, 5);
+                    tr_w(c, psi <= 0.0 ? 1 : 0);
+                    tr_v(c, psi);
+                }
                 if (psi <= 0.0) {
                     const int KK = c->m[i].d.K * c->m[i].d.K;
                     HIP_TRY(hipMemcpyAsync(st[i].theta, th2[i], KK * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1466,9 +1544,14 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
         }
     }
     for (int i = 0; i < n; ++i) {
+        // a solve that stopped at its iteration cap was carried on with; the
+        // step says so (a warning) unless it ended in another state
+        if (codes[i] == MAID_OK && (I[i].lower_status == MAID_MAXITER || I[i].cg_status == MAID_MAXITER))
+            codes[i] = MAID_MAXITER;
         I[i].status = codes[i];
         if (out) out[i] = I[i];
     }
+    if (c->strace.full) return fail(c, MAID_EINVAL, "maid_step: the decision trace buffers are too small");
     // the step's array outputs (theta, x, q) are complete when it returns
     HIP_TRY(hipStreamSynchronize(s));
     return MAID_OK;

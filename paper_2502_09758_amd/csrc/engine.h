@@ -147,6 +147,14 @@ struct maid_ctx {
     long pred_slots[4] = {0, 0, 0, 0};
     struct Graph { int kind; int chunk; int gen; hipGraphExec_t exec; };
     std::vector<Graph> graphs;
+    // decision trace of Algorithm 2 for one instance (maid_set_step_trace)
+    struct StepTrace {
+        int inst = -1;
+        int32_t* w = nullptr;
+        double* v = nullptr;
+        int32_t cap_w = 0, cap_v = 0, n_w = 0, n_v = 0;
+        bool full = false;
+    } strace;
     std::string err;
     std::string cfg;
     // per-launch timing with HIP events on the launch stream

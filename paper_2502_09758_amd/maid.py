@@ -236,6 +236,20 @@ class Maid:
         state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
         return rc, {f: getattr(info, f) for f, _ in L.maid_step_info._fields_}
 
+    def maid_step_traced(self, a, y, state: MaidState, cap=1 << 20, **hp):
+        """maid_step with its decision trace (record layout in maid.h):
+        returns (rc, info, words, values)."""
+        w = (ct.c_int32 * cap)()
+        v = (ct.c_double * cap)()
+        self._check(L.lib().maid_set_step_trace(self.handle, 0, w, cap, v, cap), "set_step_trace")
+        try:
+            rc, info = self.maid_step(a, y, state, **hp)
+        finally:
+            nw, nv = ct.c_int32(), ct.c_int32()
+            L.lib().maid_step_trace_length(self.handle, ct.byref(nw), ct.byref(nv))
+            L.lib().maid_set_step_trace(self.handle, 0, None, 0, None, 0)
+        return rc, info, list(w[:nw.value]), list(v[:nv.value])
+
 
 class MaidBatch:
     """A ragged batch of independent instances in one context (the batched

@@ -1,0 +1,112 @@
+"""Algorithm 2 on the GPU, replayed by the oracle step by step.
+
+Each GPU step (maid_step, the library's own implementation of Algorithm 2)
+records its decisions: every lower-level solve's iterations and rejected
+trials, every CG solve's iterations, every psi test's acceptance.  The
+oracle's replay mode runs the same step from the same state (the GPU's
+state before the step, up-cast exactly) taking those decisions, and the two
+traces are compared record by record: the same words, and the values each
+side computed (||grad h||, L, g, ||grad g||, r, the CG residual, ||z||, psi),
+then the state after the step (theta, x, q).  A free-running oracle step from
+the same state gives the decision-agreement rate.
+
+The plain-method workloads: 64x64 in FP64 for its ten steps (one-pass team
+loops), and 256x256 in FP32 (one-pass multi-kernel passes), with the
+benchmark's initial accuracy and step size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2502_09758_amd import _lib as L
+from paper_2502_09758_amd import synth
+from paper_2502_09758_amd.maid import Maid, MaidState
+
+pytestmark = pytest.mark.gpu
+
+HP = dict(eps_min=1e-6, max_lower_iter=2000, max_cg_iter=2000)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(np.ravel(b))
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / (nb if nb > 0 else 1.0))
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _decisions(words):
+    return [tuple(r[0]) for r in O.split_trace(words, [0.0] * 100000)]
+
+
+def replay(name, dt, n_steps, eps0, step0, tol):
+    inst = synth.make(name)
+    C, H, W, K = inst.C, inst.H, inst.W, inst.K
+    p = O.Problem.of(inst)
+    y = np.asarray(inst.y, dtype=np.float32).astype(np.float64) if dt == torch.float32 else inst.y
+    m = Maid(C, H, W, K, dt, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta)
+    a = torch.tensor(inst.a, dtype=torch.float64, device="cuda")
+    yd = torch.tensor(y, dtype=dt, device="cuda")
+    st = MaidState(a.clone(), yd.clone(), torch.zeros_like(yd), eps=eps0, delta=eps0, step=step0)
+    worst = dict(x=0.0, theta=0.0, dtheta=0.0, q=0.0, val=0.0, psi=0.0)
+    agree = total = 0
+    for k in range(n_steps):
+        th0, x0, q0 = host(st.theta), host(st.x), host(st.q)
+        e0, d0, s0, L0, k0 = st.eps, st.delta, st.step, st.L, st.k
+        rc, info, w, v = m.maid_step_traced(a, yd, st, **HP)
+        so = O.MaidState(th0, x0, q0, e0, d0, s0, L0, k0)
+        rco, infoo, wo, vo = O.maid_step_traced(p, inst.a, y, so, replay=w, **HP)
+        assert rco == rc and list(wo) == list(w), (k, rc, rco)
+        for f in ("accepted", "trials", "retries", "lower_iters", "cg_iters", "lower_status", "cg_status"):
+            assert info[f] == infoo[f], (k, f)
+        # value by value: the upper-level sums, ||z||, psi (relative to the
+        # objective values it is a difference of)
+        recs, reco = O.split_trace(w, v), O.split_trace(wo, vo)
+        ell = max(abs(info["ell_k"]), 1e-300)
+        for (rw, rv), (_, ro) in zip(recs, reco):
+            if rw[0] == 2:
+                worst["val"] = max(worst["val"], max(abs(a_ - b_) / max(abs(b_), 1e-300) for a_, b_ in zip(rv, ro)))
+            elif rw[0] == 4:
+                worst["val"] = max(worst["val"], abs(rv[0] - ro[0]) / ro[0])
+            elif rw[0] == 5:
+                worst["psi"] = max(worst["psi"], abs(rv[0] - ro[0]) / ell)
+            elif rw[0] == 1:
+                assert rv[1] == pytest.approx(ro[1], rel=1e-12)      # L: the same doublings
+        worst["theta"] = max(worst["theta"], rel(host(st.theta), so.theta))
+        if info["accepted"]:
+            worst["dtheta"] = max(worst["dtheta"], rel(host(st.theta) - th0, so.theta - th0))
+        worst["x"] = max(worst["x"], rel(host(st.x), so.x))
+        worst["q"] = max(worst["q"], rel(host(st.q), so.q))
+        assert (st.eps, st.delta, st.step, st.k) == (so.eps, so.delta, so.step, so.k)
+        # free-running oracle from the same state: do its decisions agree?
+        sf = O.MaidState(th0, x0, q0, e0, d0, s0, L0, k0)
+        _, _, wf, _ = O.maid_step_traced(p, inst.a, y, sf, **HP)
+        agree += _decisions(wf) == _decisions(w)
+        total += 1
+        print(f"[{name} step {k}] rc={rc} acc={info['accepted']} trials={info['trials']} "
+              f"retries={info['retries']} lower={info['lower_iters']} cg={info['cg_iters']} "
+              f"x {worst['x']:.2e} theta {worst['theta']:.2e} dtheta {worst['dtheta']:.2e} q {worst['q']:.2e} "
+              f"values {worst['val']:.2e} psi/ell {worst['psi']:.2e}", flush=True)
+        if rc == L.ACCURACY_FLOOR:
+            st = MaidState(a.clone(), yd.clone(), torch.zeros_like(yd), eps=eps0, delta=eps0, step=step0)
+    print(f"[{name}] free-running decision agreement {agree}/{total}", flush=True)
+    m.close()
+    for key, bound in tol.items():
+        assert worst[key] <= bound, (key, worst[key], bound)
+    return agree, total
+
+
+@pytest.mark.timeout(600)
+def test_maid_replay_fp64_64x64_ten_steps():
+    print("[case] MAID replay 64x64 FP64, 10 steps", flush=True)
+    agree, total = replay("cfg1", torch.float64, 10, 1e-5, 1e-4,
+                          dict(x=1e-10, theta=1e-12, dtheta=1e-5, q=5e-6, val=1e-10, psi=1e-10))
+    assert agree == total
+
+
+@pytest.mark.timeout(900)
+def test_maid_replay_fp32_256x256():
+    print("[case] MAID replay 256x256 FP32, 4 steps", flush=True)
+    replay("cfg2", torch.float32, 4, 1e-4, 1e-4,
+           dict(x=1e-5, theta=1e-6, dtheta=1e-4, q=1e-4, val=1e-5, psi=1e-5))

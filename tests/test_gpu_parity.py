@@ -244,3 +244,19 @@ def test_tall_tiles_solver_parity(C, H, W, K, dt):
     assert ci.status == L.OK
     qr, _ = O.adjoint_solve(p, inst.a, xt, b, tol=0.0, max_iter=ci.iters)
     assert rel(host(q), qr) <= (1e-6 if dt == "f64" else 1e-5)
+
+
+def test_maid_step_flags_capped_solves():
+    """A lower-level or CG solve that stops at its cap inside a step is
+    flagged, and the step returns MAXITER, as the oracle does."""
+    print("[case] maid_step capped solves", flush=True)
+    p, a, y = _well_conditioned()
+    m = Maid(1, p.H, p.W, 3, torch.float64, alpha=p.alpha, eps_tv=p.eps_tv, beta=p.beta)
+    for kw, flag in ((dict(max_lower_iter=3), "lower_status"), (dict(max_cg_iter=2, max_lower_iter=100000), "cg_status")):
+        st = MaidState(dev(a, torch.float64), dev(y, torch.float64), torch.zeros((1, p.H, p.W), dtype=torch.float64,
+                       device="cuda"), eps=1e-6, delta=1e-9, step=0.3)
+        so = O.MaidState(a, y, np.zeros_like(y), eps=1e-6, delta=1e-9, step=0.3)
+        rc, info = m.maid_step(dev(a, torch.float64), dev(y, torch.float64), st, eps_min=1e-9, **kw)
+        rco, infoo = O.maid_step(p, a, y, so, eps_min=1e-9, **kw)
+        assert info[flag] == L.MAXITER and rc in (L.MAXITER, L.ACCURACY_FLOOR)
+        assert (rc, info["lower_status"], info["cg_status"]) == (rco, infoo["lower_status"], infoo["cg_status"])
