@@ -156,6 +156,18 @@ int maid_set_team(maid_ctx* ctx, int32_t members);
    (measured at equal iteration counts: FP64, 30-50 iterations, <= 1.6e-6
    relative against <= 1e-6; FP32, 83 iterations, 2.2e-5 against 4.7e-5). */
 int maid_set_one_pass_cg(maid_ctx* ctx, int32_t enable);
+/* Matrix cores for the large-kernel correlations (enable != 0, the
+   default): with FP32 storage, K >= 13 and tiles of 4 or 8 rows per thread,
+   the K x K correlations of the solver passes (Proposition 1's gradient and
+   Hessian products) and of the hypergradient's convolutions run as banded
+   products on v_mfma_f32_16x16x32_f16, each FP32 operand split into two
+   FP16 parts (three products; tile and kernel scaled by powers of two),
+   accumulated in FP32; 0 = the FP32 vector ALUs.  Both are deterministic;
+   they round differently (measured on random tiles: within 4e-7 of the
+   FP64 correlation, relative to the largest output).  FP64 storage and the
+   upper-level convolutions (FP64 taps and sums) are unaffected.  Takes
+   effect at the next call. */
+int maid_set_mfma(maid_ctx* ctx, int32_t enable);
 /* Lower-level form of the instances that can take the one-pass form (one
    channel, 3 <= K <= 11, tile rows <= 4): mode -1 (the default) = the
    autotuner's choice where it ran, else the size rule; 0 = two passes per

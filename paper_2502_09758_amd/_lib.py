@@ -23,7 +23,7 @@ CODE_NAMES = {OK: "OK", MAXITER: "MAXITER", ACCURACY_FLOOR: "ACCURACY_FLOOR", EI
 
 # every entry point declared in include/maid.h
 EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string",
-           "maid_set_tile_rows", "maid_set_team", "maid_set_one_pass_cg", "maid_set_one_pass", "maid_one_pass_forms", "maid_lower_solve", "maid_upper_value_grad",
+           "maid_set_tile_rows", "maid_set_team", "maid_set_one_pass_cg", "maid_set_mfma", "maid_set_one_pass", "maid_one_pass_forms", "maid_lower_solve", "maid_upper_value_grad",
            "maid_adjoint_solve", "maid_hypergrad", "maid_apply_operator", "maid_sobolev_value", "maid_step",
            "maid_profile", "maid_profile_read", "maid_profile_name",
            "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
@@ -98,6 +98,8 @@ def lib():
     L.maid_set_team.restype = ct.c_int
     L.maid_set_one_pass_cg.argtypes = [P, i32]
     L.maid_set_one_pass_cg.restype = ct.c_int
+    L.maid_set_mfma.argtypes = [P, i32]
+    L.maid_set_mfma.restype = ct.c_int
     L.maid_set_one_pass.argtypes = [P, i32]
     L.maid_set_one_pass.restype = ct.c_int
     L.maid_one_pass_forms.argtypes = [P, ct.POINTER(i32)]

@@ -136,6 +136,13 @@ int maid_set_one_pass_cg(maid_ctx* c, int32_t enable) {
     return relayout(c);
 }
 
+int maid_set_mfma(maid_ctx* c, int32_t enable) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    c->mfma = enable != 0;
+    return relayout(c);
+}
+
 int maid_set_team(maid_ctx* c, int32_t members) {
     if (!c) return MAID_EINVAL;
     if (members < -1 || members > kTeamMax)

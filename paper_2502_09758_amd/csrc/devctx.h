@@ -145,6 +145,12 @@ template <typename T> struct Inst {
     gp<const T> y;
     gp<T> th;                       // theta in the compute type, correlation form, column-major
     gp<T> thf;                      // the flipped kernel (convolution form), column-major
+    // matrix-core operand layouts of th and thf (FP32 storage, K >= 13;
+    // nullable: the correlations then run on the vector ALUs) and the
+    // power-of-two exponent they were scaled by (one int, written with them)
+    gp<uint4> mf_th;
+    gp<uint4> mf_thf;
+    gp<int> mf_sh;
     gp<double> pA;                  // per-block partials, gradient pass (nb entries)
     gp<double> pB;                  // per-block partials, trial pass (nb entries)
     gp<int> trace;                  // rejected trials per iteration
@@ -164,6 +170,11 @@ template <typename T> struct Inst {
     gp<double> S64[2];              // one-pass CG: s = Hp, carried in FP64 (two buffers)
     // one convolution job: cv_out = cv_ker (x) cv_in [- cv_sub], partials of its square
     gp<const T> cv_ker;
+    gp<const uint4> cv_mf;          // nullable: matrix-core layout of cv_ker
+    gp<const int> cv_mfsh;          // its scale exponent
+    gp<const double> cv_ker64;      // nullable (FP32 storage): the kernel as KxK doubles, row-major;
+                                    // the job then runs with FP64 taps and FP64 sums
+    int32_t cv_flip64;              // cv_ker64 is applied flipped (true convolution)
     gp<const T> cv_in;
     gp<const T> cv_sub;
     gp<T> cv_out;

@@ -3,6 +3,7 @@
 // solve and Hessian system, the upper-level value and gradient, the
 // hypergradient of Eq. 3.2, and Algorithm 2 in lockstep over the instances).
 #include "engine.h"
+#include "mfconv.cuh"
 
 #include <algorithm>
 #include <atomic>
@@ -36,6 +37,10 @@ int fail(maid_ctx* c, int code, const std::string& msg) {
     } while (0)
 
 namespace {
+
+// Instances whose large-kernel correlations can run on the matrix cores
+// (FP32 storage, K >= 13): they carry the operand layouts of theta.
+bool mf_member(int dtype, int K) { return dtype == MAID_F32 && K >= 13 && K <= kMaxK; }
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -154,6 +159,11 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
     I.G = (T*)M.G;
     I.th = (T*)M.th_c;
     I.thf = (T*)M.thf_c;
+    if (c->mfma && M.mf[0] && !M.on_team) {
+        I.mf_th = (uint4*)M.mf[0];
+        I.mf_thf = (uint4*)M.mf[1];
+        I.mf_sh = M.mf_sh;
+    }
     I.pA = M.pA;
     I.pB = M.pB;
     I.trace = M.trace;
@@ -315,21 +325,28 @@ long next_slots(long pred, long done_so_far, long last, int first_pct) {
 }  // namespace
 
 // ------------------------------------------------------------------ set-up
-int validate_desc(const maid_desc* d, std::string& why) {
-    if (!d) { why = "desc is NULL"; return MAID_EINVAL; }
-    if (d->H < 1 || d->W < 1) { why = "H and W must be >= 1"; return MAID_EINVAL; }
-    if (d->C < 1 || d->C > kMaxC) { why = "C must be 1, 2 or 3"; return MAID_EINVAL; }
-    if (d->K < 1 || d->K > kMaxK || (d->K % 2) == 0) { why = "K must be odd, 1 <= K <= 31"; return MAID_EINVAL; }
-    if (d->K > d->H || d->K > d->W) { why = "K must not exceed H or W"; return MAID_EINVAL; }
-    if (d->dtype != MAID_F32 && d->dtype != MAID_F64) { why = "dtype must be MAID_F32 or MAID_F64"; return MAID_EINVAL; }
-    if (d->reg < 0 || d->reg > 2) { why = "reg must be 0, 1 or 2"; return MAID_EINVAL; }
-    if (!finite(d->alpha) || d->alpha < 0) { why = "alpha must be finite and >= 0"; return MAID_EINVAL; }
-    if (d->reg != MAID_REG_QUADRATIC && !(d->eps_tv > 0 && finite(d->eps_tv))) { why = "eps_tv must be > 0"; return MAID_EINVAL; }
-    if (!finite(d->beta) || d->beta < 0) { why = "beta must be finite and >= 0"; return MAID_EINVAL; }
-    if (!finite(d->h1_w0) || d->h1_w0 < 0) { why = "h1_w0 must be finite and >= 0"; return MAID_EINVAL; }
+const char* desc_problem(const maid_desc* d) {
+    if (!d) return "desc is NULL";
+    if (d->H < 1 || d->W < 1) return "H and W must be >= 1";
+    if (d->C < 1 || d->C > kMaxC) return "C must be 1, 2 or 3";
+    if (d->K < 1 || d->K > kMaxK || (d->K % 2) == 0) return "K must be odd, 1 <= K <= 31";
+    if (d->K > d->H || d->K > d->W) return "K must not exceed H or W";
+    if (d->dtype != MAID_F32 && d->dtype != MAID_F64) return "dtype must be MAID_F32 or MAID_F64";
+    if (d->reg < 0 || d->reg > 2) return "reg must be 0, 1 or 2";
+    if (!finite(d->alpha) || d->alpha < 0) return "alpha must be finite and >= 0";
+    if (d->reg != MAID_REG_QUADRATIC && !(d->eps_tv > 0 && finite(d->eps_tv))) return "eps_tv must be > 0";
+    if (!finite(d->beta) || d->beta < 0) return "beta must be finite and >= 0";
+    if (!finite(d->h1_w0) || d->h1_w0 < 0) return "h1_w0 must be finite and >= 0";
     // one channel plane is indexed with 32-bit offsets in the kernels
-    if ((double)d->H * d->W >= 2147483648.0) { why = "H*W must be below 2^31"; return MAID_EINVAL; }
-    return MAID_OK;
+    if ((double)d->H * d->W >= 2147483648.0) return "H*W must be below 2^31";
+    return nullptr;
+}
+
+int validate_desc(const maid_desc* d, std::string& why) {
+    const char* p = desc_problem(d);
+    if (!p) return MAID_OK;
+    why = p;
+    return MAID_EINVAL;
 }
 
 // Members per team of a group's persistent loops, 0 for the multi-kernel
@@ -421,6 +438,7 @@ int relayout(maid_ctx* c) {
         }
         lg.g.cg1 = lg.g.grid_f > 0 && c->cg_fuse ? 1 : 0;
         lg.team = team_members(c, lg);
+        for (int i : lg.members) c->m[i].on_team = lg.team > 0;
     }
     int base_e = 0;
     for (int i = 0; i < c->n; ++i) {
@@ -493,6 +511,7 @@ int relayout(maid_ctx* c) {
             c->cfg += buf;
         }
         if (lg.g.cg1) c->cfg += " cg-one-pass";
+        if (c->mfma && mf_member(c->dtype, lg.g.K) && (lg.g.R == 4 || lg.g.R == 8)) c->cfg += " mfma";
     }
     return MAID_OK;
 }
@@ -585,6 +604,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         total += s64;
         total += 19 * img + 6 * kern + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
                  al(kTraceCap * sizeof(int));
+        if (mf_member(c->dtype, M.d.K)) total += 2 * al(mf_frag_bytes(M.d.K)) + al(sizeof(int));
         maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe) + round8(step_blocks(M.d.H, M.d.W, M.d.K, 1));
     }
     c->ws_bytes = total;
@@ -621,6 +641,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     if (const char* t = std::getenv("MAID_TEAM")) c->team_req = std::max(-1, std::atoi(t));
     if (const char* f = std::getenv("MAID_FUSE")) c->fuse = std::strcmp(f, "0") != 0;
     if (const char* f = std::getenv("MAID_CG_ONE_PASS")) c->cg_fuse = std::strcmp(f, "0") != 0;
+    if (const char* f = std::getenv("MAID_MFMA")) c->mfma = std::strcmp(f, "0") != 0;
     if (const char* u = std::getenv("MAID_UPLOAD_KERNEL")) c->upload_kernel = std::strcmp(u, "0") != 0;
     if (const char* u = std::getenv("MAID_PRED_FIRST")) c->pred_first = std::max(1, std::min(400, std::atoi(u)));
     if (const char* u = std::getenv("MAID_PRED_FIRST_CG")) c->pred_first_cg = std::max(1, std::min(400, std::atoi(u)));
@@ -691,6 +712,10 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.pC = (double*)take(part);
         M.hg_part = (double*)take(al((size_t)kHgMaxBlocks * 1024 * sizeof(double)));
         M.trace = (int*)take(al(kTraceCap * sizeof(int)));
+        if (mf_member(c->dtype, M.d.K)) {
+            for (int k = 0; k < 2; ++k) M.mf[k] = take(al(mf_frag_bytes(M.d.K)));
+            M.mf_sh = (int*)take(al(sizeof(int)));
+        }
     }
     int rc = relayout(c);
     if (rc) {
@@ -737,6 +762,8 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         I.theta64 = theta[i];
         // set-up: X0 = X1 = x_start, KX0 = KX1 = theta*x_start in one pass
         I.cv_ker = I.thf;
+        I.cv_mf = I.mf_thf;
+        I.cv_mfsh = I.mf_sh;
         I.cv_in = xin ? (*xin)[i] : x[i];
         I.cv_out = I.KX[0];
         I.cv_out2 = I.KX[1];
@@ -1046,11 +1073,18 @@ int upper_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<cons
         t0[i].thf = (T*)M.af_c;
         t0[i].theta64 = a[i];
         t0[i].cv_ker = (T*)M.af_c;
+        // the upper level convolves in FP64 (taps and sums): its residual
+        // a*x - y is small next to a*x at a lower-level solution
+        t0[i].cv_ker64 = a[i];
+        t0[i].cv_flip64 = 1;
+        t0[i].mf_th = t0[i].mf_thf = nullptr;
         t0[i].cv_in = x[i];
         t0[i].cv_sub = y[i];
         t0[i].cv_out = (T*)M.tmp0;
         t0[i].cv_part = M.pC;
         t1[i].cv_ker = (T*)M.a_c;
+        t1[i].cv_ker64 = a[i];
+        t1[i].cv_flip64 = 0;
         t1[i].cv_in = (T*)M.tmp0;
         t1[i].cv_out = grad[i] ? grad[i] : (T*)M.gradg;
         t1[i].cv_part = M.pA;
@@ -1110,10 +1144,14 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
         const Member& M = c->m[i];
         t2[i].theta64 = theta[i];
         t2[i].cv_ker = (T*)M.thf_c;
+        t2[i].cv_mf = t2[i].mf_thf;
+        t2[i].cv_mfsh = t2[i].mf_sh;
         t2[i].cv_in = xt[i];
         t2[i].cv_sub = y[i];
         t2[i].cv_out = (T*)M.tmp0;
         t3[i].cv_ker = (T*)M.thf_c;
+        t3[i].cv_mf = t3[i].mf_thf;
+        t3[i].cv_mfsh = t3[i].mf_sh;
         t3[i].cv_in = q[i];
         t3[i].cv_out = (T*)M.tmp1;
     }
@@ -1184,6 +1222,8 @@ int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, in
     fill_base(c, 0, t[0]);
     t[0].theta64 = theta;
     t[0].cv_ker = adjoint ? t[0].th : t[0].thf;
+    t[0].cv_mf = adjoint ? t[0].mf_th : t[0].mf_thf;
+    t[0].cv_mfsh = t[0].mf_sh;
     t[0].cv_in = in;
     t[0].cv_out = out;
     TRY(upload<T>(c, ROLE_CV0, s));

@@ -64,6 +64,11 @@ struct Member {
     void* thf_c;
     void* a_c;
     void* af_c;
+    // matrix-core operand layouts of theta (FP32 storage, K >= 13; else
+    // null): [0] theta, [1] flipped theta, and their scale exponent
+    void* mf[2];
+    int* mf_sh;
+    bool on_team;               // its group runs the team loops (no matrix-core path there)
     double* th_trial;
     double* zbuf;
     double* pA;
@@ -125,6 +130,7 @@ struct maid_ctx {
     // persistent team loops for small instances (one team per XCD)
     bool fuse = true;                 // one-pass FISTA where the group allows it
     bool cg_fuse = true;              // one-pass (Chronopoulos-Gear) CG on the one-pass instances
+    bool mfma = true;                 // large-kernel correlations on the matrix cores (FP32 storage)
     int fuse_force = -1;              // autotuner's candidate: -1 none, 0 two-pass, 1 one-pass
     int fuse_pin = -1;                // the caller's choice (maid_set_one_pass): -1 none, 0, 1
     int team_req = -1;                // members per team: -1 size rule, 0 never, > 0 that many (capped)
@@ -171,6 +177,8 @@ namespace maid {
 
 int fail(maid_ctx* c, int code, const std::string& msg);
 int validate_desc(const maid_desc* d, std::string& why);
+// what is wrong with a description (a static string), or nullptr
+const char* desc_problem(const maid_desc* d);
 int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why);
 void destroy_ctx(maid_ctx* c);
 int relayout(maid_ctx* c);

@@ -36,6 +36,7 @@
 #include <stdint.h>
 
 #include "devctx.h"
+#include "mfconv.cuh"
 
 namespace maid {
 
@@ -368,6 +369,47 @@ __device__ __forceinline__ void correlate(const T* s, int pitch, const T* __rest
     }
 }
 
+// The correlation of a staged tile on the matrix cores where the tile shape
+// allows it and the instance carries the kernel's operand layout (mf,
+// nullable), else on the vector ALUs.  Every thread of the block calls it.
+// MF = false leaves the matrix-core path out of the kernel (the team loops,
+// which serve instances too small to need it).
+template <typename T, int K, int R, bool MF = true>
+__device__ __forceinline__ void correlate_sel(const T* s, int pitch, const T* __restrict__ kT, const uint4* mf,
+                                              const int* mfsh, int li0, int tx, T (&acc)[R]) {
+    if constexpr (MF && mf_ok<T, K, R>()) {
+        if (mf) {
+            __shared__ __align__(16) unsigned char mf_lds[mf_lds_bytes<K, R>()];
+            correlate_mfma<K, R>(s, pitch, mf, *(const int MAID_CONST*)mfsh, mf_lds, li0, tx, acc);
+            return;
+        }
+    }
+    correlate<T, K, R>(s, pitch, kT, li0, tx, acc);
+}
+
+// acc[o] += sum_{u,v} ker(u,v) s[(li0+o+u) pitch + tx+v] in FP64, the taps
+// read as doubles from the row-major KxK array th: ker(u,v) = th[u K + v],
+// or th[(K-1-u) K + (K-1-v)] with `flip`.
+template <typename T, int K, int R>
+__device__ __forceinline__ void correlate64(const T* s, int pitch, const double* __restrict__ th, bool flip, int li0,
+                                            int tx, double (&acc)[R]) {
+    const double MAID_CONST* kc = (const double MAID_CONST*)th;
+#pragma unroll 1
+    for (int v = 0; v < K; ++v) {
+        double col[R + K - 1];
+#pragma unroll
+        for (int t = 0; t < R + K - 1; ++t) col[t] = (double)s[(li0 + t) * pitch + tx + v];
+        const int base = flip ? (K - 1) * K + (K - 1 - v) : v;
+        const int step = flip ? -K : K;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const double w = kc[base + u * step];
+#pragma unroll
+            for (int o = 0; o < R; ++o) acc[o] = __builtin_fma(w, col[o + u], acc[o]);
+        }
+    }
+}
+
 // select one of three register arrays by a (uniform) runtime channel index
 template <typename T, int R>
 __device__ __forceinline__ T pick3(const T (&a)[R], const T (&b)[R], const T (&c)[R], int ch, int o) {
@@ -560,11 +602,40 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
     T* __restrict__ cp1 = I.cv_cp[1] ? I.cv_cp[1] + ch * HW : nullptr;
     load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(src, g); });
     __syncthreads();
+    const int gj = tj0 + tx;
+    if constexpr (sizeof(T) == 4) {
+        if (I.cv_ker64) {
+            // FP64 taps and sums; one rounding to the storage type at the store
+            double acc[R];
+#pragma unroll
+            for (int o = 0; o < R; ++o) acc[o] = 0.0;
+            correlate64<T, K, R>(s, CP, I.cv_ker64, I.cv_flip64 != 0, li0, tx, acc);
+            double sq = 0.0;
+#pragma unroll
+            for (int o = 0; o < R; ++o) {
+                const int gi = ti0 + li0 + o;
+                if (gi < H && gj < W) {
+                    const int e = gi * W + gj;
+                    double val = acc[o];
+                    if (sub) val -= (double)at(sub, e);
+                    at(out, e) = (T)val;
+                    if (out2) at(out2, e) = (T)val;
+                    if (cp0) {
+                        const T xin = s[(li0 + o + c0) * CP + tx + c0];
+                        at(cp0, e) = xin;
+                        if (cp1) at(cp1, e) = xin;
+                    }
+                    sq += val * val;
+                }
+            }
+            if (I.cv_part) block_partial(sq, I.cv_part, lb);
+            return;
+        }
+    }
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    correlate<T, K, R>(s, CP, I.cv_ker, li0, tx, acc);
-    const int gj = tj0 + tx;
+    correlate_sel<T, K, R>(s, CP, I.cv_ker, I.cv_mf, I.cv_mfsh, li0, tx, acc);
     double sq = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
@@ -732,7 +803,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
         __syncthreads();
         stage_residual();
         __syncthreads();
-        correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+        correlate_sel<T, K, R, !CO>(s_c, CP, I.th, I.mf_th, I.mf_sh, li0, tx, acc);
     }
     T gv[R];
 #pragma unroll
@@ -958,7 +1029,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
+    correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
     double ddat = 0.0;
     // small kernels: every row's loads in flight before any is used (clamped
     // addresses, no branch); large kernels keep their registers
@@ -1008,7 +1079,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
         __syncthreads();
 #pragma unroll
         for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate<T, K, R>(s_c, CP, I.thf, li0, tx, acc);
+        correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int gi = ti0 + li0 + o;
@@ -1127,7 +1198,7 @@ __device__ __forceinline__ void cg_dir_body(const Inst<T>& I, int lb, CgState& s
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    correlate<T, K, R>(s, CP, I.thf, li0, tx, acc);
+    correlate_sel<T, K, R, !CO>(s, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
     T* __restrict__ Kp = I.Kp + ch * HW;
     T* __restrict__ qc = I.q + ch * HW;
 #pragma unroll
@@ -1318,7 +1389,7 @@ __device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgSt
         __syncthreads();
         stage_kp();
         __syncthreads();
-        correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+        correlate_sel<T, K, R, !CO>(s_c, CP, I.th, I.mf_th, I.mf_sh, li0, tx, acc);
     }
     double kap = 0.0;
     T* __restrict__ Hp = I.Hp + ch * HW;
@@ -1490,12 +1561,25 @@ __global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* insts, ApgS
     }
     s_abs[t] = a;
     __syncthreads();
+    __shared__ int s_sh;
     if (t == 0) {
-        double s = 0.0;
-        for (int i = 0; i < KK; ++i) s += s_abs[i];
+        double s = 0.0, mx = 0.0;
+        for (int i = 0; i < KK; ++i) {
+            s += s_abs[i];
+            mx = fmax(mx, s_abs[i]);
+        }
         if (Lst && !(I.st0.L > 0.0)) Lst[blockIdx.x].L = s * s;
         if (slot_abs >= 0) I.red[slot_abs] = s;
+        // the matrix-core layouts: the kernel scaled by a power of two that
+        // brings its largest tap into [2^14, 2^15)
+        const float mxf = (float)mx;
+        s_sh = mxf >= 1.0e-30f ? mf_shift(mxf) : 0;
+        if (I.mf_th) *I.mf_sh = s_sh;
     }
+    if (!I.mf_th) return;
+    __syncthreads();
+    mf_fragments(I.theta64, K, false, s_sh, I.mf_th, t, 1024);
+    mf_fragments(I.theta64, K, true, s_sh, I.mf_thf, t, 1024);
 }
 
 // One block per instance: red[slot] = sum of the instance's cv_part partials;

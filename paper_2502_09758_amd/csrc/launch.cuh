@@ -9,18 +9,25 @@
 
 namespace maid {
 
-// Raise the dynamic-LDS limit of a kernel if it needs more than 64 KiB.
+// Raise the dynamic-LDS limit of a kernel if it needs more than 64 KiB
+// together with its static LDS (the matrix-core correlation's tiles).
 template <typename Kern>
-static inline hipError_t ensure_lds(Kern kern, size_t bytes) {
-    if (bytes <= 65536) return hipSuccess;
+static inline hipError_t ensure_lds(Kern kern, size_t bytes, size_t static_bytes = 0) {
+    if (bytes + static_bytes <= 65536) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+// static LDS of the correlation selector in the instantiations that have
+// the matrix-core path
+template <typename T, int K, int R> constexpr size_t mf_static() {
+    if constexpr (mf_ok<T, K, R>()) return (size_t)mf_lds_bytes<K, R>() + 64;
+    else return 0;
 }
 
 template <typename T, int K, int R>
 static hipError_t conv_kr(const Group& g, const Inst<T>* insts, hipStream_t s) {
     const size_t lds = sizeof(T) * lds_conv(K, R);
     auto kern = k_conv<T, K, R>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only);
 }
@@ -29,7 +36,7 @@ template <typename T, int K, int R>
 static hipError_t apg_grad_kr(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s) {
     const size_t lds = sizeof(T) * lds_apg_grad(K, R, g.C, g.nw);
     auto kern = k_apg_grad<T, K, R>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout);
 }
@@ -38,7 +45,7 @@ template <typename T, int K, int R>
 static hipError_t apg_trial_kr(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s) {
     const size_t lds = sizeof(T) * lds_apg_trial(K, R, g.C);
     auto kern = k_apg_trial<T, K, R>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout);
 }
@@ -48,7 +55,7 @@ static hipError_t cg_dir_kr(const Group& g, const Inst<T>* insts, const CgState*
                             hipStream_t s) {
     const size_t lds = sizeof(T) * lds_cg_dir(K, R);
     auto kern = k_cg_dir<T, K, R>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout, init);
 }
@@ -58,7 +65,7 @@ static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState*
                             hipStream_t s) {
     const size_t lds = sizeof(T) * lds_cg_hvp(K, R, g.C, g.nw);
     auto kern = k_cg_hvp<T, K, R>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(g.grid), dim3(kNT), lds, s, insts, g.blk, g.only, sin, sout, init);
 }
@@ -83,7 +90,7 @@ static hipError_t apg_team_krs(const Group& g, const Inst<T>* insts, const int* 
                                const TeamCtl& ctl, long max_slots, hipStream_t s) {
     const size_t lds = apg_team_lds<T, K, R, STEP>(g);
     auto kern = k_apg_team<T, K, R, STEP>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(kTeamXcd * ctl.P), dim3(STEP ? kStepNT : kNT), lds, s, insts, list, nlist, st, ctl,
                   max_slots);
@@ -101,7 +108,7 @@ static hipError_t cg_team_krs(const Group& g, const Inst<T>* insts, const int* l
                               const TeamCtl& ctl, long max_slots, hipStream_t s) {
     const size_t lds = cg_team_lds<T, K, R, STEP>(g);
     auto kern = k_cg_team<T, K, R, STEP>;
-    hipError_t e = ensure_lds(kern, lds);
+    hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
     return launch(kern, dim3(kTeamXcd * ctl.P), dim3(STEP ? kStepNT : kNT), lds, s, insts, list, nlist, st, n, ctl,
                   max_slots);
@@ -119,8 +126,9 @@ static hipError_t cg_team_kr(const Group& g, const Inst<T>* insts, const int* li
 template <typename T, int K, int R, bool STEP, bool STEP_CG>
 static hipError_t team_occupancy_krs(const Group& g, int* blocks_per_cu) {
     int a = 0, b = 0;
-    hipError_t e = ensure_lds(k_apg_team<T, K, R, STEP>, apg_team_lds<T, K, R, STEP>(g));
-    if (e == hipSuccess) e = ensure_lds(k_cg_team<T, K, R, STEP_CG>, cg_team_lds<T, K, R, STEP_CG>(g));
+    hipError_t e = ensure_lds(k_apg_team<T, K, R, STEP>, apg_team_lds<T, K, R, STEP>(g), mf_static<T, K, R>());
+    if (e == hipSuccess)
+        e = ensure_lds(k_cg_team<T, K, R, STEP_CG>, cg_team_lds<T, K, R, STEP_CG>(g), mf_static<T, K, R>());
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_apg_team<T, K, R, STEP>, STEP ? kStepNT : kNT,
                                                          apg_team_lds<T, K, R, STEP>(g));
@@ -146,7 +154,7 @@ static hipError_t apg_step_kr(const Group& g, const Inst<T>* insts, const ApgSta
     if constexpr (K >= 3 && K <= 11) {
         const size_t lds = sizeof(T) * lds_apg_step<K, R>();
         auto kern = k_apg_step<T, K, R>;
-        hipError_t e = ensure_lds(kern, lds);
+        hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
         if (e != hipSuccess) return e;
         return launch(kern, dim3(g.grid_f), dim3(kStepNT), lds, s, insts, g.blk_f, g.only, sin, sout);
     } else {
@@ -159,7 +167,7 @@ static hipError_t cg_step_kr(const Group& g, const Inst<T>* insts, const CgState
     if constexpr (K >= 3 && K <= 11) {
         const size_t lds = sizeof(T) * lds_cg_step<K, R>();
         auto kern = k_cg_step<T, K, R>;
-        hipError_t e = ensure_lds(kern, lds);
+        hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
         if (e != hipSuccess) return e;
         return launch(kern, dim3(g.grid_f), dim3(kStepNT), lds, s, insts, g.blk_f, g.only, sin, sout);
     } else {

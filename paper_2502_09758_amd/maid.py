@@ -119,6 +119,11 @@ class Maid:
         """Opt in to the one-pass (Chronopoulos-Gear) CG on one-pass instances."""
         self._check(L.lib().maid_set_one_pass_cg(self.handle, int(bool(enable))), "set_one_pass_cg")
 
+    def set_mfma(self, enable: bool):
+        """Large-kernel correlations on the matrix cores (FP32 storage, K >= 13,
+        4 or 8 rows per thread; the default) or on the vector ALUs."""
+        self._check(L.lib().maid_set_mfma(self.handle, int(bool(enable))), "set_mfma")
+
     def set_one_pass(self, mode: int):
         """Lower-level form where the one-pass form applies: -1 tuned or size
         rule (default), 0 two-pass, 1 one-pass."""
@@ -276,6 +281,7 @@ class MaidBatch:
     set_tile_rows = Maid.set_tile_rows
     set_team = Maid.set_team
     set_one_pass_cg = Maid.set_one_pass_cg
+    set_mfma = Maid.set_mfma
     set_one_pass = Maid.set_one_pass
     one_pass_forms = Maid.one_pass_forms
     profile = Maid.profile
