@@ -422,3 +422,57 @@ def conv_at(p: Problem, th, x, idx):
     lib().oracle_conv_at(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(x, p.shape)),
                          idx.ctypes.data_as(ct.POINTER(ct.c_int64)), len(idx), _d(out))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Section 4.1's baselines on the 2D problem (ADP-IFT, ADP-LISTA).  Pinned in
+# tests/test_oracle_adp.py: the fixed-step iteration against its Fourier
+# closed form and against a torch autograd iteration; the LISTA gradient
+# against torch autograd through the unrolled iterations and against central
+# differences of the unrolled loss; the IFT step against the dense
+# implicit-function route.
+# ----------------------------------------------------------------------------
+def gd_solve(p: Problem, th, y, x0, step, n_iter):
+    """The baselines' lower-level iteration: proximal gradient with a fixed
+    step; the smooth regulariser's proximal map is the identity, so
+    x_{k+1} = x_k - step grad_x h(x_k; theta) (Proposition 1's gradient),
+    n_iter times.  Returns (x_n, [x_0, ..., x_{n-1}])."""
+    x = _f64(x0, p.shape).copy()
+    xs = []
+    for _ in range(int(n_iter)):
+        xs.append(x.copy())
+        x = x - step * h_grad(p, th, y, x)
+    return x, xs
+
+
+def ift_step(p: Problem, a, y, theta, x0, q0, n_lower, lam_x, cg_tol, max_cg, step):
+    """One ADP-IFT upper iteration: n_lower fixed-step iterations from x0, the
+    implicit-function hypergradient there (CG on Algorithm 1's Hessian system
+    from q0 to ||r|| <= cg_tol ||grad g||, then Eq. 3.2 with the Sobolev
+    term), and theta - step z.  Returns a dict (theta, x, q, z, loss =
+    g(x) + r(theta) before the step, cg_iters)."""
+    x, _ = gd_solve(p, theta, y, x0, lam_x, n_lower)
+    grad, g, gn = upper_value_grad(p, a, y, x)
+    loss = g + sobolev_value(p, theta, a)
+    q, ci = adjoint_solve(p, theta, x, grad, q0=q0, tol=cg_tol * gn, max_iter=max_cg)
+    z, _ = hypergrad(p, theta, a, y, x, q, with_r=True)
+    return dict(theta=_f64(theta) - step * z, x=x, q=q, z=z, loss=loss, cg_iters=ci["iters"])
+
+
+def lista_grad(p: Problem, a, y, theta, x0, n_unroll, lam_x):
+    """ADP-LISTA's gradient: F(theta) = g(x_n) + r(theta), x_n the n_unroll
+    fixed-step iterations from x0 (held fixed), differentiated in reverse
+    through the iterations.  With w = dF/dx_{k+1}, the step
+    x_{k+1} = x_k - lam grad_x h(x_k; theta) adds
+    -lam (d grad_x h(x_k) / d theta)^T w = lam z(x_k, w) to dF/dtheta (z the
+    correlation of Eq. 3.2 without r) and passes w - lam H(x_k) w back to
+    x_k; w starts at grad g(x_n).  Returns (dF/dtheta, F, x_n)."""
+    x, xs = gd_solve(p, theta, y, x0, lam_x, n_unroll)
+    w, g, _ = upper_value_grad(p, a, y, x)
+    loss = g + sobolev_value(p, theta, a)
+    dth = sobolev_grad(p, theta, a)
+    for k in range(int(n_unroll) - 1, -1, -1):
+        z, _ = hypergrad(p, theta, None, y, xs[k], w, with_r=False)
+        dth = dth + lam_x * z
+        w = w - lam_x * h_hvp(p, theta, xs[k], w)
+    return dth, loss, x

@@ -306,3 +306,54 @@ def make_batch(n: int = 64, seed: int = 404, size_cap: int | None = None) -> lis
         inst.meta = dict(dtype="f32", shapes=shapes, index=b)
         out.append(inst)
     return out
+
+
+# ----------------------------------------------------------------------------
+# Section 4.1's 1D deconvolution data
+# ----------------------------------------------------------------------------
+@dataclass
+class Signal1D:
+    name: str
+    n: int
+    A: np.ndarray        # n x n Gaussian blur matrix (the known operator; B_0 = A)
+    x_true: np.ndarray
+    y: np.ndarray
+    alpha1: float
+    alpha2: float
+    meta: dict
+
+
+def gaussian_matrix(n: int, sigma: float) -> np.ndarray:
+    """The full n x n matrix of a 1D convolution with a Gaussian of standard
+    deviation sigma (samples), truncated at 4 sigma, zero boundary, taps
+    normalised to sum 1 in the interior."""
+    r = int(np.ceil(4 * sigma))
+    t = np.arange(-r, r + 1, dtype=np.float64)
+    k = np.exp(-0.5 * (t / sigma) ** 2)
+    k /= k.sum()
+    A = np.zeros((n, n))
+    for i in range(n):
+        for o, w in zip(range(-r, r + 1), k):
+            j = i + o
+            if 0 <= j < n:
+                A[i, j] = w
+    return A
+
+
+def make_1d(n: int = 512, seed: int = 7, sigma: float = 5.0, noise: float = 5e-3, alpha1: float = 1.2e-3,
+            alpha2: float = 4e-3, pieces: int | None = None) -> Signal1D:
+    """A piecewise-constant signal (jumps at random positions, levels
+    U[-1, 1], a quarter of the pieces at zero), blurred by the Gaussian
+    matrix of Section 4.1 (sigma 5) plus N(0, noise^2) noise; Section 4.1's
+    elastic-net weights."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = pieces or max(4, n // 32)
+    cuts = np.sort(rng.choice(np.arange(1, n), size=m - 1, replace=False))
+    levels = rng.uniform(-1.0, 1.0, size=m)
+    levels[rng.random(m) < 0.25] = 0.0
+    x = np.zeros(n)
+    for lv, a, b in zip(levels, np.concatenate([[0], cuts]), np.concatenate([cuts, [n]])):
+        x[a:b] = lv
+    A = gaussian_matrix(n, sigma)
+    y = A @ x + noise * rng.standard_normal(n)
+    return Signal1D("1d", n, A, x, y, alpha1, alpha2, dict(sigma=sigma, noise=noise, seed=seed, pieces=m))
