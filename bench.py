@@ -117,7 +117,7 @@ def roofline_for(prof: dict, N: int, K: int, esz: int, C: int):
 
 KERNEL_SOURCES = ("paper_2502_09758_amd/csrc/kernels.cuh", "paper_2502_09758_amd/csrc/launch.cuh",
                   "paper_2502_09758_amd/csrc/devctx.h", "paper_2502_09758_amd/csrc/step.cuh",
-                  "paper_2502_09758_amd/csrc/team.cuh")
+                  "paper_2502_09758_amd/csrc/team.cuh", "paper_2502_09758_amd/csrc/mfconv.cuh")
 
 
 def kernel_source_hash() -> str:
@@ -238,6 +238,211 @@ def inexact_gradient_work(insts, dt, tol_lower=1e-3, tol_cg=1e-3):
     return out
 
 
+def batch_maid_work(insts, dt, steps=20, eps0=1e-3, step0=1e-4):
+    """The batched form's MAID run: `steps` Algorithm 2 iterations for every
+    instance of the ragged batch, each instance with its own adaptive
+    tolerances, step size and decisions, once through one maid_batch_steps
+    call (lockstep: all instances that need a solve share its launches) and once
+    through one plain context per instance (same tile heights and lower-level
+    forms, so bitwise the same solves and decisions).  Pixel-iterations count
+    (lower + CG iterations) x C*H*W over all instances and steps."""
+    import torch
+    from paper_2502_09758_amd import _lib as L
+    from paper_2502_09758_amd.maid import Maid, MaidBatch, MaidState
+
+    specs = [dict(C=i.C, H=i.H, W=i.W, K=i.K, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta) for i in insts]
+    th = [torch.tensor(i.a, dtype=torch.float64, device="cuda") for i in insts]
+    ys = [torch.tensor(i.y, dtype=dt, device="cuda") for i in insts]
+    mb = MaidBatch(specs, dt)
+    rows = mb.autotune(th, ys)
+    forms = mb.one_pass_forms()
+    solos = []
+    for k, i in enumerate(insts):
+        m = Maid(i.C, i.H, i.W, i.K, dt, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta)
+        m.set_tile_rows(rows[k])
+        m.set_one_pass(forms[k])
+        solos.append(m)
+    n = len(insts)
+    pix = [i.C * i.H * i.W for i in insts]
+    # the batch's caps: every solve of the 64 instances stops at 500 iterations
+    hp = dict(BENCH_HP, max_lower_iter=500, max_cg_iter=500)
+
+    def states():
+        return [MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=eps0, delta=eps0, step=step0)
+                for a, y in zip(th, ys)]
+
+    def batched():
+        st = states()
+        work = acc = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(0, steps, 5):
+            _, infos = mb.maid_steps(th, ys, st, min(5, steps - k), **hp)
+            work += sum((f["lower_iters"] + f["cg_iters"]) * p for f, p in zip(infos, pix))
+            acc += sum(f["accepted"] for f in infos)
+            print(f"[bench] batched MAID: {k + min(5, steps - k)} steps, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, work, acc, st
+
+    def plain():
+        st = states()
+        work = acc = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n):
+            for _ in range(steps):
+                rc, f = solos[k].maid_step(th[k], ys[k], st[k], **hp)
+                work += (f["lower_iters"] + f["cg_iters"]) * pix[k]
+                acc += f["accepted"]
+                if rc not in (L.OK, L.MAXITER):     # the accuracy floor (or an error) ends the run
+                    break
+            if k % 8 == 7:
+                print(f"[bench] plain MAID: {k + 1} instances, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, work, acc, st
+
+    tb, wb, ab, sb = batched()
+    tp, wp, ap, sp = plain()
+    same = all(torch.equal(a.theta, b.theta) and torch.equal(a.x, b.x) for a, b in zip(sb, sp))
+    out = dict(instances=n, steps=steps, eps0=eps0, step0=step0, hparams=hp,
+               pixel_iterations=wb, accepted_steps=ab,
+               batched_ms=round(tb * 1e3, 3), plain_ms=round(tp * 1e3, 3),
+               batched_pixel_iterations_per_s=round(wb / tb, 1), plain_pixel_iterations_per_s=round(wp / tp, 1),
+               speedup=round(tp / tb, 3), same_work=wb == wp, bitwise_equal=bool(same), tiles=mb.config())
+    mb.close()
+    for m in solos:
+        m.close()
+    return out
+
+
+def adp_compare(workload="cfg2", budget_s=4.0, n_lower=500, n_unroll=50, lam_x=0.1):
+    """Section 4.1's comparison, on a 2D workload and this library's kernels:
+    MAID (Algorithm 2), ADP-IFT (n_lower fixed-step lower-level iterations,
+    then the implicit-function hypergradient) and ADP-LISTA (n_unroll
+    unrolled iterations, differentiated in reverse), all from theta_0 = a and
+    x_0 = y with the same initial upper step, each for budget_s of wall time.
+    Per method: the upper-level loss g(x) + r(theta) it computes at its
+    iterate against time; then the time each needs to reach the best loss
+    that all three reach (the paper reports MAID at about 1/2 of ADP-LISTA's
+    and 1/4 of ADP-IFT's time on its 1D problem)."""
+    import torch
+    from paper_2502_09758_amd import _lib as L
+    from paper_2502_09758_amd import synth
+    from paper_2502_09758_amd.maid import Maid, MaidState
+
+    inst = synth.make(workload)
+    dt = torch.float64 if inst.meta["dtype"] == "f64" else torch.float32
+    C, H, W, K = inst.C, inst.H, inst.W, inst.K
+    ms = MAID_SETTINGS[workload]
+    a = torch.tensor(inst.a, dtype=torch.float64, device="cuda")
+    y = torch.tensor(inst.y, dtype=dt, device="cuda")
+
+    def state():
+        return MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=ms["eps0"], delta=ms["eps0"],
+                         step=ms["step0"])
+
+    def run(method):
+        m = Maid(C, H, W, K, dt, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta)
+        if method == "lista":
+            m.set_one_pass(0)
+        st = state()
+        traj, lower, cg, steps = [], 0, 0, 0
+        diverged = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            try:
+                if method == "maid":
+                    rc, f = m.maid_step(a, y, st, **BENCH_HP)
+                elif method == "ift":
+                    rc, f = m.ift_step(a, y, st, n_lower=n_lower, lambda_x=lam_x, cg_tol=1e-3, max_cg=1000)
+                else:
+                    rc, f = m.lista_step(a, y, st, n_unroll=n_unroll, lambda_x=lam_x)
+            except L.MaidError as e:
+                # a fixed upper step can drive theta where the fixed lower step no longer converges
+                diverged = dict(step=steps, error=str(e))
+                break
+            torch.cuda.synchronize()
+            steps += 1
+            lower += f["lower_iters"]
+            cg += f["cg_iters"]
+            traj.append((time.perf_counter() - t0, f["ell_k"]))
+            if method == "maid" and rc == L.ACCURACY_FLOOR:
+                break
+        m.close()
+        losses = [v for _, v in traj] or [float("nan")]
+        return dict(steps=steps, lower_iters=lower, cg_or_hessian_products=cg,
+                    seconds=round(traj[-1][0], 3) if traj else 0.0, loss_first=losses[0], loss_best=min(losses),
+                    loss_last=losses[-1], diverged=diverged, traj=traj)
+
+    out = {m: run(m) for m in ("maid", "ift", "lista")}
+    reached = [r for r in out.values() if r["traj"]]
+    target = max(r["loss_best"] for r in reached)
+    for r in out.values():
+        hit = [t for t, v in r.pop("traj") if v <= target]
+        r["seconds_to_target"] = round(hit[0], 4) if hit else None
+    tm = out["maid"]["seconds_to_target"]
+
+    def frac(other):
+        t = out[other]["seconds_to_target"]
+        return round(tm / t, 4) if (tm is not None and t) else None
+    return dict(workload=f"{workload}: {H}x{W}x{C}, {K}x{K} kernel, FP32 storage" if dt == torch.float32 else workload,
+                budget_s=budget_s, lambda_x=lam_x, n_lower_ift=n_lower, n_unroll_lista=n_unroll,
+                step0=ms["step0"], eps0=ms["eps0"], target_loss=target, methods=out,
+                maid_time_fraction_of_ift=frac("ift"), maid_time_fraction_of_lista=frac("lista"))
+
+
+def dense1d_work(n=1024, batch=64, steps=3, iters=200):
+    """Section 4.1's 1D problem, batched: `batch` signals of n samples (the
+    Gaussian sigma-5 matrix, the elastic net), B_0 = A.  The lower-level
+    solver's throughput over `iters` fixed proximal-gradient iterations of
+    the whole batch (an iteration reads B twice, by rows and by columns:
+    2 n^2 FP64 values per instance, the algorithmic bytes of the roofline),
+    then `steps` Algorithm 2 iterations of the batch with Section 4.1's
+    settings (eps_0 = 1e-2, initial step 0.1, lambda_x = 0.1, at most 300
+    lower-level iterations)."""
+    import numpy as np
+    import torch
+    from paper_2502_09758_amd import synth
+    from paper_2502_09758_amd.maid import Maid1D
+
+    sigs = [synth.make_1d(n=n, seed=100 + k) for k in range(batch)]
+    A = torch.tensor(sigs[0].A, dtype=torch.float64, device="cuda")
+    y = torch.tensor(np.stack([s.y for s in sigs]), dtype=torch.float64, device="cuda")
+    m = Maid1D(n, batch, sigs[0].alpha1, sigs[0].alpha2)
+    B = A.unsqueeze(0).repeat(batch, 1, 1).contiguous()
+    x = torch.zeros((batch, n), dtype=torch.float64, device="cuda")
+    m.lower_solve(B, y, x.clone(), 0.1, 0.0, max_iter=16)
+    x1 = x.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.lower_solve(B, y, x1, 0.1, 0.0, max_iter=iters)
+    torch.cuda.synchronize()
+    t_it = (time.perf_counter() - t0) / iters
+    gbs = batch * 2 * n * n * 8 / t_it / 1e9
+    q = torch.zeros_like(x)
+    sched = [dict(eps=1e-2, delta=1e-2, step=0.1, k=0) for _ in range(batch)]
+    hp = dict(max_lower_iter=300, max_cg_iter=1000, eps_min=1e-6)
+    lower = cg = acc = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, infos = m.step(A, y, B, x, q, sched, lam_x=0.1, **hp)
+        lower += sum(f["lower_iters"] for f in infos)
+        cg += sum(f["cg_iters"] for f in infos)
+        acc += sum(f["accepted"] for f in infos)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    m.close()
+    return dict(workload=f"{batch} signals x {n} samples, full {n}x{n} operators, FP64",
+                lower_iteration_ms=round(t_it * 1e3, 4),
+                lower_iteration_GB_s=round(gbs, 1), lower_iteration_hbm_frac=round(gbs / (PEAK_HBM / 1e9), 3),
+                maid_steps=steps, maid_ms_per_step=round(ts / steps * 1e3, 2), lower_iters=lower, cg_iters=cg,
+                accepted=acc, sample_iterations_per_s=round((lower + cg) * n / ts, 1))
+
+
 def autograd_work(inst, dt, tol=1e-3, cg_tol=1e-3):
     """The autograd form (forward: lower-level solve; backward: CG adjoint and
     the theta correlation) against the same three plain calls, at the same
@@ -283,6 +488,59 @@ def autograd_work(inst, dt, tol=1e-3, cg_tol=1e-3):
                tiles=m.config())
     m.close()
     return out
+
+
+def roofline_sweep(iters: int = 12):
+    """Per-kernel throughput over working sets of at least 1 GB: 4096x4096x1
+    and 2048x2048x3 (FP32 storage) with K in {5, 7, 9, 13, 15, 21, 31}
+    (normalised Gaussian kernels, sigma = K/6, on the piecewise-constant
+    image of the 256x256 plain-method recipe at that size): a fixed number
+    of lower-level and CG iterations with every launch timed, the algorithmic
+    bytes and flops of each kernel kind (kernel_model) over its average
+    launch time, against the HBM and vector-ALU peaks."""
+    import numpy as np
+    import torch
+    from paper_2502_09758_amd import synth
+    from paper_2502_09758_amd.maid import Maid
+
+    rows = []
+    for C, H, W in ((1, 4096, 4096), (3, 2048, 2048)):
+        base = synth.make("cfg2", H=H, W=W, C=C, K=5)
+        y = torch.tensor(base.y, dtype=torch.float32, device="cuda")
+        N = C * H * W
+        for K in (5, 7, 9, 13, 15, 21, 31):
+            c0 = (K - 1) // 2
+            u = np.arange(K) - c0
+            g = np.exp(-(u[:, None] ** 2 + u[None, :] ** 2) / (2.0 * (K / 6.0) ** 2))
+            th = torch.tensor(g / g.sum(), dtype=torch.float64, device="cuda")
+            m = Maid(C, H, W, K, torch.float32, alpha=base.alpha, eps_tv=base.eps_tv)
+            rows_auto = m.autotune(th, y)
+            x = y.clone()
+            q = torch.zeros_like(y)
+            m.lower_solve(th, y, x, 0.0, max_iter=2)
+            m.profile(True)
+            m.lower_solve(th, y, x, 0.0, max_iter=iters, L_est=1.5)
+            m.adjoint_solve(th, x, y, q, 0.0, max_iter=iters)
+            torch.cuda.synchronize()
+            prof = m.profile_read()
+            m.profile(False)
+            kinds = {}
+            for name, (launches, work, ms) in prof.items():
+                if work == 0 or name in ("other", "hg_corr"):
+                    continue
+                b, f = kernel_model(name, K, 4, C)
+                us = ms * 1e3 / launches
+                gbs = b * N * work / launches / (us * 1e-6) / 1e9
+                tfs = f * N * work / launches / (us * 1e-6) / 1e12
+                kinds[name] = dict(avg_us=round(us, 2), work_launches=work, GB_s=round(gbs, 1),
+                                   hbm_frac=round(gbs / (PEAK_HBM / 1e9), 3), TFLOP_s=round(tfs, 2),
+                                   alu_frac=round(tfs / (PEAK_FP32 / 1e12), 3))
+            rows.append(dict(shape=f"{C}x{H}x{W}", K=K, tiles=m.config(), autotuned_rows=rows_auto, kernels=kinds))
+            print(f"[sweep] {C}x{H}x{W} K={K}: " + ", ".join(f"{k} {v['avg_us']} us ({v['hbm_frac']} HBM, "
+                                                             f"{v['alu_frac']} ALU)" for k, v in kinds.items()),
+                  file=sys.stderr, flush=True)
+            m.close()
+    return rows
 
 
 def cpu_model() -> str:
@@ -344,6 +602,16 @@ def cpu_baseline(inst, budget_s: float = 15.0, single_budget_s: float = 8.0):
     return out
 
 
+def leg(fn, *a, **kw):
+    """A secondary measurement: its failure is recorded in the line instead
+    of ending the benchmark."""
+    try:
+        return fn(*a, **kw)
+    except Exception as e:  # noqa: BLE001
+        print(f"[bench] {fn.__name__} failed: {e}", file=sys.stderr, flush=True)
+        return dict(error=f"{type(e).__name__}: {e}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +622,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="per-kernel roofline sweep over >= 1 GB working sets instead of the benchmark")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="MAID steps of the batched-vs-plain MAID run (0: skip it)")
+    ap.add_argument("--adp-budget", type=float, default=4.0,
+                    help="seconds per method of the MAID / ADP-IFT / ADP-LISTA comparison (0: skip it)")
+    ap.add_argument("--d1-batch", type=int, default=64,
+                    help="signals of the 1D problem's batched measurement (0: skip it)")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-vs-plain comparison")
     ap.add_argument("--rows", type=int, default=0,
                     help="pin the tile height (rows per thread) instead of running the autotuner")
@@ -365,6 +641,11 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.sweep:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"sweep": roofline_sweep()}), flush=True)
         return
 
     import torch
@@ -384,6 +665,16 @@ def main():
     if not args.no_batch:
         print("[bench] batched vs plain (64-instance ragged batch)", file=sys.stderr, flush=True)
         out["batched_vs_plain"] = inexact_gradient_work(synth.make_batch(), torch.float32)
+    if not args.no_batch and args.batch_steps > 0:
+        print(f"[bench] batched MAID: {args.batch_steps} steps of the 64-instance ragged batch", file=sys.stderr,
+              flush=True)
+        out["batch_maid_steps"] = leg(batch_maid_work, synth.make_batch(), torch.float32, steps=args.batch_steps)
+    if args.adp_budget > 0:
+        print("[bench] MAID vs ADP-IFT vs ADP-LISTA (256x256)", file=sys.stderr, flush=True)
+        out["adp_baselines"] = leg(adp_compare, "cfg2", budget_s=args.adp_budget)
+    if args.d1_batch > 0:
+        print(f"[bench] 1D problem: {args.d1_batch} signals of 1024 samples", file=sys.stderr, flush=True)
+        out["dense1d"] = leg(dense1d_work, n=1024, batch=args.d1_batch)
     if not args.no_autograd:
         print("[bench] autograd vs plain (512x512x3, K=15)", file=sys.stderr, flush=True)
         out["autograd_vs_plain"] = autograd_work(synth.make("cfg3"), torch.float32)

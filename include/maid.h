@@ -46,6 +46,7 @@ extern "C" {
 #endif
 
 enum { MAID_F32 = 0, MAID_F64 = 1 };
+enum { MAID_BOUNDARY_ZERO = 0, MAID_BOUNDARY_PERIODIC = 1 };
 enum { MAID_REG_TV = 0, MAID_REG_TV_CHANNELWISE = 1, MAID_REG_QUADRATIC = 2 };
 
 enum {
@@ -61,13 +62,16 @@ enum {
 
 /* Problem description.  C in 1..3, K odd with 1 <= K <= 31 and K <= min(H,W),
    H*W < 2^31.
+   boundary: MAID_BOUNDARY_ZERO (the blur reads zero outside the image; the
+   setting of Section 4.2's experiments, and the only one the kernels
+   implement: MAID_BOUNDARY_PERIODIC is rejected with MAID_EINVAL).
    reg: MAID_REG_TV (smoothed TV, one gradient magnitude per pixel over all
    channels), MAID_REG_TV_CHANNELWISE (one per channel and pixel) or
    MAID_REG_QUADRATIC (R = 1/2 ||Dx||^2, the Tikhonov case).  alpha >= 0,
    eps_tv > 0 (TV only), beta >= 0, h1_w0 = weight of the L2 part of the H1
    norm (1 full norm, 0 seminorm). */
 typedef struct {
-    int32_t H, W, C, K, dtype, reg;
+    int32_t H, W, C, K, dtype, boundary, reg;
     double alpha, eps_tv, beta, h1_w0;
 } maid_desc;
 
@@ -213,8 +217,40 @@ int maid_lower_solve(maid_ctx* ctx, const void* theta, const void* y, void* x,
                      double tol, int32_t max_iter, double* L_inout,
                      maid_solve_info* info, int32_t* trace_bt, hipStream_t stream);
 
-/* Upper-level value and gradient at x: rho = a*x - y, g = 1/2||rho||^2,
-   grad_out = a.rho (adjoint convolution; nullable), gradnorm = ||grad||_2. */
+/* Outcome of maid_lower_solve_refined's Newton steps. */
+typedef struct {
+    int32_t newton_steps;   /* steps taken (an undone step not counted) */
+    int32_t cg_iters;       /* CG iterations over all steps */
+    int32_t status;         /* MAID_OK: rel_step <= rel_tol; MAID_MAXITER otherwise */
+    double rel_step;        /* ||d|| / ||x|| of the last step taken */
+    double grad_norm;       /* ||grad_x h|| at the returned x (residual with FP64 sums) */
+} maid_refine_info;
+
+/* The precision form of Algorithm 1's lower-level solve (Section 4's
+   accuracy at any storage type): maid_lower_solve to tol (FISTA), then
+   Newton refinement -- steps x <- x - d with
+   (theta.theta* + alpha grad^2 R(x)) d = grad_x h(x) (Proposition 1's
+   Hessian and gradient), d solved by CG (the adjoint kernels) in the
+   storage type to 1e-2 relative residual.  With FP32 storage this is
+   mixed-precision iterative refinement: the iterate is accumulated in FP64,
+   its gradient is evaluated by the FP64 passes of a companion FP64 context
+   of the same shape (allocated at the first call on the context, about
+   twice the context's own workspace, kept until maid_destroy), and x is that
+   iterate rounded to FP32.  Steps stop when ||d|| <= rel_tol ||x||, when a
+   step is larger than the one before (it is undone; MAXITER), or after
+   max_newton steps.  Arrays as in maid_lower_solve; info describes the
+   FISTA phase, rinfo (nullable) the refinement (grad_norm: the FP64
+   gradient norm at the FP64 iterate).  Returns the FISTA phase's error if
+   it failed, else MAID_OK / MAID_MAXITER of the refinement, or an error. */
+int maid_lower_solve_refined(maid_ctx* ctx, const void* theta, const void* y, void* x, double tol,
+                             int32_t max_iter, double rel_tol, int32_t max_newton, int32_t max_cg,
+                             double* L_inout, maid_solve_info* info, maid_refine_info* rinfo,
+                             hipStream_t stream);
+
+/* Upper-level value and gradient at x (Eq. 2.5 with T(a, .) the blur by the
+   known kernel a; its gradient is the right-hand side of Algorithm 1's
+   Hessian system): rho = a*x - y, g = 1/2||rho||^2, grad_out = a.rho
+   (adjoint convolution; nullable), gradnorm = ||grad||_2. */
 int maid_upper_value_grad(maid_ctx* ctx, const void* a, const void* y, const void* x,
                           void* grad_out, double* g_out, double* gradnorm_out,
                           hipStream_t stream);
@@ -285,6 +321,63 @@ int maid_set_step_trace(maid_ctx* ctx, int32_t inst, int32_t* words, int32_t cap
                         int32_t cap_values);
 int maid_step_trace_length(const maid_ctx* ctx, int32_t* n_words, int32_t* n_values);
 
+/* ---------------------------------------------------------------- Section 4.1's baselines
+   The two methods MAID is compared with in Section 4.1 (ADP-IFT and
+   ADP-LISTA), rebuilt on this library's kernels for the 2D problem.  Both
+   run the proximal-gradient iteration of the lower level with a fixed step
+   lambda_x; the smooth TV regulariser's proximal map is the identity, so an
+   iteration is x <- x - lambda_x grad_x h(x; theta).  Single-instance
+   contexts only. */
+
+/* n_iter fixed-step iterations x_{k+1} = x_k - step grad_x h(x_k; theta)
+   (fewer if ||grad_x h(x_k)|| <= tol first; tol = 0: exactly n_iter), on the
+   FISTA passes with the momentum off and every step accepted.  x: in x_0,
+   out the last iterate.  hist (DEVICE, nullable, n_iter*C*H*W elements of
+   the storage type): x_1 .. x_n in order, x_k at hist + (k-1)*C*H*W; it
+   needs the two-pass lower-level form (maid_set_one_pass(ctx, 0) for
+   instances that would take the one-pass form; MAID_EINVAL otherwise).
+   info as for maid_lower_solve (iters = steps taken, backtracks 0, L =
+   1/step).  Returns MAID_OK if the tolerance was met, MAID_MAXITER after
+   n_iter steps, or an error. */
+int maid_gd_solve(maid_ctx* ctx, const void* theta, const void* y, void* x, double step, int32_t n_iter,
+                  double tol, void* hist, maid_solve_info* info, hipStream_t stream);
+
+/* Proposition 1's Hessian of the lower level at x applied to w:
+   out = (theta.theta* + alpha grad^2 R(x)) w, computed by the adjoint
+   solve's set-up passes (the same kernels and arithmetic as its products).
+   out must not alias x or w. */
+int maid_hessian_apply(maid_ctx* ctx, const void* theta, const void* x, const void* w, void* out,
+                       hipStream_t stream);
+
+/* One upper-level iteration of ADP-IFT: n_lower fixed-step iterations of
+   the lower level from state->x (warm start), the upper-level gradient
+   there, CG on H(x) q = grad g (Algorithm 1's Hessian system) from state->q
+   to ||r|| <= cg_tol ||grad g|| or max_cg iterations, the hypergradient z of
+   Eq. (3.2) (with the Sobolev term), and theta <- theta - state->step z.
+   state->theta, x and q are updated in place, state->k incremented (eps,
+   delta, L unused).  info (HOST, nullable): lower_iters, cg_iters, ell_k =
+   g(x) + r(theta) before the step, znorm = ||z||, cg_status; accepted =
+   trials = 1.  Returns MAID_MAXITER if CG stopped at max_cg. */
+int maid_ift_step(maid_ctx* ctx, const void* a, const void* y, maid_state* state, int32_t n_lower,
+                  double lambda_x, double cg_tol, int32_t max_cg, maid_step_info* info, hipStream_t stream);
+
+/* One upper-level iteration of ADP-LISTA: n_unroll fixed-step iterations
+   from state->x, keeping every iterate (library workspace, allocated at the
+   first call and grown on demand: (n_unroll + 1)*C*H*W elements), the loss
+   g(x_n) + r(theta), its exact gradient in theta through the unrolled
+   iterations by the reverse recursion
+     w_n = grad g(x_n),  dtheta = grad r(theta) + lambda_x sum_k z(x_k, w_{k+1}),
+     w_k = w_{k+1} - lambda_x H(x_k) w_{k+1},
+   with z(x, w) = -(d grad_x h / d theta)^T w (the correlation of Eq. 3.2)
+   and H Proposition 1's Hessian, and theta <- theta - state->step dtheta.
+   state->x becomes x_n, state->k is incremented (q, eps, delta, L unused).
+   Needs the two-pass lower-level form (maid_set_one_pass(ctx, 0);
+   MAID_EINVAL otherwise).  info (HOST, nullable): lower_iters = n_unroll,
+   cg_iters = Hessian products taken, ell_k = the loss before the step,
+   znorm = ||dtheta||; accepted = trials = 1. */
+int maid_lista_step(maid_ctx* ctx, const void* a, const void* y, maid_state* state, int32_t n_unroll,
+                    double lambda_x, maid_step_info* info, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batched form
    One context over n independent problem instances of different sizes (a
    ragged batch; each instance has its own maid_desc, all with the same
@@ -307,6 +400,8 @@ int maid_step_trace_length(const maid_ctx* ctx, int32_t* n_words, int32_t* n_val
    MAID_OK, else the code of the first instance that did not (instances with
    a negative code leave their outputs unwritten; the others are written). */
 int maid_create_batch(const maid_desc* descs, int32_t n, maid_ctx** out);
+/* The same call under the name maid_batch_create. */
+int maid_batch_create(const maid_desc* descs, int32_t n, maid_ctx** out);
 /* Number of instances of a context (0 for NULL). */
 int32_t maid_batch_size(const maid_ctx* ctx);
 /* maid_lower_solve for every instance i: theta[i], y[i], x[i] (in/out),
@@ -336,6 +431,18 @@ int maid_batch_hypergrad(maid_ctx* ctx, const void* const* theta, const void* co
 int maid_batch_step(maid_ctx* ctx, const void* const* a, const void* const* y,
                     maid_state* states, const maid_hparams* hp, maid_step_info* info,
                     hipStream_t stream);
+/* n_steps (>= 1) outer iterations of Algorithm 2 for every instance, in
+   lockstep as maid_batch_step (the same as n_steps calls of it, except that
+   an instance whose step returns MAID_ACCURACY_FLOOR or an error takes no
+   further step).  info[i] (HOST, nullable): accepted, trials, retries,
+   lower_iters and cg_iters summed over the instance's steps; psi, ell_k,
+   ell_next, znorm and status of its last step; lower_status / cg_status
+   MAID_MAXITER if any of its solves stopped at the cap.  Returns the first
+   instance's final code that is not MAID_OK (a cap reached in any step
+   counts as MAID_MAXITER unless a later step ended the instance's run). */
+int maid_batch_steps(maid_ctx* ctx, const void* const* a, const void* const* y,
+                     maid_state* states, const maid_hparams* hp, maid_step_info* info,
+                     int32_t n_steps, hipStream_t stream);
 
 /* Kernel timing (for measurement and profiling tools).  maid_profile(ctx, 1)
    resets the counters and, until maid_profile(ctx, 0), launches every kernel

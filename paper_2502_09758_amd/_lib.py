@@ -15,6 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmaid.so")
 
 MAID_F32, MAID_F64 = 0, 1
+MAID_BOUNDARY_ZERO, MAID_BOUNDARY_PERIODIC = 0, 1
 MAID_REG_TV, MAID_REG_TV_CHANNELWISE, MAID_REG_QUADRATIC = 0, 1, 2
 OK, MAXITER, ACCURACY_FLOOR = 0, 1, 2
 EINVAL, ENOMEM, EHIP, NOT_SPD, NONFINITE = -1, -2, -3, -4, -5
@@ -28,13 +29,17 @@ EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string
            "maid_profile", "maid_profile_read", "maid_profile_name",
            "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
            "maid_batch_step", "maid_autotune", "maid_batch_upper_value_grad", "maid_batch_hypergrad",
-           "maid_set_step_trace", "maid_step_trace_length")
+           "maid_set_step_trace", "maid_step_trace_length", "maid_lower_solve_refined",
+           "maid_batch_create", "maid_batch_steps",
+           "maid_gd_solve", "maid_hessian_apply", "maid_ift_step", "maid_lista_step",
+           "maid1d_create", "maid1d_destroy", "maid1d_last_error", "maid1d_lower_solve", "maid1d_upper_value_grad",
+           "maid1d_adjoint_solve", "maid1d_hypergrad", "maid1d_step")
 PROF_KINDS = 12
 
 
 class maid_desc(ct.Structure):
     _fields_ = [("H", ct.c_int32), ("W", ct.c_int32), ("C", ct.c_int32), ("K", ct.c_int32),
-                ("dtype", ct.c_int32), ("reg", ct.c_int32), ("alpha", ct.c_double),
+                ("dtype", ct.c_int32), ("boundary", ct.c_int32), ("reg", ct.c_int32), ("alpha", ct.c_double),
                 ("eps_tv", ct.c_double), ("beta", ct.c_double), ("h1_w0", ct.c_double)]
 
 
@@ -43,11 +48,24 @@ class maid_solve_info(ct.Structure):
                 ("res_norm", ct.c_double), ("obj", ct.c_double), ("L", ct.c_double)]
 
 
+class maid_refine_info(ct.Structure):
+    _fields_ = [("newton_steps", ct.c_int32), ("cg_iters", ct.c_int32), ("status", ct.c_int32),
+                ("rel_step", ct.c_double), ("grad_norm", ct.c_double)]
+
+
 class maid_hparams(ct.Structure):
     _fields_ = [("rho_lo", ct.c_double), ("rho_hi", ct.c_double), ("nu_lo", ct.c_double),
                 ("nu_hi", ct.c_double), ("lambda_", ct.c_double), ("mu", ct.c_double),
                 ("L_g", ct.c_double), ("eps_min", ct.c_double), ("max_bt", ct.c_int32),
                 ("max_lower_iter", ct.c_int32), ("max_cg_iter", ct.c_int32)]
+
+
+class maid1d_desc(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("batch", ct.c_int32), ("alpha1", ct.c_double), ("alpha2", ct.c_double)]
+
+
+class maid1d_sched(ct.Structure):
+    _fields_ = [("eps", ct.c_double), ("delta", ct.c_double), ("step", ct.c_double), ("k", ct.c_int32)]
 
 
 class maid_state(ct.Structure):
@@ -106,6 +124,9 @@ def lib():
     L.maid_one_pass_forms.restype = ct.c_int
     L.maid_lower_solve.argtypes = [P, P, P, P, d, i32, dp, ct.POINTER(maid_solve_info), ct.POINTER(i32), P]
     L.maid_lower_solve.restype = ct.c_int
+    L.maid_lower_solve_refined.argtypes = [P, P, P, P, d, i32, d, i32, i32, dp, ct.POINTER(maid_solve_info),
+                                           ct.POINTER(maid_refine_info), P]
+    L.maid_lower_solve_refined.restype = ct.c_int
     L.maid_upper_value_grad.argtypes = [P, P, P, P, P, dp, dp, P]
     L.maid_upper_value_grad.restype = ct.c_int
     L.maid_adjoint_solve.argtypes = [P, P, P, P, P, d, i32, ct.POINTER(maid_solve_info), P]
@@ -137,6 +158,37 @@ def lib():
     L.maid_batch_step.argtypes = [P, PP, PP, ct.POINTER(maid_state), ct.POINTER(maid_hparams),
                                   ct.POINTER(maid_step_info), P]
     L.maid_batch_step.restype = ct.c_int
+    L.maid_batch_steps.argtypes = [P, PP, PP, ct.POINTER(maid_state), ct.POINTER(maid_hparams),
+                                   ct.POINTER(maid_step_info), i32, P]
+    L.maid_batch_steps.restype = ct.c_int
+    L.maid_batch_create.argtypes = [ct.POINTER(maid_desc), i32, ct.POINTER(P)]
+    L.maid_batch_create.restype = ct.c_int
+    L.maid_gd_solve.argtypes = [P, P, P, P, d, i32, d, P, ct.POINTER(maid_solve_info), P]
+    L.maid_gd_solve.restype = ct.c_int
+    L.maid_hessian_apply.argtypes = [P, P, P, P, P, P]
+    L.maid_hessian_apply.restype = ct.c_int
+    L.maid_ift_step.argtypes = [P, P, P, ct.POINTER(maid_state), i32, d, d, i32, ct.POINTER(maid_step_info), P]
+    L.maid_ift_step.restype = ct.c_int
+    L.maid_lista_step.argtypes = [P, P, P, ct.POINTER(maid_state), i32, d, ct.POINTER(maid_step_info), P]
+    L.maid_lista_step.restype = ct.c_int
+    SI = ct.POINTER(maid_solve_info)
+    L.maid1d_create.argtypes = [ct.POINTER(maid1d_desc), ct.POINTER(P)]
+    L.maid1d_create.restype = ct.c_int
+    L.maid1d_destroy.argtypes = [P]
+    L.maid1d_destroy.restype = None
+    L.maid1d_last_error.argtypes = [P]
+    L.maid1d_last_error.restype = ct.c_char_p
+    L.maid1d_lower_solve.argtypes = [P, P, P, P, d, dp, i32, SI, P]
+    L.maid1d_lower_solve.restype = ct.c_int
+    L.maid1d_upper_value_grad.argtypes = [P, P, P, P, P, dp, dp, P]
+    L.maid1d_upper_value_grad.restype = ct.c_int
+    L.maid1d_adjoint_solve.argtypes = [P, P, P, P, P, dp, i32, SI, P]
+    L.maid1d_adjoint_solve.restype = ct.c_int
+    L.maid1d_hypergrad.argtypes = [P, P, P, P, P, P, dp, P]
+    L.maid1d_hypergrad.restype = ct.c_int
+    L.maid1d_step.argtypes = [P, P, P, P, P, P, ct.POINTER(maid1d_sched), ct.POINTER(maid_hparams), d,
+                              ct.POINTER(maid_step_info), P]
+    L.maid1d_step.restype = ct.c_int
     L.maid_batch_upper_value_grad.argtypes = [P, PP, PP, PP, PP, dp, dp, P]
     L.maid_batch_upper_value_grad.restype = ct.c_int
     L.maid_batch_hypergrad.argtypes = [P, PP, PP, PP, PP, PP, i32, PP, dp, P]

@@ -12,6 +12,10 @@ upper-level term: given v = dL/dxhat it solves H q = v by conjugate gradients
 
 Both directions run in the HIP kernels of libmaid; this module only wires
 them into torch.autograd.  The CG tolerance is relative to ||v||.
+
+With `record` (a dict) the calls leave what a replay needs in it: "lower"
+(the forward solve's SolveInfo, with its backtracking trace), "cg" (the
+adjoint solve's SolveInfo) and "q" (the adjoint solution).
 """
 from __future__ import annotations
 
@@ -23,14 +27,17 @@ from .maid import Maid
 class MaidSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, y, maid: Maid, tol: float = 1e-4, cg_tol: float = 1e-6, max_iter: int = 300,
-                max_cg: int = 1000, x0=None):
+                max_cg: int = 1000, x0=None, record=None):
         theta_c = theta.detach().contiguous()
         y_c = y.detach().contiguous()
         x = (x0.detach() if x0 is not None else y_c).clone().contiguous()
-        info = maid.lower_solve(theta_c, y_c, x, tol, max_iter)
+        info = maid.lower_solve(theta_c, y_c, x, tol, max_iter, trace=record is not None)
         ctx.maid = maid
         ctx.cg_tol, ctx.max_cg = cg_tol, max_cg
         ctx.info = info
+        ctx.record = record
+        if record is not None:
+            record["lower"] = info
         ctx.save_for_backward(theta_c, y_c, x)
         return x
 
@@ -43,15 +50,19 @@ class MaidSolve(torch.autograd.Function):
         vn = float(v.double().norm())
         dtheta = dy = None
         if vn > 0:
-            maid.adjoint_solve(theta, x, v, q, ctx.cg_tol * vn, ctx.max_cg)
+            ci = maid.adjoint_solve(theta, x, v, q, ctx.cg_tol * vn, ctx.max_cg)
+            if ctx.record is not None:
+                ctx.record["cg"] = ci
+        if ctx.record is not None:
+            ctx.record["q"] = q.clone()
         if ctx.needs_input_grad[0]:
             dtheta, _ = maid.hypergrad(theta, None, y, x, q, with_r=False)
             dtheta = dtheta.to(theta.dtype)
         if ctx.needs_input_grad[1]:
             dy = maid.apply_operator(theta, q)
-        return dtheta, dy, None, None, None, None, None, None
+        return dtheta, dy, None, None, None, None, None, None, None
 
 
-def maid_solve(theta, y, maid: Maid, tol=1e-4, cg_tol=1e-6, max_iter=300, max_cg=1000, x0=None):
+def maid_solve(theta, y, maid: Maid, tol=1e-4, cg_tol=1e-6, max_iter=300, max_cg=1000, x0=None, record=None):
     """Differentiable lower-level solve (see MaidSolve)."""
-    return MaidSolve.apply(theta, y, maid, tol, cg_tol, max_iter, max_cg, x0)
+    return MaidSolve.apply(theta, y, maid, tol, cg_tol, max_iter, max_cg, x0, record)

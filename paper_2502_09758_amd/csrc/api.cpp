@@ -4,6 +4,7 @@
 #include "maid.h"
 
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -194,6 +195,34 @@ int maid_lower_solve(maid_ctx* c, const void* theta, const void* y, void* x, dou
         return lower_one<double>(c, (const double*)theta, (const double*)y, (double*)x, tol, max_iter, L_inout, info,
                                  trace_bt, s);
     return lower_one<float>(c, (const double*)theta, (const float*)y, (float*)x, tol, max_iter, L_inout, info, trace_bt, s);
+}
+
+int maid_lower_solve_refined(maid_ctx* c, const void* theta, const void* y, void* x, double tol, int32_t max_iter,
+                             double rel_tol, int32_t max_newton, int32_t max_cg, double* L_inout, maid_solve_info* info,
+                             maid_refine_info* rinfo, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (int rc = need_single(c, "lower_solve_refined")) return rc;
+    if (!theta || !y || !x || !L_inout) return fail(c, MAID_EINVAL, "lower_solve_refined: NULL argument");
+    if (bad_tol(tol) || bad_tol(rel_tol)) return fail(c, MAID_EINVAL, "lower_solve_refined: tolerances must be finite and >= 0");
+    if (max_iter < 0 || max_newton < 0 || max_cg < 0)
+        return fail(c, MAID_EINVAL, "lower_solve_refined: iteration caps must be >= 0");
+    if (!std::isfinite(*L_inout)) return fail(c, MAID_EINVAL, "lower_solve_refined: L must be finite");
+    const double cg_rel = 1e-2;
+    int rc;
+    if (c->dtype == MAID_F64) {
+        rc = lower_one<double>(c, (const double*)theta, (const double*)y, (double*)x, tol, max_iter, L_inout, info,
+                               nullptr, s);
+        if (rc < 0) return rc;
+        const int r2 = refine_one<double>(c, (const double*)theta, (const double*)y, (double*)x, rel_tol, max_newton,
+                                          max_cg, cg_rel, rinfo, s);
+        return r2 ? r2 : (rinfo && rinfo->status ? rinfo->status : MAID_OK);
+    }
+    rc = lower_one<float>(c, (const double*)theta, (const float*)y, (float*)x, tol, max_iter, L_inout, info, nullptr, s);
+    if (rc < 0) return rc;
+    const int r2 = refine_one<float>(c, (const double*)theta, (const float*)y, (float*)x, rel_tol, max_newton, max_cg,
+                                     cg_rel, rinfo, s);
+    return r2 ? r2 : (rinfo && rinfo->status ? rinfo->status : MAID_OK);
 }
 
 int maid_upper_value_grad(maid_ctx* c, const void* a, const void* y, const void* x, void* grad_out, double* g_out,
@@ -474,6 +503,123 @@ int maid_batch_step(maid_ctx* c, const void* const* a, const void* const* y, mai
                                codes.data(), s);
     if (rc) return rc;
     return report(c, combine_codes(codes.data(), n), "batch_step");
+}
+
+int maid_batch_steps(maid_ctx* c, const void* const* a, const void* const* y, maid_state* states, const maid_hparams* hp,
+                     maid_step_info* info, int32_t n_steps, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (!a || !y || !states || !hp) return fail(c, MAID_EINVAL, "batch_steps: NULL argument");
+    if (n_steps < 1) return fail(c, MAID_EINVAL, "batch_steps: n_steps must be >= 1");
+    if (int rc = check_hparams(c, hp)) return rc;
+    for (int i = 0; i < c->n; ++i) {
+        if (!a[i] || !y[i]) return fail(c, MAID_EINVAL, "batch_steps: NULL argument");
+        if (int rc = check_state(c, &states[i])) return rc;
+    }
+    const int n = c->n;
+    std::vector<char> act(n, 1);
+    std::vector<int> codes(n, MAID_OK), last(n, MAID_OK);
+    std::vector<maid_step_info> one(n), sum(n);
+    std::memset(sum.data(), 0, n * sizeof(maid_step_info));
+    for (int k = 0; k < n_steps; ++k) {
+        bool any_act = false;
+        for (char v : act) any_act = any_act || v;
+        if (!any_act) break;
+        int rc;
+        if (c->dtype == MAID_F64)
+            rc = step_batch<double>(c, cast_all<const double*>(a, n), cast_all<const double*>(y, n), states, hp,
+                                    one.data(), codes.data(), s, &act);
+        else
+            rc = step_batch<float>(c, cast_all<const double*>(a, n), cast_all<const float*>(y, n), states, hp,
+                                   one.data(), codes.data(), s, &act);
+        if (rc) return rc;
+        for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            maid_step_info& t = sum[i];
+            const maid_step_info& o = one[i];
+            t.accepted += o.accepted;
+            t.trials += o.trials;
+            t.retries += o.retries;
+            t.lower_iters += o.lower_iters;
+            t.cg_iters += o.cg_iters;
+            t.psi = o.psi;
+            t.ell_k = o.ell_k;
+            t.ell_next = o.ell_next;
+            t.znorm = o.znorm;
+            t.status = o.status;
+            if (o.lower_status) t.lower_status = o.lower_status;
+            if (o.cg_status) t.cg_status = o.cg_status;
+            // a capped solve is carried on with; the floor or an error ends the instance's run
+            if (codes[i] == MAID_MAXITER) {
+                if (last[i] == MAID_OK) last[i] = MAID_MAXITER;
+            } else if (codes[i] != MAID_OK) {
+                last[i] = codes[i];
+            }
+            if (codes[i] != MAID_OK && codes[i] != MAID_MAXITER) act[i] = 0;
+        }
+    }
+    if (info)
+        for (int i = 0; i < n; ++i) info[i] = sum[i];
+    return report(c, combine_codes(last.data(), n), "batch_steps");
+}
+
+int maid_batch_create(const maid_desc* descs, int32_t n, maid_ctx** out) { return maid_create_batch(descs, n, out); }
+
+// ---------------------------------------------------------------------- Section 4.1's baselines
+int maid_gd_solve(maid_ctx* c, const void* theta, const void* y, void* x, double step, int32_t n_iter, double tol,
+                  void* hist, maid_solve_info* info, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (int rc = need_single(c, "gd_solve")) return rc;
+    if (!theta || !y || !x) return fail(c, MAID_EINVAL, "gd_solve: NULL argument");
+    if (!(step > 0.0) || !std::isfinite(step)) return fail(c, MAID_EINVAL, "gd_solve: step must be finite and > 0");
+    if (n_iter < 0) return fail(c, MAID_EINVAL, "gd_solve: n_iter must be >= 0");
+    if (bad_tol(tol)) return fail(c, MAID_EINVAL, "gd_solve: tol must be finite and >= 0");
+    if (c->dtype == MAID_F64)
+        return gd_one<double>(c, (const double*)theta, (const double*)y, (double*)x, step, n_iter, tol, (double*)hist,
+                              info, s);
+    return gd_one<float>(c, (const double*)theta, (const float*)y, (float*)x, step, n_iter, tol, (float*)hist, info, s);
+}
+
+int maid_hessian_apply(maid_ctx* c, const void* theta, const void* x, const void* w, void* out, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (int rc = need_single(c, "hessian_apply")) return rc;
+    if (!theta || !x || !w || !out) return fail(c, MAID_EINVAL, "hessian_apply: NULL argument");
+    if (out == w || out == x) return fail(c, MAID_EINVAL, "hessian_apply: out must not alias x or w");
+    if (c->dtype == MAID_F64)
+        return hessian_one<double>(c, (const double*)theta, (const double*)x, (const double*)w, (double*)out, s);
+    return hessian_one<float>(c, (const double*)theta, (const float*)x, (const float*)w, (float*)out, s);
+}
+
+int maid_ift_step(maid_ctx* c, const void* a, const void* y, maid_state* st, int32_t n_lower, double lambda_x,
+                  double cg_tol, int32_t max_cg, maid_step_info* info, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (int rc = need_single(c, "ift_step")) return rc;
+    if (!a || !y || !st || !st->theta || !st->x || !st->q) return fail(c, MAID_EINVAL, "ift_step: NULL argument");
+    if (n_lower < 0 || max_cg < 0) return fail(c, MAID_EINVAL, "ift_step: iteration counts must be >= 0");
+    if (!(lambda_x > 0.0) || !std::isfinite(lambda_x) || !(st->step > 0.0) || !std::isfinite(st->step))
+        return fail(c, MAID_EINVAL, "ift_step: lambda_x and the step must be finite and > 0");
+    if (bad_tol(cg_tol)) return fail(c, MAID_EINVAL, "ift_step: cg_tol must be finite and >= 0");
+    if (c->dtype == MAID_F64)
+        return ift_step_one<double>(c, (const double*)a, (const double*)y, st, n_lower, lambda_x, cg_tol, max_cg, info,
+                                    s);
+    return ift_step_one<float>(c, (const double*)a, (const float*)y, st, n_lower, lambda_x, cg_tol, max_cg, info, s);
+}
+
+int maid_lista_step(maid_ctx* c, const void* a, const void* y, maid_state* st, int32_t n_unroll, double lambda_x,
+                    maid_step_info* info, hipStream_t s) {
+    if (!c) return MAID_EINVAL;
+    c->err.clear();
+    if (int rc = need_single(c, "lista_step")) return rc;
+    if (!a || !y || !st || !st->theta || !st->x) return fail(c, MAID_EINVAL, "lista_step: NULL argument");
+    if (n_unroll < 1) return fail(c, MAID_EINVAL, "lista_step: n_unroll must be >= 1");
+    if (!(lambda_x > 0.0) || !std::isfinite(lambda_x) || !(st->step > 0.0) || !std::isfinite(st->step))
+        return fail(c, MAID_EINVAL, "lista_step: lambda_x and the step must be finite and > 0");
+    if (c->dtype == MAID_F64)
+        return lista_step_one<double>(c, (const double*)a, (const double*)y, st, n_unroll, lambda_x, info, s);
+    return lista_step_one<float>(c, (const double*)a, (const float*)y, st, n_unroll, lambda_x, info, s);
 }
 
 }  // extern "C"

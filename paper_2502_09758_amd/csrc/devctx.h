@@ -46,8 +46,13 @@ struct ApgState {
     int32_t status, done, phase;
     int32_t cur, prev, nxt;      // rotation of the three x / Kx buffers
     int32_t trace_cap;
-    int32_t resync;              // theta*x recomputed exactly when iters % resync < 2 (0: never)
+    int32_t resync;              // theta*x - y recomputed when iters % resync < 2 (0: never)
+    int32_t resync_full;         // ... from theta*x+ - y in FP64 (taps and sums), moving the base
+                                 // point there, when iters % resync_full == 0; else as
+                                 // theta*(x+ - x_base) + r_base (0: never)
     int32_t pp;                  // one-pass form: half of pA / pB the last pass wrote its partials to
+    int32_t fixed;               // fixed-step gradient descent (Section 4.1's baselines): no
+                                 // momentum (m = 0) and every trial accepted, L = 1/step
 };
 
 // CG state, one per instance, in three arrays: the direction pass reads the
@@ -140,7 +145,9 @@ template <typename T> struct Inst {
     int64_t N;                   // C*H*W
     // lower level (FISTA)
     gp<T> X[3];                     // iterates (rotating: cur, prev, next)
-    gp<T> KX[3];                    // theta * x, kept by linearity
+    gp<T> KX[3];                    // residuals theta * x - y, kept by linearity
+    gp<T> xb;                       // base point of the residual recomputation
+    gp<T> rb;                       // its residual theta * xb - y (FP64 sums, rounded once)
     gp<T> G;                        // gradient at the extrapolated point
     gp<const T> y;
     gp<T> th;                       // theta in the compute type, correlation form, column-major
@@ -155,6 +162,7 @@ template <typename T> struct Inst {
     gp<double> pB;                  // per-block partials, trial pass (nb entries)
     gp<int> trace;                  // rejected trials per iteration
     gp<T> xout;                     // where the returned point is written
+    gp<T> hist;                     // nullable (two-pass form): iterate k+1 written to hist + k*N
     // conjugate gradients
     gp<T> q;
     gp<T> r;
@@ -174,12 +182,14 @@ template <typename T> struct Inst {
     gp<const int> cv_mfsh;          // its scale exponent
     gp<const double> cv_ker64;      // nullable (FP32 storage): the kernel as KxK doubles, row-major;
                                     // the job then runs with FP64 taps and FP64 sums
+    gp<double> cv_out64;            // nullable (with cv_ker64): cv_out kept in FP64 here instead
     int32_t cv_flip64;              // cv_ker64 is applied flipped (true convolution)
     gp<const T> cv_in;
     gp<const T> cv_sub;
     gp<T> cv_out;
     gp<T> cv_out2;                  // nullable: a second copy of cv_out
-    gp<T> cv_cp[2];                 // nullable: copies of cv_in
+    gp<T> cv_out3;                  // nullable: a third copy of cv_out
+    gp<T> cv_cp[3];                 // nullable: copies of cv_in
     gp<double> cv_part;             // nullable
     gp<const double> cv_prev_part;  // nullable: partials of an earlier pass, summed by block 0 into red[cv_prev_slot]
     // kernel preparation: theta64 (K*K doubles) -> th / thf
@@ -189,6 +199,18 @@ template <typename T> struct Inst {
     gp<const double> sob_th;
     gp<const double> sob_a;
     double beta, h1_w0;
+    // batched hypergradient (Eq. 3.2): the correlation of (hg_rho, hg_q) and
+    // (hg_w, cv_in) on hg_nblk blocks from block hg_base of its launch
+    // (hg_nblk == 0: not in the launch), then z = -that + with_r grad r(theta64)
+    // against hg_a, and ||z||^2 into *hg_zn2
+    gp<const double> hg_rho;        // rho and theta*q in FP64 (FP32 storage: formed with FP64 taps
+    gp<const double> hg_w;          // and sums, never rounded; FP64 storage: the images themselves)
+    gp<const T> hg_q;
+    gp<double> hg_part;
+    gp<const double> hg_a;
+    gp<double> hg_z;
+    gp<double> hg_zn2;
+    int32_t hg_nblk, hg_base, hg_with_r;
     // initial solver states, copied into the state arrays by the preparation
     // pass at the start of a solve (one upload per solve carries both)
     ApgState st0;

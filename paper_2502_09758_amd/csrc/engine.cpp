@@ -156,6 +156,8 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
         I.X[k] = (T*)M.X[k];
         I.KX[k] = (T*)M.KX[k];
     }
+    I.xb = (T*)M.xb;
+    I.rb = (T*)M.rb;
     I.G = (T*)M.G;
     I.th = (T*)M.th_c;
     I.thf = (T*)M.thf_c;
@@ -332,6 +334,8 @@ const char* desc_problem(const maid_desc* d) {
     if (d->K < 1 || d->K > kMaxK || (d->K % 2) == 0) return "K must be odd, 1 <= K <= 31";
     if (d->K > d->H || d->K > d->W) return "K must not exceed H or W";
     if (d->dtype != MAID_F32 && d->dtype != MAID_F64) return "dtype must be MAID_F32 or MAID_F64";
+    if (d->boundary == MAID_BOUNDARY_PERIODIC) return "boundary: periodic convolution is not implemented (zero boundary only)";
+    if (d->boundary != MAID_BOUNDARY_ZERO) return "boundary must be MAID_BOUNDARY_ZERO";
     if (d->reg < 0 || d->reg > 2) return "reg must be 0, 1 or 2";
     if (!finite(d->alpha) || d->alpha < 0) return "alpha must be finite and >= 0";
     if (d->reg != MAID_REG_QUADRATIC && !(d->eps_tv > 0 && finite(d->eps_tv))) return "eps_tv must be > 0";
@@ -562,6 +566,8 @@ void destroy_ctx(maid_ctx* c) {
     if (c->tab_host) (void)hipHostFree(c->tab_host);
     if (c->maps) (void)hipFree(c->maps);
     if (c->team_arrive) (void)hipFree(c->team_arrive);
+    if (c->adp_ws) (void)hipFree(c->adp_ws);
+    if (c->ref64) destroy_ctx(c->ref64);
     delete c;
 }
 
@@ -602,9 +608,10 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         // FP64 s buffers of the one-pass CG, for instances that can take it
         const size_t s64 = step_ok(M.d.C, M.d.K, 1) ? 2 * al((size_t)M.N * sizeof(double)) : 0;
         total += s64;
-        total += 19 * img + 6 * kern + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
+        total += 21 * img + 6 * kern + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
                  al(kTraceCap * sizeof(int));
         if (mf_member(c->dtype, M.d.K)) total += 2 * al(mf_frag_bytes(M.d.K)) + al(sizeof(int));
+        if (c->dtype == MAID_F32) total += 2 * al((size_t)M.N * sizeof(double));
         maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe) + round8(step_blocks(M.d.H, M.d.W, M.d.K, 1));
     }
     c->ws_bytes = total;
@@ -651,6 +658,13 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     // period of the exact recomputation of theta*x in the lower-level solve
     c->kx_resync = c->dtype == MAID_F64 ? 32 : 8;
     if (const char* r = std::getenv("MAID_KX_RESYNC")) c->kx_resync = std::max(0, std::atoi(r));
+    // FP32 storage: a residual recomputed relative to the base point stays
+    // accurate while x stays near it; the base moves (FP64 recomputation)
+    // every 64 iterations.  FP64 storage needs no base moves.
+    c->kx_resync_full = c->dtype == MAID_F64 ? 0 : 64;
+    if (const char* r = std::getenv("MAID_KX_RESYNC_FULL")) c->kx_resync_full = std::max(0, std::atoi(r));
+    if (c->kx_resync_full > 0 && c->kx_resync > 0 && c->kx_resync_full % c->kx_resync != 0)
+        c->kx_resync_full = (c->kx_resync_full / c->kx_resync + 1) * c->kx_resync;
     std::memset(c->st_host, 0, c->st_bytes);
     std::memset(c->tab_host, 0, tab_bytes);
     {
@@ -681,6 +695,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         const size_t part = al(nblk * sizeof(double));
         for (int k = 0; k < 3; ++k) M.X[k] = take(img);
         for (int k = 0; k < 3; ++k) M.KX[k] = take(img);
+        M.xb = take(img);
+        M.rb = take(img);
         M.G = take(img);
         M.cq = take(img);
         M.cr = take(img);
@@ -695,6 +711,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.cS64[1] = s64 ? (double*)take(al((size_t)M.N * sizeof(double))) : nullptr;
         M.tmp0 = take(img);
         M.tmp1 = take(img);
+        for (int k = 0; k < 2; ++k)
+            M.hg64[k] = c->dtype == MAID_F32 ? (double*)take(al((size_t)M.N * sizeof(double))) : (double*)(k ? M.tmp1 : M.tmp0);
         M.xtrial = take(img);
         M.gradg = take(img);
         M.th_c = take(kern);
@@ -756,19 +774,29 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         h.nxt = 2;
         h.trace_cap = kTraceCap;
         h.resync = c->kx_resync;
+        h.resync_full = c->kx_resync > 0 ? c->kx_resync_full : 0;
+        h.fixed = c->lower_fixed ? 1 : 0;
         Inst<T>& I = tab[i];
+        if (n == 1) I.hist = (T*)c->lower_hist;
         I.y = y[i];
         I.xout = x[i];
         I.theta64 = theta[i];
-        // set-up: X0 = X1 = x_start, KX0 = KX1 = theta*x_start in one pass
+        // set-up in one pass: X0 = X1 = x_start, KX0 = KX1 = theta*x_start - y
+        // (FP64 taps and sums for FP32 storage), and the residual's base
+        // point xb = x_start with rb = that residual
         I.cv_ker = I.thf;
         I.cv_mf = I.mf_thf;
         I.cv_mfsh = I.mf_sh;
+        I.cv_ker64 = theta[i];
+        I.cv_flip64 = 1;
         I.cv_in = xin ? (*xin)[i] : x[i];
+        I.cv_sub = y[i];
         I.cv_out = I.KX[0];
         I.cv_out2 = I.KX[1];
+        I.cv_out3 = I.rb;
         I.cv_cp[0] = I.X[0];
         I.cv_cp[1] = I.X[1];
+        I.cv_cp[2] = I.xb;
     }
     // the initial states travel in the table; the preparation pass copies them
     for (int i = 0; i < n; ++i) tab[i].st0 = c->apg_h[i];
@@ -1125,6 +1153,38 @@ int upper_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
     return upper_impl<T>(c, act, a, y, x, grad, g_out, gn_out, nullptr, nullptr, s);
 }
 
+// ------------------------------------------------------------------ Hessian product (Proposition 1)
+// out = (theta.theta* + alpha grad^2 R(x)) w for a single instance: the set-up
+// passes of the adjoint solve with q0 = w leave H q0 in the Hp buffer (the
+// product its first residual rhs - H q0 is formed from), so the product is
+// the CG kernels' own.
+template <typename T>
+int hessian_one(maid_ctx* c, const double* theta, const T* x, const T* w, T* out, hipStream_t s) {
+    Inst<T>* tab = tab_host<T>(c, ROLE_CG);
+    const Inst<T>* tabd = tab_dev<T>(c, ROLE_CG);
+    const Member& M = c->m[0];
+    CgState& h = c->cg_h[0];
+    std::memset(&h, 0, sizeof(h));
+    h.status = ST_OK;
+    h.first = 1;
+    fill_base(c, 0, tab[0]);
+    tab[0].xt = x;
+    tab[0].b = w;
+    tab[0].q0 = w;
+    tab[0].theta64 = theta;
+    tab[0].cg0 = h;
+    {
+        ProfScope ps_(c, MAID_PROF_OTHER, s);
+        TRY(upload_prep<T>(c, ROLE_CG, 1, nullptr, c->cg[0], -1, s));
+    }
+    CgState** S = c->cg;
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
+    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
+    HIP_TRY(hipMemcpyAsync(out, M.cHp, (size_t)M.N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAID_OK;
+}
+
 // ------------------------------------------------------------------ hypergradient (Eq. 3.2)
 // znorm_out == nullptr: ||z||^2 stays in the reduction slots (no host
 // round trip; the next read-back of the slots brings it).
@@ -1149,11 +1209,44 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
         t2[i].cv_in = xt[i];
         t2[i].cv_sub = y[i];
         t2[i].cv_out = (T*)M.tmp0;
+        // rho = theta*x - y is a small difference of large terms, and the two
+        // correlations of Eq. 3.2 nearly cancel: with FP32 storage rho and
+        // theta*q are formed with FP64 taps and sums and kept in FP64
+        t2[i].cv_ker64 = theta[i];
+        t2[i].cv_flip64 = 1;
+        if (sizeof(T) == 4) t2[i].cv_out64 = M.hg64[0];
         t3[i].cv_ker = (T*)M.thf_c;
         t3[i].cv_mf = t3[i].mf_thf;
         t3[i].cv_mfsh = t3[i].mf_sh;
         t3[i].cv_in = q[i];
         t3[i].cv_out = (T*)M.tmp1;
+        if (sizeof(T) == 4) {
+            t3[i].cv_ker64 = theta[i];
+            t3[i].cv_flip64 = 1;
+            t3[i].cv_out64 = M.hg64[1];
+        }
+    }
+    // the correlations and their finishing, batched per tile class: each
+    // instance keeps its own block count, so z is bitwise the same in any batch
+    int hg_blocks[2] = {0, 0};
+    for (int i = 0; i < n; ++i) {
+        if (!act[i]) continue;
+        const Member& M = c->m[i];
+        Inst<T>& I = t2[i];
+        const int cls = M.d.K <= 16 ? 0 : 1;
+        I.hg_rho = M.hg64[0];
+        I.hg_w = M.hg64[1];
+        I.hg_q = q[i];
+        I.hg_part = M.hg_part;
+        I.hg_nblk = std::min(kHgMaxBlocks, hg_items(M.shape));
+        I.hg_base = hg_blocks[cls];
+        hg_blocks[cls] += I.hg_nblk;
+        I.hg_with_r = with_r && M.d.beta != 0.0;
+        I.hg_a = I.hg_with_r ? a[i] : nullptr;
+        I.beta = M.d.beta;
+        I.h1_w0 = M.d.h1_w0;
+        I.hg_z = z[i];
+        I.hg_zn2 = c->red + (size_t)i * kRedSlots + kRedZ;
     }
     const Inst<T>* d2 = tab_dev<T>(c, ROLE_CV2);
     const Inst<T>* d3 = tab_dev<T>(c, ROLE_CV3);
@@ -1164,16 +1257,10 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
     }
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d2, s));
     for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, d3, s));
-    for (int i = 0; i < n; ++i) {
-        if (!act[i]) continue;
-        const Member& M = c->m[i];
-        const int nblk = std::min(kHgMaxBlocks, hg_items(M.shape));
-        const int wr = with_r && M.d.beta != 0.0;
-        LAUNCH(MAID_PROF_HG_CORR, Ops<T>::hg_corr(M.shape, (const T*)M.tmp0, q[i], (const T*)M.tmp1, xt[i], M.hg_part,
-                                                  nblk, s));
-        LAUNCH(MAID_PROF_OTHER, launch_hg_final(M.shape, M.d.beta, M.d.h1_w0, M.hg_part, nblk, theta[i],
-                                                wr ? a[i] : nullptr, wr, z[i], c->red + (size_t)i * kRedSlots + kRedZ, s));
-    }
+    for (int cls = 0; cls < 2; ++cls)
+        if (hg_blocks[cls]) LAUNCH(MAID_PROF_HG_CORR, Ops<T>::hg_corr_batch(cls ? 32 : 16, hg_blocks[cls], d2, n, s));
+    for (int cls = 0; cls < 2; ++cls)
+        if (hg_blocks[cls]) LAUNCH(MAID_PROF_OTHER, Ops<T>::hg_final_batch(cls ? 32 : 16, d2, n, s));
     if (!znorm_out) return MAID_OK;
     TRY(pull_red(c, s));
     for (int i = 0; i < n; ++i)
@@ -1387,7 +1474,7 @@ int tr_lower(maid_ctx* c, int i, int role, const maid_solve_info& li, hipStream_
 
 template <typename T>
 int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
-               const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s) {
+               const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s, const std::vector<char>* active) {
     struct InStep {
         maid_ctx* c;
         InStep(maid_ctx* cc) : c(cc) { c->in_step = true; }
@@ -1424,7 +1511,7 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
         codes[i] = MAID_OK;
     }
     std::vector<int> j(n, hp->max_bt), rc(n);
-    std::vector<char> need(n, 1);
+    std::vector<char> need = active ? *active : std::vector<char>(n, 1);
     std::vector<double> tol(n), dtol(n), L(n), g_k(n), n_k(n), r_k(n), ell_k(n), znorm(n), g_n(n), n_n(n), r_n(n);
     std::vector<maid_solve_info> li(n), ci(n);
     while (any(need)) {
@@ -1597,6 +1684,146 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
     return MAID_OK;
 }
 
+// The precision form's refinement of a lower-level solution: Newton steps
+// x <- x - d with H(x) d = grad h(x) (Proposition 1's Hessian and gradient),
+// d from CG in the storage type to cg_rel relative residual.  With FP64
+// storage the gradient comes from a zero-iteration lower-level solve.  With
+// FP32 storage this is mixed-precision iterative refinement: the iterate is
+// accumulated in FP64 (x64), its gradient evaluated by the FP64 passes of a
+// companion FP64 context of the same shape (FP64 storage and arithmetic:
+// the gradient's cancellations stay in FP64), rounded to FP32 as CG's
+// right-hand side, and the FP32 CG correction added to x64; x is x64 rounded
+// once at each step.  d is small next to x, so its FP32 rounding is too.
+// Stops when ||d|| <= rel_tol ||x||, when the steps stop shrinking (the last
+// one is undone), or after max_newton steps.
+namespace {
+// the FP64 companion of an FP32 context (created at the first refinement,
+// on the two-pass form so that the gradient lands in its G)
+int companion64(maid_ctx* c, maid_ctx** out) {
+    if (!c->ref64) {
+        maid_desc d = c->m[0].d;
+        d.dtype = MAID_F64;
+        std::string why;
+        maid_ctx* r = nullptr;
+        const int rc = create_ctx(&d, 1, &r, why);
+        if (rc) return fail(c, rc, "refinement: FP64 companion context: " + why);
+        r->fuse = false;
+        r->team_req = 0;
+        const int rr = relayout(r);
+        if (rr) {
+            destroy_ctx(r);
+            return fail(c, rr, "refinement: FP64 companion layout failed");
+        }
+        c->ref64 = r;
+    }
+    *out = c->ref64;
+    return MAID_OK;
+}
+}  // namespace
+
+template <typename T>
+int refine_one(maid_ctx* c, const double* theta, const T* y, T* x, double rel_tol, int max_newton, int max_cg,
+               double cg_rel, maid_refine_info* out, hipStream_t s) {
+    constexpr bool kMixed = sizeof(T) == 4;
+    Member& M = c->m[0];
+    // FP32: the FP64 companion, x64 and y64 in its workspace
+    maid_ctx* c64 = nullptr;
+    double* x64 = nullptr;
+    double* y64 = nullptr;
+    if constexpr (kMixed) {
+        TRY(companion64(c, &c64));
+        y64 = (double*)c64->m[0].tmp0;
+        x64 = (double*)c64->m[0].tmp1;
+        HIP_TRY((launch_cast<float, double>((const float*)y, y64, M.N, s)));
+        HIP_TRY((launch_cast<float, double>((const float*)x, x64, M.N, s)));
+    }
+    // FP64 storage: the gradient must land in the workspace's G (two-pass form)
+    const bool fuse = c->fuse;
+    if (!kMixed && fuse) {
+        c->fuse = false;
+        TRY(relayout(c));
+    }
+    auto restore = [&]() -> int {
+        if (kMixed || !fuse) return MAID_OK;
+        c->fuse = true;
+        return relayout(c);
+    };
+    maid_refine_info r{};
+    T* G = (T*)M.G;
+    T* d = (T*)M.xtrial;
+    double* part = M.hg_part;
+    constexpr int kBlocks = 512;
+    std::vector<double> hp(2 * kBlocks);
+    double prev_step = HUGE_VAL;
+    int rc = MAID_OK;
+    for (int k = 0; k <= max_newton; ++k) {
+        // gradient at x (a zero-iteration solve rewrites x with the same values)
+        double L = 0.0;
+        maid_solve_info gi{};
+        int code = MAID_OK;
+        if constexpr (kMixed) {
+            rc = lower_batch<double>(c64, std::vector<char>(1, 1), std::vector<const double*>(1, theta),
+                                     std::vector<const double*>(1, y64), std::vector<double*>(1, x64),
+                                     std::vector<double>(1, 0.0), 0, &L, &gi, &code, nullptr, s);
+            if (rc) rc = fail(c, rc, "refinement: FP64 gradient: " + c64->err);
+        } else {
+            rc = lower_batch<T>(c, std::vector<char>(1, 1), std::vector<const double*>(1, theta),
+                                std::vector<const T*>(1, y), std::vector<T*>(1, x), std::vector<double>(1, 0.0), 0, &L,
+                                &gi, &code, nullptr, s);
+        }
+        if (rc == MAID_OK && code < 0) rc = code;
+        if (rc) break;
+        r.grad_norm = gi.res_norm;
+        if (k == max_newton || r.grad_norm == 0.0) break;
+        if constexpr (kMixed) HIP_TRY((launch_cast<double, float>((const double*)c64->m[0].G, (float*)G, M.N, s)));
+        // Newton direction: CG from zero on H(x) d = G
+        HIP_TRY(hipMemsetAsync(d, 0, (size_t)M.N * sizeof(T), s));
+        maid_solve_info ci{};
+        code = MAID_OK;
+        rc = adjoint_batch<T>(c, std::vector<char>(1, 1), std::vector<const double*>(1, theta), std::vector<const T*>(1, x),
+                              std::vector<const T*>(1, G), std::vector<T*>(1, d),
+                              std::vector<double>(1, cg_rel * r.grad_norm), max_cg, &ci, &code, s);
+        if (rc == MAID_OK && code < 0) rc = code;
+        if (rc) break;
+        r.cg_iters += ci.iters;
+        if constexpr (kMixed)
+            HIP_TRY(launch_axpy_mixed(x64, (const float*)d, -1.0, M.N, (float*)x, part, kBlocks, s));
+        else
+            HIP_TRY(launch_axpy_norms<T>(x, d, T(-1), M.N, part, kBlocks, s));
+        HIP_TRY(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double dd = 0.0, xx = 0.0;
+        for (int b = 0; b < kBlocks; ++b) {
+            dd += hp[2 * b];
+            xx += hp[2 * b + 1];
+        }
+        const double step = xx > 0.0 ? std::sqrt(dd / xx) : 0.0;
+        r.newton_steps += 1;
+        if (step > prev_step) {
+            // the steps grew: undo this one and stop
+            if constexpr (kMixed)
+                HIP_TRY(launch_axpy_mixed(x64, (const float*)d, 1.0, M.N, (float*)x, part, kBlocks, s));
+            else
+                HIP_TRY(launch_axpy_norms<T>(x, d, T(1), M.N, part, kBlocks, s));
+            r.newton_steps -= 1;
+            r.status = MAID_MAXITER;
+            prev_step = step;
+            max_newton = k + 1;   // one more gradient, at the restored point
+            continue;
+        }
+        r.rel_step = step;
+        prev_step = step;
+        if (step <= rel_tol) max_newton = k + 1;   // converged: report the gradient there
+    }
+    if (rc == MAID_OK && r.status == MAID_OK && r.rel_step > rel_tol) r.status = MAID_MAXITER;
+    if (kMixed && rc == MAID_OK) HIP_TRY(hipStreamSynchronize(s));
+    const int rr = restore();
+    if (out) *out = r;
+    if (rc) return rc;
+    return rr;
+}
+
+
 #define MAID_ENGINE_INSTANTIATE(T)                                                                                       \
     template int lower_batch<T>(maid_ctx*, const std::vector<char>&, const std::vector<const double*>&,                 \
                                 const std::vector<const T*>&, const std::vector<T*>&, const std::vector<double>&, int,  \
@@ -1616,7 +1843,10 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
     template int autotune_batch<T>(maid_ctx*, const std::vector<const double*>&, const std::vector<const T*>&, int,   \
                                    int32_t*, hipStream_t);                                                               \
     template int step_batch<T>(maid_ctx*, const std::vector<const double*>&, const std::vector<const T*>&, maid_state*, \
-                               const maid_hparams*, maid_step_info*, int*, hipStream_t);
+                               const maid_hparams*, maid_step_info*, int*, hipStream_t, const std::vector<char>*);  \
+    template int refine_one<T>(maid_ctx*, const double*, const T*, T*, double, int, int, double, maid_refine_info*,   \
+                               hipStream_t);                                                                            \
+    template int hessian_one<T>(maid_ctx*, const double*, const T*, const T*, T*, hipStream_t);
 
 MAID_ENGINE_INSTANTIATE(float)
 MAID_ENGINE_INSTANTIATE(double)

@@ -48,6 +48,8 @@ struct Member {
     // device workspace, carved from the context's allocation
     void* X[3];
     void* KX[3];
+    void* xb;                   // base point of the lower-level residual recomputation
+    void* rb;                   // its residual theta*xb - y
     void* G;
     void* cq;
     void* cr;
@@ -58,6 +60,7 @@ struct Member {
     double* cS64[2];            // one-pass CG: s = Hp in FP64 (one-channel instances with 3 <= K <= 11)
     void* tmp0;
     void* tmp1;
+    double* hg64[2];   // FP32 storage: rho and theta*q of the hypergradient, kept in FP64
     void* xtrial;
     void* gradg;
     void* th_c;
@@ -145,7 +148,21 @@ struct maid_ctx {
     bool upload_kernel = true;        // tables go up by a copy kernel reading mapped host memory
     int pred_first = 100;             // first chunk of a solve: this percentage of the predicted slots
     int pred_first_cg = 100;          // the same for the CG solves
-    int kx_resync = 16;               // exact theta*x every kx_resync iterations (twice in a row)
+    int kx_resync = 16;               // residual recomputed every kx_resync iterations (twice in a row)
+    int kx_resync_full = 0;           // ... from scratch in FP64 every kx_resync_full (0: never)
+    // fixed-step descent for the next lower-level solves (Section 4.1's
+    // baselines; set by their entry points for one call): no momentum,
+    // every step accepted; hist (single instance, two-pass form) receives
+    // the iterates
+    bool lower_fixed = false;
+    void* lower_hist = nullptr;
+    // the ADP baselines' workspace (unrolled iterates, adjoint vectors),
+    // allocated at their first call and grown on demand
+    char* adp_ws = nullptr;
+    size_t adp_ws_bytes = 0;
+    // FP64 companion of an FP32 context: the precision form's refinement
+    // evaluates its gradients there (created at the first refinement)
+    maid_ctx* ref64 = nullptr;
     // slots the last solve of each kind needed (sizes the first chunk of the
     // next): lower level for callers, for Algorithm 2's InexactGradient and
     // for its psi trials (their counts differ: the first starts from the
@@ -177,8 +194,15 @@ namespace maid {
 
 int fail(maid_ctx* c, int code, const std::string& msg);
 int validate_desc(const maid_desc* d, std::string& why);
+// Newton refinement of the single instance's lower-level solution x (see
+// maid_lower_solve_refined)
+template <typename T>
+int refine_one(maid_ctx* c, const double* theta, const T* y, T* x, double rel_tol, int max_newton, int max_cg,
+               double cg_rel, maid_refine_info* out, hipStream_t s);
+
 // what is wrong with a description (a static string), or nullptr
 const char* desc_problem(const maid_desc* d);
+
 int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why);
 void destroy_ctx(maid_ctx* c);
 int relayout(maid_ctx* c);
@@ -215,8 +239,28 @@ template <typename T>
 int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const std::vector<const T*>& y, int probe_iters,
                    int32_t* rows_out, hipStream_t s);
 template <typename T>
+// active (nullable): the instances that take the step (the others are left
+// as they are, their info zeroed and code MAID_OK)
 int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vector<const T*>& y, maid_state* st,
-               const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s);
+               const maid_hparams* hp, maid_step_info* out, int* codes, hipStream_t s,
+               const std::vector<char>* active = nullptr);
+
+// Proposition 1's Hessian at x applied to w (single instance), by the
+// adjoint solve's set-up passes.
+template <typename T>
+int hessian_one(maid_ctx* c, const double* theta, const T* x, const T* w, T* out, hipStream_t s);
+
+// Section 4.1's baselines (adp.cpp), single instance: fixed-step descent
+// (hist nullable), one ADP-IFT and one ADP-LISTA upper-level iteration.
+template <typename T>
+int gd_one(maid_ctx* c, const double* theta, const T* y, T* x, double step, int n_iter, double tol, T* hist,
+           maid_solve_info* info, hipStream_t s);
+template <typename T>
+int ift_step_one(maid_ctx* c, const double* a, const T* y, maid_state* st, int n_lower, double lambda_x,
+                 double cg_tol, int max_cg, maid_step_info* info, hipStream_t s);
+template <typename T>
+int lista_step_one(maid_ctx* c, const double* a, const T* y, maid_state* st, int n_unroll, double lambda_x,
+                   maid_step_info* info, hipStream_t s);
 
 // MAID_OK if every code is MAID_OK, else the first code that is not.
 int combine_codes(const int* codes, int n);

@@ -260,7 +260,8 @@ __device__ __forceinline__ void put_state(ApgState* __restrict__ o, const ApgSta
     o->L = s.L; o->t = s.t; o->t_prev = s.t_prev; o->m = s.m; o->gn2 = s.gn2; o->tol = s.tol;
     o->delta_last = s.delta_last; o->max_iter = s.max_iter; o->iters = s.iters; o->bt = s.bt;
     o->nb_iter = s.nb_iter; o->status = s.status; o->done = s.done; o->phase = s.phase; o->cur = s.cur;
-    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->resync = s.resync; o->pp = s.pp;
+    o->prev = s.prev; o->nxt = s.nxt; o->trace_cap = s.trace_cap; o->resync = s.resync;
+    o->resync_full = s.resync_full; o->pp = s.pp; o->fixed = s.fixed;
 }
 __device__ __forceinline__ void put_state(CgState* __restrict__ o, const CgState& s) {
     o->gamma = s.gamma; o->kappa = s.kappa; o->a = s.a; o->tol = s.tol; o->max = s.max; o->iters = s.iters;
@@ -389,23 +390,21 @@ __device__ __forceinline__ void correlate_sel(const T* s, int pitch, const T* __
 
 // acc[o] += sum_{u,v} ker(u,v) s[(li0+o+u) pitch + tx+v] in FP64, the taps
 // read as doubles from the row-major KxK array th: ker(u,v) = th[u K + v],
-// or th[(K-1-u) K + (K-1-v)] with `flip`.
+// or th[(K-1-u) K + (K-1-v)] with `flip`.  Both tap loops stay rolled and
+// the staged values are read per tap (few registers: the solver passes
+// call it rarely, next to register-hungry code).
 template <typename T, int K, int R>
 __device__ __forceinline__ void correlate64(const T* s, int pitch, const double* __restrict__ th, bool flip, int li0,
                                             int tx, double (&acc)[R]) {
     const double MAID_CONST* kc = (const double MAID_CONST*)th;
 #pragma unroll 1
-    for (int v = 0; v < K; ++v) {
-        double col[R + K - 1];
+    for (int u = 0; u < K; ++u) {
+#pragma unroll 1
+        for (int v = 0; v < K; ++v) {
+            const double w = kc[flip ? (K - 1 - u) * K + (K - 1 - v) : u * K + v];
+            const T* col = s + (li0 + u) * pitch + tx + v;
 #pragma unroll
-        for (int t = 0; t < R + K - 1; ++t) col[t] = (double)s[(li0 + t) * pitch + tx + v];
-        const int base = flip ? (K - 1) * K + (K - 1 - v) : v;
-        const int step = flip ? -K : K;
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            const double w = kc[base + u * step];
-#pragma unroll
-            for (int o = 0; o < R; ++o) acc[o] = __builtin_fma(w, col[o + u], acc[o]);
+            for (int o = 0; o < R; ++o) acc[o] = __builtin_fma(w, (double)col[o * pitch], acc[o]);
         }
     }
 }
@@ -499,13 +498,13 @@ __device__ __forceinline__ T tv_grad_px(const T* s_v, const T* s_w, int ch, int 
     return tv_grad_px_h<T, tile_h(R)>(s_v, s_w, ch, reg, li, tx, gi, gj, H, W);
 }
 
-// Occupancy floor (waves per SIMD) the compiler must keep: the ALU-bound
-// large-kernel passes with tall tiles need enough waves to hide their LDS
-// latency, so their register budget is capped near that of the plain
-// convolution.
-// (FP32 storage only; the FP64 instantiations keep the compiler's choice).
+// Occupancy floor (waves per SIMD) the compiler must keep for the
+// large-kernel passes with tall tiles (FP32 storage only; the FP64
+// instantiations keep the compiler's choice).  With the matrix-core
+// correlation's LDS these passes hold 2-4 blocks per CU, so a higher floor
+// would only cap their registers (and made the trial pass spill).
 template <typename T> __host__ __device__ constexpr int min_waves(int K, int R) {
-    return sizeof(T) == 4 && seq_lds(K) && R >= 4 ? (R == 8 ? 5 : 6) : 1;
+    return sizeof(T) == 4 && seq_lds(K) && R >= 4 ? (R == 8 ? 3 : 4) : 1;
 }
 
 // Several tiles staged together: every tile's global loads are issued (held
@@ -598,14 +597,18 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
     const T* __restrict__ sub = I.cv_sub ? I.cv_sub + ch * HW : nullptr;
     T* __restrict__ out = I.cv_out + ch * HW;
     T* __restrict__ out2 = I.cv_out2 ? I.cv_out2 + ch * HW : nullptr;
+    T* __restrict__ out3 = I.cv_out3 ? I.cv_out3 + ch * HW : nullptr;
     T* __restrict__ cp0 = I.cv_cp[0] ? I.cv_cp[0] + ch * HW : nullptr;
     T* __restrict__ cp1 = I.cv_cp[1] ? I.cv_cp[1] + ch * HW : nullptr;
+    T* __restrict__ cp2 = I.cv_cp[2] ? I.cv_cp[2] + ch * HW : nullptr;
     load_tile<CR, CP, CP>(s, ti0 - c0, tj0 - c0, H, W, [&](int g) { return at(src, g); });
     __syncthreads();
     const int gj = tj0 + tx;
     if constexpr (sizeof(T) == 4) {
         if (I.cv_ker64) {
-            // FP64 taps and sums; one rounding to the storage type at the store
+            // FP64 taps and sums; one rounding to the storage type at the
+            // store, none where the job keeps the result in FP64 (cv_out64)
+            double* __restrict__ out64 = I.cv_out64 ? I.cv_out64 + ch * HW : nullptr;
             double acc[R];
 #pragma unroll
             for (int o = 0; o < R; ++o) acc[o] = 0.0;
@@ -618,12 +621,18 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
                     const int e = gi * W + gj;
                     double val = acc[o];
                     if (sub) val -= (double)at(sub, e);
-                    at(out, e) = (T)val;
+                    if (out64) {
+                        at(out64, e) = val;
+                    } else {
+                        at(out, e) = (T)val;
+                    }
                     if (out2) at(out2, e) = (T)val;
+                    if (out3) at(out3, e) = (T)val;
                     if (cp0) {
                         const T xin = s[(li0 + o + c0) * CP + tx + c0];
                         at(cp0, e) = xin;
                         if (cp1) at(cp1, e) = xin;
+                        if (cp2) at(cp2, e) = xin;
                     }
                     sq += val * val;
                 }
@@ -646,10 +655,12 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
             if (sub) val -= at(sub, e);
             at(out, e) = val;
             if (out2) at(out2, e) = val;
+            if (out3) at(out3, e) = val;
             if (cp0) {
                 const T xin = s[(li0 + o + c0) * CP + tx + c0];
                 at(cp0, e) = xin;
                 if (cp1) at(cp1, e) = xin;
+                if (cp2) at(cp2, e) = xin;
             }
             sq += (double)val * (double)val;
         }
@@ -680,8 +691,8 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
     if (trialed) {
         cur = st.nxt;
         prev = st.cur;
-        tnext = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.t * st.t));
-        mnext = (st.t - 1.0) / tnext;
+        tnext = st.fixed ? 1.0 : 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.t * st.t));
+        mnext = st.fixed ? 0.0 : (st.t - 1.0) / tnext;
     }
 
     constexpr int c0 = (K - 1) / 2, CP = cv_pitch(K), CR = cv_rows(K, R);
@@ -701,7 +712,6 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
     const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], prev);
     const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], cur) + ch * HW;
     const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], prev) + ch * HW;
-    const T* __restrict__ Yc = I.y + ch * HW;
 
     // stage v for every channel (the TV magnitude couples them) and the data
     // residual theta*v - y of this block's channel
@@ -712,7 +722,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
     auto stage_residual = [&]() {
         load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
             const T kx = ld<CO>(KX, g);
-            return dfma(m, kx - ld<CO>(KXP, g), kx) - ld<CO>(Yc, g);
+            return dfma(m, kx - ld<CO>(KXP, g), kx);
         });
     };
     auto vfun = [&](int c) {
@@ -727,7 +737,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
         auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, vfun(C > 2 ? 2 : 0));
         auto rs = stage<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, [&](int g) {
             const T kx = ld<CO>(KX, g);
-            return dfma(m, kx - ld<CO>(KXP, g), kx) - ld<CO>(Yc, g);
+            return dfma(m, kx - ld<CO>(KXP, g), kx);
         });
         v0.fetch(H, W);
         if (C > 1) v1.fetch(H, W);
@@ -751,7 +761,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
                 st.done = 1;
                 st.status = ST_NONFINITE;
                 compute = false;
-            } else if (delta <= -st.gn2 / (2.0 * st.L)) {
+            } else if (st.fixed || delta <= -st.gn2 / (2.0 * st.L)) {
                 if (writer && I.trace && st.iters < st.trace_cap) I.trace[st.iters] = st.nb_iter;
                 st.iters += 1;
                 st.nxt = st.prev;
@@ -1021,7 +1031,6 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
     const bool exact = st.resync > 0 && (st.iters % st.resync) < 2;
     const T* __restrict__ KXc = KX + ch * HW;
     const T* __restrict__ KXPc = KXP + ch * HW;
-    const T* __restrict__ Yc = Y + ch * HW;
     const T* __restrict__ Xc0 = X + ch * HW;
     const T* __restrict__ XPc0 = XP + ch * HW;
     T* __restrict__ XNc = XN + ch * HW;
@@ -1034,14 +1043,13 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
     // small kernels: every row's loads in flight before any is used (clamped
     // addresses, no branch); large kernels keep their registers
     constexpr int RL = SEQ ? 1 : R;
-    T kxr[RL], kxpr[RL], yr[RL], xr[RL], xpr[RL];
+    T kxr[RL], kxpr[RL], xr[RL], xpr[RL];
     if constexpr (!SEQ) {
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int e = clampi(ti0 + li0 + o, H - 1) * W + clampi(gj, W - 1);
             kxr[o] = ld<CO>(KXc, e);
             kxpr[o] = ld<CO>(KXPc, e);
-            yr[o] = ld<CO>(Yc, e);
             xr[o] = ld<CO>(Xc0, e);
             xpr[o] = ld<CO>(XPc0, e);
         }
@@ -1055,35 +1063,77 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
             if constexpr (SEQ) {
                 kxr[0] = ld<CO>(KXc, e);
                 kxpr[0] = ld<CO>(KXPc, e);
-                yr[0] = ld<CO>(Yc, e);
                 xr[0] = ld<CO>(Xc0, e);
                 xpr[0] = ld<CO>(XPc0, e);
             }
+            // the residual at v by linearity, and its increment d = theta*dl
             const T kv = dfma(m, kxr[q] - kxpr[q], kxr[q]);
             const T d = acc[o];
-            const double rv = (double)kv - (double)yr[q];
-            ddat += (double)d * (rv + 0.5 * (double)d);
-            at(XNc, e) = dfma(m, xr[q] - xpr[q], xr[q]) + s_c[(li + c0) * CP + tx + c0];
+            ddat += (double)d * ((double)kv + 0.5 * (double)d);
+            const T xn = dfma(m, xr[q] - xpr[q], xr[q]) + s_c[(li + c0) * CP + tx + c0];
+            at(XNc, e) = xn;
+            if (I.hist) {
+                T* __restrict__ hp = I.hist + (int64_t)st.iters * I.N + ch * HW;
+                at(hp, e) = xn;
+            }
             if (!exact) at(KXNc, e) = kv + d;
         }
     }
     if (exact) {
-        // theta*x+ from the stored x+ = v + dl, staged with its halo
+        // the residual at x+ = v + dl recomputed from x+ (staged with its
+        // halo): in full, theta*x+ - y with FP64 taps and sums, and x+ with
+        // that residual become the base point; otherwise relative to the
+        // base, r_base + theta*(x+ - x_base), whose small difference the
+        // storage type convolves accurately
+        const bool full = st.resync_full > 0 && (st.iters % st.resync_full) == 0;
         const T* Xc = X + ch * HW;
         const T* XPc = XP + ch * HW;
+        const T* XBc = I.xb + ch * HW;
+        const T* RBc = I.rb + ch * HW;
         __syncthreads();
-        load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
-            const T xv = ld<CO>(Xc, g);
-            return dfma(m, xv - ld<CO>(XPc, g), xv) + ld<CO>(Gc, g) * ninvL;
-        });
+        if (full) {
+            load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
+                const T xv = ld<CO>(Xc, g);
+                return dfma(m, xv - ld<CO>(XPc, g), xv) + ld<CO>(Gc, g) * ninvL;
+            });
+        } else {
+            load_tile<CR, CP, CP>(s_c, ti0 - c0, tj0 - c0, H, W, [&](int g) {
+                const T xv = ld<CO>(Xc, g);
+                return (dfma(m, xv - ld<CO>(XPc, g), xv) + ld<CO>(Gc, g) * ninvL) - ld<CO>(XBc, g);
+            });
+        }
         __syncthreads();
+        if (full) {
+            double a64[R];
 #pragma unroll
-        for (int o = 0; o < R; ++o) acc[o] = T(0);
-        correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
+            for (int o = 0; o < R; ++o) a64[o] = 0.0;
+            correlate64<T, K, R>(s_c, CP, I.theta64, true, li0, tx, a64);
+            T* __restrict__ XBw = I.xb + ch * HW;
+            T* __restrict__ RBw = I.rb + ch * HW;
+            const T* __restrict__ Yc = Y + ch * HW;
 #pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int gi = ti0 + li0 + o;
-            if (gi < H && gj < W) at(KXNc, gi * W + gj) = acc[o];
+            for (int o = 0; o < R; ++o) {
+                const int gi = ti0 + li0 + o;
+                if (gi < H && gj < W) {
+                    const int e = gi * W + gj;
+                    const T r = (T)(a64[o] - (double)ld<CO>(Yc, e));
+                    at(KXNc, e) = r;
+                    at(RBw, e) = r;
+                    at(XBw, e) = s_c[(li0 + o + c0) * CP + tx + c0];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < R; ++o) acc[o] = T(0);
+            correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
+#pragma unroll
+            for (int o = 0; o < R; ++o) {
+                const int gi = ti0 + li0 + o;
+                if (gi < H && gj < W) {
+                    const int e = gi * W + gj;
+                    at(KXNc, e) = ld<CO>(RBc, e) + acc[o];
+                }
+            }
         }
     }
     block_partial(ddat + I.pr.alpha * dtv, I.pB, lb);
@@ -1620,13 +1670,16 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kHgTI = 16, kHgTJ = 64;
 
+// One block's share: items b0, b0 + nb, ... of the instance; its K x K
+// partial sum goes to part[b0].
 template <typename T, int KT>
-__global__ __launch_bounds__(kNT) void k_hg_corr(int C, int H, int W, int K, const T* __restrict__ rho, const T* __restrict__ q,
-                                                 const T* __restrict__ wq, const T* __restrict__ xt, double* __restrict__ part) {
+__device__ __forceinline__ void hg_corr_blk(int C, int H, int W, int K, const double* __restrict__ rho,
+                                            const T* __restrict__ q, const double* __restrict__ wq,
+                                            const T* __restrict__ xt, double* __restrict__ part, int b0, int nb) {
     constexpr int NO = KT / 16;
     constexpr int AP = kHgTJ + 1;            // A tile: rows TI+K-1, cols TJ
     constexpr int BP = kHgTJ + kMaxK;        // B tile: rows TI, cols TJ+K-1
-    __shared__ T sA[(kHgTI + kMaxK - 1) * AP];
+    __shared__ double sA[(kHgTI + kMaxK - 1) * AP];
     __shared__ T sB[kHgTI * BP];
     __shared__ double s_red[4][KT * KT];
     const int c0 = (K - 1) / 2;
@@ -1642,18 +1695,18 @@ __global__ __launch_bounds__(kNT) void k_hg_corr(int C, int H, int W, int K, con
         for (int bq = 0; bq < NO; ++bq) acc[a][bq] = d4_t{0.0, 0.0, 0.0, 0.0};
 
     const int arows = kHgTI + K - 1, bcols = kHgTJ + K - 1;
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    for (int item = b0; item < nitems; item += nb) {
         const int term = item & 1;
         const int ch = (item >> 1) % C;
         const int sp = (item >> 1) / C;
         const int ti0 = (sp / ntj) * kHgTI, tj0 = (sp % ntj) * kHgTJ;
-        const T* Asrc = (term ? wq : rho) + ch * HW;
+        const double* Asrc = (term ? wq : rho) + ch * HW;
         const T* Bsrc = (term ? xt : q) + ch * HW;
         __syncthreads();
         for (int idx = threadIdx.x; idx < arows * kHgTJ; idx += kNT) {
             const int r = idx / kHgTJ, cc = idx - r * kHgTJ;
             const int gi = ti0 - c0 + r, gj = tj0 + cc;
-            sA[r * AP + cc] = (gi >= 0 && gi < H && gj < W) ? Asrc[gi * W + gj] : T(0);
+            sA[r * AP + cc] = (gi >= 0 && gi < H && gj < W) ? Asrc[gi * W + gj] : 0.0;
         }
         for (int idx = threadIdx.x; idx < kHgTI * bcols; idx += kNT) {
             const int r = idx / bcols, cc = idx - r * bcols;
@@ -1693,14 +1746,33 @@ __global__ __launch_bounds__(kNT) void k_hg_corr(int C, int H, int W, int K, con
             }
     __syncthreads();
     for (int i = threadIdx.x; i < KT * KT; i += kNT)
-        part[(size_t)blockIdx.x * KT * KT + i] = ((s_red[0][i] + s_red[1][i]) + s_red[2][i]) + s_red[3][i];
+        part[(size_t)b0 * KT * KT + i] = ((s_red[0][i] + s_red[1][i]) + s_red[2][i]) + s_red[3][i];
 }
 
-// z = -sum_blocks Z + with_r * grad r(theta); ||z||^2 into *znorm2.
+// The correlations of a batch (a plain solve is a batch of one) in one
+// launch per tile class KT: the
+// instances of the class (K <= 16 for KT = 16) with hg_nblk > 0 own
+// consecutive block ranges [hg_base, hg_base + hg_nblk) and each range
+// runs exactly as a launch of its own would (so the partial sums, and z,
+// are bitwise those of the per-instance form).
+template <typename T, int KT>
+__global__ __launch_bounds__(kNT) void k_hg_corr_batch(const Inst<T>* __restrict__ insts, int n) {
+    const int b = (int)blockIdx.x;
+    for (int i = 0; i < n; ++i) {
+        const Inst<T>& I = insts[i];
+        if ((I.K <= 16) != (KT == 16) || b < I.hg_base || b >= I.hg_base + I.hg_nblk) continue;
+        hg_corr_blk<T, KT>(I.pr.C, I.pr.H, I.pr.W, I.K, I.hg_rho, I.hg_q, I.hg_w, I.cv_in, I.hg_part, b - I.hg_base,
+                           I.hg_nblk);
+        return;
+    }
+}
+
+// z = -sum_blocks Z + with_r * grad r(theta); ||z||^2 into *znorm2 (a block
+// of 1024 threads).
 template <int KT>
-__global__ __launch_bounds__(1024) void k_hg_final(double beta, double h1_w0, const double* __restrict__ part, int nblk, int K,
-                                                   const double* __restrict__ th, const double* __restrict__ a, int with_r,
-                                                   double* __restrict__ z, double* __restrict__ znorm2) {
+__device__ __forceinline__ void hg_final_blk(double beta, double h1_w0, const double* __restrict__ part, int nblk, int K,
+                                             const double* __restrict__ th, const double* __restrict__ a, int with_r,
+                                             double* __restrict__ z, double* __restrict__ znorm2) {
     __shared__ double s_e[1024];
     __shared__ double s_z[1024];
     __shared__ double s_g[1024];
@@ -1745,6 +1817,14 @@ __global__ __launch_bounds__(1024) void k_hg_final(double beta, double h1_w0, co
         for (int i = 0; i < KK; ++i) s += s_z[i];
         *znorm2 = s;
     }
+}
+
+// block i finishes instance i of a batched correlation launch (if it was in it)
+template <typename T, int KT>
+__global__ __launch_bounds__(1024) void k_hg_final_batch(const Inst<T>* __restrict__ insts) {
+    const Inst<T>& I = insts[blockIdx.x];
+    if (I.hg_nblk <= 0 || (I.K <= 16) != (KT == 16)) return;
+    hg_final_blk<KT>(I.beta, I.h1_w0, I.hg_part, I.hg_nblk, I.K, I.theta64, I.hg_a, I.hg_with_r, I.hg_z, I.hg_zn2);
 }
 
 }  // namespace maid

@@ -25,8 +25,8 @@
 // magnitude into [2^14, 2^15), and the kernel likewise (its exponent comes
 // with the fragments); the accumulated sums are scaled back exactly.
 //
-// Work split: the four waves of a block take a quarter of the chunks each
-// and accumulate every output block of the tile; their partial sums are
+// Work split: the four waves of a block take every fourth chunk each and
+// accumulate every output block of the tile; their partial sums are
 // combined through LDS in a fixed order ((w0 + w2) + (w1 + w3)), so the
 // result is deterministic.
 #pragma once
@@ -54,12 +54,15 @@ template <typename T, int K, int R> __host__ __device__ constexpr bool mf_ok() {
 // Bytes of the B-operand layout of one kernel (hi and lo parts).
 __host__ __device__ constexpr int mf_frag_bytes(int K) { return ((K * (((K + 15) + 7) / 8 * 8) + 31) / 32) * 2 * 64 * 16; }
 
+// row pitch (floats) of the wave partial sums
+constexpr int kMfPP = 68;
+
 // LDS the correlation needs beside the staged tile: the two FP16 tiles,
 // which the wave partial sums reuse afterwards.
 template <int K, int R> __host__ __device__ constexpr int mf_lds_bytes() {
     constexpr int CR = 4 * R + K - 1;
     constexpr int tiles = 2 * CR * MfGeom<K>::P16 * 2;
-    constexpr int parts = 2 * 4 * R * 64 * 4;
+    constexpr int parts = 2 * 4 * R * kMfPP * 4;
     return tiles > parts ? tiles : parts;
 }
 
@@ -112,23 +115,29 @@ __device__ __forceinline__ void mf_fragments(const double* __restrict__ theta, i
 // of the stencil passes (lane tx of wave wy holds rows wy R .. wy R+R-1 of
 // column tx), ker given by its fragments `frag` and the power of two
 // `ksh` they were scaled by.  s: the staged FP32 tile (4R+K-1 rows, 64+K-1
-// columns, read only).  lds: mf_lds_bytes<K,R>() bytes of LDS, 16-byte
-// aligned.  Every thread of the block must call it (it has barriers).
+// columns, read only, 8-byte aligned).  lds: mf_lds_bytes<K,R>() bytes of
+// LDS, 16-byte aligned.  Every thread of the block must call it (it has barriers).
 template <int K, int R>
 __device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const uint4* __restrict__ frag, int ksh,
                                                unsigned char* lds, int li0, int tx, float (&acc)[R]) {
     using G = MfGeom<K>;
-    constexpr int TH = 4 * R, CR = TH + K - 1, CP = 64 + K - 1, NB = R, P16 = G::P16;
+    constexpr int TH = 4 * R, CR = TH + K - 1, CP = 64 + K - 1, NB = R, P16 = G::P16, PP = kMfPP;
     __shared__ float s_mx[4];
     _Float16* Sh = reinterpret_cast<_Float16*>(lds);
     _Float16* Sl = Sh + CR * P16;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
-    // the tile's largest magnitude (max is exact: any order gives the same)
+    // the tile's largest magnitude (max is exact: any order gives the same),
+    // read as float2 over the flat tile (rows are whole pairs: CP is even)
+    static_assert(CP % 2 == 0 && P16 % 8 == 0, "tile shapes");
     float mx = 0.0f;
-    for (int e = t; e < CR * CP; e += 256) {
-        const int r = e / CP, c = e - r * CP;
-        mx = fmaxf(mx, fabsf(s[r * pitch + c]));
+    {
+        constexpr int N2 = CR * CP / 2;
+        const float2* s2 = reinterpret_cast<const float2*>(s);
+        for (int e = t; e < N2; e += 256) {
+            const float2 v = s2[e];
+            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
@@ -138,12 +147,27 @@ __device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const 
     // a tile of zeros (or one below the normal range) keeps shift 0
     const int sh = mx >= 1.0e-30f ? mf_shift(mx) : 0;
     const float scale = mf_pow2(sh);
-    for (int e = t; e < CR * P16; e += 256) {
-        const int r = e / P16, c = e - r * P16;
-        const float v = c < CP ? s[r * pitch + c] * scale : 0.0f;
-        const _Float16 h = (_Float16)v;
-        Sh[e] = h;
-        Sl[e] = (_Float16)(v - (float)h);
+    // the split: each thread converts runs of 8 columns of one row (float2
+    // reads, one 16-byte write per part); columns past the tile are zero
+    {
+        constexpr int NS = P16 / 8;
+        for (int e = t; e < CR * NS; e += 256) {
+            const int r = e / NS, c = 8 * (e - r * NS);
+            union { _Float16 h[8]; uint4 v; } hi, lo;
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                float2 v = make_float2(0.0f, 0.0f);
+                if (c + k < CP) v = *reinterpret_cast<const float2*>(s + r * pitch + c + k);
+                const float a = v.x * scale, b = v.y * scale;
+                const _Float16 ha = (_Float16)a, hb = (_Float16)b;
+                hi.h[k] = ha;
+                hi.h[k + 1] = hb;
+                lo.h[k] = (_Float16)(a - (float)ha);
+                lo.h[k + 1] = (_Float16)(b - (float)hb);
+            }
+            *reinterpret_cast<uint4*>(Sh + r * P16 + c) = hi.v;
+            *reinterpret_cast<uint4*>(Sl + r * P16 + c) = lo.v;
+        }
     }
     __syncthreads();
 
@@ -151,33 +175,46 @@ __device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const 
 #pragma unroll
     for (int b = 0; b < NB; ++b) d[b] = mf_f4{0.0f, 0.0f, 0.0f, 0.0f};
     const int r16 = lane & 15, g = lane >> 4;
-    const int c_lo = (w * G::NC) >> 2, c_hi = ((w + 1) * G::NC) >> 2;
+    // chunks dealt round-robin to the waves (c = w, w+4, ...); the B
+    // fragments of the next chunk are loaded while this chunk's products
+    // run (the last prefetch re-reads the last chunk: no branch in the loop)
     const uint4* __restrict__ F = frag + lane;
-#pragma unroll 2
-    for (int c = c_lo; c < c_hi; ++c) {
-        const uint4 bh4 = F[(2 * c) * 64], bl4 = F[(2 * c + 1) * 64];
+    const int nw = (G::NC - w + 3) >> 2;
+    uint4 bh4 = F[(2 * w) * 64], bl4 = F[(2 * w + 1) * 64];
+#pragma unroll 1
+    for (int i = 0; i < nw; ++i) {
+        const int c = w + 4 * i;
         const mf_h8 bh = __builtin_bit_cast(mf_h8, bh4), bl = __builtin_bit_cast(mf_h8, bl4);
+        const int cn = c + 4 < G::NC ? c + 4 : G::NC - 1;
+        bh4 = F[(2 * cn) * 64];
+        bl4 = F[(2 * cn + 1) * 64];
         const int k0 = 32 * c + 8 * g;
         int u = k0 / G::Lm;
         const int m0 = k0 - u * G::Lm;
         u = u < K ? u : K - 1;               // padding rows: the fragments are zero there
         const int base = (r16 + u) * P16 + m0;
+        mf_h8 ah[NB], al[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int off = base + 16 * (b >> 2) * P16 + 16 * (b & 3);
-            const mf_h8 ah = *reinterpret_cast<const mf_h8*>(Sh + off);
-            const mf_h8 al = *reinterpret_cast<const mf_h8*>(Sl + off);
-            d[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, d[b], 0, 0, 0);
-            d[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, d[b], 0, 0, 0);
-            d[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, d[b], 0, 0, 0);
+            ah[b] = *reinterpret_cast<const mf_h8*>(Sh + off);
+            al[b] = *reinterpret_cast<const mf_h8*>(Sl + off);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            d[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[b], bh, d[b], 0, 0, 0);
+            d[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[b], bl, d[b], 0, 0, 0);
+            d[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[b], bh, d[b], 0, 0, 0);
         }
     }
     __syncthreads();   // every wave is done with the FP16 tiles
 
-    // wave partials: lane (g, r16) holds rows 4g..4g+3, column r16 of each block
-    float* P = reinterpret_cast<float*>(lds);   // [2][TH][64]
+    // wave partials: lane (g, r16) holds rows 4g..4g+3, column r16 of each
+    // block; rows padded to PP floats so that the four rows a write covers
+    // fall in different LDS banks
+    float* P = reinterpret_cast<float*>(lds);   // [2][TH][PP]
     auto at_p = [&](int half, int b, int k) -> float& {
-        return P[(half * TH + 16 * (b >> 2) + 4 * g + k) * 64 + 16 * (b & 3) + r16];
+        return P[(half * TH + 16 * (b >> 2) + 4 * g + k) * PP + 16 * (b & 3) + r16];
     };
     if (w >= 2) {
 #pragma unroll
@@ -200,7 +237,7 @@ __device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const 
 #pragma unroll
     for (int o = 0; o < R; ++o) {
         const int row = li0 + o;
-        const float v = P[row * 64 + tx] + P[(TH + row) * 64 + tx];
+        const float v = P[row * PP + tx] + P[(TH + row) * PP + tx];
         acc[o] += (v * unscale_x) * unscale_k;
     }
     __syncthreads();   // the LDS region may be reused by the caller

@@ -94,18 +94,28 @@ template <typename T> struct Ops {
     static hipError_t cg_team(const Group& g, const Inst<T>* insts, const int* list, int nlist, CgState* st, int n,
                               const TeamCtl& ctl, long max_slots, hipStream_t s);
     static hipError_t team_occupancy(const Group& g, int* blocks_per_cu);
-    static hipError_t hg_corr(const Shape& d, const T* rho, const T* q, const T* w, const T* xt, double* part, int nblk,
-                              hipStream_t s);
+    // batched forms: all instances of tile class kt (16: K <= 16, else 32),
+    // `blocks` = the class's total hg_nblk; the finishing launch has n blocks
+    static hipError_t hg_corr_batch(int kt, int blocks, const Inst<T>* insts, int n, hipStream_t s);
+    static hipError_t hg_final_batch(int kt, const Inst<T>* insts, int n, hipStream_t s);
 };
 
-hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
-                           const double* a, int with_r, double* z, double* znorm2, hipStream_t s);
 // Copy bytes (a multiple of 4) from device-mapped host memory to the device.
 hipError_t launch_upload(const void* src_host, size_t bytes, void* dst, hipStream_t s);
 // XCD of each block of a kTeamXcd x kTeamMax grid (out: that many ints).
 hipError_t launch_team_map(int* out, hipStream_t s);
 hipError_t launch_publish(const void* src, size_t bytes, void* dst_host, unsigned* flag_host, hipStream_t s);
 hipError_t launch_theta_step(const double* th, const double* z, double step, double* out, int KK, hipStream_t s);
+// x += alpha d (n elements), per-block FP64 partials of d^2 and the new x^2
+// into part[2b], part[2b+1] (blocks of them)
+template <typename T>
+hipError_t launch_axpy_norms(T* x, const T* d, T alpha, int64_t n, double* part, int blocks, hipStream_t s);
+// dst = (D) src
+template <typename S, typename D>
+hipError_t launch_cast(const S* src, D* dst, int64_t n, hipStream_t s);
+// x64 += alpha d, x32 = (float) x64, partials of d^2 and x64^2 (2 per block)
+hipError_t launch_axpy_mixed(double* x64, const float* d, double alpha, int64_t n, float* x32, double* part, int blocks,
+                             hipStream_t s);
 hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s);
 int hg_items(const Shape& d);
 

@@ -7,6 +7,72 @@
 
 namespace maid {
 
+// x += alpha d over n elements, with per-block FP64 partial sums of d^2
+// (part[2b]) and of the new x^2 (part[2b+1]); grid-stride, kNT threads.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_axpy_norms(T* __restrict__ x, const T* __restrict__ d, T alpha, int64_t n,
+                                                    double* __restrict__ part) {
+    double dd = 0.0, xx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
+        const T di = d[i];
+        const T xi = x[i] + alpha * di;
+        x[i] = xi;
+        dd += (double)di * (double)di;
+        xx += (double)xi * (double)xi;
+    }
+    block_sum2<4>(dd, xx);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = dd;
+        part[2 * blockIdx.x + 1] = xx;
+    }
+}
+
+template <typename T>
+hipError_t launch_axpy_norms(T* x, const T* d, T alpha, int64_t n, double* part, int blocks, hipStream_t s) {
+    return launch(k_axpy_norms<T>, dim3(blocks), dim3(kNT), 0, s, x, d, alpha, n, part);
+}
+template hipError_t launch_axpy_norms<float>(float*, const float*, float, int64_t, double*, int, hipStream_t);
+template hipError_t launch_axpy_norms<double>(double*, const double*, double, int64_t, double*, int, hipStream_t);
+
+// dst[i] = (D) src[i] over n elements (grid-stride, kNT threads).
+template <typename S, typename D>
+__global__ __launch_bounds__(kNT) void k_cast(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) dst[i] = (D)src[i];
+}
+
+template <typename S, typename D>
+hipError_t launch_cast(const S* src, D* dst, int64_t n, hipStream_t s) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + kNT - 1) / kNT, 2048));
+    return launch(k_cast<S, D>, dim3(blocks), dim3(kNT), 0, s, src, dst, n);
+}
+template hipError_t launch_cast<float, double>(const float*, double*, int64_t, hipStream_t);
+template hipError_t launch_cast<double, float>(const double*, float*, int64_t, hipStream_t);
+
+// x64 += alpha d (d in FP32, the sum in FP64), x32 = x64 rounded, per-block
+// FP64 partials of d^2 (part[2b]) and x64^2 (part[2b+1]).
+__global__ __launch_bounds__(kNT) void k_axpy_mixed(double* __restrict__ x64, const float* __restrict__ d, double alpha,
+                                                    int64_t n, float* __restrict__ x32, double* __restrict__ part) {
+    double dd = 0.0, xx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
+        const double di = (double)d[i];
+        const double xi = x64[i] + alpha * di;
+        x64[i] = xi;
+        x32[i] = (float)xi;
+        dd += di * di;
+        xx += xi * xi;
+    }
+    block_sum2<4>(dd, xx);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = dd;
+        part[2 * blockIdx.x + 1] = xx;
+    }
+}
+
+hipError_t launch_axpy_mixed(double* x64, const float* d, double alpha, int64_t n, float* x32, double* part, int blocks,
+                             hipStream_t s) {
+    return launch(k_axpy_mixed, dim3(blocks), dim3(kNT), 0, s, x64, d, alpha, n, x32, part);
+}
+
 // out = th - s z  (double, K*K)
 __global__ void k_theta_step(const double* __restrict__ th, const double* __restrict__ z, double s, double* __restrict__ out, int KK) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -170,11 +236,15 @@ hipError_t Ops<T>::cg_init(int grid_e, const int* blk_e, int only, const Inst<T>
 }
 
 template <typename T>
-hipError_t Ops<T>::hg_corr(const Shape& d, const T* rho, const T* q, const T* w, const T* xt, double* part, int nblk,
-                           hipStream_t s) {
-    if (d.K <= 16)
-        return launch((k_hg_corr<T, 16>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
-    return launch((k_hg_corr<T, 32>), dim3(nblk), dim3(kNT), 0, s, d.C, d.H, d.W, d.K, rho, q, w, xt, part);
+hipError_t Ops<T>::hg_corr_batch(int kt, int blocks, const Inst<T>* insts, int n, hipStream_t s) {
+    if (kt == 16) return launch((k_hg_corr_batch<T, 16>), dim3(blocks), dim3(kNT), 0, s, insts, n);
+    return launch((k_hg_corr_batch<T, 32>), dim3(blocks), dim3(kNT), 0, s, insts, n);
+}
+
+template <typename T>
+hipError_t Ops<T>::hg_final_batch(int kt, const Inst<T>* insts, int n, hipStream_t s) {
+    if (kt == 16) return launch((k_hg_final_batch<T, 16>), dim3(n), dim3(1024), 0, s, insts);
+    return launch((k_hg_final_batch<T, 32>), dim3(n), dim3(1024), 0, s, insts);
 }
 
 // dst[i] = src[i] for `words` 32-bit words, src in host memory mapped for the
@@ -232,13 +302,6 @@ LaunchTiming& launch_timing() {
 
 int hg_items(const Shape& d) {
     return ((d.W + kHgTJ - 1) / kHgTJ) * ((d.H + kHgTI - 1) / kHgTI) * d.C * 2;
-}
-
-hipError_t launch_hg_final(const Shape& d, double beta, double h1_w0, const double* part, int nblk, const double* th,
-                           const double* a, int with_r, double* z, double* znorm2, hipStream_t s) {
-    if (d.K <= 16)
-        return launch(k_hg_final<16>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
-    return launch(k_hg_final<32>, dim3(1), dim3(1024), 0, s, beta, h1_w0, part, nblk, d.K, th, a, with_r, z, znorm2);
 }
 
 hipError_t launch_theta_step(const double* th, const double* z, double step, double* out, int KK, hipStream_t s) {

@@ -93,20 +93,19 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
     if (!start) {
         cur = st.nxt;
         prev = st.cur;
-        tnext = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.t * st.t));
-        mnext = (st.t - 1.0) / tnext;
+        tnext = st.fixed ? 1.0 : 0.5 * (1.0 + sqrt(1.0 + 4.0 * st.t * st.t));
+        mnext = st.fixed ? 0.0 : (st.t - 1.0) / tnext;
     }
-    // tile pixels of this thread: theta*x, theta*x_prev and y for the data part
-    T kxr[R], kxpr[R], yr[R];
+    // tile pixels of this thread: the residuals theta*x - y at x and x_prev
+    T kxr[R], kxpr[R];
     auto stage_point = [&](int ci, int pi, T m) {
         const T* __restrict__ X = pick(I.X[0], I.X[1], I.X[2], ci);
         const T* __restrict__ XP = pick(I.X[0], I.X[1], I.X[2], pi);
         const T* __restrict__ KX = pick(I.KX[0], I.KX[1], I.KX[2], ci);
         const T* __restrict__ KXP = pick(I.KX[0], I.KX[1], I.KX[2], pi);
-        const T* __restrict__ Y = I.y;
         auto rs = stage<CRE, CP, CP, kStepNT>(s_r, ei0 - c0, ej0 - c0, [&](int g) {
             const T kx = ld<CO>(KX, g);
-            return dfma(m, kx - ld<CO>(KXP, g), kx) - ld<CO>(Y, g);
+            return dfma(m, kx - ld<CO>(KXP, g), kx);
         });
         auto vs = stage<VRE, VP, VP, kStepNT>(s_v, ei0 - 1, ej0 - 1, [&](int g) {
             const T xv = ld<CO>(X, g);
@@ -119,7 +118,6 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
             const int e = clampi(ti0 + wv * R + o, H - 1) * W + clampi(tj0 + tx, W - 1);
             kxr[o] = ld<CO>(KX, e);
             kxpr[o] = ld<CO>(KXP, e);
-            yr[o] = ld<CO>(Y, e);
         }
         warm_taps<T, K>(I.th, I.thf);
         rs.put();
@@ -154,7 +152,7 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
         if (!finite_d(delta)) {
             st.done = 1;
             st.status = ST_NONFINITE;
-        } else if (delta <= -st.gn2 / (2.0 * st.L)) {
+        } else if (st.fixed || delta <= -st.gn2 / (2.0 * st.L)) {
             if (writer && I.trace && st.iters < st.trace_cap) I.trace[st.iters] = st.nb_iter;
             st.iters += 1;
             st.nxt = st.prev;
@@ -261,28 +259,56 @@ __device__ __forceinline__ void apg_step_body(const Inst<T>& I, int lb, ApgState
             const int e = gi * W + oj;
             const T kv = dfma(m, kxr[o] - kxpr[o], kxr[o]);
             const T d = dacc[o];
-            const double rv = (double)kv - (double)yr[o];
-            ddat += (double)d * (rv + 0.5 * (double)d);
+            ddat += (double)d * ((double)kv + 0.5 * (double)d);
             at(XN, e) = s_v[(li0 + o + c0 + 1) * VP + tx + c0 + 1] + s_g[(li0 + o + c0) * CP + tx + c0];
             if (!exact) at(KXN, e) = kv + d;
         }
     }
     if (exact) {
-        // theta*x+ from x+ = v + dl on E (zero outside the image)
+        // the residual at x+ = v + dl (formed on E, zero outside the image):
+        // in full, theta*x+ - y with FP64 taps and sums, x+ becoming the base
+        // point; otherwise r_base + theta*(x+ - x_base)
+        const bool full = st.resync_full > 0 && (st.iters % st.resync_full) == 0;
+        T* __restrict__ XB = I.xb;
+        T* __restrict__ RB = I.rb;
+        const T* __restrict__ Y = I.y;
         T* s_x = s_r;
         __syncthreads();
         for (int idx = threadIdx.x; idx < step_th(RE) * kTW; idx += kStepNT) {
             const int r = idx / kTW, cc = idx - r * kTW;
-            s_x[r * CP + cc] = s_v[(r + 1) * VP + cc + 1] + s_g[r * CP + cc];
+            const int gi = ei0 + r, gj = ej0 + cc;
+            const T xb = (full || !inside(gi, gj, H, W)) ? T(0) : ld<CO>(XB, clampi(gi, H - 1) * W + clampi(gj, W - 1));
+            s_x[r * CP + cc] = (s_v[(r + 1) * VP + cc + 1] + s_g[r * CP + cc]) - xb;
         }
         __syncthreads();
+        if (full) {
+            double a64[R];
 #pragma unroll
-        for (int o = 0; o < R; ++o) dacc[o] = T(0);
-        correlate<T, K, R>(s_x, CP, I.thf, li0, tx, dacc);
+            for (int o = 0; o < R; ++o) a64[o] = 0.0;
+            correlate64<T, K, R>(s_x, CP, I.theta64, true, li0, tx, a64);
 #pragma unroll
-        for (int o = 0; o < R; ++o) {
-            const int gi = ti0 + li0 + o;
-            if (lane_in && gi < H && oj < W) at(KXN, gi * W + oj) = dacc[o];
+            for (int o = 0; o < R; ++o) {
+                const int gi = ti0 + li0 + o;
+                if (lane_in && gi < H && oj < W) {
+                    const int e = gi * W + oj;
+                    const T r = (T)(a64[o] - (double)ld<CO>(Y, e));
+                    at(KXN, e) = r;
+                    at(RB, e) = r;
+                    at(XB, e) = s_x[(li0 + o + c0) * CP + tx + c0];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < R; ++o) dacc[o] = T(0);
+            correlate<T, K, R>(s_x, CP, I.thf, li0, tx, dacc);
+#pragma unroll
+            for (int o = 0; o < R; ++o) {
+                const int gi = ti0 + li0 + o;
+                if (lane_in && gi < H && oj < W) {
+                    const int e = gi * W + oj;
+                    at(KXN, e) = ld<CO>(RB, e) + dacc[o];
+                }
+            }
         }
     }
     block_partial2_1<kStepNW>(gsq, wA, ddat + I.pr.alpha * dtv, wB, lb);

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes as ct
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -63,8 +64,8 @@ class Maid:
         self.C, self.H, self.W, self.K = int(C), int(H), int(W), int(K)
         self.dtype = dtype
         self.alpha, self.eps_tv, self.beta, self.h1_w0, self.reg = alpha, eps_tv, beta, h1_w0, reg
-        self.desc = L.maid_desc(self.H, self.W, self.C, self.K, _DT[dtype], int(reg), float(alpha),
-                                float(eps_tv), float(beta), float(h1_w0))
+        self.desc = L.maid_desc(H=self.H, W=self.W, C=self.C, K=self.K, dtype=_DT[dtype], boundary=0, reg=int(reg),
+                                alpha=float(alpha), eps_tv=float(eps_tv), beta=float(beta), h1_w0=float(h1_w0))
         self._h = None
         self._h = L.create(self.desc)
 
@@ -177,6 +178,24 @@ class Maid:
         return SolveInfo(rc, info.iters, info.backtracks, info.res_norm, info.L,
                          list(tr[:info.iters]) if trace else [])
 
+    def lower_solve_refined(self, theta, y, x, tol, max_iter=300, rel_tol=1e-7, max_newton=4, max_cg=2000,
+                            L_est=0.0):
+        """The precision form: lower-level solve to `tol`, then Newton steps
+        (FP64 residual, CG correction in the storage type) until the relative
+        step is below `rel_tol`.  Returns (SolveInfo of the first phase, dict
+        of the refinement: newton_steps, cg_iters, status, rel_step,
+        grad_norm)."""
+        self._ker(theta, "theta"), self._img(y, "y"), self._img(x, "x")
+        Lc = ct.c_double(L_est)
+        info = L.maid_solve_info()
+        rinfo = L.maid_refine_info()
+        rc = L.lib().maid_lower_solve_refined(self.handle, _ptr(theta), _ptr(y), _ptr(x), float(tol), int(max_iter),
+                                              float(rel_tol), int(max_newton), int(max_cg), ct.byref(Lc),
+                                              ct.byref(info), ct.byref(rinfo), _stream())
+        self._check(rc, "lower_solve_refined")
+        return (SolveInfo(info.status, info.iters, info.backtracks, info.res_norm, info.L),
+                {f: getattr(rinfo, f) for f, _ in L.maid_refine_info._fields_})
+
     def upper_value_grad(self, a, y, x, grad_out=None):
         self._ker(a, "a"), self._img(y, "y"), self._img(x, "x")
         if grad_out is not None:
@@ -241,6 +260,64 @@ class Maid:
         state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
         return rc, {f: getattr(info, f) for f, _ in L.maid_step_info._fields_}
 
+    # ---------------------------------------------------------------- Section 4.1's baselines
+    def gd_solve(self, theta, y, x, step, n_iter, tol=0.0, hist=None):
+        """maid_gd_solve: n_iter fixed-step gradient iterations, in place in x;
+        hist (optional, n_iter x C x H x W) receives x_1 .. x_n."""
+        self._ker(theta, "theta"), self._img(y, "y"), self._img(x, "x")
+        hp = None
+        if hist is not None:
+            if not isinstance(hist, torch.Tensor) or not hist.is_cuda or hist.dtype != self.dtype or \
+                    not hist.is_contiguous() or hist.numel() < int(n_iter) * self.C * self.H * self.W:
+                raise ValueError("hist must be a contiguous CUDA tensor of n_iter*C*H*W elements of the storage type")
+            hp = hist.data_ptr()
+        info = L.maid_solve_info()
+        rc = L.lib().maid_gd_solve(self.handle, _ptr(theta), _ptr(y), _ptr(x), float(step), int(n_iter), float(tol),
+                                   hp, ct.byref(info), _stream())
+        self._check(rc, "gd_solve")
+        return SolveInfo(info.status, info.iters, info.backtracks, info.res_norm, info.L)
+
+    def hessian_apply(self, theta, x, w, out=None):
+        """maid_hessian_apply: out = H(x) w (Proposition 1's Hessian)."""
+        self._ker(theta, "theta"), self._img(x, "x"), self._img(w, "w")
+        if out is None:
+            out = torch.empty_like(w)
+        self._img(out, "out")
+        self._check(L.lib().maid_hessian_apply(self.handle, _ptr(theta), _ptr(x), _ptr(w), _ptr(out), _stream()),
+                    "hessian_apply")
+        return out
+
+    def _adp_state(self, state: MaidState):
+        return L.maid_state(state.theta.data_ptr(), state.x.data_ptr(), state.q.data_ptr(), state.eps, state.delta,
+                            state.step, state.L, state.k)
+
+    def ift_step(self, a, y, state: MaidState, n_lower=500, lambda_x=0.1, cg_tol=1e-3, max_cg=1000):
+        """maid_ift_step: one ADP-IFT upper iteration (state.step is the upper
+        step size); returns (rc, info dict)."""
+        self._ker(a, "a"), self._img(y, "y"), self._ker(state.theta, "theta")
+        self._img(state.x, "x"), self._img(state.q, "q")
+        st = self._adp_state(state)
+        info = L.maid_step_info()
+        rc = L.lib().maid_ift_step(self.handle, _ptr(a), _ptr(y), ct.byref(st), int(n_lower), float(lambda_x),
+                                   float(cg_tol), int(max_cg), ct.byref(info), _stream())
+        self._check(rc, "ift_step")
+        state.k = st.k
+        return rc, {f: getattr(info, f) for f, _ in L.maid_step_info._fields_}
+
+    def lista_step(self, a, y, state: MaidState, n_unroll=50, lambda_x=0.1):
+        """maid_lista_step: one ADP-LISTA upper iteration; returns (rc, info
+        dict).  The context must be on the two-pass form (set_one_pass(0))."""
+        self._ker(a, "a"), self._img(y, "y"), self._ker(state.theta, "theta"), self._img(state.x, "x")
+        if state.q is not None:
+            self._img(state.q, "q")
+        st = self._adp_state(state)
+        info = L.maid_step_info()
+        rc = L.lib().maid_lista_step(self.handle, _ptr(a), _ptr(y), ct.byref(st), int(n_unroll), float(lambda_x),
+                                     ct.byref(info), _stream())
+        self._check(rc, "lista_step")
+        state.k = st.k
+        return rc, {f: getattr(info, f) for f, _ in L.maid_step_info._fields_}
+
     def maid_step_traced(self, a, y, state: MaidState, cap=1 << 20, **hp):
         """maid_step with its decision trace (record layout in maid.h):
         returns (rc, info, words, values)."""
@@ -268,8 +345,10 @@ class MaidBatch:
         self.dtype = dtype
         self.specs = [dict(alpha=1e-3, eps_tv=1e-2, beta=0.0, h1_w0=1.0, reg=L.MAID_REG_TV) | dict(s) for s in specs]
         self.n = len(self.specs)
-        self.descs = [L.maid_desc(int(s["H"]), int(s["W"]), int(s["C"]), int(s["K"]), _DT[dtype], int(s["reg"]),
-                                  float(s["alpha"]), float(s["eps_tv"]), float(s["beta"]), float(s["h1_w0"]))
+        self.descs = [L.maid_desc(H=int(s["H"]), W=int(s["W"]), C=int(s["C"]), K=int(s["K"]), dtype=_DT[dtype],
+                                  boundary=0, reg=int(s["reg"]),
+                                  alpha=float(s["alpha"]), eps_tv=float(s["eps_tv"]), beta=float(s["beta"]),
+                                  h1_w0=float(s["h1_w0"]))
                       for s in self.specs]
         self._h = None
         self._h = L.create_batch(self.descs)
@@ -368,6 +447,13 @@ class MaidBatch:
     def maid_step(self, as_, ys, states, **hp):
         """One Algorithm 2 iteration for every instance (lockstep); the states
         are updated in place.  Returns (rc, [info dict])."""
+        return self.maid_steps(as_, ys, states, 0, **hp)
+
+    def maid_steps(self, as_, ys, states, n_steps, **hp):
+        """n_steps Algorithm 2 iterations for every instance in one call
+        (maid_batch_steps; n_steps == 0: one maid_batch_step); an instance
+        that reaches the accuracy floor or fails stops.  Returns (rc, [info
+        dict]) with the counts summed over each instance's steps."""
         a, y = self._kers(as_, "a"), self._imgs(ys, "y")
         self._kers([s.theta for s in states], "theta")
         self._imgs([s.x for s in states], "x"), self._imgs([s.q for s in states], "q")
@@ -377,8 +463,119 @@ class MaidBatch:
         st = (L.maid_state * self.n)(*[L.maid_state(s.theta.data_ptr(), s.x.data_ptr(), s.q.data_ptr(), s.eps,
                                                     s.delta, s.step, s.L, s.k) for s in states])
         info = (L.maid_step_info * self.n)()
-        rc = L.lib().maid_batch_step(self.handle, a, y, st, ct.byref(hpc), info, _stream())
+        if n_steps:
+            rc = L.lib().maid_batch_steps(self.handle, a, y, st, ct.byref(hpc), info, int(n_steps), _stream())
+        else:
+            rc = L.lib().maid_batch_step(self.handle, a, y, st, ct.byref(hpc), info, _stream())
         self._rc(rc, "batch_step")
         for s, c in zip(states, st):
             s.eps, s.delta, s.step, s.L, s.k = c.eps, c.delta, c.step, c.L, c.k
+        return rc, [{f: getattr(i, f) for f, _ in L.maid_step_info._fields_} for i in info]
+
+
+class Maid1D:
+    """Section 4.1's 1D problem (maid1d.h): a batch of `batch` signals of n
+    samples, full n x n operators, FP64.  B is (batch, n, n), A (n, n),
+    vectors (batch, n), all contiguous CUDA float64 tensors."""
+
+    def __init__(self, n, batch=1, alpha1=1.2e-3, alpha2=4e-3):
+        self.n, self.batch = int(n), int(batch)
+        self.alpha1, self.alpha2 = float(alpha1), float(alpha2)
+        h = ct.c_void_p()
+        self._h = None
+        rc = L.lib().maid1d_create(ct.byref(L.maid1d_desc(self.n, self.batch, self.alpha1, self.alpha2)), ct.byref(h))
+        if rc != L.OK:
+            raise L.MaidError(rc, L.lib().maid1d_last_error(None).decode())
+        self._h = h.value
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and L is not None and L._lib is not None:
+            L._lib.maid1d_destroy(ct.c_void_p(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context is closed")
+        return ct.c_void_p(self._h)
+
+    def _t(self, t, shape, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or \
+                tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of shape {tuple(shape)}")
+        return _ptr(t)
+
+    def _vec(self, t, name):
+        return self._t(t, (self.batch, self.n), name)
+
+    def _mat(self, t, name):
+        return self._t(t, (self.batch, self.n, self.n), name)
+
+    def _per(self, v):
+        v = [float(v)] * self.batch if np.isscalar(v) else [float(a) for a in v]
+        if len(v) != self.batch:
+            raise ValueError(f"need {self.batch} values")
+        return (ct.c_double * self.batch)(*v)
+
+    def _rc(self, rc, what):
+        if rc < 0:
+            raise L.MaidError(rc, f"{what}: {L.lib().maid1d_last_error(self.handle).decode()}")
+        return rc
+
+    def lower_solve(self, B, y, x, step, tol, max_iter=300):
+        """maid1d_lower_solve, in place in x; returns (rc, [SolveInfo])."""
+        info = (L.maid_solve_info * self.batch)()
+        rc = L.lib().maid1d_lower_solve(self.handle, self._mat(B, "B"), self._vec(y, "y"), self._vec(x, "x"),
+                                        float(step), self._per(tol), int(max_iter), info, _stream())
+        self._rc(rc, "lower_solve")
+        return rc, [SolveInfo(i.status, i.iters, 0, i.res_norm, i.L) for i in info]
+
+    def upper_value_grad(self, A, y, x, grad=None):
+        g = (ct.c_double * self.batch)()
+        gn = (ct.c_double * self.batch)()
+        gp = self._vec(grad, "grad") if grad is not None else None
+        rc = L.lib().maid1d_upper_value_grad(self.handle, self._t(A, (self.n, self.n), "A"), self._vec(y, "y"),
+                                             self._vec(x, "x"), gp, g, gn, _stream())
+        self._rc(rc, "upper_value_grad")
+        return list(g), list(gn)
+
+    def adjoint_solve(self, B, x, rhs, q, tol, max_iter=1000):
+        info = (L.maid_solve_info * self.batch)()
+        rc = L.lib().maid1d_adjoint_solve(self.handle, self._mat(B, "B"), self._vec(x, "x"), self._vec(rhs, "rhs"),
+                                          self._vec(q, "q"), self._per(tol), int(max_iter), info, _stream())
+        self._rc(rc, "adjoint_solve")
+        return rc, [SolveInfo(i.status, i.iters, 0, i.res_norm) for i in info]
+
+    def hypergrad(self, B, y, x, q, z=None):
+        if z is None:
+            z = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=B.device)
+        zn = (ct.c_double * self.batch)()
+        rc = L.lib().maid1d_hypergrad(self.handle, self._mat(B, "B"), self._vec(y, "y"), self._vec(x, "x"),
+                                      self._vec(q, "q"), self._mat(z, "z"), zn, _stream())
+        self._rc(rc, "hypergrad")
+        return z, list(zn)
+
+    def step(self, A, y, B, x, q, sched, lam_x=0.1, **hp):
+        """maid1d_step: one Algorithm 2 iteration per instance, B, x, q in
+        place; sched: list of dicts (eps, delta, step, k), updated in place.
+        Returns (rc, [info dict])."""
+        h = dict(DEFAULT_HPARAMS)
+        h.update(hp)
+        hpc = L.maid_hparams(**h)
+        sc = (L.maid1d_sched * self.batch)(*[L.maid1d_sched(s["eps"], s["delta"], s["step"], s.get("k", 0))
+                                             for s in sched])
+        info = (L.maid_step_info * self.batch)()
+        rc = L.lib().maid1d_step(self.handle, self._t(A, (self.n, self.n), "A"), self._vec(y, "y"), self._mat(B, "B"),
+                                 self._vec(x, "x"), self._vec(q, "q"), sc, ct.byref(hpc), float(lam_x), info,
+                                 _stream())
+        self._rc(rc, "step")
+        for s, c in zip(sched, sc):
+            s.update(eps=c.eps, delta=c.delta, step=c.step, k=c.k)
         return rc, [{f: getattr(i, f) for f, _ in L.maid_step_info._fields_} for i in info]

@@ -27,3 +27,40 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _close_gpu_contexts(request):
+    """Every library context a GPU test opens is closed when the test ends,
+    passed or failed (a failed test's traceback would otherwise keep its
+    contexts, and their device memory, streams and graphs, alive for the
+    rest of the session), and the stream is drained before the next test."""
+    if "gpu" not in request.keywords:
+        yield
+        return
+    from paper_2502_09758_amd import maid as M
+
+    opened = []
+    inits = {cls: cls.__init__ for cls in (M.Maid, M.MaidBatch)}
+
+    def wrap(cls):
+        orig = inits[cls]
+
+        def init(self, *a, **kw):
+            orig(self, *a, **kw)
+            opened.append(self)
+        return init
+
+    for cls in inits:
+        cls.__init__ = wrap(cls)
+    try:
+        yield
+    finally:
+        for cls, orig in inits.items():
+            cls.__init__ = orig
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+        for ctx in opened:
+            ctx.close()
+        opened.clear()

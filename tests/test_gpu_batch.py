@@ -127,6 +127,42 @@ def test_batch_maid_steps_equal_solo_bitwise():
     mb.close()
 
 
+def test_batch_multi_step_call_equals_single_steps():
+    """maid_batch_steps(n = 4) in one call: bitwise the states of four
+    maid_batch_step calls, the counts summed over the steps, the last step's
+    values."""
+    print("[case] maid_batch_steps(4) == 4 x maid_batch_step, f32", flush=True)
+    dt = torch.float32
+    insts = small_batch()[:4]
+    a = [dev(i.a, torch.float64) for i in insts]
+    ys = [dev(i.y, dt) for i in insts]
+
+    def fresh():
+        return [MaidState(a[k].clone(), ys[k].clone(), torch.zeros_like(ys[k]), eps=1e-3, delta=1e-3, step=1e-3)
+                for k in range(len(insts))]
+
+    hp = dict(eps_min=1e-12)
+    mb = MaidBatch([spec(i) for i in insts], dt)
+    one = fresh()
+    steps = [mb.maid_step(a, ys, one, **hp)[1] for _ in range(4)]
+    print("   statuses per step: " + str([[f["status"] for f in st] for st in steps]), flush=True)
+    # no instance ends its run early here (else the single calls go on where the multi-step call stops)
+    assert all(st[k]["status"] in (L.OK, L.MAXITER) for st in steps[:-1] for k in range(len(insts)))
+    many = fresh()
+    rc, tot = mb.maid_steps(a, ys, many, 4, **hp)
+    assert rc in (L.OK, L.MAXITER), rc
+    for k in range(len(insts)):
+        assert torch.equal(one[k].theta, many[k].theta) and torch.equal(one[k].x, many[k].x)
+        assert torch.equal(one[k].q, many[k].q)
+        assert (one[k].eps, one[k].delta, one[k].step, one[k].L, one[k].k) == \
+            (many[k].eps, many[k].delta, many[k].step, many[k].L, many[k].k)
+        for f in ("accepted", "trials", "retries", "lower_iters", "cg_iters"):
+            assert tot[k][f] == sum(st[k][f] for st in steps), (k, f)
+        for f in ("psi", "ell_k", "ell_next", "znorm"):
+            assert tot[k][f] == steps[-1][k][f], (k, f)
+    mb.close()
+
+
 def test_batch_failing_instance_isolated():
     """A NaN in one instance's data: that instance reports NONFINITE and keeps
     its x unwritten; every other instance equals its solo run."""
