@@ -255,6 +255,29 @@ int maid_upper_value_grad(maid_ctx* ctx, const void* a, const void* y, const voi
                           void* grad_out, double* g_out, double* gradnorm_out,
                           hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation): maid_upper_value_grad
+   of one instance described by `desc`, with no context.  The same kernels
+   and the same arithmetic as maid_upper_value_grad on a new context of
+   that description (tile rows from the size rule), so the results are
+   bitwise equal.  Its workspace (instance table, the kernel a in the
+   storage type, per-block partial sums, reduction slots, the residual
+   a*x - y, and the gradient when grad_out is NULL) is one fixed device
+   array of 64 MiB in the library, held by every device the library runs on
+   until the process ends: instances needing more (C*H*W*element size above
+   about 64 MiB, half that with grad_out NULL) are rejected with
+   MAID_EINVAL before any GPU work.  No hipMalloc, hipFree or other
+   allocation is made.  All calls on one device share that array and
+   overwrite it: calls that overlap on one device (other streams, other
+   host threads) race and must not be made.  Arrays as in
+   maid_upper_value_grad (device pointers, desc->dtype storage, a FP64);
+   the call synchronises `stream` and writes g and ||grad g|| to the host
+   pointers (nullable).  why (nullable): on an error, a message valid until
+   the next call on this host thread. */
+int maid_upper_value_grad_noalloc(const maid_desc* desc, const void* a, const void* y, const void* x,
+                                  void* grad_out, double* g_out, double* gradnorm_out, const char** why,
+                                  hipStream_t stream);
+
 /* Algorithm 1, Hessian system: conjugate gradients on
    (theta.theta* + alpha grad^2 R(x_tilde)) q = rhs, stopping when the
    recursive residual satisfies ||r||_2 <= tol (the accuracy delta).

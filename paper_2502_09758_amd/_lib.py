@@ -30,7 +30,7 @@ EXPORTS = ("maid_create", "maid_destroy", "maid_last_error", "maid_config_string
            "maid_create_batch", "maid_batch_size", "maid_batch_lower_solve", "maid_batch_adjoint_solve",
            "maid_batch_step", "maid_autotune", "maid_batch_upper_value_grad", "maid_batch_hypergrad",
            "maid_set_step_trace", "maid_step_trace_length", "maid_lower_solve_refined",
-           "maid_batch_create", "maid_batch_steps",
+           "maid_upper_value_grad_noalloc", "maid_batch_create", "maid_batch_steps",
            "maid_gd_solve", "maid_hessian_apply", "maid_ift_step", "maid_lista_step",
            "maid1d_create", "maid1d_destroy", "maid1d_last_error", "maid1d_lower_solve", "maid1d_upper_value_grad",
            "maid1d_adjoint_solve", "maid1d_hypergrad", "maid1d_step")
@@ -129,6 +129,9 @@ def lib():
     L.maid_lower_solve_refined.restype = ct.c_int
     L.maid_upper_value_grad.argtypes = [P, P, P, P, P, dp, dp, P]
     L.maid_upper_value_grad.restype = ct.c_int
+    L.maid_upper_value_grad_noalloc.argtypes = [ct.POINTER(maid_desc), P, P, P, P, dp, dp,
+                                                ct.POINTER(ct.c_char_p), P]
+    L.maid_upper_value_grad_noalloc.restype = ct.c_int
     L.maid_adjoint_solve.argtypes = [P, P, P, P, P, d, i32, ct.POINTER(maid_solve_info), P]
     L.maid_adjoint_solve.restype = ct.c_int
     L.maid_hypergrad.argtypes = [P, P, P, P, P, P, i32, P, dp, P]

@@ -346,6 +346,79 @@ const char* desc_problem(const maid_desc* d) {
     return nullptr;
 }
 
+template <typename T>
+int noalloc_upper_setup(const maid_desc* d, const double* a, const T* y, const T* x, T* grad_out, char* ws,
+                        size_t ws_bytes, NoallocUpper<T>* job, const char** why) {
+    static_assert(sizeof(Inst<T>) % 4 == 0 && 2 * sizeof(Inst<T>) <= 3072, "entries travel as kernel arguments");
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const Shape sh{d->C, d->H, d->W, d->K, d->reg};
+    const int R = auto_rows(sh);
+    const int nb = stencil_blocks(sh, R);
+    const size_t N = (size_t)d->C * d->H * d->W;
+    // tables, kernel copies, reduction slots, two partial arrays, the
+    // residual image and (without grad_out) the gradient
+    const size_t o_kc = al(2 * sizeof(Inst<T>));
+    const size_t o_kf = o_kc + al((size_t)d->K * d->K * sizeof(T));
+    const size_t o_red = o_kf + al((size_t)d->K * d->K * sizeof(T));
+    const size_t o_pc = o_red + al(kRedSlots * sizeof(double));
+    const size_t o_pa = o_pc + al((size_t)nb * sizeof(double));
+    const size_t o_rho = o_pa + al((size_t)nb * sizeof(double));
+    const size_t o_grad = o_rho + al(N * sizeof(T));
+    const size_t end = o_grad + (grad_out ? 0 : al(N * sizeof(T)));
+    if (end > ws_bytes) {
+        if (why)
+            *why = "upper_value_grad_noalloc: the instance needs more than the fixed 64 MiB workspace "
+                   "(C*H*W*element size must stay below about 64 MiB, 32 MiB with grad_out NULL)";
+        return MAID_EINVAL;
+    }
+    Inst<T> t[2];
+    std::memset(static_cast<void*>(t), 0, sizeof(t));
+    for (auto& I : t) {
+        I.pr = Params{d->C, d->H, d->W, d->reg, d->alpha, d->eps_tv};
+        I.K = d->K;
+        I.nb = nb;
+        I.base = 0;
+        I.N = (int64_t)N;
+        I.red = reinterpret_cast<double*>(ws + o_red);
+    }
+    // the entries of upper_impl: rho = a*x - y (flipped a), grad = a.rho
+    t[0].th = reinterpret_cast<T*>(ws + o_kc);
+    t[0].thf = reinterpret_cast<T*>(ws + o_kf);
+    t[0].theta64 = a;
+    t[0].cv_ker = reinterpret_cast<T*>(ws + o_kf);
+    t[0].cv_ker64 = a;
+    t[0].cv_flip64 = 1;
+    t[0].cv_in = x;
+    t[0].cv_sub = y;
+    t[0].cv_out = reinterpret_cast<T*>(ws + o_rho);
+    t[0].cv_part = reinterpret_cast<double*>(ws + o_pc);
+    t[1].cv_ker = reinterpret_cast<T*>(ws + o_kc);
+    t[1].cv_ker64 = a;
+    t[1].cv_flip64 = 0;
+    t[1].cv_in = reinterpret_cast<T*>(ws + o_rho);
+    t[1].cv_out = grad_out ? grad_out : reinterpret_cast<T*>(ws + o_grad);
+    t[1].cv_part = reinterpret_cast<double*>(ws + o_pa);
+    t[1].cv_prev_part = reinterpret_cast<double*>(ws + o_pc);
+    t[1].cv_prev_slot = kRedG;
+    std::memcpy(&job->words[0], &t[0], sizeof(Inst<T>));
+    std::memcpy(&job->words[1], &t[1], sizeof(Inst<T>));
+    job->g = Group{};
+    job->g.K = d->K;
+    job->g.R = R;
+    job->g.C = d->C;
+    job->g.nw = d->reg == 1 ? d->C : 1;
+    job->g.grid = nb;
+    job->g.blk = nullptr;
+    job->g.only = 0;
+    job->tab_dev = ws;
+    job->red_dev = reinterpret_cast<double*>(ws + o_red);
+    return MAID_OK;
+}
+template int noalloc_upper_setup<float>(const maid_desc*, const double*, const float*, const float*, float*, char*,
+                                        size_t, NoallocUpper<float>*, const char**);
+template int noalloc_upper_setup<double>(const maid_desc*, const double*, const double*, const double*, double*, char*,
+                                         size_t, NoallocUpper<double>*, const char**);
+
 int validate_desc(const maid_desc* d, std::string& why) {
     const char* p = desc_problem(d);
     if (!p) return MAID_OK;

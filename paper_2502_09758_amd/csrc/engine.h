@@ -203,6 +203,22 @@ int refine_one(maid_ctx* c, const double* theta, const T* y, T* x, double rel_to
 // what is wrong with a description (a static string), or nullptr
 const char* desc_problem(const maid_desc* d);
 
+// maid_upper_value_grad_noalloc: the two instance-table entries (as words,
+// to travel as kernel arguments), the launch group and the addresses inside
+// the caller's fixed workspace ws (ws_bytes) of one upper-level evaluation
+// laid out as on a new context.  MAID_EINVAL (with *why) when the instance
+// does not fit.
+template <int NW> struct Words { unsigned w[NW]; };
+template <typename T> constexpr int kInstWords = (int)(sizeof(Inst<T>) / 4);
+template <typename T> struct NoallocUpper {
+    Words<kInstWords<T>> words[2];
+    Group g;
+    char* tab_dev;     // where the two entries go
+    double* red_dev;   // the reduction slots
+};
+template <typename T>
+int noalloc_upper_setup(const maid_desc* d, const double* a, const T* y, const T* x, T* grad_out, char* ws,
+                        size_t ws_bytes, NoallocUpper<T>* job, const char** why);
 int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why);
 void destroy_ctx(maid_ctx* c);
 int relayout(maid_ctx* c);
