@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
 
 class om_problem(ct.Structure):
     _fields_ = [("C", ct.c_int32), ("H", ct.c_int32), ("W", ct.c_int32), ("K", ct.c_int32),
-                ("periodic", ct.c_int32), ("reg", ct.c_int32),
+                ("periodic", ct.c_int32), ("reg", ct.c_int32), ("kc", ct.c_int32),
                 ("alpha", ct.c_double), ("eps_tv", ct.c_double), ("beta", ct.c_double),
                 ("h1_w0", ct.c_double)]
 
@@ -158,10 +158,20 @@ class Problem:
     h1_w0: float = 1.0
     periodic: bool = False
     reg: int = 0          # 0 vectorial TV, 1 channelwise TV, 2 quadratic 1/2||Dx||^2
+    kc: int = 1           # kernel channels: 1 one shared KxK kernel, C one kernel per channel
+
+    def __post_init__(self):
+        if self.kc not in (1, self.C):
+            raise ValueError(f"kc must be 1 or C = {self.C}, got {self.kc}")
 
     def c(self) -> om_problem:
-        return om_problem(self.C, self.H, self.W, self.K, int(self.periodic), int(self.reg),
+        return om_problem(self.C, self.H, self.W, self.K, int(self.periodic), int(self.reg), int(self.kc),
                           float(self.alpha), float(self.eps_tv), float(self.beta), float(self.h1_w0))
+
+    @property
+    def tshape(self):
+        """shape of theta and a: (K, K) shared, (C, K, K) per channel"""
+        return (self.K, self.K) if self.kc == 1 else (self.kc, self.K, self.K)
 
     @property
     def shape(self):
@@ -191,14 +201,14 @@ def _f64(a, shape=None):
 
 
 def conv(p: Problem, th, x):
-    th, x = _f64(th, (p.K, p.K)), _f64(x, p.shape)
+    th, x = _f64(th, p.tshape), _f64(x, p.shape)
     out = np.empty(p.shape)
     lib().oracle_conv(ct.byref(p.c()), _d(th), _d(x), _d(out))
     return out
 
 
 def conv_adj(p: Problem, th, r):
-    th, r = _f64(th, (p.K, p.K)), _f64(r, p.shape)
+    th, r = _f64(th, p.tshape), _f64(r, p.shape)
     out = np.empty(p.shape)
     lib().oracle_conv_adj(ct.byref(p.c()), _d(th), _d(r), _d(out))
     return out
@@ -235,31 +245,31 @@ def reg_hvp(p: Problem, x, d):
 
 
 def h_value(p: Problem, th, y, x):
-    return lib().oracle_h_value(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(y, p.shape)),
+    return lib().oracle_h_value(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(y, p.shape)),
                                 _d(_f64(x, p.shape)))
 
 
 def h_grad(p: Problem, th, y, x):
     out = np.empty(p.shape)
-    lib().oracle_h_grad(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(y, p.shape)),
+    lib().oracle_h_grad(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(y, p.shape)),
                         _d(_f64(x, p.shape)), _d(out))
     return out
 
 
 def h_hvp(p: Problem, th, x, d):
     out = np.empty(p.shape)
-    lib().oracle_h_hvp(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(x, p.shape)),
+    lib().oracle_h_hvp(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(x, p.shape)),
                        _d(_f64(d, p.shape)), _d(out))
     return out
 
 
 def sobolev_value(p: Problem, th, a):
-    return lib().oracle_sobolev_value(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(a, (p.K, p.K))))
+    return lib().oracle_sobolev_value(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(a, p.tshape)))
 
 
 def sobolev_grad(p: Problem, th, a):
-    out = np.empty((p.K, p.K))
-    lib().oracle_sobolev_grad(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(a, (p.K, p.K))), _d(out))
+    out = np.empty(p.tshape)
+    lib().oracle_sobolev_grad(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(a, p.tshape)), _d(out))
     return out
 
 
@@ -276,7 +286,7 @@ def lower_solve(p: Problem, th, y, x0, tol, max_iter=300, L=0.0, replay_bt=None)
         rb = np.zeros(max(max_iter, 1), dtype=np.int32)
         rb[:len(replay_bt)] = np.asarray(replay_bt, dtype=np.int32)[:max_iter]
         rp = rb.ctypes.data_as(ct.POINTER(ct.c_int32))
-    st = lib().oracle_lower_solve(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(y, p.shape)),
+    st = lib().oracle_lower_solve(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(y, p.shape)),
                                   _d(x), float(tol), int(max_iter), ct.byref(Lc), ct.byref(info),
                                   rp, trace.ctypes.data_as(ct.POINTER(ct.c_int32)))
     d = dict(status=st, iters=info.iters, backtracks=info.backtracks, res_norm=info.res_norm,
@@ -288,7 +298,7 @@ def upper_value_grad(p: Problem, a, y, x):
     g = ct.c_double()
     gn = ct.c_double()
     grad = np.empty(p.shape)
-    lib().oracle_upper_value_grad(ct.byref(p.c()), _d(_f64(a, (p.K, p.K))), _d(_f64(y, p.shape)),
+    lib().oracle_upper_value_grad(ct.byref(p.c()), _d(_f64(a, p.tshape)), _d(_f64(y, p.shape)),
                                   _d(_f64(x, p.shape)), _d(grad), ct.byref(g), ct.byref(gn))
     return grad, g.value, gn.value
 
@@ -297,17 +307,17 @@ def adjoint_solve(p: Problem, th, xt, rhs, q0=None, tol=1e-2, max_iter=1000):
     q = np.zeros(p.shape) if q0 is None else _f64(q0, p.shape).copy()
     info = om_solve_info()
     tr = ct.c_double()
-    st = lib().oracle_adjoint_solve(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(xt, p.shape)),
+    st = lib().oracle_adjoint_solve(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(xt, p.shape)),
                                     _d(_f64(rhs, p.shape)), _d(q), float(tol), int(max_iter),
                                     ct.byref(info), ct.byref(tr))
     return q, dict(status=st, iters=info.iters, res_norm=info.res_norm, true_res=tr.value)
 
 
 def hypergrad(p: Problem, th, a, y, xt, q, with_r=True):
-    z = np.empty((p.K, p.K))
+    z = np.empty(p.tshape)
     zn = ct.c_double()
-    a_ptr = _d(_f64(a, (p.K, p.K))) if a is not None else None
-    lib().oracle_hypergrad(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), a_ptr, _d(_f64(y, p.shape)),
+    a_ptr = _d(_f64(a, p.tshape)) if a is not None else None
+    lib().oracle_hypergrad(ct.byref(p.c()), _d(_f64(th, p.tshape)), a_ptr, _d(_f64(y, p.shape)),
                            _d(_f64(xt, p.shape)), _d(_f64(q, p.shape)), int(bool(with_r)), _d(z),
                            ct.byref(zn))
     return z, zn.value
@@ -334,7 +344,7 @@ def maid_step(p: Problem, a, y, state: MaidState, **hp):
     st = om_state(_d(state.theta), _d(state.x), _d(state.q), state.eps, state.delta, state.step,
                   state.L, state.k)
     info = om_step_info()
-    rc = lib().oracle_maid_step(ct.byref(p.c()), _d(_f64(a, (p.K, p.K))), _d(_f64(y, p.shape)),
+    rc = lib().oracle_maid_step(ct.byref(p.c()), _d(_f64(a, p.tshape)), _d(_f64(y, p.shape)),
                                 ct.byref(st), ct.byref(hpc), ct.byref(info))
     state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
     return rc, {f: getattr(info, f) for f, _ in om_step_info._fields_}
@@ -358,7 +368,7 @@ def maid_step_traced(p: Problem, a, y, state: MaidState, replay=None, cap=1 << 2
         rp = np.ascontiguousarray(replay, dtype=np.int32)
         tr.replay = rp.ctypes.data_as(ct.POINTER(ct.c_int32))
         tr.n_replay = len(rp)
-    rc = lib().oracle_maid_step_traced(ct.byref(p.c()), _d(_f64(a, (p.K, p.K))), _d(_f64(y, p.shape)),
+    rc = lib().oracle_maid_step_traced(ct.byref(p.c()), _d(_f64(a, p.tshape)), _d(_f64(y, p.shape)),
                                        ct.byref(st), ct.byref(hpc), ct.byref(info), ct.byref(tr))
     state.eps, state.delta, state.step, state.L, state.k = st.eps, st.delta, st.step, st.L, st.k
     return (rc, {f: getattr(info, f) for f, _ in om_step_info._fields_},
@@ -401,7 +411,7 @@ def _idx(idx):
 def h_grad_at(p: Problem, th, y, x, idx):
     idx = _idx(idx)
     out = np.empty(len(idx))
-    lib().oracle_h_grad_at(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(y, p.shape)),
+    lib().oracle_h_grad_at(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(y, p.shape)),
                            _d(_f64(x, p.shape)), idx.ctypes.data_as(ct.POINTER(ct.c_int64)),
                            len(idx), _d(out))
     return out
@@ -410,7 +420,7 @@ def h_grad_at(p: Problem, th, y, x, idx):
 def h_hvp_at(p: Problem, th, x, d, idx):
     idx = _idx(idx)
     out = np.empty(len(idx))
-    lib().oracle_h_hvp_at(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(x, p.shape)),
+    lib().oracle_h_hvp_at(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(x, p.shape)),
                           _d(_f64(d, p.shape)), idx.ctypes.data_as(ct.POINTER(ct.c_int64)),
                           len(idx), _d(out))
     return out
@@ -419,7 +429,7 @@ def h_hvp_at(p: Problem, th, x, d, idx):
 def conv_at(p: Problem, th, x, idx):
     idx = _idx(idx)
     out = np.empty(len(idx))
-    lib().oracle_conv_at(ct.byref(p.c()), _d(_f64(th, (p.K, p.K))), _d(_f64(x, p.shape)),
+    lib().oracle_conv_at(ct.byref(p.c()), _d(_f64(th, p.tshape)), _d(_f64(x, p.shape)),
                          idx.ctypes.data_as(ct.POINTER(ct.c_int64)), len(idx), _d(out))
     return out
 

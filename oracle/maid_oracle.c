@@ -43,6 +43,14 @@ static inline int64_t npix(const om_problem* p) { return (int64_t)p->C * p->H * 
 
 static inline int wrap(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
 
+/* kernel channels and the taps that blur image channel c: theta holds kc
+   planes of KxK taps, one shared plane (kc = 1) or one per channel (kc = C) */
+static inline int nkc(const om_problem* p) { return p->kc > 1 ? p->kc : 1; }
+static inline int bad_kc(const om_problem* p) { return p->kc > 1 && p->kc != p->C; }
+static inline const double* taps(const om_problem* p, const double* th, int c) {
+    return p->kc > 1 ? th + (int64_t)c * p->K * p->K : th;
+}
+
 /* x_c(i,j) with zero extension outside the image (or periodic wrap). */
 static inline double at(const om_problem* p, const double* x, int c, int i, int j) {
     if (p->periodic) { i = wrap(i, p->H); j = wrap(j, p->W); }
@@ -67,6 +75,7 @@ static inline double dv_at(const om_problem* p, const double* x, int c, int i, i
  * ---------------------------------------------------------------------- */
 static double conv_px(const om_problem* p, const double* th, const double* x, int c, int i, int j) {
     const int K = p->K, c0 = (K - 1) / 2;
+    th = taps(p, th, c);
     double s = 0.0;
     for (int u = 0; u < K; ++u)
         for (int v = 0; v < K; ++v)
@@ -76,6 +85,7 @@ static double conv_px(const om_problem* p, const double* th, const double* x, in
 
 static double conv_adj_px(const om_problem* p, const double* th, const double* r, int c, int i, int j) {
     const int K = p->K, c0 = (K - 1) / 2;
+    th = taps(p, th, c);
     double s = 0.0;
     for (int u = 0; u < K; ++u)
         for (int v = 0; v < K; ++v)
@@ -312,22 +322,27 @@ double oracle_sobolev_value(const om_problem* p, const double* th, const double*
     const int KK = p->K * p->K;
     om_problem q; ksz_problem(p, &q);
     double* e = dalloc(KK); double* dh = dalloc(KK); double* dv = dalloc(KK);
-    for (int t = 0; t < KK; ++t) e[t] = th[t] - a[t];
-    oracle_diff(&q, e, dh, dv);
-    double s = p->h1_w0 * dot(e, e, KK) + dot(dh, dh, KK) + dot(dv, dv, KK);
+    double s = 0.0;
+    for (int k = 0; k < nkc(p); ++k) {   /* one KxK grid per kernel channel */
+        for (int t = 0; t < KK; ++t) e[t] = th[k * KK + t] - a[k * KK + t];
+        oracle_diff(&q, e, dh, dv);
+        s += p->h1_w0 * dot(e, e, KK) + dot(dh, dh, KK) + dot(dv, dv, KK);
+    }
     free(e); free(dh); free(dv);
     return p->beta * s;
 }
 
 void oracle_sobolev_grad(const om_problem* p, const double* th, const double* a, double* out) {
     const int KK = p->K * p->K;
-    if (p->beta == 0.0) { for (int t = 0; t < KK; ++t) out[t] = 0.0; return; }
+    if (p->beta == 0.0) { for (int t = 0; t < nkc(p) * KK; ++t) out[t] = 0.0; return; }
     om_problem q; ksz_problem(p, &q);
     double* e = dalloc(KK); double* dh = dalloc(KK); double* dv = dalloc(KK); double* lap = dalloc(KK);
-    for (int t = 0; t < KK; ++t) e[t] = th[t] - a[t];
-    oracle_diff(&q, e, dh, dv);
-    oracle_diff_adj(&q, dh, dv, lap);
-    for (int t = 0; t < KK; ++t) out[t] = 2.0 * p->beta * (p->h1_w0 * e[t] + lap[t]);
+    for (int k = 0; k < nkc(p); ++k) {
+        for (int t = 0; t < KK; ++t) e[t] = th[k * KK + t] - a[k * KK + t];
+        oracle_diff(&q, e, dh, dv);
+        oracle_diff_adj(&q, dh, dv, lap);
+        for (int t = 0; t < KK; ++t) out[k * KK + t] = 2.0 * p->beta * (p->h1_w0 * e[t] + lap[t]);
+    }
     free(e); free(dh); free(dv); free(lap);
 }
 
@@ -344,6 +359,15 @@ void oracle_sobolev_grad(const om_problem* p, const double* th, const double* a,
  * >= max_iter) receives the number of rejected trials per iteration.
  * ---------------------------------------------------------------------- */
 static double sum_abs(const double* a, int n) { double s = 0; for (int t = 0; t < n; ++t) s += fabs(a[t]); return s; }
+
+/* (max_c ||theta_c||_1)^2 bounds ||theta*.||^2: Young's inequality on each
+   channel's convolution, and the channels do not mix */
+static double l1_bound_sq(const om_problem* p, const double* th) {
+    const int KK = p->K * p->K;
+    double m = 0.0;
+    for (int k = 0; k < nkc(p); ++k) { double s = sum_abs(th + k * KK, KK); if (s > m) m = s; }
+    return m * m;
+}
 
 /* h(v + dl) - h(v) for the trial increment dl = -G/L, evaluated through the
    increment so that no two nearly equal objective values are subtracted:
@@ -384,14 +408,14 @@ static double h_difference(const om_problem* p, const double* th, const double* 
 int oracle_lower_solve(const om_problem* p, const double* th, const double* y, double* x,
                        double tol, int32_t max_iter, double* L_inout, om_solve_info* info,
                        const int32_t* replay_bt, int32_t* trace_bt) {
-    if (!p || !th || !y || !x || !L_inout || max_iter < 0 || tol < 0) return OM_EINVAL;
+    if (!p || !th || !y || !x || !L_inout || max_iter < 0 || tol < 0 || bad_kc(p)) return OM_EINVAL;
     const int64_t N = npix(p);
     double *xp = dalloc(N), *xc = dalloc(N), *v = dalloc(N), *G = dalloc(N);
     double *xn = dalloc(N), *rv = dalloc(N), *dl = dalloc(N), *dtmp = dalloc(N);
     memcpy(xp, x, N * sizeof(double));
     memcpy(xc, x, N * sizeof(double));
     double L = *L_inout;
-    if (!(L > 0)) { double s = sum_abs(th, p->K * p->K); L = s * s; }
+    if (!(L > 0)) L = l1_bound_sq(p, th);
     double t_prev = 1.0, t = 1.0, gn2 = 0.0;
     int n = 0, bt_total = 0, status = OM_OK;
     for (n = 0;; ++n) {
@@ -463,7 +487,7 @@ void oracle_upper_value_grad(const om_problem* p, const double* a, const double*
 int oracle_adjoint_solve(const om_problem* p, const double* th, const double* xt, const double* rhs,
                          double* q_io, double tol, int32_t max_iter, om_solve_info* info,
                          double* true_res_out) {
-    if (!p || !th || !xt || !rhs || !q_io || max_iter < 0 || tol < 0) return OM_EINVAL;
+    if (!p || !th || !xt || !rhs || !q_io || max_iter < 0 || tol < 0 || bad_kc(p)) return OM_EINVAL;
     const int64_t N = npix(p);
     double *q = dalloc(N), *r = dalloc(N), *pd = dalloc(N), *w = dalloc(N);
     memcpy(q, q_io, N * sizeof(double));
@@ -512,32 +536,35 @@ int oracle_adjoint_solve(const om_problem* p, const double* th, const double* xt
 void oracle_hypergrad(const om_problem* p, const double* th, const double* a, const double* y,
                       const double* xt, const double* q, int32_t with_r, double* z, double* znorm_out) {
     const int64_t N = npix(p);
-    const int K = p->K, c0 = (K - 1) / 2, C = p->C, H = p->H, W = p->W;
+    const int K = p->K, c0 = (K - 1) / 2, C = p->C, H = p->H, W = p->W, KC = nkc(p);
     double* rho = dalloc(N);
     double* w = dalloc(N);
     oracle_conv(p, th, xt, rho);
     for (int64_t e = 0; e < N; ++e) rho[e] -= y[e];
     oracle_conv(p, th, q, w);
-#pragma omp parallel for collapse(2) schedule(static)
+    /* a shared kernel collects every channel's products; kernel channel k of
+       a per-channel kernel only those of image channel k */
+#pragma omp parallel for collapse(3) schedule(static)
+    for (int k = 0; k < KC; ++k)
     for (int u = 0; u < K; ++u)
         for (int v = 0; v < K; ++v) {
             double s = 0.0;
-            for (int c = 0; c < C; ++c)
+            for (int c = (KC > 1 ? k : 0); c < (KC > 1 ? k + 1 : C); ++c)
                 for (int i = 0; i < H; ++i)
                     for (int j = 0; j < W; ++j) {
                         int64_t e = ((int64_t)c * H + i) * W + j;
                         s += rho[e] * at(p, q, c, i + c0 - u, j + c0 - v)
                            + w[e] * at(p, xt, c, i + c0 - u, j + c0 - v);
                     }
-            z[u * K + v] = -s;
+            z[(k * K + u) * K + v] = -s;
         }
     if (with_r && p->beta != 0.0 && a) {
-        double* gr = dalloc(K * K);
+        double* gr = dalloc(KC * K * K);
         oracle_sobolev_grad(p, th, a, gr);
-        for (int t = 0; t < K * K; ++t) z[t] += gr[t];
+        for (int t = 0; t < KC * K * K; ++t) z[t] += gr[t];
         free(gr);
     }
-    if (znorm_out) *znorm_out = sqrt(dot(z, z, K * K));
+    if (znorm_out) *znorm_out = sqrt(dot(z, z, KC * K * K));
     free(rho); free(w);
 }
 
@@ -629,15 +656,15 @@ static void traced_upper(tracer* T, int role, double g, double gn, double r) {
 
 int oracle_maid_step_traced(const om_problem* p, const double* a, const double* y, om_state* st,
                             const om_hparams* hp, om_step_info* info, om_trace* trace) {
-    if (!p || !a || !y || !st || !hp || !st->theta || !st->x || !st->q) return OM_EINVAL;
+    if (!p || !a || !y || !st || !hp || !st->theta || !st->x || !st->q || bad_kc(p)) return OM_EINVAL;
     tracer T = {trace, 0, 0};
     if (trace) { trace->n_words = 0; trace->n_values = 0; }
     const int64_t N = npix(p);
-    const int KK = p->K * p->K;
+    const int KK = nkc(p) * p->K * p->K;    /* every tap of theta */
     double *xt = dalloc(N), *xs = dalloc(N), *G = dalloc(N), *q = dalloc(N);
     double *z = dalloc(KK), *th2 = dalloc(KK);
     double Lg = hp->L_g;
-    if (!(Lg > 0)) { double s = sum_abs(a, KK); Lg = s * s; }
+    if (!(Lg > 0)) Lg = l1_bound_sq(p, a);
     om_step_info I; memset(&I, 0, sizeof(I));
     int status = OM_OK;
     int j = hp->max_bt;
@@ -755,7 +782,7 @@ void oracle_h_grad_at(const om_problem* p, const double* th, const double* y, co
                 if (!p->periodic && (ii < 0 || ii >= p->H || jj < 0 || jj >= p->W)) continue;
                 if (p->periodic) { ii = wrap(ii, p->H); jj = wrap(jj, p->W); }
                 double r = conv_px(p, th, x, c, ii, jj) - y[((int64_t)c * p->H + ii) * p->W + jj];
-                s += th[u * K + v] * r;
+                s += taps(p, th, c)[u * K + v] * r;
             }
         out[t] = s + p->alpha * reg_grad_px(p, x, c, i, j);
     }
@@ -774,7 +801,7 @@ void oracle_h_hvp_at(const om_problem* p, const double* th, const double* x, con
                 int ii = i - c0 + u, jj = j - c0 + v;
                 if (!p->periodic && (ii < 0 || ii >= p->H || jj < 0 || jj >= p->W)) continue;
                 if (p->periodic) { ii = wrap(ii, p->H); jj = wrap(jj, p->W); }
-                s += th[u * K + v] * conv_px(p, th, d, c, ii, jj);
+                s += taps(p, th, c)[u * K + v] * conv_px(p, th, d, c, ii, jj);
             }
         out[t] = s + p->alpha * reg_hvp_px(p, x, d, c, i, j);
     }

@@ -16,9 +16,12 @@
  *
  * Conventions (every array is double, contiguous, host memory):
  *   images x, y, q: planar [C][H][W], row-major, index (c,i,j), i = row;
- *   kernels theta, a: [K][K] row-major, K odd, c0 = (K-1)/2;
- *   (theta*x)_c(i,j)   = sum_{u,v} theta(u,v) x_c(i+c0-u, j+c0-v)
- *   (theta.r)_c(i,j)   = sum_{u,v} theta(u,v) r_c(i-c0+u, j-c0+v)   (adjoint)
+ *   kernels theta, a: [kc][K][K] row-major, K odd, c0 = (K-1)/2, with kc = 1
+ *   (one kernel shared by every channel) or kc = C (channel c blurred by its
+ *   own kernel theta_c: the colour variant that Section 4.2's figures imply
+ *   when they plot one channel of the kernel); theta_c means theta_0 when kc = 1;
+ *   (theta*x)_c(i,j)   = sum_{u,v} theta_c(u,v) x_c(i+c0-u, j+c0-v)
+ *   (theta.r)_c(i,j)   = sum_{u,v} theta_c(u,v) r_c(i-c0+u, j-c0+v)   (adjoint)
  *   with x = 0 outside the image (periodic mode wraps; test only).
  *   D_h x(i,j) = x(i,j+1)-x(i,j) for j<W-1 else 0, D_v likewise on rows
  *   (periodic mode wraps instead).
@@ -29,7 +32,8 @@
  *   h(x;theta) = 1/2 ||theta*x - y||^2 + alpha R(x)          (lower level)
  *   g(x)       = 1/2 ||a*x - y||^2                            (upper level)
  *   r(theta)   = beta ( w0 ||theta-a||^2 + ||D_h(theta-a)||^2 + ||D_v(theta-a)||^2 )
- *   with Neumann forward differences on the KxK grid.
+ *   with Neumann forward differences on each KxK grid (no difference across
+ *   kernel channels).
  */
 #ifndef MAID_ORACLE_H
 #define MAID_ORACLE_H
@@ -43,6 +47,7 @@ typedef struct {
     int32_t C, H, W, K;
     int32_t periodic;   /* 0 zero boundary, 1 periodic (tests only) */
     int32_t reg;        /* 0 vectorial TV, 1 channelwise TV, 2 quadratic */
+    int32_t kc;         /* kernel channels: 0 or 1 shared kernel, C per channel */
     double alpha, eps_tv, beta, h1_w0;
 } om_problem;
 
@@ -57,7 +62,7 @@ typedef struct {
 } om_hparams;
 
 typedef struct {
-    double *theta, *x, *q;              /* K*K, N, N (warm starts in/out) */
+    double *theta, *x, *q;              /* kc*K*K, N, N (warm starts in/out) */
     double eps, delta, step, L;
     int32_t k;
 } om_state;

@@ -181,7 +181,8 @@ def directions(n: int, K: int, seed: int = 909) -> np.ndarray:
 @dataclass
 class Instance:
     """One semi-blind deblurring problem.  Arrays are float64, images planar
-    [C][H][W], kernels [K][K]."""
+    [C][H][W], kernels [K][K] (one kernel for every channel) or [C][K][K]
+    (one per channel, from make_channelwise)."""
     name: str
     x_true: np.ndarray
     y: np.ndarray
@@ -204,7 +205,12 @@ class Instance:
     def W(self): return self.y.shape[2]
 
     @property
-    def K(self): return self.a.shape[0]
+    def K(self): return self.a.shape[-1]
+
+    @property
+    def kc(self):
+        """kernel channels: 1 for one shared [K][K] kernel, C for [C][K][K]"""
+        return 1 if self.a.ndim == 2 else self.a.shape[0]
 
 
 CONFIGS = {
@@ -277,6 +283,44 @@ def make(name: str, H: int | None = None, W: int | None = None, C: int | None = 
                      p["sigma_n"], p["alpha"], p["true"], p["init"], **kw)
     inst.meta = dict(dtype=p["dtype"], maid_steps=p.get("maid_steps"), shapes=shapes)
     return inst
+
+
+def _scaled(spec, f):
+    """The kernel recipe `spec` with its width scaled by f (Gaussian sigmas,
+    motion length)."""
+    kind = spec[0]
+    if kind in ("gauss", "diagmix"):
+        return (kind, spec[1] * f)
+    if kind == "aniso":
+        return (kind, spec[1] * f, spec[2] * f, spec[3])
+    if kind == "motion":
+        return (kind, spec[1] * f, spec[2], spec[3])
+    return spec
+
+
+def make_channelwise(name: str, H: int | None = None, W: int | None = None, C: int | None = None,
+                     K: int | None = None, seed: int | None = None, spread: float = 0.2) -> Instance:
+    """A workload of `make` with one blur kernel per colour channel, the way
+    lateral chromatic aberration blurs the channels of a lens image
+    differently: channel c's true kernel is the recipe's with its width
+    scaled by 1 + spread * (c - (C-1)/2) / ((C-1)/2), and each channel's
+    data is blurred by its own kernel.  The assumed kernel a is the recipe's
+    assumed kernel in every channel (the semi-blind start knows nothing of
+    the channels' differences).  k_true and a are [C][K][K]."""
+    inst = make(name, H=H, W=W, C=C, K=K, seed=seed)
+    p = CONFIGS[name]
+    C, K = inst.C, inst.K
+    half = max((C - 1) / 2.0, 1.0)
+    ks = np.stack([_kernel(_scaled(p["true"], 1.0 + spread * (c - (C - 1) / 2.0) / half), K)
+                   for c in range(C)])
+    rng = np.random.Generator(np.random.PCG64(inst.seed + 7919))
+    y = np.stack([fftconvolve(inst.x_true[c], ks[c], mode="same") for c in range(C)])
+    y = y + inst.sigma_n * rng.standard_normal(y.shape)
+    a = np.stack([inst.a] * C)
+    out = Instance(name=name + "_channelwise", x_true=inst.x_true, y=y, k_true=ks, a=a, alpha=inst.alpha,
+                   eps_tv=inst.eps_tv, beta=inst.beta, sigma_n=inst.sigma_n, seed=inst.seed)
+    out.meta = dict(inst.meta, spread=spread)
+    return out
 
 
 CFG4_SIZES = (128, 256, 384, 512, 768, 1024)

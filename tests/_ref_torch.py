@@ -14,9 +14,17 @@ def t(a):
 
 
 def conv(th, x, periodic=False):
-    """(th*x)(i,j) = sum th(u,v) x(i+c0-u, j+c0-v): correlation with the flipped kernel."""
+    """(th*x)(i,j) = sum th(u,v) x(i+c0-u, j+c0-v): correlation with the flipped kernel.
+    th (K, K) blurs every channel; th (C, K, K) blurs channel c with th[c]
+    (a grouped convolution)."""
     K = th.shape[-1]
     c0 = (K - 1) // 2
+    if th.dim() == 3:
+        w = th.flip(-2, -1)[:, None]
+        xx = x[None]
+        if periodic:
+            return F.conv2d(F.pad(xx, (c0, c0, c0, c0), mode="circular"), w, groups=th.shape[0])[0]
+        return F.conv2d(xx, w, padding=c0, groups=th.shape[0])[0]
     w = th.flip(0, 1)[None, None]
     xx = x[:, None]
     if periodic:
@@ -57,7 +65,8 @@ def g(a, y, x):
 
 
 def sobolev(th, a, beta, w0=1.0):
-    e = (th - a)[None]
+    e = th - a
+    e = e if e.dim() == 3 else e[None]     # one KxK grid per kernel channel
     dh, dv = diffs(e)
     return beta * (w0 * (e * e).sum() + (dh * dh).sum() + (dv * dv).sum())
 
@@ -81,11 +90,11 @@ def hess_h(th, y, x, alpha, eps, mode=0, periodic=False):
 
 
 def mixed_jac(th, y, x, alpha, eps, mode=0):
-    """J = d(grad_x h)/d theta as an N x K^2 matrix (autograd)."""
-    K = th.shape[-1]
+    """J = d(grad_x h)/d theta as an N x (number of taps) matrix (autograd)."""
+    shape = th.shape
 
     def f(thf):
-        return grad_h_graph(thf.reshape(K, K), y, x, alpha, eps, mode).reshape(-1)
+        return grad_h_graph(thf.reshape(shape), y, x, alpha, eps, mode).reshape(-1)
 
     return torch.autograd.functional.jacobian(f, th.reshape(-1).clone())
 
