@@ -490,6 +490,50 @@ def autograd_work(inst, dt, tol=1e-3, cg_tol=1e-3):
     return out
 
 
+def channelwise_work(name="cfg3", dt=None, tol=1e-3, cg_tol=1e-3, reps=3):
+    """One kernel per colour channel against one shared kernel on the same
+    data (the per-channel workload of synth.make_channelwise at the named
+    size): the InexactGradient calls (lower-level solve, CG adjoint,
+    hypergradient) timed for each layout, best of `reps`, with their
+    iteration counts (the two problems differ, so the counts may differ)."""
+    import torch
+    from paper_2502_09758_amd import synth
+    from paper_2502_09758_amd.maid import Maid
+
+    dt = dt or torch.float32
+    inst = synth.make_channelwise(name)
+    y = torch.tensor(inst.y, dtype=dt, device="cuda")
+    N = inst.C * inst.H * inst.W
+    out = dict(workload=f"{inst.C}x{inst.H}x{inst.W}, K={inst.K}, per-channel blur (spread "
+                        f"{inst.meta['spread']})", tol=tol, cg_tol=cg_tol)
+    for kc, th_np in ((inst.C, inst.a), (1, inst.a[0])):
+        m = Maid(inst.C, inst.H, inst.W, inst.K, dt, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta, kc=kc)
+        th = torch.tensor(th_np, dtype=torch.float64, device="cuda")
+        m.autotune(th, y)
+        best = None
+        for _ in range(reps):
+            x = y.clone()
+            q = torch.zeros_like(y)
+            g = torch.empty_like(y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            li = m.lower_solve(th, y, x, tol, max_iter=2000)
+            m.upper_value_grad(th, y, x, g)
+            ci = m.adjoint_solve(th, x, g, q, cg_tol * float(g.double().norm()), max_iter=2000)
+            m.hypergrad(th, th, y, x, q)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None or t < best else best
+        key = "per_channel" if kc > 1 else "shared"
+        work = (li.iters + ci.iters) * N
+        out[key] = dict(ms=round(best * 1e3, 3), lower_iters=li.iters, cg_iters=ci.iters,
+                        pixel_iterations_per_s=round(work / best, 1), tiles=m.config())
+        m.close()
+    out["per_channel_over_shared_rate"] = round(out["per_channel"]["pixel_iterations_per_s"] /
+                                                out["shared"]["pixel_iterations_per_s"], 3)
+    return out
+
+
 def roofline_sweep(iters: int = 12):
     """Per-kernel throughput over working sets of at least 1 GB: 4096x4096x1
     and 2048x2048x3 (FP32 storage) with K in {5, 7, 9, 13, 15, 21, 31}
@@ -632,6 +676,8 @@ def main():
     ap.add_argument("--d1-batch", type=int, default=64,
                     help="signals of the 1D problem's batched measurement (0: skip it)")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-vs-plain comparison")
+    ap.add_argument("--no-channelwise", action="store_true",
+                    help="skip the per-channel-kernel comparison")
     ap.add_argument("--rows", type=int, default=0,
                     help="pin the tile height (rows per thread) instead of running the autotuner")
     args = ap.parse_args()
@@ -678,6 +724,9 @@ def main():
     if not args.no_autograd:
         print("[bench] autograd vs plain (512x512x3, K=15)", file=sys.stderr, flush=True)
         out["autograd_vs_plain"] = autograd_work(synth.make("cfg3"), torch.float32)
+    if not args.no_channelwise:
+        print("[bench] per-channel kernels vs shared kernel (512x512x3, K=15)", file=sys.stderr, flush=True)
+        out["channelwise"] = leg(channelwise_work, "cfg3")
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(run["inst"])

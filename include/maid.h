@@ -18,9 +18,13 @@
  *   - Images (x, y, q, gradients) are DEVICE arrays, planar [C][H][W],
  *     row-major, contiguous, element type float (MAID_F32) or double
  *     (MAID_F64) as fixed at maid_create.  Kernels theta, a are DEVICE arrays
- *     of K*K doubles, row-major, K odd, centre (c0,c0), c0 = (K-1)/2.
- *   - (theta*x)_c(i,j) = sum_{u,v} theta(u,v) x_c(i+c0-u, j+c0-v): true
- *     convolution, zero outside the image, same output size.
+ *     of kc planes of K*K doubles ([kc][K][K], row-major), K odd, centre
+ *     (c0,c0), c0 = (K-1)/2, kc = 1 (one kernel blurs every channel) or
+ *     kc = C (channel c blurred by its own plane theta_c; see maid_desc).
+ *     Every "K*K doubles" below is kc*K*K doubles.
+ *   - (theta*x)_c(i,j) = sum_{u,v} theta_c(u,v) x_c(i+c0-u, j+c0-v), theta_c
+ *     the plane of channel c (plane 0 when kc = 1): true convolution, zero
+ *     outside the image, same output size.
  *   - Arrays are caller-owned and must not alias each other unless stated.
  *     The library never frees caller memory; a context owns only its
  *     workspace.
@@ -69,9 +73,16 @@ enum {
    channels), MAID_REG_TV_CHANNELWISE (one per channel and pixel) or
    MAID_REG_QUADRATIC (R = 1/2 ||Dx||^2, the Tikhonov case).  alpha >= 0,
    eps_tv > 0 (TV only), beta >= 0, h1_w0 = weight of the L2 part of the H1
-   norm (1 full norm, 0 seminorm). */
+   norm (1 full norm, 0 seminorm).
+   kc: kernel planes, 0 or 1 for one kernel shared by the channels, C for one
+   kernel per colour channel (the colour variant behind Section 4.2's plots of
+   a single kernel channel); any other value is rejected with MAID_EINVAL.
+   With kc = C the hypergradient has one K*K plane per channel (a channel's
+   plane collects only that channel's products), r(theta) sums the planes'
+   Sobolev terms (no difference across planes), and the Lipschitz bounds
+   ||theta||_1^2 and ||a||_1^2 take the largest plane's l1 norm. */
 typedef struct {
-    int32_t H, W, C, K, dtype, boundary, reg;
+    int32_t H, W, C, K, dtype, boundary, reg, kc;
     double alpha, eps_tv, beta, h1_w0;
 } maid_desc;
 
@@ -294,7 +305,8 @@ int maid_adjoint_solve(maid_ctx* ctx, const void* theta, const void* x_tilde,
 /* Algorithm 1, last line, and Eq. (3.2): the hypergradient
    z(u,v) = -sum_{c,i,j} [rho_c(i,j) q_c(i+c0-u,j+c0-v) + (theta*q)_c(i,j) x_c(i+c0-u,j+c0-v)]
             + with_r * grad r(theta)(u,v),
-   rho = theta*x_tilde - y.  z: DEVICE, K*K doubles.  a may be NULL when
+   rho = theta*x_tilde - y; with kc = C, plane c of z sums over channel c
+   only.  z: DEVICE, K*K doubles.  a may be NULL when
    with_r == 0 or beta == 0.  znorm_out (HOST, nullable) = ||z||_2. */
 int maid_hypergrad(maid_ctx* ctx, const void* theta, const void* a, const void* y,
                    const void* x_tilde, const void* q, int32_t with_r, double* z,

@@ -39,7 +39,8 @@ PROF_KINDS = 12
 
 class maid_desc(ct.Structure):
     _fields_ = [("H", ct.c_int32), ("W", ct.c_int32), ("C", ct.c_int32), ("K", ct.c_int32),
-                ("dtype", ct.c_int32), ("boundary", ct.c_int32), ("reg", ct.c_int32), ("alpha", ct.c_double),
+                ("dtype", ct.c_int32), ("boundary", ct.c_int32), ("reg", ct.c_int32), ("kc", ct.c_int32),
+                ("alpha", ct.c_double),
                 ("eps_tv", ct.c_double), ("beta", ct.c_double), ("h1_w0", ct.c_double)]
 
 

@@ -144,7 +144,7 @@ int ift_step_one(maid_ctx* c, const double* a, const T* y, maid_state* st, int n
     double zn = 0.0;
     ADP_TRY(hypergrad_batch<T>(c, one<char>(1), one<const double*>(theta), one<const double*>(a), one<const T*>(y),
                                one<const T*>(x), one<const T*>(q), 1, one<double*>(z), &zn, s));
-    ADP_HIP(launch_theta_step(theta, z, st->step, theta, M.d.K * M.d.K, s));
+    ADP_HIP(launch_theta_step(theta, z, st->step, theta, kplanes(M.d) * M.d.K * M.d.K, s));
     ADP_HIP(hipStreamSynchronize(s));
     st->k += 1;
     I.accepted = 1;
@@ -164,7 +164,7 @@ int lista_step_one(maid_ctx* c, const double* a, const T* y, maid_state* st, int
         return fail(c, MAID_EINVAL,
                     "lista_step: the unrolled iterates need the two-pass lower-level form (maid_set_one_pass(ctx, 0))");
     const size_t N = (size_t)M.N;
-    const int KK = M.d.K * M.d.K;
+    const int KK = kplanes(M.d) * M.d.K * M.d.K;
     // workspace: x_0 .. x_n (dense, x_k at xs + k N: the passes write x_{k+1}
     // at hist + k N), w, H w, the accumulated gradient, one z, partials
     const size_t img = al256(N * sizeof(T));

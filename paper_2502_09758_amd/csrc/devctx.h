@@ -137,6 +137,7 @@ template <typename T> using gp = T MAID_GLOBAL*;
 template <typename T> struct Inst {
     Params pr;                   // C, H, W, reg, alpha, eps_tv
     int32_t K;                   // kernel size
+    int32_t kc;                  // kernel planes: 1 (one kernel for every channel) or C (one per channel)
     int32_t nb, base;            // stencil blocks (tiles x channels) and first block within its group launch
     int32_t nbe, base_e;         // elementwise blocks and first block within the elementwise launch
     int32_t nbf, basef;          // blocks of the one-pass FISTA launch (0: not on that path)
@@ -150,11 +151,11 @@ template <typename T> struct Inst {
     gp<T> rb;                       // its residual theta * xb - y (FP64 sums, rounded once)
     gp<T> G;                        // gradient at the extrapolated point
     gp<const T> y;
-    gp<T> th;                       // theta in the compute type, correlation form, column-major
-    gp<T> thf;                      // the flipped kernel (convolution form), column-major
+    gp<T> th;                       // theta in the compute type, correlation form, column-major (kc planes)
+    gp<T> thf;                      // the flipped kernel (convolution form), column-major (kc planes)
     // matrix-core operand layouts of th and thf (FP32 storage, K >= 13;
     // nullable: the correlations then run on the vector ALUs) and the
-    // power-of-two exponent they were scaled by (one int, written with them)
+    // power-of-two exponent they were scaled by (one int per plane, written with them)
     gp<uint4> mf_th;
     gp<uint4> mf_thf;
     gp<int> mf_sh;
@@ -180,7 +181,7 @@ template <typename T> struct Inst {
     gp<const T> cv_ker;
     gp<const uint4> cv_mf;          // nullable: matrix-core layout of cv_ker
     gp<const int> cv_mfsh;          // its scale exponent
-    gp<const double> cv_ker64;      // nullable (FP32 storage): the kernel as KxK doubles, row-major;
+    gp<const double> cv_ker64;      // nullable (FP32 storage): the kernel as kc KxK planes of doubles, row-major;
                                     // the job then runs with FP64 taps and FP64 sums
     gp<double> cv_out64;            // nullable (with cv_ker64): cv_out kept in FP64 here instead
     int32_t cv_flip64;              // cv_ker64 is applied flipped (true convolution)
@@ -192,7 +193,7 @@ template <typename T> struct Inst {
     gp<T> cv_cp[3];                 // nullable: copies of cv_in
     gp<double> cv_part;             // nullable
     gp<const double> cv_prev_part;  // nullable: partials of an earlier pass, summed by block 0 into red[cv_prev_slot]
-    // kernel preparation: theta64 (K*K doubles) -> th / thf
+    // kernel preparation: theta64 (kc*K*K doubles) -> th / thf
     gp<const double> theta64;       // nullable: nothing to prepare
     gp<double> red;                 // per-instance reduction results (8 doubles)
     // Sobolev term r(theta) of Eq. (2.5) for the finishing pass (sob_th nullable)

@@ -144,6 +144,7 @@ template <typename T> void fill_base(maid_ctx* c, int i, Inst<T>& I) {
     const Member& M = c->m[i];
     I.pr = Params{M.d.C, M.d.H, M.d.W, M.d.reg, M.d.alpha, M.d.eps_tv};
     I.K = M.d.K;
+    I.kc = kplanes(M.d);
     I.nb = M.nb;
     I.base = M.base;
     I.nbe = M.nbe;
@@ -337,6 +338,7 @@ const char* desc_problem(const maid_desc* d) {
     if (d->boundary == MAID_BOUNDARY_PERIODIC) return "boundary: periodic convolution is not implemented (zero boundary only)";
     if (d->boundary != MAID_BOUNDARY_ZERO) return "boundary must be MAID_BOUNDARY_ZERO";
     if (d->reg < 0 || d->reg > 2) return "reg must be 0, 1 or 2";
+    if (d->kc < 0 || (d->kc > 1 && d->kc != d->C)) return "kc must be 0 or 1 (one kernel) or C (one kernel per channel)";
     if (!finite(d->alpha) || d->alpha < 0) return "alpha must be finite and >= 0";
     if (d->reg != MAID_REG_QUADRATIC && !(d->eps_tv > 0 && finite(d->eps_tv))) return "eps_tv must be > 0";
     if (!finite(d->beta) || d->beta < 0) return "beta must be finite and >= 0";
@@ -358,8 +360,8 @@ int noalloc_upper_setup(const maid_desc* d, const double* a, const T* y, const T
     // tables, kernel copies, reduction slots, two partial arrays, the
     // residual image and (without grad_out) the gradient
     const size_t o_kc = al(2 * sizeof(Inst<T>));
-    const size_t o_kf = o_kc + al((size_t)d->K * d->K * sizeof(T));
-    const size_t o_red = o_kf + al((size_t)d->K * d->K * sizeof(T));
+    const size_t o_kf = o_kc + al((size_t)kplanes(*d) * d->K * d->K * sizeof(T));
+    const size_t o_red = o_kf + al((size_t)kplanes(*d) * d->K * d->K * sizeof(T));
     const size_t o_pc = o_red + al(kRedSlots * sizeof(double));
     const size_t o_pa = o_pc + al((size_t)nb * sizeof(double));
     const size_t o_rho = o_pa + al((size_t)nb * sizeof(double));
@@ -376,6 +378,7 @@ int noalloc_upper_setup(const maid_desc* d, const double* a, const T* y, const T
     for (auto& I : t) {
         I.pr = Params{d->C, d->H, d->W, d->reg, d->alpha, d->eps_tv};
         I.K = d->K;
+        I.kc = kplanes(*d);
         I.nb = nb;
         I.base = 0;
         I.N = (int64_t)N;
@@ -664,7 +667,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     c->m.resize(n);
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     size_t total = 0, maps = 0;
-    const size_t kern = 1024 * 8;
+    // one buffer of taps: kc planes of up to 32 x 32 doubles
+    auto kern_bytes = [&](const maid_desc& d) { return al((size_t)kplanes(d) * 1024 * 8); };
     for (int i = 0; i < n; ++i) {
         Member& M = c->m[i];
         std::memset(&M, 0, sizeof(M));
@@ -681,9 +685,10 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         // FP64 s buffers of the one-pass CG, for instances that can take it
         const size_t s64 = step_ok(M.d.C, M.d.K, 1) ? 2 * al((size_t)M.N * sizeof(double)) : 0;
         total += s64;
-        total += 21 * img + 6 * kern + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
+        total += 21 * img + 6 * kern_bytes(M.d) + 9 * part + al((size_t)kHgMaxBlocks * 1024 * sizeof(double)) +
                  al(kTraceCap * sizeof(int));
-        if (mf_member(c->dtype, M.d.K)) total += 2 * al(mf_frag_bytes(M.d.K)) + al(sizeof(int));
+        if (mf_member(c->dtype, M.d.K))
+            total += 2 * al((size_t)kplanes(M.d) * mf_frag_bytes(M.d.K)) + al(kplanes(M.d) * sizeof(int));
         if (c->dtype == MAID_F32) total += 2 * al((size_t)M.N * sizeof(double));
         maps += round8(stencil_blocks(M.shape, 1)) + round8(M.nbe) + round8(step_blocks(M.d.H, M.d.W, M.d.K, 1));
     }
@@ -788,6 +793,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
             M.hg64[k] = c->dtype == MAID_F32 ? (double*)take(al((size_t)M.N * sizeof(double))) : (double*)(k ? M.tmp1 : M.tmp0);
         M.xtrial = take(img);
         M.gradg = take(img);
+        const size_t kern = kern_bytes(M.d);
         M.th_c = take(kern);
         M.thf_c = take(kern);
         M.a_c = take(kern);
@@ -804,8 +810,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         M.hg_part = (double*)take(al((size_t)kHgMaxBlocks * 1024 * sizeof(double)));
         M.trace = (int*)take(al(kTraceCap * sizeof(int)));
         if (mf_member(c->dtype, M.d.K)) {
-            for (int k = 0; k < 2; ++k) M.mf[k] = take(al(mf_frag_bytes(M.d.K)));
-            M.mf_sh = (int*)take(al(sizeof(int)));
+            for (int k = 0; k < 2; ++k) M.mf[k] = take(al((size_t)kplanes(M.d) * mf_frag_bytes(M.d.K)));
+            M.mf_sh = (int*)take(al(kplanes(M.d) * sizeof(int)));
         }
     }
     int rc = relayout(c);
@@ -1311,7 +1317,10 @@ int hypergrad_impl(maid_ctx* c, const std::vector<char>& act, const std::vector<
         I.hg_w = M.hg64[1];
         I.hg_q = q[i];
         I.hg_part = M.hg_part;
-        I.hg_nblk = std::min(kHgMaxBlocks, hg_items(M.shape));
+        // per-channel kernels: kc equal block ranges, one per channel
+        const int KP = kplanes(M.d);
+        I.hg_nblk = KP == 1 ? std::min(kHgMaxBlocks, hg_items(M.shape))
+                            : KP * std::min(kHgMaxBlocks / KP, hg_items(Shape{1, M.d.H, M.d.W, M.d.K, M.d.reg}));
         I.hg_base = hg_blocks[cls];
         hg_blocks[cls] += I.hg_nblk;
         I.hg_with_r = with_r && M.d.beta != 0.0;
@@ -1365,7 +1374,7 @@ int sobolev_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
             r_out[i] = 0.0;
             continue;
         }
-        LAUNCH(MAID_PROF_OTHER, launch_sobolev(M.d.beta, M.d.h1_w0, theta[i], a[i], M.d.K,
+        LAUNCH(MAID_PROF_OTHER, launch_sobolev(M.d.beta, M.d.h1_w0, theta[i], a[i], M.d.K, kplanes(M.d),
                                                c->red + (size_t)i * kRedSlots + kRedSob, s));
         any_work = true;
     }
@@ -1664,7 +1673,7 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
         while (any(tr)) {
             for (int i = 0; i < n; ++i) {
                 if (!tr[i]) continue;
-                const int KK = c->m[i].d.K * c->m[i].d.K;
+                const int KK = kplanes(c->m[i].d) * c->m[i].d.K * c->m[i].d.K;
                 LAUNCH(MAID_PROF_OTHER, launch_theta_step(theta[i], z[i], st[i].step, th2[i], KK, s));
                 L[i] = st[i].L;
             }
@@ -1715,7 +1724,7 @@ int step_batch(maid_ctx* c, const std::vector<const double*>& a, const std::vect
                     tr_v(c, psi);
                 }
                 if (psi <= 0.0) {
-                    const int KK = c->m[i].d.K * c->m[i].d.K;
+                    const int KK = kplanes(c->m[i].d) * c->m[i].d.K * c->m[i].d.K;
                     HIP_TRY(hipMemcpyAsync(st[i].theta, th2[i], KK * sizeof(double), hipMemcpyDeviceToDevice, s));
                     HIP_TRY(hipMemcpyAsync(x[i], xs[i], (size_t)c->m[i].N * sizeof(T), hipMemcpyDeviceToDevice, s));
                     st[i].eps *= hp->nu_hi;

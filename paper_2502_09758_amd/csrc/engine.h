@@ -28,6 +28,10 @@ constexpr int kTraceCap = 1 << 16;
 constexpr int kHgMaxBlocks = 512;
 constexpr int kEwMaxBlocks = 2048;
 
+// kernel planes of a problem: 1 for a kernel shared by the channels, C for
+// one kernel per channel (theta, a and z hold kplanes * K * K doubles)
+inline int kplanes(const maid_desc& d) { return d.kc > 1 ? d.kc : 1; }
+
 // Each pass family reads its own device copy of the instance table, so a
 // captured graph (which embeds the table address) always sees the entries
 // written for its family, and a later call can rewrite another family's

@@ -375,18 +375,26 @@ __device__ __forceinline__ void correlate(const T* s, int pitch, const T* __rest
 // nullable), else on the vector ALUs.  Every thread of the block calls it.
 // MF = false leaves the matrix-core path out of the kernel (the team loops,
 // which serve instances too small to need it).
+// kp: the kernel plane (0 for a kernel shared by the channels, the image
+// channel for per-channel kernels): taps kT + kp K^2, operand layouts
+// mf + kp (the size of one kernel's), exponent mfsh[kp].
 template <typename T, int K, int R, bool MF = true>
 __device__ __forceinline__ void correlate_sel(const T* s, int pitch, const T* __restrict__ kT, const uint4* mf,
-                                              const int* mfsh, int li0, int tx, T (&acc)[R]) {
+                                              const int* mfsh, int kp, int li0, int tx, T (&acc)[R]) {
     if constexpr (MF && mf_ok<T, K, R>()) {
         if (mf) {
             __shared__ __align__(16) unsigned char mf_lds[mf_lds_bytes<K, R>()];
-            correlate_mfma<K, R>(s, pitch, mf, *(const int MAID_CONST*)mfsh, mf_lds, li0, tx, acc);
+            correlate_mfma<K, R>(s, pitch, mf + kp * (mf_frag_bytes(K) / 16), *(const int MAID_CONST*)(mfsh + kp),
+                                 mf_lds, li0, tx, acc);
             return;
         }
     }
-    correlate<T, K, R>(s, pitch, kT, li0, tx, acc);
+    correlate<T, K, R>(s, pitch, kT + kp * K * K, li0, tx, acc);
 }
+
+// The kernel plane of image channel ch: per-channel kernels (kc > 1) hold
+// one KxK plane per channel, a shared kernel one plane.
+template <typename T> __device__ __forceinline__ int kplane(const Inst<T>& I, int ch) { return I.kc > 1 ? ch : 0; }
 
 // acc[o] += sum_{u,v} ker(u,v) s[(li0+o+u) pitch + tx+v] in FP64, the taps
 // read as doubles from the row-major KxK array th: ker(u,v) = th[u K + v],
@@ -612,7 +620,7 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
             double acc[R];
 #pragma unroll
             for (int o = 0; o < R; ++o) acc[o] = 0.0;
-            correlate64<T, K, R>(s, CP, I.cv_ker64, I.cv_flip64 != 0, li0, tx, acc);
+            correlate64<T, K, R>(s, CP, I.cv_ker64 + kplane(I, ch) * K * K, I.cv_flip64 != 0, li0, tx, acc);
             double sq = 0.0;
 #pragma unroll
             for (int o = 0; o < R; ++o) {
@@ -644,7 +652,7 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    correlate_sel<T, K, R>(s, CP, I.cv_ker, I.cv_mf, I.cv_mfsh, li0, tx, acc);
+    correlate_sel<T, K, R>(s, CP, I.cv_ker, I.cv_mf, I.cv_mfsh, kplane(I, ch), li0, tx, acc);
     double sq = 0.0;
 #pragma unroll
     for (int o = 0; o < R; ++o) {
@@ -796,7 +804,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    if (!SEQ) correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+    if (!SEQ) correlate<T, K, R>(s_c, CP, I.th + kplane(I, ch) * K * K, li0, tx, acc);
     __syncthreads();
     // SEQ: the TV gradient waits in LDS past the tile region while the
     // convolution tile reuses it (registers stay with the convolution)
@@ -813,7 +821,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
         __syncthreads();
         stage_residual();
         __syncthreads();
-        correlate_sel<T, K, R, !CO>(s_c, CP, I.th, I.mf_th, I.mf_sh, li0, tx, acc);
+        correlate_sel<T, K, R, !CO>(s_c, CP, I.th, I.mf_th, I.mf_sh, kplane(I, ch), li0, tx, acc);
     }
     T gv[R];
 #pragma unroll
@@ -1038,7 +1046,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
+    correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, kplane(I, ch), li0, tx, acc);
     double ddat = 0.0;
     // small kernels: every row's loads in flight before any is used (clamped
     // addresses, no branch); large kernels keep their registers
@@ -1107,7 +1115,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
             double a64[R];
 #pragma unroll
             for (int o = 0; o < R; ++o) a64[o] = 0.0;
-            correlate64<T, K, R>(s_c, CP, I.theta64, true, li0, tx, a64);
+            correlate64<T, K, R>(s_c, CP, I.theta64 + kplane(I, ch) * K * K, true, li0, tx, a64);
             T* __restrict__ XBw = I.xb + ch * HW;
             T* __restrict__ RBw = I.rb + ch * HW;
             const T* __restrict__ Yc = Y + ch * HW;
@@ -1125,7 +1133,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
         } else {
 #pragma unroll
             for (int o = 0; o < R; ++o) acc[o] = T(0);
-            correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
+            correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, kplane(I, ch), li0, tx, acc);
 #pragma unroll
             for (int o = 0; o < R; ++o) {
                 const int gi = ti0 + li0 + o;
@@ -1248,7 +1256,7 @@ __device__ __forceinline__ void cg_dir_body(const Inst<T>& I, int lb, CgState& s
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    correlate_sel<T, K, R, !CO>(s, CP, I.thf, I.mf_thf, I.mf_sh, li0, tx, acc);
+    correlate_sel<T, K, R, !CO>(s, CP, I.thf, I.mf_thf, I.mf_sh, kplane(I, ch), li0, tx, acc);
     T* __restrict__ Kp = I.Kp + ch * HW;
     T* __restrict__ qc = I.q + ch * HW;
 #pragma unroll
@@ -1401,7 +1409,7 @@ __device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgSt
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
-    if (!SEQ) correlate<T, K, R>(s_c, CP, I.th, li0, tx, acc);
+    if (!SEQ) correlate<T, K, R>(s_c, CP, I.th + kplane(I, ch) * K * K, li0, tx, acc);
     const T* Xv = s_x + (SEQ ? 0 : ch) * VR * VP;
     const T* Pv = s_p + (SEQ ? 0 : ch) * VR * VP;
     const T* Wt = s_w;
@@ -1439,7 +1447,7 @@ __device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgSt
         __syncthreads();
         stage_kp();
         __syncthreads();
-        correlate_sel<T, K, R, !CO>(s_c, CP, I.th, I.mf_th, I.mf_sh, li0, tx, acc);
+        correlate_sel<T, K, R, !CO>(s_c, CP, I.th, I.mf_th, I.mf_sh, kplane(I, ch), li0, tx, acc);
     }
     double kap = 0.0;
     T* __restrict__ Hp = I.Hp + ch * HW;
@@ -1568,11 +1576,13 @@ __global__ __launch_bounds__(kNT) void k_cg_init(const Inst<T>* __restrict__ ins
 
 // ------------------------------------------------------------------ small kernels
 // One block per instance: the initial solver states of the table entry go
-// into the state arrays (Lst, Cst: nullable), then theta64 (double, KxK) ->
-// th (correlation form) and thf (flipped, convolution form), both
-// column-major in the compute type; with Lst, the l1 norm squared becomes the
-// starting Lipschitz estimate when the initial one is <= 0; red[slot_abs]
-// receives the l1 norm when slot_abs >= 0.
+// into the state arrays (Lst, Cst: nullable), then theta64 (double, kc KxK
+// planes) -> th (correlation form) and thf (flipped, convolution form), both
+// column-major in the compute type, plane by plane; with Lst, the largest
+// plane l1 norm squared (a bound of ||theta*.||^2: Young's inequality per
+// channel, the channels do not mix) becomes the starting Lipschitz estimate
+// when the initial one is <= 0; red[slot_abs] receives that l1 norm when
+// slot_abs >= 0.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* insts, ApgState* __restrict__ Lst,
                                                       CgState* __restrict__ Cst, int slot_abs,
@@ -1598,38 +1608,49 @@ __global__ __launch_bounds__(1024) void k_prep_kernel(const Inst<T>* insts, ApgS
         if (Cst) put_state(&Cst[blockIdx.x], I.cg0);
     }
     if (!I.theta64) return;
-    const int K = I.K, KK = K * K;
+    const int K = I.K, KK = K * K, KP = I.kc > 1 ? I.kc : 1;
     const int t = threadIdx.x;
-    double a = 0.0;
-    if (t < KK) {
-        const int u = t / K, v = t - u * K;
-        const double w = I.theta64[t];
-        // column-major: out(u,v) at v*K+u; the flipped kernel f(u',v') = theta(K-1-u', K-1-v')
-        I.th[v * K + u] = (T)w;
-        I.thf[(K - 1 - v) * K + (K - 1 - u)] = (T)w;
-        a = fabs(w);
-    }
-    s_abs[t] = a;
-    __syncthreads();
-    __shared__ int s_sh;
-    if (t == 0) {
-        double s = 0.0, mx = 0.0;
-        for (int i = 0; i < KK; ++i) {
-            s += s_abs[i];
-            mx = fmax(mx, s_abs[i]);
+    __shared__ int s_sh[kMaxC];
+    double l1max = 0.0;
+    for (int p = 0; p < KP; ++p) {
+        const double* th64 = I.theta64 + p * KK;
+        double a = 0.0;
+        if (t < KK) {
+            const int u = t / K, v = t - u * K;
+            const double w = th64[t];
+            // column-major: out(u,v) at v*K+u; the flipped kernel f(u',v') = theta(K-1-u', K-1-v')
+            I.th[p * KK + v * K + u] = (T)w;
+            I.thf[p * KK + (K - 1 - v) * K + (K - 1 - u)] = (T)w;
+            a = fabs(w);
         }
-        if (Lst && !(I.st0.L > 0.0)) Lst[blockIdx.x].L = s * s;
-        if (slot_abs >= 0) I.red[slot_abs] = s;
-        // the matrix-core layouts: the kernel scaled by a power of two that
-        // brings its largest tap into [2^14, 2^15)
-        const float mxf = (float)mx;
-        s_sh = mxf >= 1.0e-30f ? mf_shift(mxf) : 0;
-        if (I.mf_th) *I.mf_sh = s_sh;
+        __syncthreads();   // s_abs of the previous plane has been read
+        s_abs[t] = a;
+        __syncthreads();
+        if (t == 0) {
+            double s = 0.0, mx = 0.0;
+            for (int i = 0; i < KK; ++i) {
+                s += s_abs[i];
+                mx = fmax(mx, s_abs[i]);
+            }
+            l1max = fmax(l1max, s);
+            // the matrix-core layouts: each plane scaled by a power of two
+            // that brings its largest tap into [2^14, 2^15)
+            const float mxf = (float)mx;
+            s_sh[p] = mxf >= 1.0e-30f ? mf_shift(mxf) : 0;
+            if (I.mf_th) I.mf_sh[p] = s_sh[p];
+        }
+    }
+    if (t == 0) {
+        if (Lst && !(I.st0.L > 0.0)) Lst[blockIdx.x].L = l1max * l1max;
+        if (slot_abs >= 0) I.red[slot_abs] = l1max;
     }
     if (!I.mf_th) return;
     __syncthreads();
-    mf_fragments(I.theta64, K, false, s_sh, I.mf_th, t, 1024);
-    mf_fragments(I.theta64, K, true, s_sh, I.mf_thf, t, 1024);
+    const int fw = mf_frag_bytes(K) / 16;   // one plane's layout, in uint4
+    for (int p = 0; p < KP; ++p) {
+        mf_fragments(I.theta64 + p * KK, K, false, s_sh[p], I.mf_th + p * fw, t, 1024);
+        mf_fragments(I.theta64 + p * KK, K, true, s_sh[p], I.mf_thf + p * fw, t, 1024);
+    }
 }
 
 // One block per instance: red[slot] = sum of the instance's cv_part partials;
@@ -1643,12 +1664,13 @@ __global__ __launch_bounds__(kNT) void k_finish(const Inst<T>* __restrict__ inst
         if (threadIdx.x == 0) I.red[slot] = s;
     }
     if (I.sob_th) {
-        const int K = I.K, KK = K * K;
+        // every plane's own KxK grid (no difference across planes)
+        const int K = I.K, KK = K * K, KP = I.kc > 1 ? I.kc : 1;
         const double* th = I.sob_th;
         const double* a = I.sob_a;
         double v = 0.0;
-        for (int t = threadIdx.x; t < KK; t += kNT) {
-            const int u = t / K, w = t - u * K;
+        for (int t = threadIdx.x; t < KP * KK; t += kNT) {
+            const int tp = t % KK, u = tp / K, w = tp - u * K;
             const double e = th[t] - a[t];
             const double dh = w < K - 1 ? (th[t + 1] - a[t + 1]) - e : 0.0;
             const double dv = u < K - 1 ? (th[t + K] - a[t + K]) - e : 0.0;
@@ -1754,29 +1776,39 @@ __device__ __forceinline__ void hg_corr_blk(int C, int H, int W, int K, const do
 // instances of the class (K <= 16 for KT = 16) with hg_nblk > 0 own
 // consecutive block ranges [hg_base, hg_base + hg_nblk) and each range
 // runs exactly as a launch of its own would (so the partial sums, and z,
-// are bitwise those of the per-instance form).
+// are bitwise those of the per-instance form).  With per-channel kernels
+// (kc > 1) the range splits into kc equal parts, part p correlating channel
+// p alone into its own partial sums.
 template <typename T, int KT>
 __global__ __launch_bounds__(kNT) void k_hg_corr_batch(const Inst<T>* __restrict__ insts, int n) {
     const int b = (int)blockIdx.x;
     for (int i = 0; i < n; ++i) {
         const Inst<T>& I = insts[i];
         if ((I.K <= 16) != (KT == 16) || b < I.hg_base || b >= I.hg_base + I.hg_nblk) continue;
+        if (I.kc > 1) {
+            const int nbp = I.hg_nblk / I.kc, lb = b - I.hg_base, p = lb / nbp;
+            const int64_t o = (int64_t)p * I.pr.H * I.pr.W;
+            hg_corr_blk<T, KT>(1, I.pr.H, I.pr.W, I.K, I.hg_rho + o, I.hg_q + o, I.hg_w + o, I.cv_in + o,
+                               I.hg_part + (size_t)p * nbp * KT * KT, lb - p * nbp, nbp);
+            return;
+        }
         hg_corr_blk<T, KT>(I.pr.C, I.pr.H, I.pr.W, I.K, I.hg_rho, I.hg_q, I.hg_w, I.cv_in, I.hg_part, b - I.hg_base,
                            I.hg_nblk);
         return;
     }
 }
 
-// z = -sum_blocks Z + with_r * grad r(theta); ||z||^2 into *znorm2 (a block
-// of 1024 threads).
+// z = -sum_blocks Z + with_r * grad r(theta) for one KxK plane; returns
+// ||z||^2 to thread 0 (a block of 1024 threads).
 template <int KT>
-__device__ __forceinline__ void hg_final_blk(double beta, double h1_w0, const double* __restrict__ part, int nblk, int K,
-                                             const double* __restrict__ th, const double* __restrict__ a, int with_r,
-                                             double* __restrict__ z, double* __restrict__ znorm2) {
+__device__ __forceinline__ double hg_final_blk(double beta, double h1_w0, const double* __restrict__ part, int nblk,
+                                               int K, const double* __restrict__ th, const double* __restrict__ a,
+                                               int with_r, double* __restrict__ z) {
     __shared__ double s_e[1024];
     __shared__ double s_z[1024];
     __shared__ double s_g[1024];
     const int t = threadIdx.x, KK = K * K;
+    __syncthreads();   // the previous plane's reads of the shared arrays are done
     if (t < KK) s_e[t] = (with_r && a) ? th[t] - a[t] : 0.0;
     // the sum over the correlation blocks: G = 1024 / K^2 threads per tap,
     // thread (g, tap) adds blocks g, g + G, ... in order, then the tap's
@@ -1812,11 +1844,10 @@ __device__ __forceinline__ void hg_final_blk(double beta, double h1_w0, const do
     }
     s_z[t] = zz * zz;
     __syncthreads();
-    if (t == 0) {
-        double s = 0.0;
+    double s = 0.0;
+    if (t == 0)
         for (int i = 0; i < KK; ++i) s += s_z[i];
-        *znorm2 = s;
-    }
+    return s;
 }
 
 // block i finishes instance i of a batched correlation launch (if it was in it)
@@ -1824,7 +1855,13 @@ template <typename T, int KT>
 __global__ __launch_bounds__(1024) void k_hg_final_batch(const Inst<T>* __restrict__ insts) {
     const Inst<T>& I = insts[blockIdx.x];
     if (I.hg_nblk <= 0 || (I.K <= 16) != (KT == 16)) return;
-    hg_final_blk<KT>(I.beta, I.h1_w0, I.hg_part, I.hg_nblk, I.K, I.theta64, I.hg_a, I.hg_with_r, I.hg_z, I.hg_zn2);
+    // ||z||^2: the planes' sums added in plane order
+    const int KP = I.kc > 1 ? I.kc : 1, KK = I.K * I.K, nbp = I.hg_nblk / KP;
+    double zn2 = 0.0;
+    for (int p = 0; p < KP; ++p)
+        zn2 += hg_final_blk<KT>(I.beta, I.h1_w0, I.hg_part + (size_t)p * nbp * KT * KT, nbp, I.K,
+                                I.theta64 + p * KK, I.hg_a ? I.hg_a + p * KK : nullptr, I.hg_with_r, I.hg_z + p * KK);
+    if (threadIdx.x == 0) *I.hg_zn2 = zn2;
 }
 
 }  // namespace maid

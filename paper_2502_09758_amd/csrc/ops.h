@@ -116,7 +116,9 @@ hipError_t launch_cast(const S* src, D* dst, int64_t n, hipStream_t s);
 // x64 += alpha d, x32 = (float) x64, partials of d^2 and x64^2 (2 per block)
 hipError_t launch_axpy_mixed(double* x64, const float* d, double alpha, int64_t n, float* x32, double* part, int blocks,
                              hipStream_t s);
-hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s);
+// r(theta) over kp kernel planes of KxK taps into *out (one block)
+hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, int kp, double* out,
+                          hipStream_t s);
 int hg_items(const Shape& d);
 
 extern template struct Ops<float>;

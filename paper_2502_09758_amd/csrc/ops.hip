@@ -79,31 +79,28 @@ __global__ void k_theta_step(const double* __restrict__ th, const double* __rest
     if (t < KK) out[t] = th[t] - s * z[t];
 }
 
-// Sobolev term on the KxK grid (Neumann forward differences):
-// value r = beta (w0 sum e^2 + sum (D_h e)^2 + sum (D_v e)^2), e = theta - a,
-// gradient 2 beta (w0 e + D^T D e).  One block of 1024 threads.
-__device__ __forceinline__ double sob_e(const double* s_e, int K, int u, int v) { return s_e[u * K + v]; }
-
+// Sobolev term on the KxK grid of each of kp kernel planes (Neumann forward
+// differences, none across planes):
+// value r = beta (w0 sum e^2 + sum (D_h e)^2 + sum (D_v e)^2), e = theta - a.
+// One block of 1024 threads; thread t takes taps t, t + 1024, ... and thread
+// 0 adds the threads' sums in order.
 __global__ __launch_bounds__(1024) void k_sobolev(double beta, double h1_w0, const double* __restrict__ th,
-                                                  const double* __restrict__ a, int K, double* __restrict__ out) {
-    __shared__ double s_e[1024];
+                                                  const double* __restrict__ a, int K, int kp, double* __restrict__ out) {
     __shared__ double s_r[1024];
-    const int t = threadIdx.x, KK = K * K;
-    if (t < KK) s_e[t] = th[t] - a[t];
-    __syncthreads();
+    const int KK = K * K;
     double val = 0.0;
-    if (t < KK) {
-        const int u = t / K, v = t - u * K;
-        const double e = s_e[t];
-        const double dh = (v < K - 1) ? sob_e(s_e, K, u, v + 1) - e : 0.0;
-        const double dv = (u < K - 1) ? sob_e(s_e, K, u + 1, v) - e : 0.0;
-        val = h1_w0 * e * e + dh * dh + dv * dv;
+    for (int t = threadIdx.x; t < kp * KK; t += 1024) {
+        const int tp = t % KK, u = tp / K, v = tp - u * K;
+        const double e = th[t] - a[t];
+        const double dh = (v < K - 1) ? (th[t + 1] - a[t + 1]) - e : 0.0;
+        const double dv = (u < K - 1) ? (th[t + K] - a[t + K]) - e : 0.0;
+        val += h1_w0 * e * e + dh * dh + dv * dv;
     }
-    s_r[t] = val;
+    s_r[threadIdx.x] = val;
     __syncthreads();
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int i = 0; i < KK; ++i) s += s_r[i];
+        for (int i = 0; i < 1024; ++i) s += s_r[i];
         *out = beta * s;
     }
 }
@@ -308,8 +305,9 @@ hipError_t launch_theta_step(const double* th, const double* z, double step, dou
     return launch(k_theta_step, dim3((KK + 255) / 256), dim3(256), 0, s, th, z, step, out, KK);
 }
 
-hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, double* out, hipStream_t s) {
-    return launch(k_sobolev, dim3(1), dim3(1024), 0, s, beta, h1_w0, th, a, K, out);
+hipError_t launch_sobolev(double beta, double h1_w0, const double* th, const double* a, int K, int kp, double* out,
+                          hipStream_t s) {
+    return launch(k_sobolev, dim3(1), dim3(1024), 0, s, beta, h1_w0, th, a, K, kp, out);
 }
 
 }  // namespace maid

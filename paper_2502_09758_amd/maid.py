@@ -44,7 +44,8 @@ class SolveInfo:
 
 @dataclass
 class MaidState:
-    """theta (K x K float64), x and q (C x H x W, storage dtype) on the GPU,
+    """theta (K x K float64, or C x K x K with per-channel kernels), x and q
+    (C x H x W, storage dtype) on the GPU,
     updated in place by `Maid.maid_step`."""
     theta: torch.Tensor
     x: torch.Tensor
@@ -58,14 +59,16 @@ class MaidState:
 
 class Maid:
     def __init__(self, C, H, W, K, dtype=torch.float32, alpha=1e-3, eps_tv=1e-2, beta=0.0,
-                 h1_w0=1.0, reg=L.MAID_REG_TV):
+                 h1_w0=1.0, reg=L.MAID_REG_TV, kc=1):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.C, self.H, self.W, self.K = int(C), int(H), int(W), int(K)
+        self.kc = int(kc)          # kernel planes: 1 shared kernel, C one kernel per channel
         self.dtype = dtype
         self.alpha, self.eps_tv, self.beta, self.h1_w0, self.reg = alpha, eps_tv, beta, h1_w0, reg
         self.desc = L.maid_desc(H=self.H, W=self.W, C=self.C, K=self.K, dtype=_DT[dtype], boundary=0, reg=int(reg),
-                                alpha=float(alpha), eps_tv=float(eps_tv), beta=float(beta), h1_w0=float(h1_w0))
+                                kc=self.kc, alpha=float(alpha), eps_tv=float(eps_tv), beta=float(beta),
+                                h1_w0=float(h1_w0))
         self._h = None
         self._h = L.create(self.desc)
 
@@ -98,11 +101,16 @@ class Maid:
                              f"{t.dtype} {tuple(t.shape)}")
         return t
 
+    @property
+    def kshape(self):
+        """shape of theta, a and z: (K, K) shared, (C, K, K) per channel"""
+        return (self.K, self.K) if self.kc <= 1 else (self.kc, self.K, self.K)
+
     def _ker(self, t, name):
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise ValueError(f"{name} must be a CUDA tensor")
-        if t.dtype != torch.float64 or tuple(t.shape) != (self.K, self.K) or not t.is_contiguous():
-            raise ValueError(f"{name} must be contiguous float64 of shape {(self.K, self.K)}")
+        if t.dtype != torch.float64 or tuple(t.shape) != self.kshape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous float64 of shape {self.kshape}")
         return t
 
     def _check(self, rc, what):
@@ -221,7 +229,7 @@ class Maid:
         if a is not None:
             self._ker(a, "a")
         if z is None:
-            z = torch.empty((self.K, self.K), dtype=torch.float64, device=theta.device)
+            z = torch.empty(self.kshape, dtype=torch.float64, device=theta.device)
         self._ker(z, "z")
         zn = ct.c_double()
         rc = L.lib().maid_hypergrad(self.handle, _ptr(theta), _ptr(a) if a is not None else None, _ptr(y),
@@ -343,10 +351,11 @@ class MaidBatch:
         if dtype not in _DT:
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
-        self.specs = [dict(alpha=1e-3, eps_tv=1e-2, beta=0.0, h1_w0=1.0, reg=L.MAID_REG_TV) | dict(s) for s in specs]
+        self.specs = [dict(alpha=1e-3, eps_tv=1e-2, beta=0.0, h1_w0=1.0, reg=L.MAID_REG_TV, kc=1) | dict(s)
+                      for s in specs]
         self.n = len(self.specs)
         self.descs = [L.maid_desc(H=int(s["H"]), W=int(s["W"]), C=int(s["C"]), K=int(s["K"]), dtype=_DT[dtype],
-                                  boundary=0, reg=int(s["reg"]),
+                                  boundary=0, reg=int(s["reg"]), kc=int(s["kc"]),
                                   alpha=float(s["alpha"]), eps_tv=float(s["eps_tv"]), beta=float(s["beta"]),
                                   h1_w0=float(s["h1_w0"]))
                       for s in self.specs]
@@ -382,11 +391,15 @@ class MaidBatch:
         if len(ts) != self.n:
             raise ValueError(f"{name}: need {self.n} tensors")
         for i, t in enumerate(ts):
-            K = self.specs[i]["K"]
+            ks = self._kshape(i)
             if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or \
-                    tuple(t.shape) != (K, K) or not t.is_contiguous():
-                raise ValueError(f"{name}[{i}] must be a contiguous CUDA float64 tensor of shape {(K, K)}")
+                    tuple(t.shape) != ks or not t.is_contiguous():
+                raise ValueError(f"{name}[{i}] must be a contiguous CUDA float64 tensor of shape {ks}")
         return (ct.c_void_p * self.n)(*[t.data_ptr() for t in ts])
+
+    def _kshape(self, i):
+        s = self.specs[i]
+        return (s["K"], s["K"]) if s["kc"] <= 1 else (s["kc"], s["K"], s["K"])
 
     def _rc(self, rc, what):
         if rc < 0 and rc not in (L.NOT_SPD, L.NONFINITE):
@@ -437,7 +450,7 @@ class MaidBatch:
             self._imgs(qs, "q")
         a = self._kers(as_, "a") if as_ is not None else None
         if zs is None:
-            zs = [torch.empty((s["K"], s["K"]), dtype=torch.float64, device=thetas[0].device) for s in self.specs]
+            zs = [torch.empty(self._kshape(i), dtype=torch.float64, device=thetas[0].device) for i in range(self.n)]
         z = self._kers(zs, "z")
         zn = (ct.c_double * self.n)()
         self._check(L.lib().maid_batch_hypergrad(self.handle, th, a, y, xt, q, int(bool(with_r)), z, zn, _stream()),

@@ -49,6 +49,7 @@ def _desc(**kw):
     (dict(C=0), "C must"), (dict(C=4), "C must"), (dict(dtype=2), "dtype"), (dict(reg=3), "reg"),
     (dict(alpha=-1.0), "alpha"), (dict(alpha=float("nan")), "alpha"), (dict(eps_tv=0.0), "eps_tv"),
     (dict(beta=-1.0), "beta"), (dict(H=0), "H and W"), (dict(boundary=1), "periodic"), (dict(boundary=2), "boundary"),
+    (dict(C=3, kc=2), "kc"), (dict(C=1, kc=3), "kc"), (dict(kc=-1), "kc"),
 ])
 def test_create_rejects_invalid_descriptions(lib, bad, msg):
     h = ct.c_void_p(123)
