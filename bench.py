@@ -243,8 +243,8 @@ def batch_maid_work(insts, dt, steps=20, eps0=1e-3, step0=1e-4):
     instance of the ragged batch, each instance with its own adaptive
     tolerances, step size and decisions, once through one maid_batch_steps
     call (lockstep: all instances that need a solve share its launches) and once
-    through one plain context per instance (same tile heights and lower-level
-    forms, so bitwise the same solves and decisions).  Pixel-iterations count
+    through one plain context per instance (same tile heights, lower-level
+    forms and team setting, so bitwise the same solves and decisions).  Pixel-iterations count
     (lower + CG iterations) x C*H*W over all instances and steps."""
     import torch
     from paper_2502_09758_amd import _lib as L
@@ -261,6 +261,8 @@ def batch_maid_work(insts, dt, steps=20, eps0=1e-3, step0=1e-4):
         m = Maid(i.C, i.H, i.W, i.K, dt, alpha=i.alpha, eps_tv=i.eps_tv, beta=i.beta)
         m.set_tile_rows(rows[k])
         m.set_one_pass(forms[k])
+        if "team=" not in mb.config():
+            m.set_team(0)    # the batch's passes (a lone small instance would take the team loops)
         solos.append(m)
     n = len(insts)
     pix = [i.C * i.H * i.W for i in insts]
@@ -272,17 +274,17 @@ def batch_maid_work(insts, dt, steps=20, eps0=1e-3, step0=1e-4):
                 for a, y in zip(th, ys)]
 
     def batched():
+        # one call for all the steps: an instance that reaches the accuracy
+        # floor stops there, as in the plain loop (a later call would step it
+        # again)
         st = states()
-        work = acc = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(0, steps, 5):
-            _, infos = mb.maid_steps(th, ys, st, min(5, steps - k), **hp)
-            work += sum((f["lower_iters"] + f["cg_iters"]) * p for f, p in zip(infos, pix))
-            acc += sum(f["accepted"] for f in infos)
-            print(f"[bench] batched MAID: {k + min(5, steps - k)} steps, {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
+        _, infos = mb.maid_steps(th, ys, st, steps, **hp)
+        work = sum((f["lower_iters"] + f["cg_iters"]) * p for f, p in zip(infos, pix))
+        acc = sum(f["accepted"] for f in infos)
         torch.cuda.synchronize()
+        print(f"[bench] batched MAID: {steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         return time.perf_counter() - t0, work, acc, st
 
     def plain():

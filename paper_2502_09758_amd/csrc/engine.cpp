@@ -269,8 +269,8 @@ namespace {
 enum { G_APG = 1, G_CG = 2 };
 
 template <typename F>
-int run_chunk(maid_ctx* c, int kind, int chunk, hipStream_t s, F enqueue) {
-    if (c->prof_on || !c->use_graphs) return enqueue(s);
+int run_chunk(maid_ctx* c, int kind, int chunk, hipStream_t s, F enqueue, bool graphs) {
+    if (c->prof_on || !c->use_graphs || !graphs) return enqueue(s);
     for (auto& g : c->graphs)
         if (g.kind == kind && g.chunk == chunk && g.gen == c->layout_gen) {
             HIP_TRY(hipGraphLaunch(g.exec, s));
@@ -301,10 +301,10 @@ int run_chunk(maid_ctx* c, int kind, int chunk, hipStream_t s, F enqueue) {
 // Launch `want` slots as power-of-two graph chunks back to back (no host
 // round trip between them).
 template <typename F>
-int run_slots(maid_ctx* c, int kind, long want, hipStream_t s, F enqueue) {
+int run_slots(maid_ctx* c, int kind, long want, hipStream_t s, F enqueue, bool graphs = true) {
     for (int p = 32; p >= 1; p >>= 1)
         while (want >= p) {
-            int rc = run_chunk(c, kind, p, s, [&](hipStream_t st) { return enqueue(st, p); });
+            int rc = run_chunk(c, kind, p, s, [&](hipStream_t st) { return enqueue(st, p); }, graphs);
             if (rc) return rc;
             want -= p;
         }
@@ -323,6 +323,152 @@ long next_slots(long pred, long done_so_far, long last, int first_pct) {
     if (done_so_far == 0) return pred > 0 ? std::max(1L, pred * first_pct / 100) : 1;
     if (pred > 0 && done_so_far == last) return std::max(1L, pred / 8);
     return std::min(last * 2, 64L);
+}
+
+// The launch layout of a solve over the instances of `act`.  A solve over
+// part of a batch (Algorithm 2's trial solves and retries, where instances
+// step in lockstep but need different numbers of solves) would otherwise
+// launch every block of every group in every pass, the inactive instances'
+// blocks exiting at once: per pass a dispatch of the whole batch for the
+// work of a few instances.  The sub-layout gives each group's active
+// instances consecutive block ranges, each starting at a multiple of 8 as in
+// the full layout (the same local block indices and tiles, so bitwise the
+// same results), and a group without an active instance launches nothing.
+// Its chunks run without graphs (a graph embeds its grid); team groups keep
+// their layout.
+struct SubLayout {
+    bool full = true;
+    std::vector<LaunchGroup> groups;
+    int grid_e = 0;
+    const int* blk_e = nullptr;
+    int only_e = -1;
+    std::vector<int> base, basef, base_e;   // per instance (active, compacted groups)
+    template <typename T> void apply(Inst<T>* tab, const std::vector<char>& act) const {
+        if (full) return;
+        for (size_t i = 0; i < base.size(); ++i)
+            if (act[i]) {
+                tab[i].base = base[i];
+                tab[i].basef = basef[i];
+                tab[i].base_e = base_e[i];
+            }
+    }
+};
+
+// Blocks of one pass over the multi-kernel groups for the instances of act
+// (the sub-layout's grids, without building it).
+int64_t pass_blocks(maid_ctx* c, const std::vector<char>& act) {
+    int64_t b = 0;
+    for (auto& lg : c->groups) {
+        if (lg.team > 0) continue;
+        for (int i : lg.members)
+            if (act[i]) b += round8(lg.g.grid_f > 0 ? c->m[i].nbf : c->m[i].nb);
+    }
+    return b;
+}
+
+int sub_layout(maid_ctx* c, const std::vector<char>& act, SubLayout& L, hipStream_t s);
+
+// Between chunks of a solve: once the instances still iterating hold less
+// than 60 % of the blocks the passes launch, launch theirs alone (the
+// finished ones' final states stay where the last slot left them, in the
+// arrays the solve reads them from; their table entries keep their ranges).
+template <typename T>
+int shrink_layout(maid_ctx* c, SubLayout& L, std::vector<char>& cur, const std::vector<char>& still, Inst<T>* tab,
+                  const Inst<T>* tabd, hipStream_t s) {
+    if (!c->compact || !c->sub_maps) return MAID_OK;
+    const int64_t now = pass_blocks(c, cur), left = pass_blocks(c, still);
+    if (left == 0 || left * 10 >= now * 6) return MAID_OK;
+    TRY(sub_layout(c, still, L, s));
+    L.apply(tab, still);
+    HIP_TRY(hipMemcpyAsync(const_cast<Inst<T>*>(tabd), tab, (size_t)c->n * sizeof(Inst<T>), hipMemcpyHostToDevice,
+                           s));
+    cur = still;
+    return MAID_OK;
+}
+
+int sub_layout(maid_ctx* c, const std::vector<char>& act, SubLayout& L, hipStream_t s) {
+    const int n = c->n;
+    L = SubLayout();
+    L.groups = c->groups;
+    L.grid_e = c->grid_e;
+    L.blk_e = c->blk_e;
+    L.only_e = c->only_e;
+    bool all = true;
+    for (char a : act) all = all && a;
+    if (all || !c->compact || !c->sub_maps) return MAID_OK;
+    L.full = false;
+    L.base.assign(n, 0);
+    L.basef.assign(n, 0);
+    L.base_e.assign(n, 0);
+    for (int i = 0; i < n; ++i) {   // team groups keep the full layout's ranges
+        L.base[i] = c->m[i].base;
+        L.basef[i] = c->m[i].basef;
+    }
+    int* h = c->sub_host;
+    size_t used = 0;
+    auto fill = [&](const std::vector<int>& ids, const std::vector<int>& b, int grid) {
+        for (size_t t = 0; t < ids.size(); ++t) {
+            const int end = t + 1 < ids.size() ? b[ids[t + 1]] : grid;
+            for (int k = b[ids[t]]; k < end; ++k) h[used + k] = ids[t];
+        }
+    };
+    std::vector<size_t> off(L.groups.size(), 0), offf(L.groups.size(), 0);
+    for (size_t g = 0; g < L.groups.size(); ++g) {
+        LaunchGroup& lg = L.groups[g];
+        if (lg.team > 0) continue;
+        std::vector<int> ids;
+        for (int i : lg.members)
+            if (act[i]) ids.push_back(i);
+        int base = 0, grid = 0;
+        for (int i : ids) {
+            L.base[i] = base;
+            grid = base + c->m[i].nb;
+            base = round8(grid);
+        }
+        lg.g.grid = grid;
+        lg.g.only = ids.size() == 1 ? ids[0] : -1;
+        off[g] = used;
+        fill(ids, L.base, grid);
+        used += grid;
+        int basef = 0, gridf = 0;
+        if (lg.g.grid_f > 0) {
+            for (int i : ids) {
+                L.basef[i] = basef;
+                gridf = basef + c->m[i].nbf;
+                basef = round8(gridf);
+            }
+            lg.g.grid_f = gridf;
+            offf[g] = used;
+            fill(ids, L.basef, gridf);
+            used += gridf;
+        }
+    }
+    std::vector<int> ids_e;
+    int base_e = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!act[i]) continue;
+        ids_e.push_back(i);
+        L.base_e[i] = base_e;
+        L.grid_e = base_e + c->m[i].nbe;
+        base_e = round8(L.grid_e);
+    }
+    if (ids_e.empty()) L.grid_e = 0;
+    const size_t off_e = used;
+    fill(ids_e, L.base_e, L.grid_e);
+    used += L.grid_e;
+    L.only_e = -1;
+    if (used > c->maps_cap) return fail(c, MAID_EHIP, "sub_layout: block maps exceed their allocation");
+    // the previous sub-layout's copy and the passes that read it are behind
+    // the previous solve's last state publication, which waited for them
+    HIP_TRY(hipMemcpyAsync(c->sub_maps, h, used * sizeof(int), hipMemcpyHostToDevice, s));
+    for (size_t g = 0; g < L.groups.size(); ++g) {
+        LaunchGroup& lg = L.groups[g];
+        if (lg.team > 0) continue;
+        lg.g.blk = c->sub_maps + off[g];
+        lg.g.blk_f = lg.g.grid_f > 0 ? c->sub_maps + offf[g] : nullptr;
+    }
+    L.blk_e = c->sub_maps + off_e;
+    return MAID_OK;
 }
 
 }  // namespace
@@ -641,6 +787,8 @@ void destroy_ctx(maid_ctx* c) {
     if (c->tab_dev) (void)hipFree(c->tab_dev);
     if (c->tab_host) (void)hipHostFree(c->tab_host);
     if (c->maps) (void)hipFree(c->maps);
+    if (c->sub_maps) (void)hipFree(c->sub_maps);
+    if (c->sub_host) (void)hipHostFree(c->sub_host);
     if (c->team_arrive) (void)hipFree(c->team_arrive);
     if (c->adp_ws) (void)hipFree(c->adp_ws);
     if (c->ref64) destroy_ctx(c->ref64);
@@ -710,6 +858,8 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&c->tab_host, tab_bytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipMalloc((void**)&c->maps, maps * sizeof(int));
+    if (e == hipSuccess && n > 1) e = hipMalloc((void**)&c->sub_maps, maps * sizeof(int));
+    if (e == hipSuccess && n > 1) e = hipHostMalloc((void**)&c->sub_host, maps * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemset(c->ws, 0, c->ws_bytes);
     if (e == hipSuccess) e = hipMemset(c->st_dev, 0, c->st_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
@@ -723,6 +873,7 @@ int create_ctx(const maid_desc* descs, int n, maid_ctx** out, std::string& why) 
         return code;
     }
     if (const char* g = std::getenv("MAID_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
+    if (const char* g = std::getenv("MAID_COMPACT")) c->compact = std::strcmp(g, "0") != 0;
     if (const char* t = std::getenv("MAID_TEAM")) c->team_req = std::max(-1, std::atoi(t));
     if (const char* f = std::getenv("MAID_FUSE")) c->fuse = std::strcmp(f, "0") != 0;
     if (const char* f = std::getenv("MAID_CG_ONE_PASS")) c->cg_fuse = std::strcmp(f, "0") != 0;
@@ -879,11 +1030,16 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
     }
     // the initial states travel in the table; the preparation pass copies them
     for (int i = 0; i < n; ++i) tab[i].st0 = c->apg_h[i];
+    SubLayout SL;
+    TRY(sub_layout(c, act, SL, s));
+    SL.apply(tab, act);
+    std::vector<char> cur_act = act;
     {
         ProfScope ps_(c, MAID_PROF_OTHER, s);
         TRY(upload_prep<T>(c, ROLE_APG, 1, c->apg[0], nullptr, -1, s));
     }
-    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, tabd, s));
+    for (auto& lg : SL.groups)
+        if (lg.g.grid > 0) LAUNCH(MAID_PROF_CONV, Ops<T>::conv(lg.g, tabd, s));
     // each slot is one gradient pass and one trial pass; a slot advances every
     // unfinished solve by one iteration or by one backtracking step
     const long slot_cap = (long)max_iter + 256 + 1;
@@ -909,15 +1065,15 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
             int rc = run_slots(c, G_APG, chunk, s, [&](hipStream_t s, int cnt) {
                 // one-pass groups take two iterations per slot (state there and back)
                 for (int k = 0; k < cnt; ++k) {
-                    for (auto& lg : c->groups) {
-                        if (lg.team != 0) continue;
+                    for (auto& lg : SL.groups) {
+                        if (lg.team != 0 || lg.g.grid == 0) continue;
                         if (lg.g.grid_f > 0)
                             LAUNCH(MAID_PROF_APG_STEP, Ops<T>::apg_step(lg.g, tabd, c->apg[0], c->apg[1], s));
                         else
                             LAUNCH(MAID_PROF_APG_GRAD, Ops<T>::apg_grad(lg.g, tabd, c->apg[0], c->apg[1], s));
                     }
-                    for (auto& lg : c->groups) {
-                        if (lg.team != 0) continue;
+                    for (auto& lg : SL.groups) {
+                        if (lg.team != 0 || lg.g.grid == 0) continue;
                         if (lg.g.grid_f > 0)
                             LAUNCH(MAID_PROF_APG_STEP, Ops<T>::apg_step(lg.g, tabd, c->apg[1], c->apg[0], s));
                         else
@@ -925,7 +1081,7 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
                     }
                 }
                 return (int)MAID_OK;
-            });
+            }, SL.full);
             if (rc) return rc;
             slots += chunk;
             TRY(publish(c, s, c->team_err_apg, pub_bytes));
@@ -933,6 +1089,9 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
             for (int i = 0; i < n; ++i) done = done && (c->apg_h[i].done || in_team[i]);
             if (done) break;
             if (slots > slot_cap) return fail(c, MAID_NONFINITE, "lower_solve: backtracking did not terminate");
+            std::vector<char> still(n);
+            for (int i = 0; i < n; ++i) still[i] = cur_act[i] && !c->apg_h[i].done && !in_team[i];
+            TRY(shrink_layout<T>(c, SL, cur_act, still, tab, tabd, s));
         }
     } else {
         TRY(publish(c, s, c->team_err_apg, pub_bytes));
@@ -980,7 +1139,20 @@ int lower_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<con
         c->prof_work[MAID_PROF_APG_TEAM] += wteam;
         c->prof_work[MAID_PROF_APG_STEP] += wstep;
     }
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, c->only_e, tabd, c->apg[0], s));
+    if (cur_act != act) {
+        // the layout shrank during the solve: the returned points of every
+        // instance of the solve are written over the full elementwise layout
+        // (its inactive entries have no output and return at once)
+        for (int i = 0; i < n; ++i) {
+            tab[i].base = c->m[i].base;
+            tab[i].basef = c->m[i].basef;
+            tab[i].base_e = c->m[i].base_e;
+        }
+        HIP_TRY(hipMemcpyAsync(const_cast<Inst<T>*>(tabd), tab, (size_t)n * sizeof(Inst<T>), hipMemcpyHostToDevice, s));
+        LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(c->grid_e, c->blk_e, c->only_e, tabd, c->apg[0], s));
+    } else if (SL.grid_e > 0) {
+        LAUNCH(MAID_PROF_OTHER, Ops<T>::apg_final(SL.grid_e, SL.blk_e, SL.only_e, tabd, c->apg[0], s));
+    }
     // (inside a MAID step the next work is stream-ordered after this pass,
     // and no host buffer it reads is still being copied: the last state
     // publication drained everything before it)
@@ -1034,15 +1206,21 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
         tab[i].theta64 = theta[i];
     }
     for (int i = 0; i < n; ++i) tab[i].cg0 = c->cg_h[i];
+    SubLayout SL;
+    TRY(sub_layout(c, act, SL, s));
+    SL.apply(tab, act);
+    std::vector<char> cur_act = act;
     {
         ProfScope ps_(c, MAID_PROF_OTHER, s);
         TRY(upload_prep<T>(c, ROLE_CG, 1, nullptr, c->cg[0], -1, s));
     }
     // r = rhs - H q0 (the direction pass in set-up mode copies q0 into q and p)
     CgState** S = c->cg;
-    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
-    for (auto& lg : c->groups) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
-    LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(c->grid_e, c->blk_e, c->only_e, tabd, S[0], s));
+    for (auto& lg : SL.groups)
+        if (lg.g.grid > 0) LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 1, s));
+    for (auto& lg : SL.groups)
+        if (lg.g.grid > 0) LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[0], S[2], 1, s));
+    if (SL.grid_e > 0) LAUNCH(MAID_PROF_OTHER, Ops<T>::cg_init(SL.grid_e, SL.blk_e, SL.only_e, tabd, S[0], s));
     // groups of small instances: the whole loop in one launch per group
     std::vector<char> in_team(n, 0);
     bool graph_any = false;
@@ -1059,11 +1237,11 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
     const size_t pub_bytes = 256 + n * sizeof(CgState);
     // the elementwise update pass serves the three-pass groups only
     bool hs_any = false;
-    for (auto& lg : c->groups) hs_any = hs_any || (lg.team == 0 && !lg.g.cg1);
+    for (auto& lg : SL.groups) hs_any = hs_any || (lg.team == 0 && lg.g.grid > 0 && !lg.g.cg1);
     if (graph_any) {
         // one-pass groups: the priming pass and the first iteration
-        for (auto& lg : c->groups)
-            if (lg.team == 0 && lg.g.cg1) {
+        for (auto& lg : SL.groups)
+            if (lg.team == 0 && lg.g.grid > 0 && lg.g.cg1) {
                 LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
                 LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
             }
@@ -1074,22 +1252,22 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
             // one-pass groups take two iterations per slot (state there and back)
             int rc = run_slots(c, G_CG, chunk, s, [&](hipStream_t s, int cnt) {
                 for (int k = 0; k < cnt; ++k) {
-                    for (auto& lg : c->groups) {
-                        if (lg.team != 0) continue;
+                    for (auto& lg : SL.groups) {
+                        if (lg.team != 0 || lg.g.grid == 0) continue;
                         if (lg.g.cg1) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[0], S[1], s));
                         else LAUNCH(MAID_PROF_CG_DIR, Ops<T>::cg_dir(lg.g, tabd, S[0], S[1], 0, s));
                     }
-                    for (auto& lg : c->groups) {
-                        if (lg.team != 0) continue;
+                    for (auto& lg : SL.groups) {
+                        if (lg.team != 0 || lg.g.grid == 0) continue;
                         if (lg.g.cg1) LAUNCH(MAID_PROF_CG_STEP, Ops<T>::cg_step(lg.g, tabd, S[1], S[0], s));
                         else LAUNCH(MAID_PROF_CG_HVP, Ops<T>::cg_hvp(lg.g, tabd, S[1], S[2], 0, s));
                     }
                     if (hs_any)
                         LAUNCH(MAID_PROF_CG_UPDATE,
-                               Ops<T>::cg_update(c->grid_e, c->blk_e, c->only_e, tabd, S[2], S[0], s));
+                               Ops<T>::cg_update(SL.grid_e, SL.blk_e, SL.only_e, tabd, S[2], S[0], s));
                 }
                 return (int)MAID_OK;
-            });
+            }, SL.full);
             if (rc) return rc;
             slots += chunk;
             TRY(publish(c, s, c->team_err_cg, pub_bytes));
@@ -1097,6 +1275,9 @@ int adjoint_batch(maid_ctx* c, const std::vector<char>& act, const std::vector<c
             for (int i = 0; i < n; ++i) done = done && (c->cg_h[i].done || in_team[i]);
             if (done) break;
             if (slots > (long)max_iter + 2) return fail(c, MAID_EHIP, "adjoint_solve: iteration count lost");
+            std::vector<char> still(n);
+            for (int i = 0; i < n; ++i) still[i] = cur_act[i] && !c->cg_h[i].done && !in_team[i];
+            TRY(shrink_layout<T>(c, SL, cur_act, still, tab, tabd, s));
         }
     } else {
         TRY(publish(c, s, c->team_err_cg, pub_bytes));

@@ -110,6 +110,10 @@ struct maid_ctx {
     int* maps = nullptr;
     size_t maps_cap = 0;
     int layout_gen = 0;
+    // maps of the active sub-layouts (device) and their pinned staging copy
+    int* sub_maps = nullptr;
+    int* sub_host = nullptr;
+    bool compact = true;              // solves over part of a batch launch only its blocks
     // device-resident solver states (+ pinned host mirror of the same layout)
     char* st_dev = nullptr;
     char* st_host = nullptr;
