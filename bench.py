@@ -324,11 +324,14 @@ def adp_compare(workload="cfg2", budget_s=4.0, n_lower=500, n_unroll=50, lam_x=0
     MAID (Algorithm 2), ADP-IFT (n_lower fixed-step lower-level iterations,
     then the implicit-function hypergradient) and ADP-LISTA (n_unroll
     unrolled iterations, differentiated in reverse), all from theta_0 = a and
-    x_0 = y with the same initial upper step, each for budget_s of wall time.
-    Per method: the upper-level loss g(x) + r(theta) it computes at its
-    iterate against time; then the time each needs to reach the best loss
-    that all three reach (the paper reports MAID at about 1/2 of ADP-LISTA's
-    and 1/4 of ADP-IFT's time on its 1D problem)."""
+    x_0 = y, each for budget_s of wall time.  MAID adapts its step from
+    step0; the baselines take a fixed upper step, the one MAID's
+    backtracking settled on, halved and restarted while their fixed-step
+    lower level diverges (at most three times; the steps tried are
+    reported).  Per method: the upper-level loss g(x) + r(theta) it computes
+    at its iterate against time; then the time each needs to reach the best
+    loss that all three reach (the paper reports MAID at about 1/2 of
+    ADP-LISTA's and 1/4 of ADP-IFT's time on its 1D problem)."""
     import torch
     from paper_2502_09758_amd import _lib as L
     from paper_2502_09758_amd import synth
@@ -341,15 +344,14 @@ def adp_compare(workload="cfg2", budget_s=4.0, n_lower=500, n_unroll=50, lam_x=0
     a = torch.tensor(inst.a, dtype=torch.float64, device="cuda")
     y = torch.tensor(inst.y, dtype=dt, device="cuda")
 
-    def state():
-        return MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=ms["eps0"], delta=ms["eps0"],
-                         step=ms["step0"])
+    def state(step):
+        return MaidState(a.clone(), y.clone(), torch.zeros_like(y), eps=ms["eps0"], delta=ms["eps0"], step=step)
 
-    def run(method):
+    def run(method, step):
         m = Maid(C, H, W, K, dt, alpha=inst.alpha, eps_tv=inst.eps_tv, beta=inst.beta)
         if method == "lista":
             m.set_one_pass(0)
-        st = state()
+        st = state(step)
         traj, lower, cg, steps = [], 0, 0, 0
         diverged = None
         torch.cuda.synchronize()
@@ -377,9 +379,19 @@ def adp_compare(workload="cfg2", budget_s=4.0, n_lower=500, n_unroll=50, lam_x=0
         losses = [v for _, v in traj] or [float("nan")]
         return dict(steps=steps, lower_iters=lower, cg_or_hessian_products=cg,
                     seconds=round(traj[-1][0], 3) if traj else 0.0, loss_first=losses[0], loss_best=min(losses),
-                    loss_last=losses[-1], diverged=diverged, traj=traj)
+                    loss_last=losses[-1], diverged=diverged, traj=traj, step=step, final_step=st.step)
 
-    out = {m: run(m) for m in ("maid", "ift", "lista")}
+    out = {"maid": run("maid", ms["step0"])}
+    for method in ("ift", "lista"):
+        step, tried = out["maid"]["final_step"], []
+        for _ in range(4):
+            r = run(method, step)
+            tried.append(step)
+            if r["diverged"] is None:
+                break
+            step *= 0.5
+        r["steps_tried"] = tried
+        out[method] = r
     reached = [r for r in out.values() if r["traj"]]
     target = max(r["loss_best"] for r in reached)
     for r in out.values():

@@ -96,30 +96,46 @@ __host__ __device__ constexpr int cv_pitch(int K) { return kTW + K - 1; }
 __host__ __device__ constexpr int cv_rows(int K, int R) { return tile_h(R) + K - 1; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-__host__ __device__ constexpr int lds_conv(int K, int R) { return cv_rows(K, R) * cv_pitch(K); }
+// The convolution tile's LDS region, in elements of the storage type (esz
+// bytes).  FP32 passes with 13 <= K <= 31 and 4 or 8 rows per thread may
+// correlate on the matrix cores, which write the tile's FP16 halves (two
+// tiles of pitch mf_p16 halfs) and then the waves' partial sums (two planes
+// of tile_h x 68 floats) over the staged tile, so their region is the
+// largest of the three.
+__host__ __device__ constexpr int mf_p16(int K) { return 48 + ((K + 15) + 7) / 8 * 8 + 8; }
+__host__ __device__ constexpr bool mf_tile(int K, int R, int esz) {
+    return esz == 4 && K >= 13 && K <= 31 && (R == 4 || R == 8);
+}
+__host__ __device__ constexpr int lds_conv(int K, int R, int esz) {
+    return mf_tile(K, R, esz) ? cmax(cmax(cv_rows(K, R) * cv_pitch(K), cv_rows(K, R) * mf_p16(K)), 2 * tile_h(R) * 68)
+                              : cv_rows(K, R) * cv_pitch(K);
+}
 // Large kernels are ALU-bound and need occupancy: their passes stage the TV
 // tiles and the convolution tile one after the other in one LDS region.
 // Small kernels are latency-bound: all tiles are staged at once, side by side.
 __host__ __device__ constexpr bool seq_lds(int K) { return K >= 13; }
 __host__ __device__ constexpr int lds_side(bool seq, int a, int b) { return seq ? cmax(a, b) : a + b; }
-__host__ __device__ constexpr int lds_apg_grad(int K, int R, int C, int nw) {
+__host__ __device__ constexpr int lds_apg_grad(int K, int R, int C, int nw, int esz) {
     // sequential staging parks the TV gradient of each output past the tile region
-    return lds_side(seq_lds(K), C * tv_rows(R) * tv_pitch() + nw * fx_rows(R) * fx_pitch(), lds_conv(K, R)) +
+    return lds_side(seq_lds(K), C * tv_rows(R) * tv_pitch() + nw * fx_rows(R) * fx_pitch(), lds_conv(K, R, esz)) +
            (seq_lds(K) ? R * 256 : 0);
 }
-__host__ __device__ constexpr int lds_apg_trial(int K, int R, int C) {
+__host__ __device__ constexpr int lds_apg_trial(int K, int R, int C, int esz) {
     // small kernels also stage v and the step of every channel for the TV decrease
-    return seq_lds(K) ? lds_conv(K, R) : lds_conv(K, R) + 2 * C * tv_rows(R) * tv_pitch();
+    return seq_lds(K) ? lds_conv(K, R, esz) : lds_conv(K, R, esz) + 2 * C * tv_rows(R) * tv_pitch();
 }
-__host__ __device__ constexpr int lds_cg_hvp(int K, int R, int C, int nw) {
+__host__ __device__ constexpr int lds_cg_hvp(int K, int R, int C, int nw, int esz) {
     // small kernels: the Kp tile, x and p of every channel, two weight planes;
     // large kernels: x, p of one channel and the weight planes, then the Kp
     // tile in the same region, plus a park for the TV term and p of each
     // output (2 R values per thread)
-    return seq_lds(K) ? cmax(2 * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch(), lds_conv(K, R)) + 2 * R * 256
-                      : lds_conv(K, R) + 2 * C * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch();
+    return seq_lds(K) ? cmax(2 * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch(), lds_conv(K, R, esz)) +
+                            2 * R * 256
+                      : lds_conv(K, R, esz) + 2 * C * tv_rows(R) * tv_pitch() + 2 * fx_rows(R) * fx_pitch();
 }
-__host__ __device__ constexpr int lds_cg_dir(int K, int R) { return seq_lds(K) ? lds_conv(K, R) : 2 * lds_conv(K, R); }
+__host__ __device__ constexpr int lds_cg_dir(int K, int R, int esz) {
+    return seq_lds(K) ? lds_conv(K, R, esz) : 2 * lds_conv(K, R, esz);
+}
 
 // ------------------------------------------------------------------ instance table
 // Every table pointer is a global-memory pointer: in the device pass it

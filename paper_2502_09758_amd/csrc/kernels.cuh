@@ -378,14 +378,16 @@ __device__ __forceinline__ void correlate(const T* s, int pitch, const T* __rest
 // kp: the kernel plane (0 for a kernel shared by the channels, the image
 // channel for per-channel kernels): taps kT + kp K^2, operand layouts
 // mf + kp (the size of one kernel's), exponent mfsh[kp].
+// On the matrix cores the staged tile s is overwritten (its LDS region of
+// lds_conv(K, R, sizeof(T)) elements is the correlation's work space):
+// callers read what they need of the tile before the call.
 template <typename T, int K, int R, bool MF = true>
-__device__ __forceinline__ void correlate_sel(const T* s, int pitch, const T* __restrict__ kT, const uint4* mf,
+__device__ __forceinline__ void correlate_sel(T* s, int pitch, const T* __restrict__ kT, const uint4* mf,
                                               const int* mfsh, int kp, int li0, int tx, T (&acc)[R]) {
     if constexpr (MF && mf_ok<T, K, R>()) {
         if (mf) {
-            __shared__ __align__(16) unsigned char mf_lds[mf_lds_bytes<K, R>()];
             correlate_mfma<K, R>(s, pitch, mf + kp * (mf_frag_bytes(K) / 16), *(const int MAID_CONST*)(mfsh + kp),
-                                 mf_lds, li0, tx, acc);
+                                 li0, tx, acc);
             return;
         }
     }
@@ -652,6 +654,11 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
+    // the tile's centre values (the input copies) are read before the
+    // correlation, which may overwrite the tile
+    T ctr[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) ctr[o] = cp0 ? s[(li0 + o + c0) * CP + tx + c0] : T(0);
     correlate_sel<T, K, R>(s, CP, I.cv_ker, I.cv_mf, I.cv_mfsh, kplane(I, ch), li0, tx, acc);
     double sq = 0.0;
 #pragma unroll
@@ -665,7 +672,7 @@ __global__ __launch_bounds__(kNT) void k_conv(const Inst<T>* __restrict__ insts,
             if (out2) at(out2, e) = val;
             if (out3) at(out3, e) = val;
             if (cp0) {
-                const T xin = s[(li0 + o + c0) * CP + tx + c0];
+                const T xin = ctr[o];
                 at(cp0, e) = xin;
                 if (cp1) at(cp1, e) = xin;
                 if (cp2) at(cp2, e) = xin;
@@ -756,7 +763,18 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
         if (C > 2) v2.put();
         rs.put();
     } else {
-        for (int c = 0; c < C; ++c) load_tile<VR, VP, VP>(s_v + c * VR * VP, ti0 - 1, tj0 - 1, H, W, vfun(c));
+        // every channel's v tile in one round of loads (one memory latency
+        // instead of one per channel; the residual tile follows later in the
+        // same LDS region)
+        auto v0 = stage<VR, VP, VP>(s_v, ti0 - 1, tj0 - 1, vfun(0));
+        auto v1 = stage<VR, VP, VP>(s_v + VR * VP, ti0 - 1, tj0 - 1, vfun(C > 1 ? 1 : 0));
+        auto v2 = stage<VR, VP, VP>(s_v + 2 * VR * VP, ti0 - 1, tj0 - 1, vfun(C > 2 ? 2 : 0));
+        v0.fetch(H, W);
+        if (C > 1) v1.fetch(H, W);
+        if (C > 2) v2.fetch(H, W);
+        v0.put();
+        if (C > 1) v1.put();
+        if (C > 2) v2.put();
     }
     // the backtracking decision; large kernels take it before their
     // convolution (occupancy first), small ones after it (latency first)
@@ -808,7 +826,7 @@ __device__ __forceinline__ void apg_grad_body(const Inst<T>& I, int lb, ApgState
     __syncthreads();
     // SEQ: the TV gradient waits in LDS past the tile region while the
     // convolution tile reuses it (registers stay with the convolution)
-    T* s_park = sm + cmax(C * VR * VP + nw * WR * WP, lds_conv(K, R));
+    T* s_park = sm + cmax(C * VR * VP + nw * WR * WP, lds_conv(K, R, sizeof(T)));
     T tg[SEQ ? 1 : R];
 #pragma unroll
     for (int o = 0; o < R; ++o) {
@@ -904,7 +922,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
     constexpr bool SEQ = seq_lds(K);
     constexpr int VP = tv_pitch(), VR = tv_rows(R);
     T* s_c = sm;
-    T* s_v = sm + lds_conv(K, R);       // small kernels: v and dl of every channel, one-pixel halo
+    T* s_v = sm + lds_conv(K, R, sizeof(T));   // small kernels: v and dl of every channel, one-pixel halo
     T* s_d = s_v + C * VR * VP;
     const T* Gc = G + ch * HW;
     auto sfun_v = [&](int c) {
@@ -1001,37 +1019,50 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
             }
         }
     } else {
+        // v and dl of every channel at the site and at its right and lower
+        // neighbours, all loaded before any is used: clamped addresses and a
+        // clamped channel index, so no branch separates the loads and a row
+        // costs one memory round trip instead of one per channel and term
 #pragma unroll
         for (int o = 0; o < R; ++o) {
             const int li = li0 + o, gi = ti0 + li;
-            if (li % C == ch && gi < H && gj < W) {
-                const int e = gi * W + gj;
-                const bool hx = gj < W - 1, vx = gi < H - 1;
-                double ds2 = 0.0, s2 = 0.0;
-                for (int c = 0; c < C; ++c) {
-                    const T* Xc = X + c * HW;
-                    const T* XPc = XP + c * HW;
-                    const T* Gcc = G + c * HW;
-                    auto vat = [&](int f) { const T xv = ld<CO>(Xc, f); return dfma(m, xv - ld<CO>(XPc, f), xv); };
-                    const T v0 = vat(e), d0 = ld<CO>(Gcc, e) * ninvL;
-                    const double bh = hx ? (double)(vat(e + 1) - v0) : 0.0;
-                    const double bv = vx ? (double)(vat(e + W) - v0) : 0.0;
-                    const double ah = hx ? (double)(ld<CO>(Gcc, e + 1) * ninvL - d0) : 0.0;
-                    const double av = vx ? (double)(ld<CO>(Gcc, e + W) * ninvL - d0) : 0.0;
-                    if (reg == 2) {
-                        ds2 += ah * (bh + 0.5 * ah) + av * (bv + 0.5 * av);
-                    } else if (reg == 1) {
-                        const double d2 = ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
-                        const double q2 = bh * bh + bv * bv;
-                        dtv += d2 / (sqrt(q2 + d2 + e2) + sqrt(q2 + e2));
-                    } else {
-                        ds2 += ah * (ah + 2.0 * bh) + av * (av + 2.0 * bv);
-                        s2 += bh * bh + bv * bv;
-                    }
-                }
-                if (reg == 2) dtv += ds2;
-                else if (reg == 0) dtv += ds2 / (sqrt(s2 + ds2 + e2) + sqrt(s2 + e2));
+            if (li % C != ch) continue;
+            const bool in = gi < H && gj < W;
+            const int e = clampi(gi, H - 1) * W + clampi(gj, W - 1);
+            const bool hx = in && gj < W - 1, vx = in && gi < H - 1;
+            const int eh = hx ? e + 1 : e, ev = vx ? e + W : e;
+            T xa[kMaxC][3], xb[kMaxC][3], ga[kMaxC][3];
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) {
+                const int64_t co = (int64_t)(c < C ? c : 0) * HW;
+                const T* Xc = X + co;
+                const T* XPc = XP + co;
+                const T* Gcc = G + co;
+                xa[c][0] = ld<CO>(Xc, e);
+                xa[c][1] = ld<CO>(Xc, eh);
+                xa[c][2] = ld<CO>(Xc, ev);
+                xb[c][0] = ld<CO>(XPc, e);
+                xb[c][1] = ld<CO>(XPc, eh);
+                xb[c][2] = ld<CO>(XPc, ev);
+                ga[c][0] = ld<CO>(Gcc, e);
+                ga[c][1] = ld<CO>(Gcc, eh);
+                ga[c][2] = ld<CO>(Gcc, ev);
             }
+            if (!in) continue;
+            double ds2 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) {
+                if (c >= C) break;
+                auto vat = [&](int k) { return dfma(m, xa[c][k] - xb[c][k], xa[c][k]); };
+                const T v0 = vat(0), d0 = ga[c][0] * ninvL;
+                const double bh = hx ? (double)(vat(1) - v0) : 0.0;
+                const double bv = vx ? (double)(vat(2) - v0) : 0.0;
+                const double ah = hx ? (double)(ga[c][1] * ninvL - d0) : 0.0;
+                const double av = vx ? (double)(ga[c][2] * ninvL - d0) : 0.0;
+                tv_site(bh, bv, ah, av, ds2, s2);
+            }
+            if (reg == 2) dtv += ds2;
+            else if (reg == 0) dtv += ds2 / (sqrt(s2 + ds2 + e2) + sqrt(s2 + e2));
         }
     }
 
@@ -1046,6 +1077,11 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
+    // the step dl at the outputs, read before the correlation (which may
+    // overwrite the tile)
+    T dlc[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) dlc[o] = s_c[(li0 + o + c0) * CP + tx + c0];
     correlate_sel<T, K, R, !CO>(s_c, CP, I.thf, I.mf_thf, I.mf_sh, kplane(I, ch), li0, tx, acc);
     double ddat = 0.0;
     // small kernels: every row's loads in flight before any is used (clamped
@@ -1078,7 +1114,7 @@ __device__ __forceinline__ void apg_trial_body(const Inst<T>& I, int lb, ApgStat
             const T kv = dfma(m, kxr[q] - kxpr[q], kxr[q]);
             const T d = acc[o];
             ddat += (double)d * ((double)kv + 0.5 * (double)d);
-            const T xn = dfma(m, xr[q] - xpr[q], xr[q]) + s_c[(li + c0) * CP + tx + c0];
+            const T xn = dfma(m, xr[q] - xpr[q], xr[q]) + dlc[o];
             at(XNc, e) = xn;
             if (I.hist) {
                 T* __restrict__ hp = I.hist + (int64_t)st.iters * I.N + ch * HW;
@@ -1200,7 +1236,7 @@ __device__ __forceinline__ void cg_dir_body(const Inst<T>& I, int lb, CgState& s
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* s = reinterpret_cast<T*>(smem_raw);
     constexpr bool SEQ = seq_lds(K);   // SEQ: stage r + beta p once beta is known
-    T* s_p = s + lds_conv(K, R);
+    T* s_p = s + lds_conv(K, R, sizeof(T));
     const int H = I.pr.H, W = I.pr.W;
     const int64_t HW = (int64_t)H * W;
     int ti0, tj0, ch;
@@ -1256,6 +1292,11 @@ __device__ __forceinline__ void cg_dir_body(const Inst<T>& I, int lb, CgState& s
     T acc[R];
 #pragma unroll
     for (int o = 0; o < R; ++o) acc[o] = T(0);
+    // the new direction at the outputs, read before the correlation (which
+    // may overwrite the tile)
+    T pn[R];
+#pragma unroll
+    for (int o = 0; o < R; ++o) pn[o] = s[(li0 + o + c0) * CP + tx + c0];
     correlate_sel<T, K, R, !CO>(s, CP, I.thf, I.mf_thf, I.mf_sh, kplane(I, ch), li0, tx, acc);
     T* __restrict__ Kp = I.Kp + ch * HW;
     T* __restrict__ qc = I.q + ch * HW;
@@ -1264,7 +1305,7 @@ __device__ __forceinline__ void cg_dir_body(const Inst<T>& I, int lb, CgState& s
         const int li = li0 + o, gi = ti0 + li;
         if (gi < H && gj < W) {
             const int e = gi * W + gj;
-            const T pv = s[(li + c0) * CP + tx + c0];
+            const T pv = pn[o];
             at(Pnew, e) = pv;
             at(Kp, e) = acc[o];
             if (init) at(qc, e) = pv;
@@ -1312,7 +1353,7 @@ __device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgSt
     constexpr bool SEQ = seq_lds(K);
     const int nx = SEQ ? 1 : C;
     T* s_c = sm;
-    T* s_x = SEQ ? sm : s_c + lds_conv(K, R);
+    T* s_x = SEQ ? sm : s_c + lds_conv(K, R, sizeof(T));
     T* s_p = s_x + nx * VR * VP;
     T* s_w = s_p + nx * VR * VP;
     T* s_mw = s_w + WR * WP;
@@ -1384,13 +1425,27 @@ __device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgSt
             const int eh = gjc < W - 1 ? e + 1 : e, ev = gic < H - 1 ? e + W : e;
             T s2 = T(0), mm = T(0);
             if (reg != 2) {
-                const int c_lo = reg == 1 ? ch : 0, c_hi = reg == 1 ? ch + 1 : C;
-                for (int c = c_lo; c < c_hi; ++c) {
-                    const T* xc = I.xt + c * HW;
-                    const T* pc = P + c * HW;
-                    const T x0 = ld<CO>(xc, e), p0 = ld<CO>(pc, e);
-                    const T xh = ld<CO>(xc, eh) - x0, xv = ld<CO>(xc, ev) - x0;
-                    const T ph = ld<CO>(pc, eh) - p0, pv = ld<CO>(pc, ev) - p0;
+                // every coupled channel's loads before any is used (a clamped
+                // channel index: no branch separates them)
+                const int c_lo = reg == 1 ? ch : 0, c_n = reg == 1 ? 1 : C;
+                T xa[kMaxC][3], pa[kMaxC][3];
+#pragma unroll
+                for (int k = 0; k < kMaxC; ++k) {
+                    const int64_t co = (int64_t)(c_lo + (k < c_n ? k : 0)) * HW;
+                    const T* xc = I.xt + co;
+                    const T* pc = P + co;
+                    xa[k][0] = ld<CO>(xc, e);
+                    xa[k][1] = ld<CO>(xc, eh);
+                    xa[k][2] = ld<CO>(xc, ev);
+                    pa[k][0] = ld<CO>(pc, e);
+                    pa[k][1] = ld<CO>(pc, eh);
+                    pa[k][2] = ld<CO>(pc, ev);
+                }
+#pragma unroll
+                for (int k = 0; k < kMaxC; ++k) {
+                    if (k >= c_n) break;
+                    const T xh = xa[k][1] - xa[k][0], xv = xa[k][2] - xa[k][0];
+                    const T ph = pa[k][1] - pa[k][0], pv = pa[k][2] - pa[k][0];
                     s2 += xh * xh + xv * xv;
                     mm += xh * ph + xv * pv;
                 }
@@ -1416,7 +1471,7 @@ __device__ __forceinline__ void cg_hvp_body(const Inst<T>& I, int lb, const CgSt
     const T* Mw = s_mw;
     // SEQ: the TV term and p of each output wait in LDS past the tile region
     // while the convolution tile reuses it (registers stay with the convolution)
-    T* s_park = sm + cmax(2 * VR * VP + 2 * WR * WP, lds_conv(K, R));
+    T* s_park = sm + cmax(2 * VR * VP + 2 * WR * WP, lds_conv(K, R, sizeof(T)));
     T hvv[SEQ ? 1 : R], pc[SEQ ? 1 : R];
 #pragma unroll
     for (int o = 0; o < R; ++o) {

@@ -17,15 +17,16 @@ static inline hipError_t ensure_lds(Kern kern, size_t bytes, size_t static_bytes
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 // static LDS of the correlation selector in the instantiations that have
-// the matrix-core path
+// the matrix-core path (its block maximum; the tiles live in the dynamic
+// region)
 template <typename T, int K, int R> constexpr size_t mf_static() {
-    if constexpr (mf_ok<T, K, R>()) return (size_t)mf_lds_bytes<K, R>() + 64;
+    if constexpr (mf_ok<T, K, R>()) return 64;
     else return 0;
 }
 
 template <typename T, int K, int R>
 static hipError_t conv_kr(const Group& g, const Inst<T>* insts, hipStream_t s) {
-    const size_t lds = sizeof(T) * lds_conv(K, R);
+    const size_t lds = sizeof(T) * lds_conv(K, R, sizeof(T));
     auto kern = k_conv<T, K, R>;
     hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
@@ -34,7 +35,7 @@ static hipError_t conv_kr(const Group& g, const Inst<T>* insts, hipStream_t s) {
 
 template <typename T, int K, int R>
 static hipError_t apg_grad_kr(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s) {
-    const size_t lds = sizeof(T) * lds_apg_grad(K, R, g.C, g.nw);
+    const size_t lds = sizeof(T) * lds_apg_grad(K, R, g.C, g.nw, sizeof(T));
     auto kern = k_apg_grad<T, K, R>;
     hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
@@ -43,7 +44,7 @@ static hipError_t apg_grad_kr(const Group& g, const Inst<T>* insts, const ApgSta
 
 template <typename T, int K, int R>
 static hipError_t apg_trial_kr(const Group& g, const Inst<T>* insts, const ApgState* sin, ApgState* sout, hipStream_t s) {
-    const size_t lds = sizeof(T) * lds_apg_trial(K, R, g.C);
+    const size_t lds = sizeof(T) * lds_apg_trial(K, R, g.C, sizeof(T));
     auto kern = k_apg_trial<T, K, R>;
     hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
@@ -53,7 +54,7 @@ static hipError_t apg_trial_kr(const Group& g, const Inst<T>* insts, const ApgSt
 template <typename T, int K, int R>
 static hipError_t cg_dir_kr(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init,
                             hipStream_t s) {
-    const size_t lds = sizeof(T) * lds_cg_dir(K, R);
+    const size_t lds = sizeof(T) * lds_cg_dir(K, R, sizeof(T));
     auto kern = k_cg_dir<T, K, R>;
     hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
@@ -63,7 +64,7 @@ static hipError_t cg_dir_kr(const Group& g, const Inst<T>* insts, const CgState*
 template <typename T, int K, int R>
 static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState* sin, CgState* sout, int init,
                             hipStream_t s) {
-    const size_t lds = sizeof(T) * lds_cg_hvp(K, R, g.C, g.nw);
+    const size_t lds = sizeof(T) * lds_cg_hvp(K, R, g.C, g.nw, sizeof(T));
     auto kern = k_cg_hvp<T, K, R>;
     hipError_t e = ensure_lds(kern, lds, mf_static<T, K, R>());
     if (e != hipSuccess) return e;
@@ -75,14 +76,14 @@ static hipError_t cg_hvp_kr(const Group& g, const Inst<T>* insts, const CgState*
 template <typename T, int K, int R, bool STEP>
 static size_t apg_team_lds(const Group& g) {
     if constexpr (STEP) return sizeof(T) * lds_apg_step<K, R>();
-    else return sizeof(T) * cmax(lds_apg_grad(K, R, g.C, g.nw), lds_apg_trial(K, R, g.C));
+    else return sizeof(T) * cmax(lds_apg_grad(K, R, g.C, g.nw, sizeof(T)), lds_apg_trial(K, R, g.C, sizeof(T)));
 }
 // one-pass team loops exist where the one-pass form does
 template <int K, int R> constexpr bool step_team() { return K >= 3 && K <= 11 && R <= 4; }
 template <typename T, int K, int R, bool STEP>
 static size_t cg_team_lds(const Group& g) {
     if constexpr (STEP) return sizeof(T) * lds_cg_step<K, R>();
-    else return sizeof(T) * cmax(lds_cg_dir(K, R), lds_cg_hvp(K, R, g.C, g.nw));
+    else return sizeof(T) * cmax(lds_cg_dir(K, R, sizeof(T)), lds_cg_hvp(K, R, g.C, g.nw, sizeof(T)));
 }
 
 template <typename T, int K, int R, bool STEP>

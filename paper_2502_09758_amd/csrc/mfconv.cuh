@@ -57,13 +57,15 @@ __host__ __device__ constexpr int mf_frag_bytes(int K) { return ((K * (((K + 15)
 // row pitch (floats) of the wave partial sums
 constexpr int kMfPP = 68;
 
-// LDS the correlation needs beside the staged tile: the two FP16 tiles,
-// which the wave partial sums reuse afterwards.
-template <int K, int R> __host__ __device__ constexpr int mf_lds_bytes() {
+// The correlation works in the staged tile's own LDS region: it writes the
+// tile's FP16 halves (two tiles of P16 halfs per row) over the FP32 tile,
+// then the waves' partial sums (two planes of 4R rows of kMfPP floats).
+// lds_conv(K, R, 4) floats cover all three (checked here).
+static_assert(kMfPP == 68, "partial-sum pitch of the LDS region sizing");
+template <int K, int R> __host__ __device__ constexpr bool mf_region_fits() {
     constexpr int CR = 4 * R + K - 1;
-    constexpr int tiles = 2 * CR * MfGeom<K>::P16 * 2;
-    constexpr int parts = 2 * 4 * R * kMfPP * 4;
-    return tiles > parts ? tiles : parts;
+    return MfGeom<K>::P16 == mf_p16(K) && CR * MfGeom<K>::P16 <= lds_conv(K, R, 4) &&
+           2 * 4 * R * kMfPP <= lds_conv(K, R, 4) && CR * (64 + K - 1) <= lds_conv(K, R, 4);
 }
 
 // 2^e as a float (|e| < 127)
@@ -115,15 +117,18 @@ __device__ __forceinline__ void mf_fragments(const double* __restrict__ theta, i
 // of the stencil passes (lane tx of wave wy holds rows wy R .. wy R+R-1 of
 // column tx), ker given by its fragments `frag` and the power of two
 // `ksh` they were scaled by.  s: the staged FP32 tile (4R+K-1 rows, 64+K-1
-// columns, read only, 8-byte aligned).  lds: mf_lds_bytes<K,R>() bytes of
-// LDS, 16-byte aligned.  Every thread of the block must call it (it has barriers).
+// columns, 16-byte aligned) at the start of an LDS region of
+// lds_conv(K, R, 4) floats, which the correlation overwrites (the tile is
+// gone when it returns).  Every thread of the block must call it (it has
+// barriers).
 template <int K, int R>
-__device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const uint4* __restrict__ frag, int ksh,
-                                               unsigned char* lds, int li0, int tx, float (&acc)[R]) {
+__device__ __forceinline__ void correlate_mfma(float* s, int pitch, const uint4* __restrict__ frag, int ksh, int li0,
+                                               int tx, float (&acc)[R]) {
     using G = MfGeom<K>;
     constexpr int TH = 4 * R, CR = TH + K - 1, CP = 64 + K - 1, NB = R, P16 = G::P16, PP = kMfPP;
+    static_assert(mf_region_fits<K, R>(), "the LDS region holds the FP16 tiles and the partial sums");
     __shared__ float s_mx[4];
-    _Float16* Sh = reinterpret_cast<_Float16*>(lds);
+    _Float16* Sh = reinterpret_cast<_Float16*>(s);
     _Float16* Sl = Sh + CR * P16;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 
@@ -147,26 +152,38 @@ __device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const 
     // a tile of zeros (or one below the normal range) keeps shift 0
     const int sh = mx >= 1.0e-30f ? mf_shift(mx) : 0;
     const float scale = mf_pow2(sh);
-    // the split: each thread converts runs of 8 columns of one row (float2
-    // reads, one 16-byte write per part); columns past the tile are zero
+    // the split, in place: each thread converts runs of 8 columns of one row
+    // (float2 reads; columns past the tile are zero), all of its runs read
+    // before the barrier and written after it (one 16-byte write per part)
     {
-        constexpr int NS = P16 / 8;
-        for (int e = t; e < CR * NS; e += 256) {
+        constexpr int NS = P16 / 8, IT = (CR * NS + 255) / 256;
+        union H8 { _Float16 h[8]; uint4 v; };
+        H8 hi[IT], lo[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = t + 256 * it;
             const int r = e / NS, c = 8 * (e - r * NS);
-            union { _Float16 h[8]; uint4 v; } hi, lo;
 #pragma unroll
             for (int k = 0; k < 8; k += 2) {
                 float2 v = make_float2(0.0f, 0.0f);
-                if (c + k < CP) v = *reinterpret_cast<const float2*>(s + r * pitch + c + k);
+                if (e < CR * NS && c + k < CP) v = *reinterpret_cast<const float2*>(s + r * pitch + c + k);
                 const float a = v.x * scale, b = v.y * scale;
                 const _Float16 ha = (_Float16)a, hb = (_Float16)b;
-                hi.h[k] = ha;
-                hi.h[k + 1] = hb;
-                lo.h[k] = (_Float16)(a - (float)ha);
-                lo.h[k + 1] = (_Float16)(b - (float)hb);
+                hi[it].h[k] = ha;
+                hi[it].h[k + 1] = hb;
+                lo[it].h[k] = (_Float16)(a - (float)ha);
+                lo[it].h[k + 1] = (_Float16)(b - (float)hb);
             }
-            *reinterpret_cast<uint4*>(Sh + r * P16 + c) = hi.v;
-            *reinterpret_cast<uint4*>(Sl + r * P16 + c) = lo.v;
+        }
+        __syncthreads();   // every thread has read the FP32 tile
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = t + 256 * it;
+            if (e < CR * NS) {
+                const int r = e / NS, c = 8 * (e - r * NS);
+                *reinterpret_cast<uint4*>(Sh + r * P16 + c) = hi[it].v;
+                *reinterpret_cast<uint4*>(Sl + r * P16 + c) = lo[it].v;
+            }
         }
     }
     __syncthreads();
@@ -212,7 +229,7 @@ __device__ __forceinline__ void correlate_mfma(const float* s, int pitch, const 
     // wave partials: lane (g, r16) holds rows 4g..4g+3, column r16 of each
     // block; rows padded to PP floats so that the four rows a write covers
     // fall in different LDS banks
-    float* P = reinterpret_cast<float*>(lds);   // [2][TH][PP]
+    float* P = s;   // [2][TH][PP], over the FP16 tiles
     auto at_p = [&](int half, int b, int k) -> float& {
         return P[(half * TH + 16 * (b >> 2) + 4 * g + k) * PP + 16 * (b & 3) + r16];
     };
