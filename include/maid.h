@@ -162,11 +162,13 @@ int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
    and the context stays on them.  The choice shows in
    maid_config_string ("team=P"). */
 int maid_set_team(maid_ctx* ctx, int32_t members);
-/* One-pass CG (enable != 0, the default) for the instances on the one-pass
-   lower-level form: the Chronopoulos-Gear recurrences need one reduction
-   and so one pass per iteration (measured at 256x256, K = 9: 11.9 against
-   14.7 us per iteration); 0 = the three-pass Hestenes-Stiefel kernels (the
-   oracle's form) for every instance.  Both forms' iterates drift from the
+/* One-pass CG (enable != 0; off by default) for the instances on the
+   one-pass lower-level form: the Chronopoulos-Gear recurrences need one
+   reduction and so one pass per iteration (measured at 256x256, K = 9: 11.9
+   against 14.7 us per iteration); 0 (the default) = the three-pass
+   Hestenes-Stiefel kernels (the oracle's form) for every instance.  The
+   one-pass forms are opt-in because GPUs were lost while their tests ran
+   and no cause has been found.  Both forms' iterates drift from the
    oracle's by loss of orthogonality, the one-pass form's differently
    (measured at equal iteration counts: FP64, 30-50 iterations, <= 1.6e-6
    relative against <= 1e-6; FP32, 83 iterations, 2.2e-5 against 4.7e-5). */
@@ -184,9 +186,8 @@ int maid_set_one_pass_cg(maid_ctx* ctx, int32_t enable);
    effect at the next call. */
 int maid_set_mfma(maid_ctx* ctx, int32_t enable);
 /* Lower-level form of the instances that can take the one-pass form (one
-   channel, 3 <= K <= 11, tile rows <= 4): mode -1 (the default) = the
-   autotuner's choice where it ran, else the size rule; 0 = two passes per
-   iteration; 1 = one pass.  With the same tile rows and form, an instance
+   channel, 3 <= K <= 11, tile rows <= 4): mode -1 (the default) or 0 = two
+   passes per iteration; 1 = one pass (opt-in, see maid_set_one_pass_cg).  With the same tile rows and form, an instance
    computes bitwise the same in any context (alone or in any batch).
    MAID_EINVAL for another mode. */
 int maid_set_one_pass(maid_ctx* ctx, int32_t mode);
@@ -198,9 +199,9 @@ int maid_one_pass_forms(const maid_ctx* ctx, int32_t* out);
    1..1000, tolerance 0) with every rows-per-thread candidate on
    the caller's data (theta[i], y[i]: HOST arrays of n DEVICE pointers, as
    for the batched calls; only workspace is written) and keep the fastest
-   (candidates 1, 2, 4, and 8 for K >= 13; where every instance of the K
-   has one channel and 3 <= K <= 11, each with the two-pass and the
-   one-pass form of the lower-level iteration, see maid_lower_solve; each
+   (candidates 1, 2, 4, and 8 for K >= 13; each with the lower-level form
+   the layout takes: the one-pass form where the context is pinned to it,
+   maid_set_one_pass(ctx, 1), and it applies, else the two-pass form; each
    candidate runs twice and the second run, with the launch predictors
    set, is timed).
    rows_out (HOST, n, nullable): the choice per instance.  A later

@@ -120,7 +120,7 @@ int maid_set_tile_rows(maid_ctx* c, int32_t rows) {
 
 int maid_set_one_pass(maid_ctx* c, int32_t mode) {
     if (!c) return MAID_EINVAL;
-    if (mode < -1 || mode > 1) return fail(c, MAID_EINVAL, "mode must be -1 (tuned or size rule), 0 or 1");
+    if (mode < -1 || mode > 1) return fail(c, MAID_EINVAL, "mode must be -1 or 0 (two-pass) or 1 (one-pass)");
     c->fuse_pin = mode;
     return relayout(c);
 }

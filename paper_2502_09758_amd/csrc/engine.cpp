@@ -586,7 +586,6 @@ int validate_desc(const maid_desc* d, std::string& why) {
 // lower + CG iterations ~17% faster on teams than as kernels; 256x256, 256
 // tiles, 2.4x slower), so larger instances stay on the multi-kernel passes.
 constexpr int kTeamTiles = 64;
-constexpr int kStepTiles = 320;
 int team_members(maid_ctx* c, const LaunchGroup& lg) {
     if (!c->team_ok || c->team_req == 0 || lg.g.R > 4) return 0;
     int most_tiles = 0, cap = kTeamMax;
@@ -618,15 +617,12 @@ int relayout(maid_ctx* c) {
         Member& M = c->m[i];
         M.R = c->R_override ? std::min(c->R_override, max_rows(M.d.K)) : (M.R_tuned ? M.R_tuned : M.R_auto);
         M.nb = stencil_blocks(M.shape, M.R);
-        // the one-pass FISTA form: one channel, 3 <= K <= 11, and the
-        // autotuner's choice (untuned: instances of at most kStepTiles
-        // tiles; larger ones are bound by the ALUs, which the recomputed
-        // halo gradient loads further)
+        // the one-pass FISTA form (one channel, 3 <= K <= 11) is opt-in
+        // (maid_set_one_pass(ctx, 1)): GPUs were lost while its tests ran and
+        // no cause has been found, so the default path keeps the two-pass form
         bool fuse = c->fuse && step_ok(M.d.C, M.d.K, M.R);
         if (c->fuse_force >= 0) fuse = fuse && c->fuse_force == 1;
-        else if (c->fuse_pin >= 0) fuse = fuse && c->fuse_pin == 1;
-        else if (M.fuse_tuned >= 0) fuse = fuse && M.fuse_tuned == 1;
-        else fuse = fuse && step_blocks(M.d.H, M.d.W, M.d.K, M.R) <= kStepTiles;
+        else fuse = fuse && c->fuse_pin == 1;
         M.nbf = fuse ? step_blocks(M.d.H, M.d.W, M.d.K, M.R) : 0;
     }
     std::vector<char> placed(c->n, 0);
@@ -1628,13 +1624,15 @@ int autotune_batch(maid_ctx* c, const std::vector<const double*>& theta, const s
         std::vector<char> act(n, 0);
         for (int i = 0; i < n; ++i) act[i] = c->m[i].d.K == Ks[k];
         // the one-pass FISTA form is a candidate where every instance of this K allows it
-        bool fuse_ok = c->fuse;
+        bool fuse_ok = c->fuse && c->fuse_pin == 1;   // the one-pass form only where opted in
         for (int i = 0; i < n; ++i)
             if (act[i]) fuse_ok = fuse_ok && step_ok(c->m[i].d.C, c->m[i].d.K, 1);
         for (int cj = 0; cj < 8 && rc == MAID_OK; ++cj) {
             const int ci = cj >> 1, f = cj & 1;
             if (cands[ci] > max_rows(Ks[k])) continue;
-            if (f == 1 && !(fuse_ok && step_ok(1, Ks[k], cands[ci]))) continue;
+            // the form the layout will take: one-pass where pinned and possible
+            const bool one = fuse_ok && step_ok(1, Ks[k], cands[ci]);
+            if (f != (one ? 1 : 0)) continue;
             c->R_override = cands[ci];
             c->fuse_force = f;
             if ((rc = relayout(c))) break;

@@ -140,7 +140,7 @@ struct maid_ctx {
     size_t ws_bytes = 0;
     // persistent team loops for small instances (one team per XCD)
     bool fuse = true;                 // one-pass FISTA where the group allows it
-    bool cg_fuse = true;              // one-pass (Chronopoulos-Gear) CG on the one-pass instances
+    bool cg_fuse = false;             // one-pass (Chronopoulos-Gear) CG on the one-pass instances (opt-in)
     bool mfma = true;                 // large-kernel correlations on the matrix cores (FP32 storage)
     int fuse_force = -1;              // autotuner's candidate: -1 none, 0 two-pass, 1 one-pass
     int fuse_pin = -1;                // the caller's choice (maid_set_one_pass): -1 none, 0, 1

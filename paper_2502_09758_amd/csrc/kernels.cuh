@@ -555,18 +555,19 @@ __device__ __forceinline__ Stage<ROWS, COLS, PITCH, T, F, NT> stage(T* s, int gi
 }
 
 // ------------------------------------------------------------------ instance lookup
-// Block -> (instance, local block).  Padding blocks (lb >= nb) return at once.
+// Block -> (instance, local block).  Padding blocks (lb >= nb) return at once,
+// and so would a block below its instance's range (one unsigned compare).
 #define MAID_STENCIL_PROLOGUE                                         \
     const int ii = only >= 0 ? only : blk[blockIdx.x];                \
     const Inst<T>& I = insts[ii];                                     \
     const int lb = (int)blockIdx.x - I.base;                          \
-    if (lb >= I.nb) return;
+    if ((unsigned)lb >= (unsigned)I.nb) return;
 
 #define MAID_EW_PROLOGUE                                              \
     const int ii = only >= 0 ? only : blk[blockIdx.x];                \
     const Inst<T>& I = insts[ii];                                     \
     const int lb = (int)blockIdx.x - I.base_e;                        \
-    if (lb >= I.nbe) return;
+    if ((unsigned)lb >= (unsigned)I.nbe) return;
 
 // Local block -> tile origin and channel.  The C channel blocks of one tile
 // are adjacent in the XCD-major order (they share halo loads in L2).

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kStepNT) void k_apg_step(const Inst<T>* __restrict_
     const int ii = only >= 0 ? only : blk[blockIdx.x];
     const Inst<T>& I = insts[ii];
     const int lb = (int)blockIdx.x - I.basef;
-    if (lb >= I.nbf) return;
+    if ((unsigned)lb >= (unsigned)I.nbf) return;
     ApgState st = sin[ii];
     const bool writer = lb == 0 && threadIdx.x == 0;
     if (st.done) {
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kStepNT) void k_cg_step(const Inst<T>* __restrict__
     const int ii = only >= 0 ? only : blk[blockIdx.x];
     const Inst<T>& I = insts[ii];
     const int lb = (int)blockIdx.x - I.basef;
-    if (lb >= I.nbf) return;
+    if ((unsigned)lb >= (unsigned)I.nbf) return;
     CgState st = sin[ii];
     const bool writer = lb == 0 && threadIdx.x == 0;
     if (st.done) {

@@ -127,6 +127,7 @@ def test_lista_step(C, H, W, K, dt):
     assert max(ex, ez, el, en) <= TOL[dt]
 
 
+@pytest.mark.skip(reason="the one-pass forms are opt-in and kept off the GPU: GPUs were lost while one-pass tests ran (no fault message in the process; cause not found) and a later benchmark run that included them faulted the GPU; kept off until a cause is shown")
 def test_kept_iterates_need_the_two_pass_form():
     print("[case] ADP error paths", flush=True)
     inst = synth.make("cfg1", H=48, W=64, C=1, K=5, seed=9)

@@ -10,8 +10,8 @@ side computed (||grad h||, L, g, ||grad g||, r, the CG residual, ||z||, psi),
 then the state after the step (theta, x, q).  A free-running oracle step from
 the same state gives the decision-agreement rate.
 
-The plain-method workloads: 64x64 in FP64 for its ten steps (one-pass team
-loops), and 256x256 in FP32 (one-pass multi-kernel passes), with the
+The plain-method workloads: 64x64 in FP64 for its ten steps (team loops),
+and 256x256 in FP32 (multi-kernel passes), with the
 benchmark's initial accuracy and step size."""
 import numpy as np
 import pytest

@@ -25,7 +25,7 @@ from paper_2502_09758_amd import _lib as L
 from paper_2502_09758_amd import synth
 from paper_2502_09758_amd.maid import Maid, MaidBatch, MaidState
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="the one-pass forms are opt-in and kept off the GPU: GPUs were lost while one-pass tests ran (no fault message in the process; cause not found) and a later benchmark run that included them faulted the GPU; kept off until a cause is shown")]
 
 
 def dev(a, dtype):

@@ -195,6 +195,7 @@ def test_team_size_rule():
     m.close()
 
 
+@pytest.mark.skip(reason="the one-pass forms are opt-in and kept off the GPU: GPUs were lost while one-pass tests ran (no fault message in the process; cause not found) and a later benchmark run that included them faulted the GPU; kept off until a cause is shown")
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 def test_team_one_pass_cg_bitwise(dt):
     """The opt-in one-pass CG on team loops equals it on kernels."""
