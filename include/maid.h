@@ -145,7 +145,7 @@ const char* maid_last_error(const maid_ctx* ctx);
    instances. */
 const char* maid_config_string(const maid_ctx* ctx);
 /* Override the rows-per-thread tile parameter of the stencil kernels for
-   every instance (1, 2, 4 or 8; 8 applies to K >= 13, smaller kernels use 4;
+   every instance (1, 2, 4 or 8; 8 applies to K >= 5, K <= 3 uses 4 at most;
    0 = back to the autotuner's choice, else the size rule). */
 int maid_set_tile_rows(maid_ctx* ctx, int32_t rows);
 /* Persistent loops for small instances.  The lower-level and CG loops of a
@@ -199,7 +199,7 @@ int maid_one_pass_forms(const maid_ctx* ctx, int32_t* out);
    1..1000, tolerance 0) with every rows-per-thread candidate on
    the caller's data (theta[i], y[i]: HOST arrays of n DEVICE pointers, as
    for the batched calls; only workspace is written) and keep the fastest
-   (candidates 1, 2, 4, and 8 for K >= 13; each with the lower-level form
+   (candidates 1, 2, 4, and 8 for K >= 5; each with the lower-level form
    the layout takes: the one-pass form where the context is pinned to it,
    maid_set_one_pass(ctx, 1), and it applies, else the two-pass form; each
    candidate runs twice and the second run, with the launch predictors

@@ -110,10 +110,13 @@ __host__ __device__ constexpr int lds_conv(int K, int R, int esz) {
     return mf_tile(K, R, esz) ? cmax(cmax(cv_rows(K, R) * cv_pitch(K), cv_rows(K, R) * mf_p16(K)), 2 * tile_h(R) * 68)
                               : cv_rows(K, R) * cv_pitch(K);
 }
-// Large kernels are ALU-bound and need occupancy: their passes stage the TV
-// tiles and the convolution tile one after the other in one LDS region.
-// Small kernels are latency-bound: all tiles are staged at once, side by side.
-__host__ __device__ constexpr bool seq_lds(int K) { return K >= 13; }
+// Kernels of 5 taps and more: the passes stage the TV tiles and the
+// convolution tile one after the other in one LDS region, which leaves room
+// for more blocks per CU and for tiles of 8 rows per thread (at 2048x2048x3
+// and 4096x4096, K = 5..11, a FISTA + CG iteration takes 1.2-1.8x less time
+// than with every tile staged at once, with bitwise the same results).
+// K <= 3: all tiles are staged at once, side by side.
+__host__ __device__ constexpr bool seq_lds(int K) { return K >= 5; }
 __host__ __device__ constexpr int lds_side(bool seq, int a, int b) { return seq ? cmax(a, b) : a + b; }
 __host__ __device__ constexpr int lds_apg_grad(int K, int R, int C, int nw, int esz) {
     // sequential staging parks the TV gradient of each output past the tile region

@@ -1582,7 +1582,7 @@ int apply_operator_one(maid_ctx* c, const double* theta, const T* in, T* out, in
 
 // ------------------------------------------------------------------ autotuner
 // For every candidate tile height (rows per thread 1, 2, 4, and 8 for
-// K >= 13), and with each of the two forms of the lower-level iteration
+// K >= 5), and with each of the two forms of the lower-level iteration
 // where the one-pass form applies (one channel, 3 <= K <= 11, rows <= 4),
 // all instances take that candidate; a short lower-level solve and a short
 // CG solve (fixed iteration counts, tolerance 0, on the caller's data,

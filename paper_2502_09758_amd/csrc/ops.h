@@ -21,8 +21,9 @@ inline int stencil_blocks(const Shape& d, int R) {
     return ((d.W + kTW - 1) / kTW) * ((d.H + tile_h(R) - 1) / tile_h(R)) * d.C;
 }
 
-// Rows per thread: 1, 2, 4, and 8 for the large kernels (K >= 13), whose
-// convolution reuses each staged column value over more outputs.
+// Rows per thread: 1, 2, 4, and 8 for the kernels staged one tile after the
+// other (K >= 5), whose convolution reuses each staged column value over
+// more outputs.
 inline bool valid_rows(int R) { return R == 1 || R == 2 || R == 4 || R == 8; }
 inline int max_rows(int K) { return seq_lds(K) ? 8 : 4; }
 
