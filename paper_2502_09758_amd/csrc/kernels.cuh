@@ -354,9 +354,12 @@ __device__ __forceinline__ void correlate_col(const T* s, int pitch, const T* __
 
 // Small kernels with short columns unroll the column loop too, so that the
 // LDS reads of the next columns are in flight during this column's FMAs (a
-// pass of a small image has few waves per SIMD to hide that latency).
+// pass of a small image has few waves per SIMD to hide that latency).  Tiles
+// of 8 rows per thread unroll it only up to K = 5: at K = 7 and 9 the
+// unrolled loop held 136-168 VGPRs (3 waves per SIMD, and the trial pass
+// spilled at K = 9) and ran slower than the rolled K = 11 one.
 template <typename T, int K, int R> __host__ __device__ constexpr bool corr_unrolled() {
-    return K <= 5 || (K <= 11 && K * (R + K - 1) <= (sizeof(T) == 4 ? 160 : 96));
+    return K <= 5 || (R <= 4 && K <= 11 && K * (R + K - 1) <= (sizeof(T) == 4 ? 160 : 96));
 }
 
 template <typename T, int K, int R>
